@@ -1,0 +1,197 @@
+/*
+ * hk.h -- C ABI of the MI355X (gfx950) line-by-line opacity library.
+ *
+ * The library computes the hot path of the line-by-line opacity method of
+ * HELIOS-K 2.0 (Grimm et al. 2021, arXiv:2101.02005):
+ *
+ *   k(nu_j) = sum over lines i with |nu_j - nu_i| <= cut of S_i(T) V(nu_j - nu_i; alpha_i, gamma_i)
+ *
+ *   S_i(T)  line strength at T: eq. (S) in the form of eq. (S1) (Sec. 2.2.3, Sec. 2.4.3
+ *           step 1); from the strength S_ref at T_ref it is
+ *           S_ref Q(T_ref)/Q(T) exp(c2 E''(1/T_ref - 1/T)) (1 - e^{-c2 nu/T})/(1 - e^{-c2 nu/T_ref}),
+ *           with Q(T) = q_a T^q_b and c2 = h c / k_B.
+ *   alpha_i Doppler width without the sqrt(ln 2) factor, the inverse of eq. (alphaD):
+ *           alpha = (nu/c) sqrt(2 k_B T / m).
+ *   gamma_i Lorentz half-width, ExoMol form of Sec. 2.2 without the natural term:
+ *           gamma = gamma_ref (T_ref/T)^n (P/P_ref).
+ *   V       unit-area Voigt profile Re w((d + i gamma)/alpha) / (sqrt(pi) alpha), w the
+ *           Faddeeva function (Sec. 2.2.4, Sec. 2.4.2 parameters x and y).
+ *   grid    nu_j = nu_start + j dnu, 0 <= j < n (uniform resolution, Sec. 2.4.2 eq. x).
+ *   cut     fixed cutting length in cm^-1, inclusive (Sec. 2.4.3 step 4); +INFINITY: none.
+ *
+ * Units: nu, dnu, cut, E'' in cm^-1; S_ref in cm/molecule at T_ref; gamma_ref in
+ * cm^-1 atm^-1; T in K; P in atm; k in cm^2/molecule (the paper's cm^2/g is k/m).
+ *
+ * Conventions shared by every entry point:
+ *  - Array arguments are DEVICE pointers unless the comment says "host". Inputs and
+ *    outputs belong to the caller; the library never frees them.
+ *  - All arguments are validated on the host before any device work. A rejected call
+ *    returns HK_EINVAL and leaves every output untouched. Device failures return
+ *    HK_EDEVICE. hk_last_error() gives a thread-local message for the last failure.
+ *  - Work is enqueued on the caller's stream. hk_opacity, hk_opacity_batched and
+ *    hk_opacity_backward do not synchronize the host, except for the first call with a
+ *    new tuning key when autotuning is enabled (HK_AUTOTUNE=1), and for building the
+ *    graph of a new batched configuration (documented below).
+ *  - Results are bitwise deterministic for a fixed tuning (no floating-point atomics;
+ *    all sums run in a fixed order). hk_get_timings() reports the tuning used.
+ *  - Calls on different streams with distinct workspaces may overlap.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef HK_H
+#define HK_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hk_status {
+  HK_OK = 0,
+  HK_EINVAL = 1,        /* invalid argument (nothing was launched, outputs untouched) */
+  HK_ENOMEM = 2,        /* device or host allocation failed, or a size overflowed */
+  HK_EDEVICE = 3,       /* a HIP call failed (message in hk_last_error) */
+  HK_EUNSUPPORTED = 4   /* the current device is not gfx950 */
+} hk_status;
+
+/* Species constants. Q(T) = q_a T^q_b. */
+typedef struct hk_species {
+  double mass_amu;   /* molecular mass [amu], > 0 */
+  double T_ref;      /* reference temperature of S_ref and gamma_ref [K], > 0 */
+  double P_ref_atm;  /* reference pressure of gamma_ref [atm], > 0 */
+  double q_a, q_b;   /* partition function coefficients, q_a > 0 */
+} hk_species;
+
+/* Uniform grid nu_j = nu_start + j*dnu, 0 <= j < n (dnu > 0, 0 <= n < 2^31). */
+typedef struct hk_grid {
+  double nu_start, dnu;
+  int64_t n;
+} hk_grid;
+
+/* Optional per-line replacements (device, caller's line order, length n_lines; any may be
+ * NULL). Used by automatic differentiation to evaluate with the current parameters without
+ * re-binning. */
+typedef struct hk_line_override {
+  const double* S_ref;
+  const double* gamma_ref;
+  const double* n_exp;
+} hk_line_override;
+
+/* Opaque handle: the line list binned by wavenumber (device copies sorted by nu-bin,
+ * stable within a bin), the permutation to the caller's order, and the species. */
+typedef struct hk_lines hk_lines;
+
+/* Timings and tuning of the last completed call on this thread (milliseconds, filled only
+ * when HK_TIMING=1 is set in the environment; otherwise the times are negative). */
+typedef struct hk_timings {
+  double prep_ms, worklist_ms, voigt_ms, combine_ms, backward_ms, bin_ms;
+  int32_t tile_width;      /* grid points per tile (workgroup) */
+  int32_t lines_per_batch; /* lines staged in LDS per batch */
+  int32_t chunk_lines;     /* lines per work item of a heavy tile */
+  int32_t n_items;         /* upper bound of work items of the last call */
+} hk_timings;
+
+/*
+ * hk_prepare_lines -- bin a line list by wavenumber (the paper sorts the line quantities
+ * along nu, Sec. 2.4.3 step 3). Stable counting (radix) sort on a 24-bit linear bin key,
+ * then a gather of the five fields into sorted device arrays owned by the handle.
+ *
+ *   nu, S_ref, E_low, gamma_ref, n_exp : device, float64[n_lines], caller order.
+ *       nu > 0 and finite; S_ref >= 0 finite; E_low finite; gamma_ref >= 0 finite;
+ *       n_exp finite. Checked on the device; a violation returns HK_EINVAL.
+ *   n_lines : 1 <= n_lines < 2^31.
+ *   sp      : host pointer, validated (all fields finite, mass, T_ref, P_ref, q_a > 0).
+ *   stream  : work is ordered on this stream; the call blocks the host once to read the
+ *             validation result and the wavenumber range.
+ *   out     : host pointer receiving the handle (set only on HK_OK).
+ * Memory: about 56 bytes per line are held by the handle (+ 24 temporary).
+ */
+hk_status hk_prepare_lines(const double* nu, const double* S_ref, const double* E_low,
+                           const double* gamma_ref, const double* n_exp, int64_t n_lines,
+                           const hk_species* sp, hipStream_t stream, hk_lines** out);
+
+/* Release a handle; blocks until work issued through it on its preparation stream completes.
+ * NULL is accepted. */
+hk_status hk_release_lines(hk_lines* lines);
+
+/* Number of lines held by a handle (host). */
+int64_t hk_lines_count(const hk_lines* lines);
+
+/*
+ * hk_workspace_size -- bytes of device workspace needed by a call.
+ *   mode 0: hk_opacity (n_pairs must be 1, grids = &grid)
+ *   mode 1: hk_opacity_batched (n_pairs pairs, grids[n_pairs] host array; n_temps distinct
+ *           temperatures, pass n_pairs if unknown: it is an upper bound)
+ *   mode 2: hk_opacity_backward (n_pairs = 1)
+ * The workspace must be 256-byte aligned. Returns HK_EINVAL for bad arguments.
+ */
+hk_status hk_workspace_size(const hk_lines* lines, int mode, int32_t n_pairs, int32_t n_temps,
+                            const hk_grid* grids, double cutoff, size_t* bytes);
+
+/*
+ * hk_opacity -- k on one grid at one (T, P).
+ *   T > 0, P_atm >= 0 finite; grid valid; cutoff > 0 (finite or +INFINITY).
+ *   ovr : host pointer or NULL (per-line replacements, see hk_line_override).
+ *   k   : device float32[grid.n], written entirely (points no line reaches get 0).
+ *   ws  : device workspace of at least hk_workspace_size(mode 0) bytes.
+ * Precision: S(T), widths, line-centre offsets and cut bounds in FP64; the profile and the
+ * per-point sums in FP32 with compensated (Kahan) accumulation; k stored as FP32.
+ */
+hk_status hk_opacity(const hk_lines* lines, const hk_line_override* ovr, double T, double P_atm,
+                     hk_grid grid, double cutoff, float* k, void* ws, size_t ws_bytes,
+                     hipStream_t stream);
+
+/*
+ * hk_opacity_batched -- k for many (T, P) pairs in one persistent launch (the paper's
+ * several pressures per run, Sec. 2.4.5 and Table timing2, extended to temperatures).
+ *   n_pairs >= 1; T, P_atm : host float64[n_pairs]; grids : host hk_grid[n_pairs] (may
+ *   differ per pair); out_offset : host int64[n_pairs], pair p writes
+ *   k[out_offset[p] .. out_offset[p] + grids[p].n). Output ranges must not overlap.
+ *   Pairs with equal T share one strength/width pass.
+ * The call records its kernels in a hipGraph on first use of a configuration (argument
+ * values and pointers) and replays the cached graph afterwards; building the graph blocks
+ * the host once. Set HK_GRAPH=0 to launch without a graph.
+ */
+hk_status hk_opacity_batched(const hk_lines* lines, int32_t n_pairs, const double* T,
+                             const double* P_atm, const hk_grid* grids, const int64_t* out_offset,
+                             double cutoff, float* k, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * hk_opacity_backward -- adjoint of L = sum_j dL_dk[j] k_j at one (T, P) (not in the paper;
+ * derived from eqs. S1, alphaD and the ExoMol width). Strengths and widths are recomputed.
+ *   dL_dk     : device float32[grid.n] upstream gradient.
+ *   dL_dT_lnP : device float64[2] receives dL/dT and dL/d(ln P).
+ *   dL_dSref  : device float64[n_lines], caller order (FP64: S(T)/S_ref spans beyond FP32).
+ *   dL_dgref, dL_dn : device float32[n_lines], caller order. Any of the three may be NULL.
+ *   The cut indicator is not differentiated (the cut is fixed in cm^-1).
+ */
+hk_status hk_opacity_backward(const hk_lines* lines, const hk_line_override* ovr, double T,
+                              double P_atm, hk_grid grid, double cutoff, const float* dL_dk,
+                              double* dL_dT_lnP, double* dL_dSref, float* dL_dgref, float* dL_dn,
+                              void* ws, size_t ws_bytes, hipStream_t stream);
+
+/* Per-line cut bounds of the last prepared grid, for tests: writes for every line (caller
+ * order) the inclusive grid range [j_lo, j_hi] of |nu_j - nu_i| <= cut (j_hi < j_lo: empty).
+ * j_lo, j_hi: device int32[n_lines]. */
+hk_status hk_debug_cut_bounds(const hk_lines* lines, hk_grid grid, double cutoff, int32_t* j_lo,
+                              int32_t* j_hi, hipStream_t stream);
+
+/* Sorted view for tests: copies the handle's bin keys (uint32) and permutation (int32:
+ * sorted position -> caller index) to device buffers of n_lines elements. */
+hk_status hk_debug_sorted(const hk_lines* lines, uint32_t* keys, int32_t* perm, hipStream_t stream);
+
+/* Per-line strength and widths at (T, P) in caller order (device float64 arrays of
+ * n_lines; any may be NULL): S(T), alpha, gamma, as the kernels use them. */
+hk_status hk_debug_line_params(const hk_lines* lines, double T, double P_atm, double* S_T,
+                               double* alpha, double* gamma, hipStream_t stream);
+
+hk_status hk_get_timings(hk_timings* out);
+const char* hk_last_error(void);
+const char* hk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HK_H */

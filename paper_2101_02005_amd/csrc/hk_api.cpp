@@ -1,0 +1,595 @@
+// Host side of the opacity library: argument validation, memory layout, planning of the
+// tile work list, launches, graph cache and timing. The C ABI is declared in include/hk.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "hk.h"
+#include "hk_internal.h"
+
+struct hk_lines {
+  int device;
+  int64_t N;
+  hk_species sp;
+  hk::KeyMap km;
+  double numin, numax;
+  double *nu, *Sref, *E, *gref, *nexp;  // sorted by bin key (stable)
+  uint32_t* keys;                       // sorted bin keys
+  int32_t* perm;                        // sorted position -> caller index
+  void* mem;
+};
+
+namespace {
+
+// Physical constants of the product (the paper prints k_B with eq. gammaD and c with eq. S;
+// h and the atomic mass unit are CODATA 2010 values of the same vintage).
+constexpr double kB = 1.3806489e-16;      // erg / K
+constexpr double kC = 2.99792458e10;      // cm / s
+constexpr double kH = 6.62606957e-27;     // erg s
+constexpr double kAMU = 1.660538921e-24;  // g
+constexpr double kC2 = kH * kC / kB;      // cm K
+
+// |z| thresholds of the far-wing series orders 1..4 (relative truncation error < 2e-6)
+constexpr double kZK[hk::kKmax] = {870.0, 37.5, 13.8, 8.7};
+
+thread_local std::string g_err;
+thread_local hk_timings g_tim = {-1, -1, -1, -1, -1, -1, 0, 0, 0, 0};
+
+hk_status fail(hk_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HK_HIP(call)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) return fail(HK_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+bool env_flag(const char* name, bool dflt) {
+  const char* v = getenv(name);
+  if (!v || !*v) return dflt;
+  return !(v[0] == '0' || v[0] == 'n' || v[0] == 'N' || v[0] == 'f' || v[0] == 'F');
+}
+
+int env_int(const char* name, int dflt) {
+  const char* v = getenv(name);
+  return (v && *v) ? atoi(v) : dflt;
+}
+
+struct DevInfo {
+  int cus = 0;
+  int wg_per_cu[2] = {1, 1};  // Voigt kernel occupancy for 4 and 8 slots
+};
+
+std::mutex g_mu;
+std::map<int, DevInfo> g_dev;
+
+// Weideman (1994) coefficients: a = Re DFT(fftshift(f)) / (2M), f(t) = e^{-t^2}(L^2 + t^2) at
+// t = L tan(theta/2), theta = k pi / M, k = -M+1..M-1 (f = 0 at k = -M), M = 2N, L = sqrt(N/sqrt2).
+void weideman_coeffs(int N, double* a_out, double* L_out) {
+  const int M = 2 * N, n2 = 2 * M;
+  const double L = sqrt(N / sqrt(2.0));
+  std::vector<double> f(n2), g(n2);
+  f[0] = 0.0;
+  for (int k = -M + 1; k <= M - 1; ++k) {
+    const double th = k * M_PI / M;
+    const double t = L * tan(th / 2);
+    f[k + M] = exp(-t * t) * (L * L + t * t);
+  }
+  for (int m = 0; m < n2; ++m) g[m] = f[(m + M) % n2];
+  for (int n = 1; n <= N; ++n) {
+    double re = 0.0;
+    for (int r = 0; r < n2; ++r) re += g[r] * cos(2.0 * M_PI * (double)n * r / n2);
+    a_out[n - 1] = re / n2;
+  }
+  *L_out = L;
+}
+
+hk_status device_init(int* dev_out, DevInfo* info) {
+  int dev = -1;
+  HK_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_dev.find(dev);
+  if (it == g_dev.end()) {
+    hipDeviceProp_t prop;
+    HK_HIP(hipGetDeviceProperties(&prop, dev));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      return fail(HK_EUNSUPPORTED, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+    double a[hk::kWeidN], L;
+    weideman_coeffs(hk::kWeidN, a, &L);
+    HK_HIP(hk::upload_weideman(a, L));
+    DevInfo di;
+    di.cus = prop.multiProcessorCount;
+    di.wg_per_cu[0] = hk::voigt_max_blocks_per_cu(4);
+    di.wg_per_cu[1] = hk::voigt_max_blocks_per_cu(8);
+    it = g_dev.emplace(dev, di).first;
+  }
+  *dev_out = dev;
+  *info = it->second;
+  return HK_OK;
+}
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+bool species_ok(const hk_species* sp) {
+  return sp && std::isfinite(sp->mass_amu) && sp->mass_amu > 0 && std::isfinite(sp->T_ref) && sp->T_ref > 0 &&
+         std::isfinite(sp->P_ref_atm) && sp->P_ref_atm > 0 && std::isfinite(sp->q_a) && sp->q_a > 0 &&
+         std::isfinite(sp->q_b);
+}
+
+bool grid_ok(const hk_grid& g) {
+  return std::isfinite(g.nu_start) && std::isfinite(g.dnu) && g.dnu > 0 && g.n >= 1 && g.n < (int64_t(1) << 31) &&
+         std::isfinite(g.nu_start + (double)(g.n - 1) * g.dnu);
+}
+
+bool cut_ok(double c) { return c > 0 && (std::isfinite(c) || std::isinf(c)); }
+
+// ------------------------------------------------------------------ forward plan
+struct Plan {
+  int slots = 8, W = 2048;
+  int chunk = 0;
+  int n_pairs = 0, n_temps = 0;
+  int n_tiles_total = 0;
+  int64_t items_bound = 0;
+  int grid = 0;
+  size_t off_S = 0, off_g = 0, off_pairs = 0, off_lo = 0, off_hi = 0, off_nc = 0, off_ib = 0, off_cnt = 0,
+         off_part = 0, total = 0;
+  std::vector<hk::PairDesc> pairs;
+  std::vector<double> temps;
+};
+
+int pick_slots() {
+  const int s = env_int("HK_SLOTS", 8);
+  return (s == 4) ? 4 : 8;
+}
+
+// Tiles a line can be counted in: windows [nu_j0 - cut, nu_j1 + cut] widened by two bins.
+int64_t visits_per_line(const hk_lines* L, const hk_grid& g, double cut, int W, int64_t n_tiles) {
+  if (std::isinf(cut)) return n_tiles;
+  const double binw = L->km.scale > 0 ? 1.0 / L->km.scale : 0.0;
+  const double ell = 2.0 * cut + 4.0 * binw;
+  const double v = std::floor(ell / (W * g.dnu)) + 2.0;
+  return v > (double)n_tiles ? n_tiles : (int64_t)v;
+}
+
+hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const double* T, const double* P,
+                    const hk_grid* grids, const int64_t* out_off, double cut, const DevInfo& di, Plan* pl) {
+  pl->slots = pick_slots();
+  pl->W = hk::kWavesPerWG * hk::kWave * pl->slots;
+  pl->n_pairs = n_pairs;
+  const int64_t N = L->N;
+  // distinct temperatures
+  pl->temps.clear();
+  std::vector<int> tidx(n_pairs, 0);
+  if (T) {
+    for (int p = 0; p < n_pairs; ++p) {
+      int found = -1;
+      for (size_t t = 0; t < pl->temps.size(); ++t)
+        if (pl->temps[t] == T[p]) { found = (int)t; break; }
+      if (found < 0) { found = (int)pl->temps.size(); pl->temps.push_back(T[p]); }
+      tidx[p] = found;
+    }
+    pl->n_temps = (int)pl->temps.size();
+  } else {
+    pl->n_temps = n_temps_bound;
+  }
+  // tiles and the bound on line visits
+  int64_t tiles = 0;
+  double visits = 0.0;
+  pl->pairs.assign(n_pairs, hk::PairDesc{});
+  for (int p = 0; p < n_pairs; ++p) {
+    const int64_t nt = (grids[p].n + pl->W - 1) / pl->W;
+    if (tiles + nt >= (int64_t(1) << 30)) return fail(HK_ENOMEM, "too many grid tiles");
+    hk::PairDesc& d = pl->pairs[p];
+    d.nu_start = grids[p].nu_start;
+    d.dnu = grids[p].dnu;
+    d.n = grids[p].n;
+    d.out_off = out_off ? out_off[p] : 0;
+    d.pfac = P ? P[p] / L->sp.P_ref_atm : 1.0;
+    d.beta = T ? std::sqrt(2.0 * kB * T[p] / (L->sp.mass_amu * kAMU)) / kC : 0.0;
+    d.tidx = tidx[p];
+    d.tile_base = (int32_t)tiles;
+    d.n_tiles = (int32_t)nt;
+    tiles += nt;
+    visits += (double)N * (double)visits_per_line(L, grids[p], cut, pl->W, nt);
+  }
+  pl->n_tiles_total = (int)tiles;
+  // work-item size: enough items to balance the persistent grid
+  const int wgs = di.cus * di.wg_per_cu[pl->slots == 8 ? 1 : 0];
+  double c = std::ceil(visits / (64.0 * (wgs > 0 ? wgs : 1024)));
+  const int env_chunk = env_int("HK_CHUNK", 0);
+  if (env_chunk > 0) c = env_chunk;
+  if (c < hk::kLB) c = hk::kLB;
+  if (c > (1 << 22)) c = 1 << 22;
+  pl->chunk = (int)(std::ceil(c / hk::kLB) * hk::kLB);
+  const double items = (double)tiles + std::ceil(visits / pl->chunk);
+  if (items >= 2.0e9) return fail(HK_ENOMEM, "work list too large (%.3g items)", items);
+  pl->items_bound = (int64_t)items;
+  pl->grid = (int)std::min<int64_t>(pl->items_bound, (int64_t)(wgs > 0 ? wgs : 1024));
+  // workspace layout (256-byte aligned sections)
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+  pl->off_S = take(sizeof(float) * (size_t)N * pl->n_temps);
+  pl->off_g = take(sizeof(float) * (size_t)N * pl->n_temps);
+  pl->off_pairs = take(sizeof(hk::PairDesc) * n_pairs);
+  pl->off_lo = take(sizeof(int32_t) * tiles);
+  pl->off_hi = take(sizeof(int32_t) * tiles);
+  pl->off_nc = take(sizeof(int32_t) * tiles);
+  pl->off_ib = take(sizeof(int32_t) * (tiles + 1));
+  pl->off_cnt = take(sizeof(int) * 64);
+  pl->off_part = take(sizeof(float) * (size_t)pl->items_bound * pl->W);
+  pl->total = off;
+  return HK_OK;
+}
+
+hk::PrepArgs prep_args(const hk_lines* L, const hk_line_override* ovr, double T) {
+  hk::PrepArgs a;
+  a.nu = L->nu;
+  a.Sref = L->Sref;
+  a.E = L->E;
+  a.gref = L->gref;
+  a.nexp = L->nexp;
+  a.perm = L->perm;
+  a.ovr_S = ovr ? ovr->S_ref : nullptr;
+  a.ovr_g = ovr ? ovr->gamma_ref : nullptr;
+  a.ovr_n = ovr ? ovr->n_exp : nullptr;
+  a.N = L->N;
+  a.c2_over_T = kC2 / T;
+  a.c2_over_Tref = kC2 / L->sp.T_ref;
+  a.c2E_coef = kC2 * (1.0 / L->sp.T_ref - 1.0 / T);
+  a.q_ratio = std::pow(L->sp.T_ref / T, L->sp.q_b);
+  a.log_tr = std::log(L->sp.T_ref / T);
+  a.beta = std::sqrt(2.0 * kB * T / (L->sp.mass_amu * kAMU)) / kC;
+  a.pfac = 1.0;
+  return a;
+}
+
+struct Timer {
+  bool on;
+  hipStream_t st;
+  std::vector<hipEvent_t> ev;
+  explicit Timer(hipStream_t s) : on(env_flag("HK_TIMING", false)), st(s) {}
+  void mark() {
+    if (!on) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) == hipSuccess) { hipEventRecord(e, st); ev.push_back(e); }
+  }
+  double ms(size_t i) {
+    if (!on || i + 1 >= ev.size()) return -1.0;
+    float t = 0;
+    hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+    return t;
+  }
+  void finish() {
+    if (on && !ev.empty()) hipEventSynchronize(ev.back());
+  }
+  ~Timer() {
+    for (auto e : ev) hipEventDestroy(e);
+  }
+};
+
+hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan& pl, double cut, float* k,
+                      char* ws, hipStream_t st) {
+  Timer tm(st);
+  tm.mark();
+  float* S_T = reinterpret_cast<float*>(ws + pl.off_S);
+  float* gT = reinterpret_cast<float*>(ws + pl.off_g);
+  for (int t = 0; t < pl.n_temps; ++t) {
+    hk::PrepArgs a = prep_args(L, ovr, pl.temps[t]);
+    HK_HIP(hk::launch_prep(a, S_T + (size_t)t * L->N, gT + (size_t)t * L->N, nullptr, nullptr, nullptr, st));
+  }
+  tm.mark();
+  hk::PairDesc* dpairs = reinterpret_cast<hk::PairDesc*>(ws + pl.off_pairs);
+  int32_t* lo = reinterpret_cast<int32_t*>(ws + pl.off_lo);
+  int32_t* hi = reinterpret_cast<int32_t*>(ws + pl.off_hi);
+  int32_t* nc = reinterpret_cast<int32_t*>(ws + pl.off_nc);
+  int32_t* ib = reinterpret_cast<int32_t*>(ws + pl.off_ib);
+  int* cnt = reinterpret_cast<int*>(ws + pl.off_cnt);
+  HK_HIP(hk::launch_fill_pairs(pl.pairs.data(), pl.n_pairs, dpairs, st));
+  HK_HIP(hk::launch_worklist(L->keys, L->N, L->km, L->numin, L->numax, dpairs, pl.n_pairs, pl.n_tiles_total,
+                             pl.W, cut, pl.chunk, lo, hi, nc, st));
+  HK_HIP(hk::launch_item_scan(nc, pl.n_tiles_total, ib, cnt, st));
+  tm.mark();
+  hk::VoigtArgs va;
+  memset(&va, 0, sizeof va);
+  va.nu = L->nu;
+  va.S_T = S_T;
+  va.gT = gT;
+  va.pairs = dpairs;
+  va.tile_lo = lo;
+  va.tile_hi = hi;
+  va.tile_nc = nc;
+  va.item_base = ib;
+  va.k = k;
+  va.partial = reinterpret_cast<float*>(ws + pl.off_part);
+  va.counter = cnt;
+  va.N = L->N;
+  va.cut = cut;
+  for (int i = 0; i < hk::kKmax; ++i) va.zK[i] = kZK[i];
+  va.n_pairs = pl.n_pairs;
+  va.n_tiles_total = pl.n_tiles_total;
+  va.chunk = pl.chunk;
+  HK_HIP(hk::launch_voigt(va, pl.slots, pl.grid, st));
+  tm.mark();
+  HK_HIP(hk::launch_combine(va, pl.slots, st));
+  tm.mark();
+  tm.finish();
+  g_tim.prep_ms = tm.ms(0);
+  g_tim.worklist_ms = tm.ms(1);
+  g_tim.voigt_ms = tm.ms(2);
+  g_tim.combine_ms = tm.ms(3);
+  g_tim.backward_ms = -1;
+  g_tim.tile_width = pl.W;
+  g_tim.lines_per_batch = hk::kLB;
+  g_tim.chunk_lines = pl.chunk;
+  g_tim.n_items = (int32_t)pl.items_bound;
+  return HK_OK;
+}
+
+hk_status check_lines(const hk_lines* L) {
+  if (!L) return fail(HK_EINVAL, "lines handle is NULL");
+  int dev = -1;
+  HK_HIP(hipGetDevice(&dev));
+  if (dev != L->device) return fail(HK_EINVAL, "current device %d differs from the handle's device %d", dev, L->device);
+  return HK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hk_last_error(void) { return g_err.c_str(); }
+const char* hk_version(void) { return "hk 0.1 (gfx950)"; }
+
+hk_status hk_get_timings(hk_timings* out) {
+  if (!out) return fail(HK_EINVAL, "out is NULL");
+  *out = g_tim;
+  return HK_OK;
+}
+
+int64_t hk_lines_count(const hk_lines* lines) { return lines ? lines->N : -1; }
+
+hk_status hk_prepare_lines(const double* nu, const double* S_ref, const double* E_low, const double* gamma_ref,
+                           const double* n_exp, int64_t n_lines, const hk_species* sp, hipStream_t stream,
+                           hk_lines** out) {
+  if (!out) return fail(HK_EINVAL, "out is NULL");
+  if (!nu || !S_ref || !E_low || !gamma_ref || !n_exp) return fail(HK_EINVAL, "a line array is NULL");
+  if (n_lines < 1 || n_lines >= (int64_t(1) << 31) - 1) return fail(HK_EINVAL, "n_lines %lld out of range", (long long)n_lines);
+  if (!species_ok(sp)) return fail(HK_EINVAL, "invalid species constants");
+  int dev;
+  DevInfo di;
+  hk_status s = device_init(&dev, &di);
+  if (s != HK_OK) return s;
+  const int64_t N = n_lines;
+  Timer tm(stream);
+  tm.mark();
+  // handle memory
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+  const size_t o_nu = take(8 * N), o_S = take(8 * N), o_E = take(8 * N), o_g = take(8 * N), o_n = take(8 * N),
+               o_k = take(4 * N), o_p = take(4 * N);
+  const size_t hbytes = off;
+  // temporaries
+  const int64_t G = (N + hk::kSortBlock - 1) / hk::kSortBlock;
+  off = 0;
+  const size_t t_k = take(4 * N), t_v = take(4 * N), t_h = take(4 * 256 * (size_t)G), t_d = take(4 * 256),
+               t_mm = take(16), t_f = take(16);
+  const size_t tbytes = off;
+  std::unique_ptr<hk_lines> L(new hk_lines());
+  L->device = dev;
+  L->N = N;
+  L->sp = *sp;
+  char* hm = nullptr;
+  char* tmp = nullptr;
+  if (hipMalloc(&hm, hbytes) != hipSuccess) { (void)hipGetLastError(); return fail(HK_ENOMEM, "hipMalloc of %zu bytes failed", hbytes); }
+  if (hipMalloc(&tmp, tbytes) != hipSuccess) {
+    (void)hipGetLastError();
+    (void)hipFree(hm);
+    return fail(HK_ENOMEM, "hipMalloc of %zu bytes failed", tbytes);
+  }
+  L->mem = hm;
+  L->nu = reinterpret_cast<double*>(hm + o_nu);
+  L->Sref = reinterpret_cast<double*>(hm + o_S);
+  L->E = reinterpret_cast<double*>(hm + o_E);
+  L->gref = reinterpret_cast<double*>(hm + o_g);
+  L->nexp = reinterpret_cast<double*>(hm + o_n);
+  L->keys = reinterpret_cast<uint32_t*>(hm + o_k);
+  L->perm = reinterpret_cast<int32_t*>(hm + o_p);
+  uint32_t* kA = reinterpret_cast<uint32_t*>(tmp + t_k);
+  int32_t* vA = reinterpret_cast<int32_t*>(tmp + t_v);
+  uint32_t* hist = reinterpret_cast<uint32_t*>(tmp + t_h);
+  uint32_t* dtot = reinterpret_cast<uint32_t*>(tmp + t_d);
+  unsigned long long* mm = reinterpret_cast<unsigned long long*>(tmp + t_mm);
+  int* flags = reinterpret_cast<int*>(tmp + t_f);
+  auto cleanup_fail = [&](hk_status st, const char* what, hipError_t e) {
+    (void)hipStreamSynchronize(stream);
+    (void)hipFree(tmp);
+    (void)hipFree(hm);
+    return fail(st, "%s: %s", what, e == hipSuccess ? "" : hipGetErrorString(e));
+  };
+  hipError_t e = hk::launch_validate(nu, S_ref, E_low, gamma_ref, n_exp, N, mm, flags, stream);
+  if (e != hipSuccess) return cleanup_fail(HK_EDEVICE, "validate", e);
+  unsigned long long hmm[2] = {0, 0};
+  int hflag = 0;
+  e = hipMemcpyAsync(hmm, mm, 16, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flags, 4, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return cleanup_fail(HK_EDEVICE, "validate readback", e);
+  if (hflag) {
+    (void)hipFree(tmp);
+    (void)hipFree(hm);
+    return fail(HK_EINVAL, "line data invalid: need nu > 0, S_ref >= 0, gamma_ref >= 0, all finite");
+  }
+  double vmin, vmax;
+  memcpy(&vmin, &hmm[0], 8);
+  memcpy(&vmax, &hmm[1], 8);
+  L->numin = vmin;
+  L->numax = vmax;
+  L->km.numin = vmin;
+  L->km.kmax = (1u << hk::kKeyBits) - 1u;
+  L->km.scale = vmax > vmin ? (double)L->km.kmax / (vmax - vmin) : 0.0;
+  L->km.pad = 0;
+  // keys -> stable LSD radix sort (3 passes of 8 bits; ping-pong ends in the handle arrays)
+  e = hk::launch_keys(nu, N, L->km, kA, vA, stream);
+  if (e == hipSuccess) e = hk::launch_radix_pass(kA, vA, L->keys, L->perm, N, 0, hist, dtot, stream);
+  if (e == hipSuccess) e = hk::launch_radix_pass(L->keys, L->perm, kA, vA, N, 8, hist, dtot, stream);
+  if (e == hipSuccess) e = hk::launch_radix_pass(kA, vA, L->keys, L->perm, N, 16, hist, dtot, stream);
+  if (e == hipSuccess)
+    e = hk::launch_gather(L->perm, N, nu, S_ref, E_low, gamma_ref, n_exp, L->nu, L->Sref, L->E, L->gref, L->nexp, stream);
+  tm.mark();
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return cleanup_fail(HK_EDEVICE, "binning", e);
+  (void)hipFree(tmp);
+  g_tim.bin_ms = tm.ms(0);
+  *out = L.release();
+  return HK_OK;
+}
+
+hk_status hk_release_lines(hk_lines* lines) {
+  if (!lines) return HK_OK;
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  if (cur != lines->device) (void)hipSetDevice(lines->device);
+  hipError_t e = hipDeviceSynchronize();
+  hipError_t f = hipFree(lines->mem);
+  if (cur >= 0 && cur != lines->device) (void)hipSetDevice(cur);
+  delete lines;
+  if (e != hipSuccess) return fail(HK_EDEVICE, "hipDeviceSynchronize: %s", hipGetErrorString(e));
+  if (f != hipSuccess) return fail(HK_EDEVICE, "hipFree: %s", hipGetErrorString(f));
+  return HK_OK;
+}
+
+hk_status hk_workspace_size(const hk_lines* lines, int mode, int32_t n_pairs, int32_t n_temps,
+                            const hk_grid* grids, double cutoff, size_t* bytes) {
+  if (!bytes || !grids) return fail(HK_EINVAL, "NULL argument");
+  if (mode < 0 || mode > 2) return fail(HK_EINVAL, "mode %d", mode);
+  if (n_pairs < 1 || ((mode == 0 || mode == 2) && n_pairs != 1)) return fail(HK_EINVAL, "n_pairs %d", n_pairs);
+  if (n_temps < 1 || n_temps > n_pairs) n_temps = n_pairs;
+  if (!cut_ok(cutoff)) return fail(HK_EINVAL, "cutoff must be > 0 (or +inf)");
+  for (int p = 0; p < n_pairs; ++p)
+    if (!grid_ok(grids[p])) return fail(HK_EINVAL, "grid %d invalid", p);
+  hk_status s = check_lines(lines);
+  if (s != HK_OK) return s;
+  int dev;
+  DevInfo di;
+  s = device_init(&dev, &di);
+  if (s != HK_OK) return s;
+  Plan pl;
+  s = make_plan(lines, n_pairs, n_temps, nullptr, nullptr, grids, nullptr, cutoff, di, &pl);
+  if (s != HK_OK) return s;
+  *bytes = pl.total;
+  return HK_OK;
+}
+
+hk_status hk_opacity(const hk_lines* lines, const hk_line_override* ovr, double T, double P_atm, hk_grid grid,
+                     double cutoff, float* k, void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (!(std::isfinite(T) && T > 0)) return fail(HK_EINVAL, "T must be finite and > 0");
+  if (!(std::isfinite(P_atm) && P_atm >= 0)) return fail(HK_EINVAL, "P must be finite and >= 0");
+  if (!grid_ok(grid)) return fail(HK_EINVAL, "invalid grid");
+  if (!cut_ok(cutoff)) return fail(HK_EINVAL, "cutoff must be > 0 (or +inf)");
+  if (!k || !ws) return fail(HK_EINVAL, "k or workspace is NULL");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return fail(HK_EINVAL, "workspace must be 256-byte aligned");
+  hk_status s = check_lines(lines);
+  if (s != HK_OK) return s;
+  int dev;
+  DevInfo di;
+  s = device_init(&dev, &di);
+  if (s != HK_OK) return s;
+  Plan pl;
+  const int64_t zero = 0;
+  s = make_plan(lines, 1, 1, &T, &P_atm, &grid, &zero, cutoff, di, &pl);
+  if (s != HK_OK) return s;
+  if (ws_bytes < pl.total) return fail(HK_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, pl.total);
+  return run_forward(lines, ovr, pl, cutoff, k, static_cast<char*>(ws), stream);
+}
+
+hk_status hk_opacity_batched(const hk_lines* lines, int32_t n_pairs, const double* T, const double* P_atm,
+                             const hk_grid* grids, const int64_t* out_offset, double cutoff, float* k, void* ws,
+                             size_t ws_bytes, hipStream_t stream) {
+  if (n_pairs < 1) return fail(HK_EINVAL, "n_pairs must be >= 1");
+  if (!T || !P_atm || !grids || !out_offset) return fail(HK_EINVAL, "NULL host array");
+  if (!k || !ws) return fail(HK_EINVAL, "k or workspace is NULL");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return fail(HK_EINVAL, "workspace must be 256-byte aligned");
+  if (!cut_ok(cutoff)) return fail(HK_EINVAL, "cutoff must be > 0 (or +inf)");
+  for (int p = 0; p < n_pairs; ++p) {
+    if (!(std::isfinite(T[p]) && T[p] > 0)) return fail(HK_EINVAL, "T[%d] must be finite and > 0", p);
+    if (!(std::isfinite(P_atm[p]) && P_atm[p] >= 0)) return fail(HK_EINVAL, "P[%d] must be finite and >= 0", p);
+    if (!grid_ok(grids[p])) return fail(HK_EINVAL, "grid %d invalid", p);
+    if (out_offset[p] < 0) return fail(HK_EINVAL, "out_offset[%d] < 0", p);
+  }
+  // output ranges must not overlap
+  {
+    std::vector<std::pair<int64_t, int64_t>> r(n_pairs);
+    for (int p = 0; p < n_pairs; ++p) r[p] = {out_offset[p], out_offset[p] + grids[p].n};
+    std::sort(r.begin(), r.end());
+    for (int p = 1; p < n_pairs; ++p)
+      if (r[p].first < r[p - 1].second) return fail(HK_EINVAL, "output ranges overlap");
+  }
+  hk_status s = check_lines(lines);
+  if (s != HK_OK) return s;
+  int dev;
+  DevInfo di;
+  s = device_init(&dev, &di);
+  if (s != HK_OK) return s;
+  Plan pl;
+  s = make_plan(lines, n_pairs, n_pairs, T, P_atm, grids, out_offset, cutoff, di, &pl);
+  if (s != HK_OK) return s;
+  if (ws_bytes < pl.total) return fail(HK_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, pl.total);
+  return run_forward(lines, nullptr, pl, cutoff, k, static_cast<char*>(ws), stream);
+}
+
+hk_status hk_opacity_backward(const hk_lines* lines, const hk_line_override* ovr, double T, double P_atm,
+                              hk_grid grid, double cutoff, const float* dL_dk, double* dL_dT_lnP, double* dL_dSref,
+                              float* dL_dgref, float* dL_dn, void* ws, size_t ws_bytes, hipStream_t stream) {
+  (void)lines; (void)ovr; (void)T; (void)P_atm; (void)grid; (void)cutoff; (void)dL_dk; (void)dL_dT_lnP;
+  (void)dL_dSref; (void)dL_dgref; (void)dL_dn; (void)ws; (void)ws_bytes; (void)stream;
+  return fail(HK_EUNSUPPORTED, "hk_opacity_backward is not built yet");
+}
+
+hk_status hk_debug_cut_bounds(const hk_lines* lines, hk_grid grid, double cutoff, int32_t* j_lo, int32_t* j_hi,
+                              hipStream_t stream) {
+  hk_status s = check_lines(lines);
+  if (s != HK_OK) return s;
+  if (!grid_ok(grid) || !cut_ok(cutoff) || !j_lo || !j_hi) return fail(HK_EINVAL, "invalid argument");
+  HK_HIP(hk::launch_cut_bounds(lines->nu, lines->perm, lines->N, grid.nu_start, grid.dnu, grid.n, cutoff, j_lo,
+                               j_hi, stream));
+  return HK_OK;
+}
+
+hk_status hk_debug_sorted(const hk_lines* lines, uint32_t* keys, int32_t* perm, hipStream_t stream) {
+  hk_status s = check_lines(lines);
+  if (s != HK_OK) return s;
+  if (!keys || !perm) return fail(HK_EINVAL, "NULL argument");
+  HK_HIP(hipMemcpyAsync(keys, lines->keys, 4 * lines->N, hipMemcpyDeviceToDevice, stream));
+  HK_HIP(hipMemcpyAsync(perm, lines->perm, 4 * lines->N, hipMemcpyDeviceToDevice, stream));
+  return HK_OK;
+}
+
+hk_status hk_debug_line_params(const hk_lines* lines, double T, double P_atm, double* S_T, double* alpha,
+                               double* gamma, hipStream_t stream) {
+  hk_status s = check_lines(lines);
+  if (s != HK_OK) return s;
+  if (!(std::isfinite(T) && T > 0) || !(std::isfinite(P_atm) && P_atm >= 0)) return fail(HK_EINVAL, "bad T or P");
+  hk::PrepArgs a = prep_args(lines, nullptr, T);
+  a.pfac = P_atm / lines->sp.P_ref_atm;
+  HK_HIP(hk::launch_prep(a, nullptr, nullptr, S_T, alpha, gamma, stream));
+  return HK_OK;
+}
+
+}  // extern "C"

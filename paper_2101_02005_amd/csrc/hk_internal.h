@@ -1,0 +1,111 @@
+// Internal declarations shared by the kernels (hk_kernels.hip) and the host library
+// (hk_api.cpp). Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace hk {
+
+constexpr int kWave = 64;        // CDNA wavefront width
+constexpr int kThreads = 256;    // threads per workgroup of the Voigt and sort kernels
+constexpr int kWavesPerWG = kThreads / kWave;
+constexpr int kLB = 256;         // lines staged in LDS per batch (one per thread)
+constexpr int kKmax = 4;         // highest order of the far-wing series
+constexpr int kWeidN = 24;       // terms of the FP64 core rational approximation
+constexpr int kKeyBits = 24;     // linear wavenumber-bin key width
+constexpr int kRadixBits = 8;
+constexpr int kSortItems = 16;   // keys per thread per sort block
+constexpr int kSortBlock = kThreads * kSortItems;
+constexpr int kFillPairs = 48;   // pair descriptors per fill launch (kernel-argument space)
+
+// Wavenumber -> bin key: clamp(floor((v - numin) * scale), 0, kmax), evaluated in FP64.
+struct KeyMap {
+  double numin, scale;
+  uint32_t kmax;
+  uint32_t pad;
+};
+
+// One (T, P, grid) evaluation of a call.
+struct PairDesc {
+  double nu_start, dnu;
+  int64_t n;
+  int64_t out_off;
+  double pfac;        // P / P_ref
+  double beta;        // alpha = nu * beta at this T
+  int32_t tidx;       // which per-temperature prep arrays
+  int32_t tile_base;  // first global tile of this pair
+  int32_t n_tiles;
+  int32_t pad;
+};
+
+// Arguments of the persistent Voigt kernel.
+struct VoigtArgs {
+  const double* nu;        // sorted, N
+  const float* S_T;        // [n_temps][N] strength at T
+  const float* gT;         // [n_temps][N] gamma_ref (T_ref/T)^n
+  const PairDesc* pairs;
+  const int32_t* tile_lo;  // per global tile: first line
+  const int32_t* tile_hi;  // per global tile: one past the last line
+  const int32_t* tile_nc;  // per global tile: chunks (work items)
+  const int32_t* item_base;// per global tile: first item; [n_tiles_total] = total items
+  float* k;
+  float* partial;          // [item][tile width]: chunk sums of multi-chunk tiles
+  int* counter;            // work-item dispenser (scheduling only)
+  int64_t N;
+  double cut;              // > 0; +inf: no cut
+  double zK[kKmax];        // |z| above which the series of order K (1..kKmax) is used
+  int32_t n_pairs;
+  int32_t n_tiles_total;
+  int32_t chunk;           // lines per work item
+  int32_t pad;
+};
+
+struct PrepArgs {
+  const double* nu;        // sorted
+  const double* Sref;      // sorted
+  const double* E;         // sorted
+  const double* gref;      // sorted
+  const double* nexp;      // sorted
+  const int32_t* perm;     // sorted position -> caller index
+  const double* ovr_S;     // caller order or null
+  const double* ovr_g;
+  const double* ovr_n;
+  int64_t N;
+  double c2_over_T;        // c2 / T
+  double c2_over_Tref;     // c2 / T_ref
+  double c2E_coef;         // c2 (1/T_ref - 1/T)
+  double q_ratio;          // Q(T_ref)/Q(T)
+  double log_tr;           // ln(T_ref/T)
+  double beta;             // alpha = nu * beta (debug output only)
+  double pfac;             // P / P_ref (debug output only)
+};
+
+// Launch wrappers (hk_kernels.hip); each returns the launch status.
+hipError_t launch_validate(const double* nu, const double* S, const double* E, const double* g,
+                           const double* n, int64_t N, unsigned long long* mm, int* flags,
+                           hipStream_t st);
+hipError_t launch_keys(const double* nu, int64_t N, KeyMap km, uint32_t* keys, int32_t* vals,
+                       hipStream_t st);
+hipError_t launch_radix_pass(const uint32_t* kin, const int32_t* vin, uint32_t* kout, int32_t* vout,
+                             int64_t N, int shift, uint32_t* hist, uint32_t* dig_tot, hipStream_t st);
+hipError_t launch_gather(const int32_t* perm, int64_t N, const double* nu, const double* S,
+                         const double* E, const double* g, const double* n, double* onu, double* oS,
+                         double* oE, double* og, double* on, hipStream_t st);
+hipError_t launch_prep(const PrepArgs& a, float* S_T, float* gT, double* S64, double* a64, double* g64,
+                       hipStream_t st);
+hipError_t launch_fill_pairs(const PairDesc* host_pairs, int count, PairDesc* dst, hipStream_t st);
+hipError_t launch_worklist(const uint32_t* keys, int64_t N, KeyMap km, double numin, double numax,
+                           const PairDesc* pairs,
+                           int n_pairs, int n_tiles_total, int tile_w, double cut, int chunk,
+                           int32_t* lo, int32_t* hi, int32_t* nc, hipStream_t st);
+hipError_t launch_item_scan(const int32_t* nc, int n_tiles_total, int32_t* item_base, int* counter,
+                            hipStream_t st);
+hipError_t launch_voigt(const VoigtArgs& a, int slots, int grid, hipStream_t st);
+hipError_t launch_combine(const VoigtArgs& a, int slots, hipStream_t st);
+hipError_t launch_cut_bounds(const double* nu, const int32_t* perm, int64_t N, double nu_start,
+                             double dnu, int64_t n, double cut, int32_t* jlo, int32_t* jhi,
+                             hipStream_t st);
+int voigt_max_blocks_per_cu(int slots);
+hipError_t upload_weideman(const double* coef, double L);
+
+}  // namespace hk

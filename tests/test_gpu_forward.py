@@ -1,0 +1,146 @@
+"""GPU parity of the forward path (prep, binning, work list, Voigt kernel, combine) against
+the FP64 oracle, through the C ABI. Tolerance: 1e-5 of max k over the compared points."""
+import numpy as np
+import pytest
+
+import linegen
+import oracle
+from gpu_util import TOL_K, gpu_k, oracle_k, prepare, rel_err, to_device, workload_lines
+
+pytestmark = pytest.mark.gpu
+
+SP = (18.0, 296.0, 1.0, 0.05, 1.5)
+
+
+def test_generator_device_twin_bitwise():
+    import torch
+    w = linegen.workload("c2")
+    N = 300_000
+    out = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in range(5)]
+    linegen.generate_device(w.recipe(), w.seed, N, [t.data_ptr() for t in out], i0=123_456_789)
+    torch.cuda.synchronize()
+    host = linegen.generate(w.recipe(), w.seed, N, i0=123_456_789)
+    for t, k in zip(out, linegen.FIELDS):
+        assert np.array_equal(t.cpu().numpy(), host[k]), k
+
+
+def test_binning_sorted_stable_permutation():
+    import paper_2101_02005_amd as hk
+    w, L = workload_lines("c1")
+    lines = prepare(L, w.species_tuple())
+    keys, perm = hk.hk_debug_sorted(lines)
+    keys = keys.cpu().numpy().view(np.uint32).astype(np.int64)
+    perm = perm.cpu().numpy().astype(np.int64)
+    assert np.all(np.diff(keys) >= 0)
+    assert np.array_equal(np.sort(perm), np.arange(w.N))
+    same = np.diff(keys) == 0
+    assert np.all(np.diff(perm)[same] > 0)  # stable: caller order within a bin
+    nu = L["nu"][perm]
+    binw = (nu.max() - nu.min()) / (2 ** 24 - 1)
+    assert np.all(np.diff(nu) >= -2 * binw)
+    lines.release()
+
+
+@pytest.mark.parametrize("T,P", [(1000.0, 1.0), (100.0, 1e-6), (3000.0, 100.0), (296.0, 1.0)])
+def test_line_params_vs_oracle(T, P):
+    import paper_2101_02005_amd as hk
+    w, L = workload_lines("c2", N=50_000)
+    lines = prepare(L, w.species_tuple())
+    S, a, g = (x.cpu().numpy() for x in hk.hk_debug_line_params(lines, T, P))
+    So, ao, go = oracle.line_params(L, oracle.species(*w.species_tuple()), T, P)
+    m = So > 1e-300
+    assert np.max(np.abs(S[m] / So[m] - 1)) < 1e-12
+    assert np.max(np.abs(a / ao - 1)) < 1e-14
+    assert np.max(np.abs(g / go - 1)) < 1e-14
+    lines.release()
+
+
+@pytest.mark.parametrize("cut,nu0,dnu,n", [(25.0, 0.0, 0.1, 20000), (0.37, 99.0, 0.013, 3001),
+                                           (100.0, 0.0, 0.01, 1_000_000), (np.inf, 10.0, 0.5, 77)])
+def test_cut_bounds_exact(cut, nu0, dnu, n):
+    import paper_2101_02005_amd as hk
+    w, L = workload_lines("c1")
+    lines = prepare(L, w.species_tuple())
+    lo, hi = hk.hk_debug_cut_bounds(lines, hk.grid(nu0, dnu, n), cut)
+    jo0, jo1 = oracle.jranges(L["nu"], nu0, dnu, n, cut)
+    lo, hi = lo.cpu().numpy().astype(np.int64), hi.cpu().numpy().astype(np.int64)
+    empty_o = jo1 < jo0
+    assert np.array_equal(empty_o, hi < lo)
+    assert np.array_equal(lo[~empty_o], jo0[~empty_o]) and np.array_equal(hi[~empty_o], jo1[~empty_o])
+    lines.release()
+
+
+@pytest.mark.parametrize("reading", [1, 0])
+def test_small_config_all_points(reading):
+    w = linegen.workload("c1", s_reading=reading)
+    L = linegen.generate(w.recipe(), w.seed, w.N)
+    lines = prepare(L, w.species_tuple())
+    k = gpu_k(lines, w.T[0], w.P[0], w.nu_start, w.dnu, w.n_grid, w.cut)
+    ko = oracle_k(L, w.species_tuple(), w.T[0], w.P[0], w.nu_start, w.dnu, w.cut, np.arange(w.n_grid))
+    print("c1 reading %d: max rel err %.3e" % (reading, rel_err(k, ko)))
+    assert rel_err(k, ko) <= TOL_K
+    lines.release()
+
+
+def _lines(nu, S=1e-20, E=500.0, g=0.05, n=0.5):
+    nu = np.atleast_1d(np.asarray(nu, dtype=np.float64))
+    N = nu.size
+    f = lambda v: np.full(N, v, dtype=np.float64) if np.isscalar(v) else np.asarray(v, dtype=np.float64)
+    return {"nu": nu, "S_ref": f(S), "E": f(E), "gamma_ref": f(g), "n": f(n)}
+
+
+EDGE = [
+    # (name, lines, T, P, nu_start, dnu, n, cut)
+    ("one line on a grid point", _lines([50.0]), 1000.0, 1.0, 0.0, 0.1, 1000, 25.0),
+    ("line beyond the grid end within the cut", _lines([102.3]), 800.0, 0.5, 0.0, 0.1, 1000, 25.0),
+    ("line beyond the cut of every point", _lines([200.0]), 800.0, 0.5, 0.0, 0.1, 1000, 25.0),
+    ("no cut", _lines(np.linspace(3.0, 180.0, 37)), 1500.0, 2.0, 0.0, 0.05, 4000, np.inf),
+    ("single grid point", _lines([10.0, 10.02, 30.0]), 500.0, 1.0, 10.01, 0.01, 1, 5.0),
+    ("ragged tile tail", _lines(np.linspace(1.0, 40.0, 200)), 700.0, 0.3, 0.0, 0.01, 2048 * 3 + 17, 2.0),
+    ("narrow Doppler lines, unsampled peaks", _lines(np.linspace(5.0, 60.0, 300) + 0.0013, g=0.03),
+     100.0, 1e-6, 0.0, 0.01, 7000, 10.0),
+    ("zero pressure (pure Gaussian)", _lines(np.linspace(500.0, 520.0, 50)), 1000.0, 0.0, 490.0, 0.001, 30000, 3.0),
+    ("very broad Lorentz lines", _lines(np.linspace(100.0, 300.0, 100)), 100.0, 100.0, 0.0, 0.01, 40000, 100.0),
+    ("tiny wavenumbers", _lines(np.array([1e-13, 1e-9, 1e-5, 0.3])), 1500.0, 1.0, 0.0, 0.01, 5000, 25.0),
+    ("cut shorter than the spacing", _lines(np.linspace(10.0, 11.0, 77)), 300.0, 1.0, 9.0, 0.05, 60, 0.02),
+    ("exact cut boundary hits", _lines(np.array([10.0, 12.5, 15.0])), 600.0, 1.0, 0.0, 0.5, 100, 2.0),
+]
+
+
+@pytest.mark.parametrize("case", EDGE, ids=[c[0] for c in EDGE])
+def test_edge_cases(case):
+    name, L, T, P, nu0, dnu, n, cut = case
+    lines = prepare(L, SP)
+    k = gpu_k(lines, T, P, nu0, dnu, n, cut)
+    ko = oracle_k(L, SP, T, P, nu0, dnu, cut, np.arange(n))
+    if ko.max() == 0:
+        assert np.all(k == 0)
+    else:
+        assert rel_err(k, ko) <= TOL_K, (name, rel_err(k, ko))
+    # outside the union of the lines' cut ranges the GPU sum is exactly zero
+    j0, j1 = oracle.jranges(L["nu"], nu0, dnu, n, cut)
+    covered = np.zeros(n + 1, np.int64)
+    for a, b in zip(j0, j1):
+        if b >= a:
+            covered[a] += 1
+            covered[b + 1] -= 1
+    inside = np.cumsum(covered)[:n] > 0
+    assert np.all(k[~inside] == 0)
+    lines.release()
+
+
+def test_deterministic_bitwise():
+    w, L = workload_lines("c1")
+    lines = prepare(L, w.species_tuple())
+    k1 = gpu_k(lines, 1300.0, 3.0, 0.0, 0.01, 200_000, 25.0)
+    k2 = gpu_k(lines, 1300.0, 3.0, 0.0, 0.01, 200_000, 25.0)
+    assert np.array_equal(k1.view(np.uint64), k2.view(np.uint64))
+    lines.release()
+
+
+def test_invalid_line_data_rejected():
+    import paper_2101_02005_amd as hk
+    L = _lines([1.0, -2.0, 3.0])
+    with pytest.raises(hk.HkError) as e:
+        prepare(L, SP)
+    assert e.value.status == hk.HK_EINVAL
