@@ -148,14 +148,16 @@ struct Plan {
   int n_tiles_total = 0;
   int64_t items_bound = 0;
   int grid = 0;
-  size_t off_S = 0, off_g = 0, off_pairs = 0, off_lo = 0, off_hi = 0, off_nc = 0, off_ib = 0, off_cnt = 0,
-         off_part = 0, total = 0;
+  size_t off_S = 0, off_g = 0, off_gr = 0, off_pairs = 0, off_lo = 0, off_hi = 0, off_nc = 0, off_ib = 0,
+         off_cnt = 0, off_part = 0, total = 0;
+  int n_grids = 0;
   std::vector<hk::PairDesc> pairs;
   std::vector<double> temps;
+  std::vector<hk_grid> grids;  // distinct grids
 };
 
 int pick_slots() {
-  const int s = env_int("HK_SLOTS", 8);
+  const int s = env_int("HK_SLOTS", 4);
   return (s == 4) ? 4 : 8;
 }
 
@@ -189,6 +191,18 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   } else {
     pl->n_temps = n_temps_bound;
   }
+  // distinct grids (pairs with equal grids share one grid-record array)
+  pl->grids.clear();
+  std::vector<int> gidx(n_pairs, 0);
+  for (int p = 0; p < n_pairs; ++p) {
+    int found = -1;
+    for (size_t q = 0; q < pl->grids.size(); ++q)
+      if (pl->grids[q].nu_start == grids[p].nu_start && pl->grids[q].dnu == grids[p].dnu &&
+          pl->grids[q].n == grids[p].n) { found = (int)q; break; }
+    if (found < 0) { found = (int)pl->grids.size(); pl->grids.push_back(grids[p]); }
+    gidx[p] = found;
+  }
+  pl->n_grids = (int)pl->grids.size();
   // tiles and the bound on line visits
   int64_t tiles = 0;
   double visits = 0.0;
@@ -204,6 +218,7 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
     d.pfac = P ? P[p] / L->sp.P_ref_atm : 1.0;
     d.beta = T ? std::sqrt(2.0 * kB * T[p] / (L->sp.mass_amu * kAMU)) / kC : 0.0;
     d.tidx = tidx[p];
+    d.gidx = gidx[p];
     d.tile_base = (int32_t)tiles;
     d.n_tiles = (int32_t)nt;
     tiles += nt;
@@ -227,6 +242,7 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
   pl->off_S = take(sizeof(float) * (size_t)N * pl->n_temps);
   pl->off_g = take(sizeof(float) * (size_t)N * pl->n_temps);
+  pl->off_gr = take(sizeof(int4) * (size_t)N * pl->n_grids);
   pl->off_pairs = take(sizeof(hk::PairDesc) * n_pairs);
   pl->off_lo = take(sizeof(int32_t) * tiles);
   pl->off_hi = take(sizeof(int32_t) * tiles);
@@ -294,6 +310,10 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
     hk::PrepArgs a = prep_args(L, ovr, pl.temps[t]);
     HK_HIP(hk::launch_prep(a, S_T + (size_t)t * L->N, gT + (size_t)t * L->N, nullptr, nullptr, nullptr, st));
   }
+  int4* grec = reinterpret_cast<int4*>(ws + pl.off_gr);
+  for (int q = 0; q < pl.n_grids; ++q)
+    HK_HIP(hk::launch_gridrec(L->nu, L->N, pl.grids[q].nu_start, pl.grids[q].dnu, pl.grids[q].n, cut,
+                              grec + (size_t)q * L->N, st));
   tm.mark();
   hk::PairDesc* dpairs = reinterpret_cast<hk::PairDesc*>(ws + pl.off_pairs);
   int32_t* lo = reinterpret_cast<int32_t*>(ws + pl.off_lo);
@@ -311,6 +331,7 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   va.nu = L->nu;
   va.S_T = S_T;
   va.gT = gT;
+  va.grec = grec;
   va.pairs = dpairs;
   va.tile_lo = lo;
   va.tile_hi = hi;
@@ -321,7 +342,7 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   va.counter = cnt;
   va.N = L->N;
   va.cut = cut;
-  for (int i = 0; i < hk::kKmax; ++i) va.zK[i] = kZK[i];
+  for (int i = 0; i < hk::kKmax; ++i) va.zK[i] = (float)kZK[i];
   va.n_pairs = pl.n_pairs;
   va.n_tiles_total = pl.n_tiles_total;
   va.chunk = pl.chunk;

@@ -35,7 +35,7 @@ struct PairDesc {
   int32_t tidx;       // which per-temperature prep arrays
   int32_t tile_base;  // first global tile of this pair
   int32_t n_tiles;
-  int32_t pad;
+  int32_t gidx;       // which grid-record array (pairs with equal grids share one)
 };
 
 // Arguments of the persistent Voigt kernel.
@@ -43,6 +43,7 @@ struct VoigtArgs {
   const double* nu;        // sorted, N
   const float* S_T;        // [n_temps][N] strength at T
   const float* gT;         // [n_temps][N] gamma_ref (T_ref/T)^n
+  const int4* grec;        // [n_grids][N] (offset bits, reference index, cut lo, cut hi)
   const PairDesc* pairs;
   const int32_t* tile_lo;  // per global tile: first line
   const int32_t* tile_hi;  // per global tile: one past the last line
@@ -53,7 +54,7 @@ struct VoigtArgs {
   int* counter;            // work-item dispenser (scheduling only)
   int64_t N;
   double cut;              // > 0; +inf: no cut
-  double zK[kKmax];        // |z| above which the series of order K (1..kKmax) is used
+  float zK[kKmax];         // |z| above which the series of order K (1..kKmax) is used
   int32_t n_pairs;
   int32_t n_tiles_total;
   int32_t chunk;           // lines per work item
@@ -100,6 +101,8 @@ hipError_t launch_worklist(const uint32_t* keys, int64_t N, KeyMap km, double nu
                            int32_t* lo, int32_t* hi, int32_t* nc, hipStream_t st);
 hipError_t launch_item_scan(const int32_t* nc, int n_tiles_total, int32_t* item_base, int* counter,
                             hipStream_t st);
+hipError_t launch_gridrec(const double* nu, int64_t N, double nu_start, double dnu, int64_t n, double cut,
+                          int4* grec, hipStream_t st);
 hipError_t launch_voigt(const VoigtArgs& a, int slots, int grid, hipStream_t st);
 hipError_t launch_combine(const VoigtArgs& a, int slots, hipStream_t st);
 hipError_t launch_cut_bounds(const double* nu, const int32_t* perm, int64_t N, double nu_start,

@@ -254,6 +254,19 @@ __global__ void k_fill_pairs(PairPack pk, PairDesc* dst) {
   if ((int)threadIdx.x < pk.count) dst[threadIdx.x] = pk.p[threadIdx.x];
 }
 
+// Force a value that is uniform across the wave into scalar registers (its load may have
+// been a vector load, e.g. through a pointer the compiler cannot prove unclobbered).
+template <typename T>
+__device__ __forceinline__ T wave_uniform(const T& v) {
+  static_assert(sizeof(T) % 4 == 0, "4-byte granular");
+  T out;
+  const int* src = reinterpret_cast<const int*>(&v);
+  int* dst = reinterpret_cast<int*>(&out);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  return out;
+}
+
 // ------------------------------------------------------------------------ worklist
 __device__ __forceinline__ int find_pair(const PairDesc* pairs, int n_pairs, int g) {
   int lo = 0, hi = n_pairs - 1;
@@ -327,23 +340,42 @@ __global__ __launch_bounds__(1024) void k_item_scan(const int32_t* __restrict__ 
 // Re w(x + iy), y >= 0, by J.A.C. Weideman's rational approximation ("Computation of the
 // complex error function", SIAM J. Numer. Anal. 31 (1994) 1497-1518) with N = kWeidN terms:
 // w = 2 p(Z)/(L - iz)^2 + (1/sqrt(pi))/(L - iz), Z = (L + iz)/(L - iz), in FP64.
-__device__ __forceinline__ double weideman_re(double x, double y) {
-  const double L = c_weidL;
+__device__ __forceinline__ double weideman_re(double x, double y, const double* __restrict__ wc) {
+  const double L = wc[kWeidN];
   const double dr = L + y, di = -x;  // L - iz
   const double nr = L - y, ni = x;   // L + iz
   const double inv = 1.0 / (dr * dr + di * di);
   const double Zr = (nr * dr + ni * di) * inv;
   const double Zi = (ni * dr - nr * di) * inv;
-  double pr = c_weid[kWeidN - 1], pi = 0.0;
-#pragma unroll
+  double pr = wc[kWeidN - 1], pi = 0.0;
+#pragma unroll 4
   for (int m = kWeidN - 2; m >= 0; --m) {
-    const double t = fma(pr, Zr, fma(-pi, Zi, c_weid[m]));
+    const double t = fma(pr, Zr, fma(-pi, Zi, wc[m]));
     pi = fma(pr, Zi, pi * Zr);
     pr = t;
   }
-  const double ur = dr * inv, ui = -di * inv;        // 1/(L - iz)
+  const double ur = dr * inv, ui = -di * inv;               // 1/(L - iz)
   const double vr = ur * ur - ui * ui, vi = 2.0 * ur * ui;  // 1/(L - iz)^2
   return 2.0 * (pr * vr - pi * vi) + 0.56418958354775628695 * ur;
+}
+
+// Per-line, per-grid record: the parts of a line's evaluation that depend on the grid but
+// not on T or P, all decided in FP64: x = bits of the FP32 offset delta = nu_{jref} - nu_i,
+// y = jref (grid point nearest the centre, clamped to the grid), z, w = inclusive cut bounds
+// (z > w: the line reaches no point).
+__global__ __launch_bounds__(kThreads) void k_gridrec(const double* __restrict__ nu, int64_t N, double nu_start,
+                                                      double dnu, int64_t n, double cut, int4* __restrict__ grec) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double nu0 = nu[i];
+  int64_t jlo, jhi;
+  cut_range(nu0, nu_start, dnu, n, cut, jlo, jhi);
+  double jr = rint((nu0 - nu_start) / dnu);
+  jr = jr < 0.0 ? 0.0 : (jr > (double)(n - 1) ? (double)(n - 1) : jr);
+  const int64_t jref = (int64_t)jr;
+  const double delta = __dsub_rn(grid_nu(nu_start, dnu, jref), nu0);
+  if (jlo > jhi) { jlo = 1; jhi = 0; }
+  grec[i] = make_int4(__float_as_int((float)delta), (int)jref, (int)jlo, (int)jhi);
 }
 
 // Line record layout in LDS (structure of arrays, one entry per staged line):
@@ -351,46 +383,41 @@ __device__ __forceinline__ double weideman_re(double x, double y) {
 //        gamma^2/s, with s = max(alpha^2, gamma^2)
 //   F1 = (Ah, lo_rel, hi_rel, ampc): S gamma/(pi s), cut bounds relative to the reference
 //        index, S/(sqrt(pi) alpha)
-//   K2, K3, K4a/K4b: Ah * series coefficients for orders 2, 3, 4
-//   D64, IA, Y: FP64 offset, 1/alpha, gamma/alpha for the core
-//   code[w]: per wave, 4 bits per slot (bits 0-2 path: 0 skip, 1-4 series order, 5 core;
-//            bit 3: the slot straddles a cut bound)
+//   KA, KB, KC: Ah times the far-wing series coefficients (see wing_coeffs)
+//   code[w]: for wave w, bits 0-2 series order K used for all its non-core slots (0: the line
+//            does not reach the wave), bit 3 some lanes fall outside the cut range, bits 4-11
+//            the slots that hold the line core (|z| below the last series threshold)
+//   list[w]: the staged lines reaching wave w, grouped by series order (see line_group)
 struct LineLDS {
   float4 F0[kLB];
   float4 F1[kLB];
-  float2 K2[kLB];
-  float4 K3[kLB];
-  float4 K4a[kLB];
-  float2 K4b[kLB];
-  double D64[kLB];
-  double IA[kLB];
-  double Y[kLB];
-  uint32_t code[kWavesPerWG][kLB];
+  float4 KA[kLB];   // c1, c2(K=2), c2(K>=3), c3(K=3)
+  float4 KB[kLB];   // c4(K=3), c3(K=4), c4(K=4), c5(K=4)
+  float KC[kLB];    // c6(K=4)
+  uint4 code[kLB];                  // component w: the code word of wave w
+  uint8_t list[kWavesPerWG][kLB];
 };
 
 // Far-wing series of the Voigt profile in q = 1/(D^2 + gamma^2), from the asymptotic
 // expansion w(z) ~ (i/sqrt(pi)) sum_k (2k-1)!!/(2^k z^(2k+1)): with t = alpha^2 q and
 // u = gamma^2 q,  V = (S gamma/pi) q sum_{k<K} a_k t^k P_k(u), a_k = (2k-1)!!/2^k,
-// P_k(u) = U_2k(sqrt(1-u)) (Chebyshev polynomials of the second kind) expanded in u.
+// P_k(u) = U_2k(sqrt(1-u)) (Chebyshev polynomials of the second kind) expanded in u:
+// P_0 = 1, P_1 = 3 - 4u, P_2 = 5 - 20u + 16u^2, P_3 = 7 - 56u + 112u^2 - 64u^3.
 // Truncated at order K its relative error is below 2e-6 for |z| above zK[K-1].
-// Written as a polynomial in qh = s q (s = max(alpha^2, gamma^2), so qh <= 1) with
-// coefficients C_M = sum_{k+l=M, k<K} a_k f_{k,l} (alpha^2/s)^k (-gamma^2/s)^l.
-__device__ __forceinline__ void series_coeffs(int K, double a2, double g2, double* C) {
-  // f_{k,l}: coefficients of P_k(u) = sum_l f_{k,l} (-u)^l
-  const double f[4][4] = {{1, 0, 0, 0}, {3, 4, 0, 0}, {5, 20, 16, 0}, {7, 56, 112, 64}};
-  const double ak[4] = {1.0, 0.5, 0.75, 1.875};
-  for (int M = 1; M <= 2 * K - 2; ++M) {
-    double c = 0.0;
-    for (int k = (M + 1) / 2; k <= M && k < K; ++k) {
-      const int l = M - k;
-      if (l > k) continue;
-      double term = ak[k] * f[k][l];
-      for (int r = 0; r < k; ++r) term *= a2;
-      for (int r = 0; r < l; ++r) term *= -g2;
-      c += term;
-    }
-    C[M - 1] = c;
-  }
+// Written as a polynomial sum_M c_M qh^(M+1) in qh = s q (s = max(alpha^2, gamma^2) keeps
+// qh <= 1 and the coefficients O(1)), with a = alpha^2/s, g = gamma^2/s in [0, 1]:
+//   K=2: c1 = 3a/2, c2 = -2ag
+//   K=3: c1, c2 = -2ag + 15a^2/4, c3 = -15a^2 g, c4 = 12 a^2 g^2
+//   K=4: c1, c2 (as K=3), c3 = -15a^2 g + 105a^3/8, c4 = 12a^2g^2 - 105a^3 g, c5 = 210 a^3 g^2,
+//        c6 = -120 a^3 g^3
+__device__ __forceinline__ void wing_coeffs(float a, float g, float Ah, float4& KA, float4& KB, float& KC) {
+  const float a2 = a * a, a3 = a2 * a, g2 = g * g;
+  const float c2_2 = -2.0f * a * g;
+  const float c3_3 = -15.0f * a2 * g;
+  const float c4_3 = 12.0f * a2 * g2;
+  KA = make_float4(Ah * (1.5f * a), Ah * c2_2, Ah * (c2_2 + 3.75f * a2), Ah * c3_3);
+  KB = make_float4(Ah * c4_3, Ah * (c3_3 + 13.125f * a3), Ah * (c4_3 - 105.0f * a3 * g), Ah * (210.0f * a3 * g2));
+  KC = Ah * (-120.0f * a3 * g2 * g);
 }
 
 template <int P>
@@ -405,70 +432,141 @@ __device__ __forceinline__ void kahan_flush(float (&part)[P], float (&s)[P], flo
   }
 }
 
-// Stage one line for a tile: every tile-dependent quantity the waves need, and for each
-// wave a 4-bit path code per 64-point slot. Lines that do not reach the tile get code 0.
+// Stage one line for a tile from its grid record and its strength/width at T: the FP32
+// quantities the waves need, and for each wave its code word. Lines that do not reach the
+// tile keep code 0 for every wave. Every decision that needs FP64 (cut bounds, reference
+// point, offset) is already in the grid record; the rest needs ~1e-7 and is done in FP32
+// (products ordered so that no intermediate underflows for relevant lines).
 template <int P>
-__device__ __forceinline__ void stage_line(LineLDS& L, int tid, double nu0, double S, double gTv,
-                                           const PairDesc& pd, double cut, const double* zK,
-                                           int64_t tile0, uint32_t (&codes)[kWavesPerWG]) {
+__device__ __forceinline__ void stage_line(LineLDS& L, int tid, const int4 gr, double nu0, float S, float gTv,
+                                           const PairDesc& pd, const float* zK, int64_t tile0,
+                                           uint32_t (&codes)[kWavesPerWG]) {
   constexpr int W = kWavesPerWG * kWave * P;
-  const double gam = gTv * pd.pfac;
-  const double alpha = nu0 * pd.beta;
-  int64_t jlo, jhi;
-  cut_range(nu0, pd.nu_start, pd.dnu, pd.n, cut, jlo, jhi);
-  const int64_t tile1 = tile0 + W - 1;
-  if (!(S > 0.0) || jlo > jhi || jhi < tile0 || jlo > tile1) return;
-  const double a2 = alpha * alpha, g2 = gam * gam;
-  const double sc = a2 > g2 ? a2 : g2;
-  const double rs = 1.0 / sqrt(sc);
-  if (!(sc > 0.0) || !isfinite(rs)) return;
-  const double cpos = (nu0 - pd.nu_start) / pd.dnu;  // line centre in grid units
-  double jr = rint(cpos);
-  jr = jr < 0.0 ? 0.0 : (jr > (double)(pd.n - 1) ? (double)(pd.n - 1) : jr);
-  const int64_t jref = (int64_t)jr;  // grid point nearest the centre, clamped to the grid
-  const double delta = __dsub_rn(grid_nu(pd.nu_start, pd.dnu, jref), nu0);
-  const double Ah = S * gam / (M_PI * sc);
-  L.F0[tid] = make_float4((float)(delta * rs), (float)(jref - tile0), (float)(pd.dnu * rs), (float)(g2 / sc));
-  L.F1[tid] = make_float4((float)Ah, (float)(jlo - jref), (float)(jhi - jref),
-                          (float)(S / (1.7724538509055160273 * alpha)));
-  double C[6];
-  series_coeffs(2, a2 / sc, g2 / sc, C);
-  L.K2[tid] = make_float2((float)(Ah * C[0]), (float)(Ah * C[1]));
-  series_coeffs(3, a2 / sc, g2 / sc, C);
-  L.K3[tid] = make_float4((float)(Ah * C[0]), (float)(Ah * C[1]), (float)(Ah * C[2]), (float)(Ah * C[3]));
-  series_coeffs(4, a2 / sc, g2 / sc, C);
-  L.K4a[tid] = make_float4((float)(Ah * C[0]), (float)(Ah * C[1]), (float)(Ah * C[2]), (float)(Ah * C[3]));
-  L.K4b[tid] = make_float2((float)(Ah * C[4]), (float)(Ah * C[5]));
-  L.D64[tid] = delta;
-  L.IA[tid] = 1.0 / alpha;
-  L.Y[tid] = gam / alpha;
-  // zone K: points with |z| < zK[K], i.e. |nu_j - nu0| < sqrt(zK^2 alpha^2 - gamma^2); as a
-  // range of slots (slot sigma covers points tile0 + 64 sigma .. + 63), widened slightly
-  int zlo[kKmax], zhi[kKmax];
-  const double crel = cpos - (double)tile0;
+  const int jref = gr.y, jlo = gr.z, jhi = gr.w;
+  if (!(S > 0.0f) || jlo > jhi || (int64_t)jhi < tile0 || (int64_t)jlo > tile0 + (W - 1)) return;
+  const float alpha = (float)(nu0 * pd.beta);
+  const float gam = gTv * (float)pd.pfac;
+  const float a2 = alpha * alpha, g2 = gam * gam;
+  const float sc = a2 > g2 ? a2 : g2;
+  if (!(sc > 0.0f)) return;
+  const float rs = __frsqrt_rn(sc);
+  const float isc = rs * rs;
+  const float delta = __int_as_float(gr.x);
+  const int jt = (int)((int64_t)jref - tile0);
+  const float Ah = S * (gam * isc) * 0.318309886183790672f;  // S gamma / (pi s)
+  L.F0[tid] = make_float4(delta * rs, (float)jt, (float)pd.dnu * rs, g2 * isc);
+  L.F1[tid] = make_float4(Ah, (float)(jlo - jref), (float)(jhi - jref), S / (1.7724538509055160273f * alpha));
+  wing_coeffs(a2 * isc, g2 * isc, Ah, L.KA[tid], L.KB[tid], L.KC[tid]);
+  // zone K: points with |z| < zK[K], i.e. |j - c| < sqrt(zK^2 alpha^2 - gamma^2)/dnu around the
+  // centre c (tile-local points); a slot [s0, s1] meets it when s0 < c + h and s1 > c - h
+  const float inv_dnu = (float)(1.0 / pd.dnu);
+  const float af = alpha * inv_dnu, gf = gam * inv_dnu;
+  const float c = (float)jt - delta * inv_dnu;
+  float zl[kKmax], zh[kKmax];
+#pragma unroll
   for (int K = 0; K < kKmax; ++K) {
-    const double zz = zK[K] * alpha;
-    const double h2 = zz * zz - g2;
-    if (h2 <= 0.0) { zlo[K] = 1; zhi[K] = 0; continue; }
-    const double h = sqrt(h2) / pd.dnu * (1.0 + 1e-6) + 1e-3;
-    double lo_s = ceil((crel - h - 63.0) / 64.0), hi_s = floor((crel + h) / 64.0);
-    lo_s = lo_s < -1.0 ? -1.0 : (lo_s > 1e6 ? 1e6 : lo_s);
-    hi_s = hi_s < -1.0 ? -1.0 : (hi_s > 1e6 ? 1e6 : hi_s);
-    zlo[K] = (int)lo_s;
-    zhi[K] = (int)hi_s;
+    const float zz = zK[K] * af;
+    const float h2 = zz * zz - gf * gf;
+    const float h = h2 > 0.0f ? sqrtf(h2) * 1.00001f + 1e-3f : -1.0f;
+    zl[K] = c - h;
+    zh[K] = c + h;
   }
+  const int clo = (int)((int64_t)jlo - tile0 < -1 ? -1 : (int64_t)jlo - tile0);
+  const int chi = (int)((int64_t)jhi - tile0 > W ? W : (int64_t)jhi - tile0);
+#pragma unroll
   for (int w = 0; w < kWavesPerWG; ++w) {
-    uint32_t cw = 0u;
-    for (int p = 0; p < P; ++p) {
-      const int sg = w * P + p;
-      const int64_t s0 = tile0 + (int64_t)sg * kWave, s1 = s0 + kWave - 1;
-      if (s1 < jlo || s0 > jhi) continue;
-      uint32_t path = 1u;
-      for (int K = 0; K < kKmax; ++K) path += (sg >= zlo[K] && sg <= zhi[K]) ? 1u : 0u;
-      const uint32_t msk = (s0 >= jlo && s1 <= jhi) ? 0u : 8u;
-      cw |= (path | msk) << (4 * p);
+    const int w0 = w * kWave * P, w1 = w0 + kWave * P - 1;
+    uint32_t code = 0u;
+    if (!(chi < w0 || clo > w1)) {
+      uint32_t K = 0u, core = 0u;
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const int s0 = w0 + p * kWave, s1 = s0 + kWave - 1;
+        if (s1 < clo || s0 > chi) continue;
+        uint32_t path = 1u;
+#pragma unroll
+        for (int z = 0; z < kKmax; ++z) path += ((float)s0 < zh[z] && (float)s1 > zl[z]) ? 1u : 0u;
+        if (path > (uint32_t)kKmax) core |= 1u << p;
+        else K = path > K ? path : K;
+      }
+      if (K == 0u) K = 1u;  // only core slots: the order is unused
+      code = K | ((w0 >= clo && w1 <= chi) ? 0u : 8u) | (core << 4);
     }
-    codes[w] = cw;
+    codes[w] = code;
+  }
+}
+
+// One line, all slots of this wave, series order K. MASK: lanes outside the cut range add
+// nothing. CORE: the slots in coremask are skipped here (their core is evaluated separately).
+template <int P, int K, bool MASK, bool CORE>
+__device__ __forceinline__ void wing_slots(float (&part)[P], float kf0, const float4& f0, const float4& f1,
+                                           const float4& ka, const float4& kb, float kc, uint32_t coremask) {
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    if (CORE && ((coremask >> p) & 1u)) continue;
+    const float kf = kf0 + (float)(kWave * p);
+    const float D = __builtin_fmaf(kf, f0.z, f0.x);
+    const float R = __builtin_fmaf(D, D, f0.w);
+    const float q = __builtin_amdgcn_rcpf(R);
+    float t;
+    if (K == 1) {
+      t = f1.x;
+    } else if (K == 2) {
+      t = __builtin_fmaf(ka.y, q, ka.x);
+      t = __builtin_fmaf(t, q, f1.x);
+    } else if (K == 3) {
+      t = __builtin_fmaf(kb.x, q, ka.w);
+      t = __builtin_fmaf(t, q, ka.z);
+      t = __builtin_fmaf(t, q, ka.x);
+      t = __builtin_fmaf(t, q, f1.x);
+    } else {
+      t = __builtin_fmaf(kc, q, kb.w);
+      t = __builtin_fmaf(t, q, kb.z);
+      t = __builtin_fmaf(t, q, kb.y);
+      t = __builtin_fmaf(t, q, ka.z);
+      t = __builtin_fmaf(t, q, ka.x);
+      t = __builtin_fmaf(t, q, f1.x);
+    }
+    if (MASK) {
+      const bool in = (kf >= f1.y) && (kf <= f1.z);
+      part[p] = in ? __builtin_fmaf(t, q, part[p]) : part[p];
+    } else {
+      part[p] = __builtin_fmaf(t, q, part[p]);
+    }
+  }
+}
+
+template <int P, int K>
+__device__ __forceinline__ void wing_dispatch(float (&part)[P], float kf0, const float4& f0, const float4& f1,
+                                              const float4& ka, const float4& kb, float kc, uint32_t masked,
+                                              uint32_t coremask) {
+  if (coremask) wing_slots<P, K, true, true>(part, kf0, f0, f1, ka, kb, kc, coremask);
+  else if (masked) wing_slots<P, K, true, false>(part, kf0, f0, f1, ka, kb, kc, 0u);
+  else wing_slots<P, K, false, false>(part, kf0, f0, f1, ka, kb, kc, 0u);
+}
+
+// Group of a staged line for one wave: 0 does not reach the wave, 1..4 unmasked wing-only
+// line of series order K, 5 general (some lanes outside the cut, or core slots).
+__device__ __forceinline__ int line_group(uint32_t code) {
+  if (code == 0u) return 0;
+  return (code & 0xFF8u) ? 5 : (int)(code & 7u);
+}
+
+// Per-wave wing loop over the lines of one group (all unmasked, no core slots).
+template <int P, int K>
+__device__ __forceinline__ void group_loop(const LineLDS& L, int wv, int i0, int i1, float jl0, float (&part)[P],
+                                           float (&s)[P], float (&cc)[P], int& nproc) {
+  for (int i = i0; i < i1; ++i) {
+    const int l = __builtin_amdgcn_readfirstlane((int)L.list[wv][i]);
+    const float4 f0 = L.F0[l];
+    const float4 f1 = L.F1[l];
+    float4 ka = make_float4(0.f, 0.f, 0.f, 0.f), kb = ka;
+    float kc = 0.f;
+    if (K >= 2) ka = L.KA[l];
+    if (K >= 3) kb = L.KB[l];
+    if (K >= 4) kc = L.KC[l];
+    wing_slots<P, K, false, false>(part, jl0 - f0.y, f0, f1, ka, kb, kc, 0u);
+    if ((++nproc & 15) == 0) kahan_flush<P>(part, s, cc);
   }
 }
 
@@ -476,9 +574,15 @@ template <int P>
 __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
   constexpr int W = kWavesPerWG * kWave * P;  // tile width in grid points
   __shared__ LineLDS L;
+  __shared__ double sW[kWeidN + 1];  // core rational-approximation coefficients and scale
   __shared__ int sItem, sTile, sPair;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
+  if (tid < kWeidN) sW[tid] = c_weid[tid];
+  if (tid == kWeidN) sW[kWeidN] = c_weidL;
   const int total = a.item_base[a.n_tiles_total];
+  const float jl0 = (float)(wv * kWave * P + lane);  // this lane's first tile point
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
   for (;;) {
     if (tid == 0) {
@@ -495,107 +599,115 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
       }
     }
     __syncthreads();
-    const int it = sItem;
+    const int it = __builtin_amdgcn_readfirstlane(sItem);
     if (it >= total) break;
-    const int g = sTile;
-    const PairDesc pd = a.pairs[sPair];
-    const int chunk_idx = it - a.item_base[g];
-    const int nc = a.tile_nc[g];
+    const int g = __builtin_amdgcn_readfirstlane(sTile);
+    const PairDesc pd = wave_uniform(a.pairs[__builtin_amdgcn_readfirstlane(sPair)]);
+    const int ibase = __builtin_amdgcn_readfirstlane(a.item_base[g]);
+    const int chunk_idx = it - ibase;
+    const int nc = __builtin_amdgcn_readfirstlane(a.tile_nc[g]);
     const int64_t tile0 = (int64_t)(g - pd.tile_base) * W;
-    const int64_t line_lo = (int64_t)a.tile_lo[g] + (int64_t)chunk_idx * a.chunk;
+    const int64_t line_lo = (int64_t)__builtin_amdgcn_readfirstlane(a.tile_lo[g]) + (int64_t)chunk_idx * a.chunk;
     int64_t line_hi = line_lo + a.chunk;
-    if (line_hi > a.tile_hi[g]) line_hi = a.tile_hi[g];
+    const int64_t thi = __builtin_amdgcn_readfirstlane(a.tile_hi[g]);
+    if (line_hi > thi) line_hi = thi;
     const float* __restrict__ S_T = a.S_T + (int64_t)pd.tidx * a.N;
     const float* __restrict__ gT = a.gT + (int64_t)pd.tidx * a.N;
+    const int4* __restrict__ grec = a.grec + (int64_t)pd.gidx * a.N;
 
-    float jl[P], s[P], cc[P], part[P];
+    float s[P], cc[P], part[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-      jl[p] = (float)(wv * kWave * P + p * kWave + lane);
       s[p] = 0.0f;
       cc[p] = 0.0f;
       part[p] = 0.0f;
     }
+    int nproc = 0;
 
     for (int64_t b = line_lo; b < line_hi; b += kLB) {
-      // ---- stage one batch of lines: one thread per line, FP64 where it matters
+      // ---- stage one batch of lines: one thread per line
       {
         const int64_t li = b + tid;
         uint32_t codes[kWavesPerWG] = {0u, 0u, 0u, 0u};
-        if (li < line_hi)
-          stage_line<P>(L, tid, a.nu[li], (double)S_T[li], (double)gT[li], pd, a.cut, a.zK, tile0, codes);
-        for (int w = 0; w < kWavesPerWG; ++w) L.code[w][tid] = codes[w];
+        if (li < line_hi) stage_line<P>(L, tid, grec[li], a.nu[li], S_T[li], gT[li], pd, a.zK, tile0, codes);
+        L.code[tid] = make_uint4(codes[0], codes[1], codes[2], codes[3]);
       }
       __syncthreads();
-
-      // ---- accumulate: this wave's slots over the staged lines, in staging order
-      const int nb = (int)((line_hi - b) < kLB ? (line_hi - b) : kLB);
-      for (int l = 0; l < nb; ++l) {
-        const uint32_t code = __builtin_amdgcn_readfirstlane(L.code[wv][l]);
-        if (code != 0u) {
-          const float4 f0 = L.F0[l];
-          const float4 f1 = L.F1[l];
-          uint32_t core_slots = 0u;
+      // ---- this wave's list of the staged lines that reach it, grouped by series order and in
+      //      staging order within a group (wave ballots; deterministic)
+      int o[7];
+      {
+        const uint32_t* code_w = reinterpret_cast<const uint32_t*>(L.code) + wv;
+        int grp[kLB / kWave];
+        int cnt[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
-          for (int p = 0; p < P; ++p) {
-            const uint32_t cs = (code >> (4 * p)) & 15u;
-            if (cs == 0u) continue;
-            const uint32_t path = cs & 7u;
-            if (path == 5u) { core_slots |= 1u << p; continue; }
-            const float kf = jl[p] - f0.y;
-            const float D = __builtin_fmaf(kf, f0.z, f0.x);
-            const float R = __builtin_fmaf(D, D, f0.w);
-            const float q = __builtin_amdgcn_rcpf(R);
-            float t;
-            if (path == 1u) {
-              t = f1.x;
-            } else if (path == 2u) {
-              const float2 c = L.K2[l];
-              t = __builtin_fmaf(c.y, q, c.x);
-              t = __builtin_fmaf(t, q, f1.x);
-            } else if (path == 3u) {
-              const float4 c = L.K3[l];
-              t = __builtin_fmaf(c.w, q, c.z);
-              t = __builtin_fmaf(t, q, c.y);
-              t = __builtin_fmaf(t, q, c.x);
-              t = __builtin_fmaf(t, q, f1.x);
-            } else {
-              const float4 c = L.K4a[l];
-              const float2 e = L.K4b[l];
-              t = __builtin_fmaf(e.y, q, e.x);
-              t = __builtin_fmaf(t, q, c.w);
-              t = __builtin_fmaf(t, q, c.z);
-              t = __builtin_fmaf(t, q, c.y);
-              t = __builtin_fmaf(t, q, c.x);
-              t = __builtin_fmaf(t, q, f1.x);
-            }
-            if (cs & 8u) {
-              const bool in = (kf >= f1.y) && (kf <= f1.z);
-              part[p] = in ? __builtin_fmaf(t, q, part[p]) : part[p];
-            } else {
-              part[p] = __builtin_fmaf(t, q, part[p]);
-            }
-          }
-          // core slots: FP64 rational approximation for every lane of the slot
-          while (core_slots) {
-            const int p = __builtin_ctz(core_slots);
-            core_slots &= core_slots - 1u;
-            const float kf = (float)(wv * kWave * P + p * kWave + lane) - f0.y;
-            const double D = fma((double)kf, pd.dnu, L.D64[l]);
-            const float v = f1.w * (float)weideman_re(D * L.IA[l], L.Y[l]);
-            const bool msk = ((code >> (4 * p)) & 8u) != 0u;
-            const bool in = !msk || ((kf >= f1.y) && (kf <= f1.z));
-            const float add = in ? v : 0.0f;
+        for (int r = 0; r < kLB / kWave; ++r) {
+          grp[r] = line_group(code_w[4 * (r * kWave + lane)]);
 #pragma unroll
-            for (int q2 = 0; q2 < P; ++q2)
-              if (q2 == p) part[q2] += add;
+          for (int gg = 1; gg <= 5; ++gg) cnt[gg] += (int)__popcll(__ballot(grp[r] == gg));
+        }
+        o[1] = 0;
+#pragma unroll
+        for (int gg = 1; gg <= 5; ++gg) o[gg + 1] = o[gg] + cnt[gg];
+        int st[6];
+#pragma unroll
+        for (int gg = 1; gg <= 5; ++gg) st[gg] = o[gg];
+#pragma unroll
+        for (int r = 0; r < kLB / kWave; ++r) {
+#pragma unroll
+          for (int gg = 1; gg <= 5; ++gg) {
+            const uint64_t m = __ballot(grp[r] == gg);
+            if (grp[r] == gg) L.list[wv][st[gg] + (int)__popcll(m & lt)] = (uint8_t)(r * kWave + lane);
+            st[gg] += (int)__popcll(m);
           }
         }
-        if ((l & 15) == 15) kahan_flush<P>(part, s, cc);
       }
-      kahan_flush<P>(part, s, cc);
+
+      // ---- accumulate: fast groups, then the general group
+      {
+        group_loop<P, 1>(L, wv, o[1], o[2], jl0, part, s, cc, nproc);
+        group_loop<P, 2>(L, wv, o[2], o[3], jl0, part, s, cc, nproc);
+        group_loop<P, 3>(L, wv, o[3], o[4], jl0, part, s, cc, nproc);
+        group_loop<P, 4>(L, wv, o[4], o[5], jl0, part, s, cc, nproc);
+        for (int i = o[5]; i < o[6]; ++i) {
+          const int l = __builtin_amdgcn_readfirstlane((int)L.list[wv][i]);
+          const uint32_t code = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t*>(L.code)[4 * l + wv]);
+          const float4 f0 = L.F0[l];
+          const float4 f1 = L.F1[l];
+          const float4 ka = L.KA[l];
+          const float4 kb = L.KB[l];
+          const float kc = L.KC[l];
+          const float kf0 = jl0 - f0.y;
+          const uint32_t K = code & 7u, masked = code & 8u, coremask = (code >> 4) & 0xFFu;
+          if (K == 1u) wing_dispatch<P, 1>(part, kf0, f0, f1, ka, kb, kc, masked, coremask);
+          else if (K == 2u) wing_dispatch<P, 2>(part, kf0, f0, f1, ka, kb, kc, masked, coremask);
+          else if (K == 3u) wing_dispatch<P, 3>(part, kf0, f0, f1, ka, kb, kc, masked, coremask);
+          else wing_dispatch<P, 4>(part, kf0, f0, f1, ka, kb, kc, masked, coremask);
+          if (coremask) {
+            // core slots: FP64 rational approximation for every lane of the slot, from the
+            // line's FP64 centre and widths
+            const int64_t li = b + l;
+            const double nu0 = a.nu[li];
+            const double alpha = nu0 * pd.beta;
+            const double y = (double)gT[li] * pd.pfac / alpha;
+            const double ia = 1.0 / alpha;
+            const double d64 = __dsub_rn(grid_nu(pd.nu_start, pd.dnu, (int64_t)f0.y + tile0), nu0);
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+              if (!((coremask >> p) & 1u)) continue;
+              const float kf = kf0 + (float)(kWave * p);
+              const double D = fma((double)kf, pd.dnu, d64);
+              const float v = f1.w * (float)weideman_re(D * ia, y, sW);
+              const bool in = (kf >= f1.y) && (kf <= f1.z);
+              part[p] += in ? v : 0.0f;
+            }
+          }
+          if ((++nproc & 15) == 0) kahan_flush<P>(part, s, cc);
+        }
+      }
       __syncthreads();
     }
+    kahan_flush<P>(part, s, cc);
 
     // ---- output: the tile directly, or this chunk's partial tile
 #pragma unroll
@@ -605,7 +717,7 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
       if (nc == 1) {
         if (tile0 + local < pd.n) a.k[pd.out_off + tile0 + local] = v;
       } else {
-        a.partial[((int64_t)(a.item_base[g] + chunk_idx)) * W + local] = v;
+        a.partial[((int64_t)it) * W + local] = v;
       }
     }
     __syncthreads();
@@ -705,6 +817,13 @@ hipError_t launch_worklist(const uint32_t* keys, int64_t N, KeyMap km, double nu
 hipError_t launch_item_scan(const int32_t* nc, int n_tiles_total, int32_t* item_base, int* counter,
                             hipStream_t st) {
   hipLaunchKernelGGL(k_item_scan, dim3(1), dim3(1024), 0, st, nc, n_tiles_total, item_base, counter);
+  return hipGetLastError();
+}
+
+hipError_t launch_gridrec(const double* nu, int64_t N, double nu_start, double dnu, int64_t n, double cut,
+                          int4* grec, hipStream_t st) {
+  hipLaunchKernelGGL(k_gridrec, dim3(blocks_for(N, kThreads)), dim3(kThreads), 0, st, nu, N, nu_start, dnu, n, cut,
+                     grec);
   return hipGetLastError();
 }
 
