@@ -347,6 +347,7 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   va.n_tiles_total = pl.n_tiles_total;
   va.chunk = pl.chunk;
   HK_HIP(hk::launch_voigt(va, pl.slots, pl.grid, st));
+  HK_HIP(hk::launch_core(va, pl.slots, pl.grid, st));
   tm.mark();
   HK_HIP(hk::launch_combine(va, pl.slots, st));
   tm.mark();

@@ -104,6 +104,7 @@ hipError_t launch_item_scan(const int32_t* nc, int n_tiles_total, int32_t* item_
 hipError_t launch_gridrec(const double* nu, int64_t N, double nu_start, double dnu, int64_t n, double cut,
                           int4* grec, hipStream_t st);
 hipError_t launch_voigt(const VoigtArgs& a, int slots, int grid, hipStream_t st);
+hipError_t launch_core(const VoigtArgs& a, int slots, int grid, hipStream_t st);
 hipError_t launch_combine(const VoigtArgs& a, int slots, hipStream_t st);
 hipError_t launch_cut_bounds(const double* nu, const int32_t* perm, int64_t N, double nu_start,
                              double dnu, int64_t n, double cut, int32_t* jlo, int32_t* jhi,

@@ -314,7 +314,7 @@ __global__ __launch_bounds__(1024) void k_item_scan(const int32_t* __restrict__ 
                                                     int32_t* __restrict__ item_base, int* counter) {
   __shared__ int32_t s[1024];
   __shared__ int32_t carry;
-  if (threadIdx.x == 0) { carry = 0; counter[0] = 0; }
+  if (threadIdx.x == 0) { carry = 0; counter[0] = 0; counter[1] = 0; }
   __syncthreads();
   for (int c0 = 0; c0 < n; c0 += 1024) {
     const int i = c0 + threadIdx.x;
@@ -384,17 +384,21 @@ __global__ __launch_bounds__(kThreads) void k_gridrec(const double* __restrict__
 //   F1 = (Ah, lo_rel, hi_rel, ampc): S gamma/(pi s), cut bounds relative to the reference
 //        index, S/(sqrt(pi) alpha)
 //   KA, KB, KC: Ah times the far-wing series coefficients (see wing_coeffs)
-//   code[w]: for wave w, bits 0-2 series order K used for all its non-core slots (0: the line
-//            does not reach the wave), bit 3 some lanes fall outside the cut range, bits 4-11
-//            the slots that hold the line core (|z| below the last series threshold)
+//   CZ: the line's core points (|z| below the last series threshold) within its cut range,
+//       as an inclusive tile-local range (empty: x > y)
+//   code[w]: for wave w, bits 0-2 series order K used for its wing points (0: the line does
+//            not reach the wave), bit 3 some lanes fall outside the cut range, bit 4 some of
+//            its points are core points
 //   list[w]: the staged lines reaching wave w, grouped by series order (see line_group)
+template <int P>
 struct LineLDS {
   float4 F0[kLB];
   float4 F1[kLB];
   float4 KA[kLB];   // c1, c2(K=2), c2(K>=3), c3(K=3)
   float4 KB[kLB];   // c4(K=3), c3(K=4), c4(K=4), c5(K=4)
   float KC[kLB];    // c6(K=4)
-  uint4 code[kLB];                  // component w: the code word of wave w
+  int2 CZ[kLB];
+  uint4 code[kLB];  // component w: the code word of wave w
   uint8_t list[kWavesPerWG][kLB];
 };
 
@@ -438,7 +442,7 @@ __device__ __forceinline__ void kahan_flush(float (&part)[P], float (&s)[P], flo
 // point, offset) is already in the grid record; the rest needs ~1e-7 and is done in FP32
 // (products ordered so that no intermediate underflows for relevant lines).
 template <int P>
-__device__ __forceinline__ void stage_line(LineLDS& L, int tid, const int4 gr, double nu0, float S, float gTv,
+__device__ __forceinline__ void stage_line(LineLDS<P>& L, int tid, const int4 gr, double nu0, float S, float gTv,
                                            const PairDesc& pd, const float* zK, int64_t tile0,
                                            uint32_t (&codes)[kWavesPerWG]) {
   constexpr int W = kWavesPerWG * kWave * P;
@@ -473,37 +477,45 @@ __device__ __forceinline__ void stage_line(LineLDS& L, int tid, const int4 gr, d
   }
   const int clo = (int)((int64_t)jlo - tile0 < -1 ? -1 : (int64_t)jlo - tile0);
   const int chi = (int)((int64_t)jhi - tile0 > W ? W : (int64_t)jhi - tile0);
+  // core points: strictly inside the last zone, and within the cut range
+  int czl = 1, czh = 0;
+  if (zh[kKmax - 1] > zl[kKmax - 1]) {
+    const float fl = floorf(zl[kKmax - 1]) + 1.0f, fh = ceilf(zh[kKmax - 1]) - 1.0f;
+    czl = fl < (float)clo ? clo : (fl > (float)(W + 1) ? W + 1 : (int)fl);
+    czh = fh > (float)chi ? chi : (fh < -2.0f ? -2 : (int)fh);
+  }
+  L.CZ[tid] = make_int2(czl, czh);
 #pragma unroll
   for (int w = 0; w < kWavesPerWG; ++w) {
     const int w0 = w * kWave * P, w1 = w0 + kWave * P - 1;
     uint32_t code = 0u;
     if (!(chi < w0 || clo > w1)) {
-      uint32_t K = 0u, core = 0u;
+      uint32_t K = 1u;
 #pragma unroll
       for (int p = 0; p < P; ++p) {
         const int s0 = w0 + p * kWave, s1 = s0 + kWave - 1;
         if (s1 < clo || s0 > chi) continue;
         uint32_t path = 1u;
 #pragma unroll
-        for (int z = 0; z < kKmax; ++z) path += ((float)s0 < zh[z] && (float)s1 > zl[z]) ? 1u : 0u;
-        if (path > (uint32_t)kKmax) core |= 1u << p;
-        else K = path > K ? path : K;
+        for (int z = 0; z < kKmax - 1; ++z) path += ((float)s0 < zh[z] && (float)s1 > zl[z]) ? 1u : 0u;
+        K = path > K ? path : K;
       }
-      if (K == 0u) K = 1u;  // only core slots: the order is unused
-      code = K | ((w0 >= clo && w1 <= chi) ? 0u : 8u) | (core << 4);
+      const bool core = (czl > w0 ? czl : w0) <= (czh < w1 ? czh : w1);
+      if (core) K = kKmax;  // the wing points next to the core need the highest order
+      code = K | ((w0 >= clo && w1 <= chi) ? 0u : 8u) | (core ? 16u : 0u);
     }
     codes[w] = code;
   }
 }
 
 // One line, all slots of this wave, series order K. MASK: lanes outside the cut range add
-// nothing. CORE: the slots in coremask are skipped here (their core is evaluated separately).
-template <int P, int K, bool MASK, bool CORE>
+// nothing. EXCL: lanes in [xl, xh] (the line's core points, relative index) add nothing.
+template <int P, int K, bool MASK, bool EXCL>
 __device__ __forceinline__ void wing_slots(float (&part)[P], float kf0, const float4& f0, const float4& f1,
-                                           const float4& ka, const float4& kb, float kc, uint32_t coremask) {
+                                           const float4& ka, const float4& kb, float kc, float xl = 0.f,
+                                           float xh = -1.f) {
 #pragma unroll
   for (int p = 0; p < P; ++p) {
-    if (CORE && ((coremask >> p) & 1u)) continue;
     const float kf = kf0 + (float)(kWave * p);
     const float D = __builtin_fmaf(kf, f0.z, f0.x);
     const float R = __builtin_fmaf(D, D, f0.w);
@@ -527,8 +539,10 @@ __device__ __forceinline__ void wing_slots(float (&part)[P], float kf0, const fl
       t = __builtin_fmaf(t, q, ka.x);
       t = __builtin_fmaf(t, q, f1.x);
     }
-    if (MASK) {
-      const bool in = (kf >= f1.y) && (kf <= f1.z);
+    if (MASK || EXCL) {
+      bool in = true;
+      if (MASK) in = (kf >= f1.y) && (kf <= f1.z);
+      if (EXCL) in = in && ((kf < xl) || (kf > xh));
       part[p] = in ? __builtin_fmaf(t, q, part[p]) : part[p];
     } else {
       part[p] = __builtin_fmaf(t, q, part[p]);
@@ -536,25 +550,16 @@ __device__ __forceinline__ void wing_slots(float (&part)[P], float kf0, const fl
   }
 }
 
-template <int P, int K>
-__device__ __forceinline__ void wing_dispatch(float (&part)[P], float kf0, const float4& f0, const float4& f1,
-                                              const float4& ka, const float4& kb, float kc, uint32_t masked,
-                                              uint32_t coremask) {
-  if (coremask) wing_slots<P, K, true, true>(part, kf0, f0, f1, ka, kb, kc, coremask);
-  else if (masked) wing_slots<P, K, true, false>(part, kf0, f0, f1, ka, kb, kc, 0u);
-  else wing_slots<P, K, false, false>(part, kf0, f0, f1, ka, kb, kc, 0u);
-}
-
 // Group of a staged line for one wave: 0 does not reach the wave, 1..4 unmasked wing-only
 // line of series order K, 5 general (some lanes outside the cut, or core slots).
 __device__ __forceinline__ int line_group(uint32_t code) {
   if (code == 0u) return 0;
-  return (code & 0xFF8u) ? 5 : (int)(code & 7u);
+  return (code & 24u) ? 5 : (int)(code & 7u);
 }
 
 // Per-wave wing loop over the lines of one group (all unmasked, no core slots).
 template <int P, int K>
-__device__ __forceinline__ void group_loop(const LineLDS& L, int wv, int i0, int i1, float jl0, float (&part)[P],
+__device__ __forceinline__ void group_loop(const LineLDS<P>& L, int wv, int i0, int i1, float jl0, float (&part)[P],
                                            float (&s)[P], float (&cc)[P], int& nproc) {
   for (int i = i0; i < i1; ++i) {
     const int l = __builtin_amdgcn_readfirstlane((int)L.list[wv][i]);
@@ -565,7 +570,7 @@ __device__ __forceinline__ void group_loop(const LineLDS& L, int wv, int i0, int
     if (K >= 2) ka = L.KA[l];
     if (K >= 3) kb = L.KB[l];
     if (K >= 4) kc = L.KC[l];
-    wing_slots<P, K, false, false>(part, jl0 - f0.y, f0, f1, ka, kb, kc, 0u);
+    wing_slots<P, K, false, false>(part, jl0 - f0.y, f0, f1, ka, kb, kc);
     if ((++nproc & 15) == 0) kahan_flush<P>(part, s, cc);
   }
 }
@@ -573,13 +578,10 @@ __device__ __forceinline__ void group_loop(const LineLDS& L, int wv, int i0, int
 template <int P>
 __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
   constexpr int W = kWavesPerWG * kWave * P;  // tile width in grid points
-  __shared__ LineLDS L;
-  __shared__ double sW[kWeidN + 1];  // core rational-approximation coefficients and scale
+  __shared__ LineLDS<P> L;
   __shared__ int sItem, sTile, sPair;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
-  if (tid < kWeidN) sW[tid] = c_weid[tid];
-  if (tid == kWeidN) sW[kWeidN] = c_weidL;
   const int total = a.item_base[a.n_tiles_total];
   const float jl0 = (float)(wv * kWave * P + lane);  // this lane's first tile point
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -678,29 +680,17 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
           const float4 kb = L.KB[l];
           const float kc = L.KC[l];
           const float kf0 = jl0 - f0.y;
-          const uint32_t K = code & 7u, masked = code & 8u, coremask = (code >> 4) & 0xFFu;
-          if (K == 1u) wing_dispatch<P, 1>(part, kf0, f0, f1, ka, kb, kc, masked, coremask);
-          else if (K == 2u) wing_dispatch<P, 2>(part, kf0, f0, f1, ka, kb, kc, masked, coremask);
-          else if (K == 3u) wing_dispatch<P, 3>(part, kf0, f0, f1, ka, kb, kc, masked, coremask);
-          else wing_dispatch<P, 4>(part, kf0, f0, f1, ka, kb, kc, masked, coremask);
-          if (coremask) {
-            // core slots: FP64 rational approximation for every lane of the slot, from the
-            // line's FP64 centre and widths
-            const int64_t li = b + l;
-            const double nu0 = a.nu[li];
-            const double alpha = nu0 * pd.beta;
-            const double y = (double)gT[li] * pd.pfac / alpha;
-            const double ia = 1.0 / alpha;
-            const double d64 = __dsub_rn(grid_nu(pd.nu_start, pd.dnu, (int64_t)f0.y + tile0), nu0);
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-              if (!((coremask >> p) & 1u)) continue;
-              const float kf = kf0 + (float)(kWave * p);
-              const double D = fma((double)kf, pd.dnu, d64);
-              const float v = f1.w * (float)weideman_re(D * ia, y, sW);
-              const bool in = (kf >= f1.y) && (kf <= f1.z);
-              part[p] += in ? v : 0.0f;
-            }
+          if (code & 16u) {
+            const int czl = __builtin_amdgcn_readfirstlane(L.CZ[l].x);
+            const int czh = __builtin_amdgcn_readfirstlane(L.CZ[l].y);
+            const float jt = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(f0.y)));
+            wing_slots<P, kKmax, true, true>(part, kf0, f0, f1, ka, kb, kc, (float)czl - jt, (float)czh - jt);
+          } else {
+            const uint32_t K = code & 7u;
+            if (K == 1u) wing_slots<P, 1, true, false>(part, kf0, f0, f1, ka, kb, kc);
+            else if (K == 2u) wing_slots<P, 2, true, false>(part, kf0, f0, f1, ka, kb, kc);
+            else if (K == 3u) wing_slots<P, 3, true, false>(part, kf0, f0, f1, ka, kb, kc);
+            else wing_slots<P, 4, true, false>(part, kf0, f0, f1, ka, kb, kc);
           }
           if ((++nproc & 15) == 0) kahan_flush<P>(part, s, cc);
         }
@@ -718,6 +708,192 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
         if (tile0 + local < pd.n) a.k[pd.out_off + tile0 + local] = v;
       } else {
         a.partial[((int64_t)it) * W + local] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------- core pass
+// The core points of every line (|z| below the last series threshold, within the cut) are
+// evaluated here, after the wing pass, over the same work items: each wave queues the
+// (line, point) pairs that fall on its points, evaluates 64 at a time with the FP64 rational
+// approximation (from the line's FP64 centre and widths) and adds them to its points in line
+// order (one round of LDS updates per line; a line's pairs have distinct points), then adds
+// the Kahan-summed result to the tile. Deterministic for a fixed tuning.
+template <int P>
+struct CoreLDS {
+  int4 C[kLB];                  // (core lo, core hi, jt, ampc bits); lo > hi: no core in the tile
+  uint8_t list[kWavesPerWG][kLB];
+  uint32_t queue[kWavesPerWG][kWave];
+  float acc[kWavesPerWG][kWave * P];
+};
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_core(VoigtArgs a) {
+  constexpr int W = kWavesPerWG * kWave * P;
+  __shared__ CoreLDS<P> L;
+  __shared__ double sW[kWeidN + 1];
+  __shared__ int sItem, sTile, sPair;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int w0 = wv * kWave * P, w1 = w0 + kWave * P - 1;
+  if (tid < kWeidN) sW[tid] = c_weid[tid];
+  if (tid == kWeidN) sW[kWeidN] = c_weidL;
+#pragma unroll
+  for (int p = 0; p < P; ++p) L.acc[wv][p * kWave + lane] = 0.0f;
+  const int total = a.item_base[a.n_tiles_total];
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const float zc = a.zK[kKmax - 1];
+
+  for (;;) {
+    if (tid == 0) {
+      const int it = atomicAdd(a.counter + 1, 1);
+      sItem = it;
+      if (it < total) {
+        int lo = 0, hi = a.n_tiles_total - 1;
+        while (lo < hi) {
+          const int m = (lo + hi + 1) >> 1;
+          if (a.item_base[m] <= it) lo = m; else hi = m - 1;
+        }
+        sTile = lo;
+        sPair = find_pair(a.pairs, a.n_pairs, lo);
+      }
+    }
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(sItem);
+    if (it >= total) break;
+    const int g = __builtin_amdgcn_readfirstlane(sTile);
+    const PairDesc pd = wave_uniform(a.pairs[__builtin_amdgcn_readfirstlane(sPair)]);
+    const int ibase = __builtin_amdgcn_readfirstlane(a.item_base[g]);
+    const int chunk_idx = it - ibase;
+    const int nc = __builtin_amdgcn_readfirstlane(a.tile_nc[g]);
+    const int64_t tile0 = (int64_t)(g - pd.tile_base) * W;
+    const int64_t line_lo = (int64_t)__builtin_amdgcn_readfirstlane(a.tile_lo[g]) + (int64_t)chunk_idx * a.chunk;
+    int64_t line_hi = line_lo + a.chunk;
+    const int64_t thi = __builtin_amdgcn_readfirstlane(a.tile_hi[g]);
+    if (line_hi > thi) line_hi = thi;
+    const float* __restrict__ S_T = a.S_T + (int64_t)pd.tidx * a.N;
+    const float* __restrict__ gT = a.gT + (int64_t)pd.tidx * a.N;
+    const int4* __restrict__ grec = a.grec + (int64_t)pd.gidx * a.N;
+    const float inv_dnu = (float)(1.0 / pd.dnu);
+
+    float s[P], cc[P], part[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) { s[p] = 0.0f; cc[p] = 0.0f; part[p] = 0.0f; }
+    bool any = false;
+
+    for (int64_t b = line_lo; b < line_hi; b += kLB) {
+      // stage: each line's core points in this tile (tile-local, within the cut range)
+      int czl = 1, czh = 0, jt = 0;
+      float ampc = 0.0f;
+      {
+        const int64_t li = b + tid;
+        if (li < line_hi) {
+          const int4 gr = grec[li];
+          const float S = S_T[li];
+          const int jref = gr.y, jlo = gr.z, jhi = gr.w;
+          if (S > 0.0f && jlo <= jhi && (int64_t)jhi >= tile0 && (int64_t)jlo <= tile0 + (W - 1)) {
+            const double nu0 = a.nu[li];
+            const float alpha = (float)(nu0 * pd.beta);
+            const float gam = gT[li] * (float)pd.pfac;
+            jt = (int)((int64_t)jref - tile0);
+            const float af = alpha * inv_dnu, gf = gam * inv_dnu;
+            const float zz = zc * af;
+            const float h2 = zz * zz - gf * gf;
+            if (h2 > 0.0f) {
+              const float h = sqrtf(h2) * 1.00001f + 1e-3f;
+              const float c = (float)jt - __int_as_float(gr.x) * inv_dnu;
+              const int clo = (int)((int64_t)jlo - tile0 < -1 ? -1 : (int64_t)jlo - tile0);
+              const int chi = (int)((int64_t)jhi - tile0 > W ? W : (int64_t)jhi - tile0);
+              const float fl = floorf(c - h) + 1.0f, fh = ceilf(c + h) - 1.0f;
+              czl = fl < (float)clo ? clo : (fl > (float)(W + 1) ? W + 1 : (int)fl);
+              czh = fh > (float)chi ? chi : (fh < -2.0f ? -2 : (int)fh);
+              ampc = S / (1.7724538509055160273f * alpha);
+            }
+          }
+        }
+        L.C[tid] = make_int4(czl, czh, jt, __float_as_int(ampc));
+      }
+      __syncthreads();
+      // this wave's list of lines with core points on its span, in staging order
+      int nl = 0;
+      {
+#pragma unroll
+        for (int r = 0; r < kLB / kWave; ++r) {
+          const int4 c = L.C[r * kWave + lane];
+          const int lo = c.x > w0 ? c.x : w0, hi = c.y < w1 ? c.y : w1;
+          const bool has = lo <= hi;
+          const uint64_t m = __ballot(has);
+          if (has) L.list[wv][nl + (int)__popcll(m & lt)] = (uint8_t)(r * kWave + lane);
+          nl += (int)__popcll(m);
+        }
+      }
+      // queue, evaluate, accumulate
+      int qn = 0;
+      for (int i = 0; i <= nl; ++i) {
+        int j0 = 1, j1 = 0, l = 0;
+        if (i < nl) {
+          l = __builtin_amdgcn_readfirstlane((int)L.list[wv][i]);
+          const int cl = __builtin_amdgcn_readfirstlane(L.C[l].x), ch = __builtin_amdgcn_readfirstlane(L.C[l].y);
+          j0 = cl > w0 ? cl : w0;
+          j1 = ch < w1 ? ch : w1;
+        }
+        while (j0 <= j1 || (i == nl && qn > 0)) {
+          const int take = j0 <= j1 ? ((j1 - j0 + 1) < (kWave - qn) ? (j1 - j0 + 1) : (kWave - qn)) : 0;
+          if (lane < take) L.queue[wv][qn + lane] = ((uint32_t)l << 16) | (uint32_t)(j0 + lane - w0);
+          qn += take;
+          j0 += take;
+          if (qn == kWave || (i == nl && qn > 0)) {
+            const bool valid = lane < qn;
+            const uint32_t e = valid ? L.queue[wv][lane] : 0u;
+            const int el = (int)(e >> 16), jw = (int)(e & 0xFFFFu);
+            float v = 0.0f;
+            if (valid) {
+              const int4 c = L.C[el];
+              const int64_t li = b + el;
+              const double nu0 = a.nu[li];
+              const double alpha = nu0 * pd.beta;
+              const double y = (double)gT[li] * pd.pfac / alpha;
+              const double d64 = __dsub_rn(grid_nu(pd.nu_start, pd.dnu, (int64_t)c.z + tile0), nu0);
+              const double D = (double)(w0 + jw - c.z) * pd.dnu + d64;
+              v = __int_as_float(c.w) * (float)weideman_re(D / alpha, y, sW);
+            }
+            uint64_t rem = __ballot(valid);
+            while (rem) {
+              const int lf = __builtin_amdgcn_readlane(el, (int)__builtin_ctzll(rem));
+              const bool mine = valid && el == lf && ((rem >> lane) & 1ull);
+              if (mine) L.acc[wv][jw] += v;
+              rem &= ~__ballot(mine);
+            }
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+              part[p] += L.acc[wv][p * kWave + lane];
+              L.acc[wv][p * kWave + lane] = 0.0f;
+            }
+            kahan_flush<P>(part, s, cc);
+            qn = 0;
+            any = true;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // add the core sums to the wing pass's tile (or partial tile)
+    if (__builtin_amdgcn_readfirstlane((int)any)) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) {
+        const int local = w0 + p * kWave + lane;
+        const float v = s[p] - cc[p];
+        if (nc == 1) {
+          if (tile0 + local < pd.n) {
+            float* dst = a.k + pd.out_off + tile0 + local;
+            *dst = *dst + v;
+          }
+        } else {
+          float* dst = a.partial + (int64_t)it * W + local;
+          *dst = *dst + v;
+        }
       }
     }
     __syncthreads();
@@ -830,6 +1006,13 @@ hipError_t launch_gridrec(const double* nu, int64_t N, double nu_start, double d
 hipError_t launch_voigt(const VoigtArgs& a, int slots, int grid, hipStream_t st) {
   if (slots == 8) hipLaunchKernelGGL(k_voigt<8>, dim3(grid), dim3(kThreads), 0, st, a);
   else if (slots == 4) hipLaunchKernelGGL(k_voigt<4>, dim3(grid), dim3(kThreads), 0, st, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_core(const VoigtArgs& a, int slots, int grid, hipStream_t st) {
+  if (slots == 8) hipLaunchKernelGGL(k_core<8>, dim3(grid), dim3(kThreads), 0, st, a);
+  else if (slots == 4) hipLaunchKernelGGL(k_core<4>, dim3(grid), dim3(kThreads), 0, st, a);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
