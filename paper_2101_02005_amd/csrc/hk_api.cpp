@@ -39,8 +39,9 @@ constexpr double kH = 6.62606957e-27;     // erg s
 constexpr double kAMU = 1.660538921e-24;  // g
 constexpr double kC2 = kH * kC / kB;      // cm K
 
-// |z| thresholds of the far-wing series orders 1..4 (relative truncation error < 2e-6)
-constexpr double kZK[hk::kKmax] = {870.0, 37.5, 13.8, 8.7};
+// |z| thresholds of the far-wing series orders 1..5 (relative truncation error < 2e-6);
+// below the last one the core approximation is used
+constexpr double kZK[hk::kKmax] = {870.0, 37.5, 13.8, 8.7, 6.75};
 
 thread_local std::string g_err;
 thread_local hk_timings g_tim = {-1, -1, -1, -1, -1, -1, 0, 0, 0, 0};

@@ -10,8 +10,8 @@ constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kThreads = 256;    // threads per workgroup of the Voigt and sort kernels
 constexpr int kWavesPerWG = kThreads / kWave;
 constexpr int kLB = 256;         // lines staged in LDS per batch (one per thread)
-constexpr int kKmax = 4;         // highest order of the far-wing series
-constexpr int kWeidN = 24;       // terms of the FP64 core rational approximation
+constexpr int kKmax = 5;         // highest order of the far-wing series
+constexpr int kWeidN = 20;       // terms of the FP64 core rational approximation
 constexpr int kKeyBits = 24;     // linear wavenumber-bin key width
 constexpr int kRadixBits = 8;
 constexpr int kSortItems = 16;   // keys per thread per sort block

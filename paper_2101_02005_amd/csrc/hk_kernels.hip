@@ -340,11 +340,20 @@ __global__ __launch_bounds__(1024) void k_item_scan(const int32_t* __restrict__ 
 // Re w(x + iy), y >= 0, by J.A.C. Weideman's rational approximation ("Computation of the
 // complex error function", SIAM J. Numer. Anal. 31 (1994) 1497-1518) with N = kWeidN terms:
 // w = 2 p(Z)/(L - iz)^2 + (1/sqrt(pi))/(L - iz), Z = (L + iz)/(L - iz), in FP64.
+// 1/d for normal d > 0 to ~1 ulp: hardware estimate refined by two Newton steps
+__device__ __forceinline__ double rcp64(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = fma(-d, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-d, r, 1.0);
+  return fma(r, e, r);
+}
+
 __device__ __forceinline__ double weideman_re(double x, double y, const double* __restrict__ wc) {
   const double L = wc[kWeidN];
   const double dr = L + y, di = -x;  // L - iz
   const double nr = L - y, ni = x;   // L + iz
-  const double inv = 1.0 / (dr * dr + di * di);
+  const double inv = rcp64(dr * dr + di * di);
   const double Zr = (nr * dr + ni * di) * inv;
   const double Zi = (ni * dr - nr * di) * inv;
   double pr = wc[kWeidN - 1], pi = 0.0;
@@ -381,9 +390,10 @@ __global__ __launch_bounds__(kThreads) void k_gridrec(const double* __restrict__
 // Line record layout in LDS (structure of arrays, one entry per staged line):
 //   F0 = (dh, jt, dnh, gh): offset delta/sqrt(s), reference index - tile start, dnu/sqrt(s),
 //        gamma^2/s, with s = max(alpha^2, gamma^2)
-//   F1 = (Ah, lo_rel, hi_rel, ampc): S gamma/(pi s), cut bounds relative to the reference
-//        index, S/(sqrt(pi) alpha)
-//   KA, KB, KC: Ah times the far-wing series coefficients (see wing_coeffs)
+//   F1 = (Ah, lo_rel, hi_rel, a): S gamma/(pi s), cut bounds relative to the reference
+//        index, alpha^2/s
+//   KA, KB, KC: Ah times the far-wing series coefficients of orders 2-4 (see wing_coeffs);
+//        order 5 is formed on the fly from a = alpha^2/s and g = gamma^2/s
 //   CZ: the line's core points (|z| below the last series threshold) within its cut range,
 //       as an inclusive tile-local range (empty: x > y)
 //   code[w]: for wave w, bits 0-2 series order K used for its wing points (0: the line does
@@ -414,6 +424,9 @@ struct LineLDS {
 //   K=3: c1, c2 = -2ag + 15a^2/4, c3 = -15a^2 g, c4 = 12 a^2 g^2
 //   K=4: c1, c2 (as K=3), c3 = -15a^2 g + 105a^3/8, c4 = 12a^2g^2 - 105a^3 g, c5 = 210 a^3 g^2,
 //        c6 = -120 a^3 g^3
+//   K=5: c1..c3 (as K=4), c4 = 12a^2g^2 - 105a^3g + 945a^4/16, c5 = 210a^3g^2 - 1575a^4g/2,
+//        c6 = -120a^3g^3 + 2835a^4g^2, c7 = -3780a^4g^3, c8 = 1680a^4g^4
+//   (a_4 = 105/16; P_4(u) = 9 - 120u + 432u^2 - 576u^3 + 256u^4)
 __device__ __forceinline__ void wing_coeffs(float a, float g, float Ah, float4& KA, float4& KB, float& KC) {
   const float a2 = a * a, a3 = a2 * a, g2 = g * g;
   const float c2_2 = -2.0f * a * g;
@@ -459,7 +472,7 @@ __device__ __forceinline__ void stage_line(LineLDS<P>& L, int tid, const int4 gr
   const int jt = (int)((int64_t)jref - tile0);
   const float Ah = S * (gam * isc) * 0.318309886183790672f;  // S gamma / (pi s)
   L.F0[tid] = make_float4(delta * rs, (float)jt, (float)pd.dnu * rs, g2 * isc);
-  L.F1[tid] = make_float4(Ah, (float)(jlo - jref), (float)(jhi - jref), S / (1.7724538509055160273f * alpha));
+  L.F1[tid] = make_float4(Ah, (float)(jlo - jref), (float)(jhi - jref), a2 * isc);
   wing_coeffs(a2 * isc, g2 * isc, Ah, L.KA[tid], L.KB[tid], L.KC[tid]);
   // zone K: points with |z| < zK[K], i.e. |j - c| < sqrt(zK^2 alpha^2 - gamma^2)/dnu around the
   // centre c (tile-local points); a slot [s0, s1] meets it when s0 < c + h and s1 > c - h
@@ -531,11 +544,20 @@ __device__ __forceinline__ void wing_slots(float (&part)[P], float kf0, const fl
       t = __builtin_fmaf(t, q, ka.z);
       t = __builtin_fmaf(t, q, ka.x);
       t = __builtin_fmaf(t, q, f1.x);
-    } else {
+    } else if (K == 4) {
       t = __builtin_fmaf(kc, q, kb.w);
       t = __builtin_fmaf(t, q, kb.z);
       t = __builtin_fmaf(t, q, kb.y);
       t = __builtin_fmaf(t, q, ka.z);
+      t = __builtin_fmaf(t, q, ka.x);
+      t = __builtin_fmaf(t, q, f1.x);
+    } else {  // K == 5: ka = (c1, c2, c3, c4), kb = (c5, c6, c7, c8)
+      t = __builtin_fmaf(kb.w, q, kb.z);
+      t = __builtin_fmaf(t, q, kb.y);
+      t = __builtin_fmaf(t, q, kb.x);
+      t = __builtin_fmaf(t, q, ka.w);
+      t = __builtin_fmaf(t, q, ka.z);
+      t = __builtin_fmaf(t, q, ka.y);
       t = __builtin_fmaf(t, q, ka.x);
       t = __builtin_fmaf(t, q, f1.x);
     }
@@ -550,11 +572,11 @@ __device__ __forceinline__ void wing_slots(float (&part)[P], float kf0, const fl
   }
 }
 
-// Group of a staged line for one wave: 0 does not reach the wave, 1..4 unmasked wing-only
-// line of series order K, 5 general (some lanes outside the cut, or core slots).
+// Group of a staged line for one wave: 0 does not reach the wave, 1..4 unmasked line of
+// series order K without core points, 5 general (order 5, lanes outside the cut, or core points).
 __device__ __forceinline__ int line_group(uint32_t code) {
   if (code == 0u) return 0;
-  return (code & 24u) ? 5 : (int)(code & 7u);
+  return ((code & 24u) || (code & 7u) > 4u) ? 5 : (int)(code & 7u);
 }
 
 // Per-wave wing loop over the lines of one group (all unmasked, no core slots).
@@ -680,18 +702,29 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
           const float4 kb = L.KB[l];
           const float kc = L.KC[l];
           const float kf0 = jl0 - f0.y;
-          if (code & 16u) {
-            const int czl = __builtin_amdgcn_readfirstlane(L.CZ[l].x);
-            const int czh = __builtin_amdgcn_readfirstlane(L.CZ[l].y);
-            const float jt = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(f0.y)));
-            wing_slots<P, kKmax, true, true>(part, kf0, f0, f1, ka, kb, kc, (float)czl - jt, (float)czh - jt);
-          } else {
-            const uint32_t K = code & 7u;
-            if (K == 1u) wing_slots<P, 1, true, false>(part, kf0, f0, f1, ka, kb, kc);
-            else if (K == 2u) wing_slots<P, 2, true, false>(part, kf0, f0, f1, ka, kb, kc);
-            else if (K == 3u) wing_slots<P, 3, true, false>(part, kf0, f0, f1, ka, kb, kc);
-            else wing_slots<P, 4, true, false>(part, kf0, f0, f1, ka, kb, kc);
-          }
+          const uint32_t K = code & 7u;
+          if (K == 5u) {
+            // order-5 coefficients from a = alpha^2/s, g = gamma^2/s, times Ah
+            const float av = f1.w, gv = f0.w, A = f1.x;
+            const float a2 = av * av, a3 = a2 * av, a4 = a2 * a2, g2 = gv * gv, g3 = g2 * gv;
+            const float4 k5a = make_float4(A * (1.5f * av), A * (-2.0f * av * gv + 3.75f * a2),
+                                           A * (-15.0f * a2 * gv + 13.125f * a3),
+                                           A * (12.0f * a2 * g2 - 105.0f * a3 * gv + 59.0625f * a4));
+            const float4 k5b = make_float4(A * (210.0f * a3 * g2 - 787.5f * a4 * gv),
+                                           A * (-120.0f * a3 * g3 + 2835.0f * a4 * g2), A * (-3780.0f * a4 * g3),
+                                           A * (1680.0f * a4 * g2 * g2));
+            if (code & 16u) {
+              const int czl = __builtin_amdgcn_readfirstlane(L.CZ[l].x);
+              const int czh = __builtin_amdgcn_readfirstlane(L.CZ[l].y);
+              const float jt = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(f0.y)));
+              wing_slots<P, 5, true, true>(part, kf0, f0, f1, k5a, k5b, 0.f, (float)czl - jt, (float)czh - jt);
+            } else {
+              wing_slots<P, 5, true, false>(part, kf0, f0, f1, k5a, k5b, 0.f);
+            }
+          } else if (K == 1u) wing_slots<P, 1, true, false>(part, kf0, f0, f1, ka, kb, kc);
+          else if (K == 2u) wing_slots<P, 2, true, false>(part, kf0, f0, f1, ka, kb, kc);
+          else if (K == 3u) wing_slots<P, 3, true, false>(part, kf0, f0, f1, ka, kb, kc);
+          else wing_slots<P, 4, true, false>(part, kf0, f0, f1, ka, kb, kc);
           if ((++nproc & 15) == 0) kahan_flush<P>(part, s, cc);
         }
       }
@@ -854,10 +887,10 @@ __global__ __launch_bounds__(kThreads) void k_core(VoigtArgs a) {
               const int64_t li = b + el;
               const double nu0 = a.nu[li];
               const double alpha = nu0 * pd.beta;
-              const double y = (double)gT[li] * pd.pfac / alpha;
+              const double y = (double)gT[li] * pd.pfac * rcp64(alpha);
               const double d64 = __dsub_rn(grid_nu(pd.nu_start, pd.dnu, (int64_t)c.z + tile0), nu0);
               const double D = (double)(w0 + jw - c.z) * pd.dnu + d64;
-              v = __int_as_float(c.w) * (float)weideman_re(D / alpha, y, sW);
+              v = __int_as_float(c.w) * (float)weideman_re(D * rcp64(alpha), y, sW);
             }
             uint64_t rem = __ballot(valid);
             while (rem) {
