@@ -40,6 +40,7 @@ class Species(ctypes.Structure):
 
 
 _lib = None
+GH_NODES = 32  # Gauss-Hermite nodes of the far-wing profile derivatives
 _D = ctypes.POINTER(ctypes.c_double)
 _I64 = ctypes.POINTER(ctypes.c_int64)
 
@@ -63,6 +64,13 @@ def _load():
         lib.or_count_evals.restype = ctypes.c_int64
         lib.or_jranges.argtypes = [i64, _D, dbl, dbl, i64, dbl, _I64, _I64]
         lib.or_num_threads.restype = ctypes.c_int
+        lib.or_voigt_derivs_arr.argtypes = [i64, _D, _D, _D, _D, _D]
+        lib.or_set_gauss_hermite.argtypes = [ctypes.c_int, _D, _D]
+        lib.or_set_gauss_hermite.restype = ctypes.c_int
+        t, w = np.polynomial.hermite.hermgauss(GH_NODES)
+        t, w = _d(t), _d(w)
+        if lib.or_set_gauss_hermite(GH_NODES, _p(t), _p(w)) != 0:
+            raise RuntimeError("or_set_gauss_hermite failed")
         _lib = lib
     return _lib
 
@@ -103,6 +111,16 @@ def voigt(delta, alpha, gamma):
     out = np.empty_like(d)
     _load().or_voigt_arr(d.size, _p(d), _p(a), _p(g), _p(out))
     return out
+
+
+def voigt_derivs(delta, alpha, gamma):
+    """(dV/dgamma, dV/dalpha) of the unit-area Voigt profile (closed form near the centre,
+    Gauss-Hermite quadrature of the convolution integral for |z| >= 10)."""
+    d, a, g = np.broadcast_arrays(_d(delta), _d(alpha), _d(gamma))
+    d, a, g = _d(d).ravel(), _d(a).ravel(), _d(g).ravel()
+    dg, da = np.empty_like(d), np.empty_like(d)
+    _load().or_voigt_derivs_arr(d.size, _p(d), _p(a), _p(g), _p(dg), _p(da))
+    return dg, da
 
 
 def line_params(lines, sp, T, P):

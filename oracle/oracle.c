@@ -62,6 +62,7 @@ static const double OR_H = 6.62606957e-27;
 static const double OR_AMU = 1.660538921e-24;
 static const double OR_SQRT_PI = 1.7724538509055160273;
 static const double OR_TWO_OVER_SQRT_PI = 1.1283791670955125739;
+static const double OR_PI = 3.14159265358979323846;
 
 typedef struct or_species {
   double mass_amu;   /* molecular mass [amu] */
@@ -219,6 +220,63 @@ void or_voigt_arr(int64_t n, const double* delta, const double* alpha, const dou
   for (int64_t i = 0; i < n; ++i) V[i] = or_voigt(delta[i], alpha[i], gamma[i]);
 }
 
+/* Gauss-Hermite rule for the weight exp(-t^2): nodes and weights are handed in by the Python
+ * side (a library routine), OR_GH_MAX at most. */
+#define OR_GH_MAX 64
+static int or_gh_n = 0;
+static double or_gh_t[OR_GH_MAX], or_gh_w[OR_GH_MAX];
+
+int or_set_gauss_hermite(int n, const double* t, const double* w) {
+  if (n < 1 || n > OR_GH_MAX) return -1;
+  for (int k = 0; k < n; ++k) { or_gh_t[k] = t[k]; or_gh_w[k] = w[k]; }
+  or_gh_n = n;
+  return 0;
+}
+
+/* |z| from which the profile derivatives are integrated instead of taken from w'(z). */
+#define OR_DERIV_ZQUAD 10.0
+
+/* dV/dgamma and dV/dalpha of the unit-area Voigt profile at offset delta.
+ * Near the centre (|z| < 10, z = (delta + i gamma)/alpha) from w'(z) = -2 z w(z) + 2i/sqrt(pi):
+ *   dK/dx = -2 (xK - yL),  dK/dy = 2 (xL + yK) - 2/sqrt(pi),
+ *   dV/dgamma = (dK/dy) / (sqrt(pi) alpha^2),  dV/dalpha = -(K + x dK/dx + y dK/dy) / (sqrt(pi) alpha^2).
+ * These lose about |z|^2 in relative precision to cancellation (dK/dy falls as 1/|z|^2 while each of
+ * its terms stays O(1)), so for |z| >= 10 the profile is written as the convolution of the Gaussian
+ * and the Lorentzian, V = pi^-1/2 int exp(-t^2) L(delta - alpha t) dt with L(x) = gamma/(pi (x^2 + gamma^2)),
+ * the derivatives are taken under the integral and the integral is done by Gauss-Hermite
+ * quadrature (the integrand is analytic in |t| < |z|, so the rule converges geometrically):
+ *   dV/dgamma = pi^-1/2 sum_k w_k (x_k^2 - gamma^2) / (pi (x_k^2 + gamma^2)^2),
+ *   dV/dalpha = pi^-1/2 sum_k w_k t_k 2 gamma x_k / (pi (x_k^2 + gamma^2)^2),  x_k = delta - alpha t_k. */
+static void or_voigt_derivs(double delta, double alpha, double gamma, double* dVdg, double* dVda) {
+  const double x = delta / alpha, y = gamma / alpha;
+  if (x * x + y * y < OR_DERIV_ZQUAD * OR_DERIV_ZQUAD || or_gh_n == 0) {
+    double K, L;
+    or_faddeeva(x, y, &K, &L);
+    const double Kx = -2.0 * (x * K - y * L);
+    const double Ky = 2.0 * (x * L + y * K) - OR_TWO_OVER_SQRT_PI;
+    const double den = OR_SQRT_PI * alpha * alpha;
+    *dVdg = Ky / den;
+    *dVda = -(K + x * Kx + y * Ky) / den;
+    return;
+  }
+  double sg = 0.0, sa = 0.0;
+  for (int k = 0; k < or_gh_n; ++k) {
+    const double xk = delta - alpha * or_gh_t[k];
+    const double d = xk * xk + gamma * gamma;
+    const double inv = 1.0 / (OR_PI * d * d);
+    sg += or_gh_w[k] * (xk * xk - gamma * gamma) * inv;
+    sa += or_gh_w[k] * or_gh_t[k] * 2.0 * gamma * xk * inv;
+  }
+  *dVdg = sg / OR_SQRT_PI;
+  *dVda = sa / OR_SQRT_PI;
+}
+
+void or_voigt_derivs_arr(int64_t n, const double* delta, const double* alpha, const double* gamma,
+                         double* dVdg, double* dVda) {
+  #pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) or_voigt_derivs(delta[i], alpha[i], gamma[i], &dVdg[i], &dVda[i]);
+}
+
 /* grid point: nu_j = nu_start + j*dnu, a product then a sum */
 static inline double or_grid(double nu_start, double dnu, int64_t j) {
   const double p = (double)j * dnu;
@@ -328,15 +386,11 @@ int or_gradient(int64_t N, const double* nu, const double* Sref, const double* E
     or_sum sV = {0, 0}, sY = {0, 0}, sA = {0, 0};
     for (int64_t j = j0; j <= j1; ++j) {
       const double d = or_grid(nu_start, dnu, j) - nu[i];
-      const double x = d / al, y = ga / al;
-      double K, L;
-      or_faddeeva(x, y, &K, &L);
-      const double Kx = -2.0 * (x * K - y * L);
-      const double Ky = 2.0 * (x * L + y * K) - OR_TWO_OVER_SQRT_PI;
-      const double den = OR_SQRT_PI * al;
-      or_sum_add(&sV, g[j] * (K / den));
-      or_sum_add(&sY, g[j] * (Ky / (den * al)));
-      or_sum_add(&sA, g[j] * (-(K + x * Kx + y * Ky) / (den * al)));
+      double dVdg, dVda;
+      or_voigt_derivs(d, al, ga, &dVdg, &dVda);
+      or_sum_add(&sV, g[j] * or_voigt(d, al, ga));
+      or_sum_add(&sY, g[j] * dVdg);
+      or_sum_add(&sA, g[j] * dVda);
     }
     const double gs = or_sum_get(&sV), gg = S * or_sum_get(&sY), gal = S * or_sum_get(&sA);
     if (GS) GS[q] = gs;

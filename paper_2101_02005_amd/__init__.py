@@ -6,3 +6,4 @@ from ._lib import (HK_EDEVICE, HK_EINVAL, HK_ENOMEM, HK_EUNSUPPORTED, HK_OK, Gri
                    LineOverride, Lines, Species, grid, hk_debug_cut_bounds, hk_debug_line_params,
                    hk_debug_sorted, hk_get_timings, hk_opacity, hk_opacity_backward, hk_opacity_batched,
                    hk_prepare_lines, hk_release_lines, hk_workspace_size, load, species)
+from .autograd import HkOpacityFn, opacity  # noqa: F401,E402

@@ -81,6 +81,15 @@ struct DevInfo {
 std::mutex g_mu;
 std::map<int, DevInfo> g_dev;
 
+// Cached graphs of batched calls, keyed by every argument value and pointer of the call.
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+std::mutex g_graph_mu;
+std::map<std::string, GraphEntry> g_graphs;
+std::map<int, hipStream_t> g_capture_stream;  // per device
+
 // Weideman (1994) coefficients: a = Re DFT(fftshift(f)) / (2M), f(t) = e^{-t^2}(L^2 + t^2) at
 // t = L tan(theta/2), theta = k pi / M, k = -M+1..M-1 (f = 0 at k = -M), M = 2N, L = sqrt(N/sqrt2).
 void weideman_coeffs(int N, double* a_out, double* L_out) {
@@ -255,6 +264,22 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   return HK_OK;
 }
 
+// Backward workspace: grid records, per-line (dL/dT, dL/dlnP) terms, reduction partials.
+constexpr int kBwdPartials = 256;
+struct BwdLayout {
+  size_t off_gr = 0, off_contrib = 0, off_part = 0, total = 0;
+};
+BwdLayout backward_layout(int64_t N) {
+  BwdLayout b;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
+  b.off_gr = take(sizeof(int4) * (size_t)N);
+  b.off_contrib = take(2 * sizeof(double) * (size_t)N);
+  b.off_part = take(2 * sizeof(double) * kBwdPartials);
+  b.total = off;
+  return b;
+}
+
 hk::PrepArgs prep_args(const hk_lines* L, const hk_line_override* ovr, double T) {
   hk::PrepArgs a;
   a.nu = L->nu;
@@ -302,8 +327,9 @@ struct Timer {
 };
 
 hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan& pl, double cut, float* k,
-                      char* ws, hipStream_t st) {
+                      char* ws, hipStream_t st, bool timed = true) {
   Timer tm(st);
+  tm.on = tm.on && timed;
   tm.mark();
   float* S_T = reinterpret_cast<float*>(ws + pl.off_S);
   float* gT = reinterpret_cast<float*>(ws + pl.off_g);
@@ -486,6 +512,20 @@ hk_status hk_prepare_lines(const double* nu, const double* S_ref, const double* 
 
 hk_status hk_release_lines(hk_lines* lines) {
   if (!lines) return HK_OK;
+  {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+      const void* h = nullptr;
+      memcpy(&h, it->first.data(), sizeof h);
+      if (h == lines) {
+        (void)hipGraphExecDestroy(it->second.exec);
+        (void)hipGraphDestroy(it->second.graph);
+        it = g_graphs.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
   int cur = -1;
   (void)hipGetDevice(&cur);
   if (cur != lines->device) (void)hipSetDevice(lines->device);
@@ -513,6 +553,10 @@ hk_status hk_workspace_size(const hk_lines* lines, int mode, int32_t n_pairs, in
   DevInfo di;
   s = device_init(&dev, &di);
   if (s != HK_OK) return s;
+  if (mode == 2) {
+    *bytes = backward_layout(lines->N).total;
+    return HK_OK;
+  }
   Plan pl;
   s = make_plan(lines, n_pairs, n_temps, nullptr, nullptr, grids, nullptr, cutoff, di, &pl);
   if (s != HK_OK) return s;
@@ -574,15 +618,115 @@ hk_status hk_opacity_batched(const hk_lines* lines, int32_t n_pairs, const doubl
   s = make_plan(lines, n_pairs, n_pairs, T, P_atm, grids, out_offset, cutoff, di, &pl);
   if (s != HK_OK) return s;
   if (ws_bytes < pl.total) return fail(HK_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, pl.total);
-  return run_forward(lines, nullptr, pl, cutoff, k, static_cast<char*>(ws), stream);
+  if (!env_flag("HK_GRAPH", true))
+    return run_forward(lines, nullptr, pl, cutoff, k, static_cast<char*>(ws), stream);
+  // graph key: every argument value and pointer, and the tuning
+  std::string key;
+  auto put = [&](const void* p, size_t n) { key.append(static_cast<const char*>(p), n); };
+  const void* ptrs[3] = {lines, k, ws};
+  put(ptrs, sizeof ptrs);
+  put(&ws_bytes, sizeof ws_bytes);
+  put(&cutoff, sizeof cutoff);
+  put(&n_pairs, sizeof n_pairs);
+  put(&pl.slots, sizeof pl.slots);
+  put(&pl.chunk, sizeof pl.chunk);
+  put(T, sizeof(double) * n_pairs);
+  put(P_atm, sizeof(double) * n_pairs);
+  put(grids, sizeof(hk_grid) * n_pairs);
+  put(out_offset, sizeof(int64_t) * n_pairs);
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  auto it = g_graphs.find(key);
+  if (it == g_graphs.end()) {
+    hipStream_t cap;
+    auto cs = g_capture_stream.find(dev);
+    if (cs == g_capture_stream.end()) {
+      HK_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      g_capture_stream[dev] = cap;
+    } else {
+      cap = cs->second;
+    }
+    GraphEntry ge;
+    HK_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    hk_status rs = run_forward(lines, nullptr, pl, cutoff, k, static_cast<char*>(ws), cap, false);
+    hipGraph_t graph = nullptr;
+    hipError_t ec = hipStreamEndCapture(cap, &graph);
+    if (rs != HK_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rs;
+    }
+    if (ec != hipSuccess) return fail(HK_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+    ge.graph = graph;
+    hipError_t ei = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return fail(HK_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+    }
+    it = g_graphs.emplace(key, ge).first;
+  }
+  Timer tm(stream);
+  tm.mark();
+  HK_HIP(hipGraphLaunch(it->second.exec, stream));
+  tm.mark();
+  tm.finish();
+  g_tim.prep_ms = g_tim.worklist_ms = g_tim.combine_ms = -1;
+  g_tim.voigt_ms = tm.ms(0);  // whole graph
+  g_tim.tile_width = pl.W;
+  g_tim.lines_per_batch = hk::kLB;
+  g_tim.chunk_lines = pl.chunk;
+  g_tim.n_items = (int32_t)pl.items_bound;
+  return HK_OK;
 }
 
 hk_status hk_opacity_backward(const hk_lines* lines, const hk_line_override* ovr, double T, double P_atm,
                               hk_grid grid, double cutoff, const float* dL_dk, double* dL_dT_lnP, double* dL_dSref,
                               float* dL_dgref, float* dL_dn, void* ws, size_t ws_bytes, hipStream_t stream) {
-  (void)lines; (void)ovr; (void)T; (void)P_atm; (void)grid; (void)cutoff; (void)dL_dk; (void)dL_dT_lnP;
-  (void)dL_dSref; (void)dL_dgref; (void)dL_dn; (void)ws; (void)ws_bytes; (void)stream;
-  return fail(HK_EUNSUPPORTED, "hk_opacity_backward is not built yet");
+  if (!(std::isfinite(T) && T > 0)) return fail(HK_EINVAL, "T must be finite and > 0");
+  if (!(std::isfinite(P_atm) && P_atm >= 0)) return fail(HK_EINVAL, "P must be finite and >= 0");
+  if (!grid_ok(grid)) return fail(HK_EINVAL, "invalid grid");
+  if (!cut_ok(cutoff)) return fail(HK_EINVAL, "cutoff must be > 0 (or +inf)");
+  if (!dL_dk || !dL_dT_lnP || !ws) return fail(HK_EINVAL, "dL_dk, dL_dT_lnP or workspace is NULL");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0) return fail(HK_EINVAL, "workspace must be 256-byte aligned");
+  hk_status s = check_lines(lines);
+  if (s != HK_OK) return s;
+  int dev;
+  DevInfo di;
+  s = device_init(&dev, &di);
+  if (s != HK_OK) return s;
+  const BwdLayout bl = backward_layout(lines->N);
+  if (ws_bytes < bl.total) return fail(HK_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, bl.total);
+  Timer tm(stream);
+  tm.mark();
+  char* w = static_cast<char*>(ws);
+  int4* grec = reinterpret_cast<int4*>(w + bl.off_gr);
+  double* contrib = reinterpret_cast<double*>(w + bl.off_contrib);
+  double* part = reinterpret_cast<double*>(w + bl.off_part);
+  HK_HIP(hk::launch_gridrec(lines->nu, lines->N, grid.nu_start, grid.dnu, grid.n, cutoff, grec, stream));
+  hk::AdjArgs a;
+  memset(&a, 0, sizeof a);
+  a.pa = prep_args(lines, ovr, T);
+  a.pa.pfac = P_atm / lines->sp.P_ref_atm;
+  a.grec = grec;
+  a.g = dL_dk;
+  a.nu_start = grid.nu_start;
+  a.dnu = grid.dnu;
+  a.n = grid.n;
+  a.T = T;
+  a.q_b = lines->sp.q_b;
+  for (int i = 0; i < hk::kKmax; ++i) a.zK[i] = (float)kZK[i];
+  a.dSref = dL_dSref;
+  a.dgref = dL_dgref;
+  a.dn = dL_dn;
+  a.contrib = contrib;
+  const int64_t want = (lines->N + hk::kWavesPerWG - 1) / hk::kWavesPerWG;
+  const int64_t cap = (int64_t)di.cus * 8;
+  const int blocks = (int)std::max<int64_t>(1, std::min(want, cap));
+  if (lines->N > 0) HK_HIP(hk::launch_adjoint(a, blocks, stream));
+  HK_HIP(hk::launch_reduce2(contrib, lines->N, part, kBwdPartials, dL_dT_lnP, stream));
+  tm.mark();
+  tm.finish();
+  g_tim.prep_ms = g_tim.worklist_ms = g_tim.voigt_ms = g_tim.combine_ms = -1;
+  g_tim.backward_ms = tm.ms(0);
+  return HK_OK;
 }
 
 hk_status hk_debug_cut_bounds(const hk_lines* lines, hk_grid grid, double cutoff, int32_t* j_lo, int32_t* j_hi,

@@ -81,6 +81,21 @@ struct PrepArgs {
   double pfac;             // P / P_ref (debug output only)
 };
 
+// Arguments of the adjoint kernel (one (T, P) and one grid).
+struct AdjArgs {
+  PrepArgs pa;             // line data, temperature constants, beta and pfac
+  const int4* grec;        // grid records of the grid
+  const float* g;          // dL/dk on the grid
+  double nu_start, dnu;
+  int64_t n;
+  double T, q_b;
+  float zK[kKmax];
+  double* dSref;           // caller order, nullable
+  float* dgref;            // caller order, nullable
+  float* dn;               // caller order, nullable
+  double* contrib;         // [N][2], sorted order: per-line dL/dT and dL/dlnP terms
+};
+
 // Launch wrappers (hk_kernels.hip); each returns the launch status.
 hipError_t launch_validate(const double* nu, const double* S, const double* E, const double* g,
                            const double* n, int64_t N, unsigned long long* mm, int* flags,
@@ -109,6 +124,9 @@ hipError_t launch_combine(const VoigtArgs& a, int slots, hipStream_t st);
 hipError_t launch_cut_bounds(const double* nu, const int32_t* perm, int64_t N, double nu_start,
                              double dnu, int64_t n, double cut, int32_t* jlo, int32_t* jhi,
                              hipStream_t st);
+hipError_t launch_adjoint(const AdjArgs& a, int grid, hipStream_t st);
+hipError_t launch_reduce2(const double* contrib, int64_t N, double* partial, int n_partial, double* out,
+                          hipStream_t st);
 int voigt_max_blocks_per_cu(int slots);
 hipError_t upload_weideman(const double* coef, double L);
 

@@ -933,6 +933,218 @@ __global__ __launch_bounds__(kThreads) void k_core(VoigtArgs a) {
   }
 }
 
+// ------------------------------------------------------------------------ adjoint
+// w(x + iy) = K + iL in FP64 by the same rational approximation (both parts).
+__device__ __forceinline__ void weideman_w(double x, double y, const double* __restrict__ wc, double& K, double& L) {
+  const double Lw = wc[kWeidN];
+  const double dr = Lw + y, di = -x;
+  const double nr = Lw - y, ni = x;
+  const double inv = rcp64(dr * dr + di * di);
+  const double Zr = (nr * dr + ni * di) * inv;
+  const double Zi = (ni * dr - nr * di) * inv;
+  double pr = wc[kWeidN - 1], pi = 0.0;
+#pragma unroll 4
+  for (int m = kWeidN - 2; m >= 0; --m) {
+    const double t = fma(pr, Zr, fma(-pi, Zi, wc[m]));
+    pi = fma(pr, Zi, pi * Zr);
+    pr = t;
+  }
+  const double ur = dr * inv, ui = -di * inv;
+  const double vr = ur * ur - ui * ui, vi = 2.0 * ur * ui;
+  K = 2.0 * (pr * vr - pi * vi) + 0.56418958354775628695 * ur;
+  L = 2.0 * (pr * vi + pi * vr) + 0.56418958354775628695 * ui;
+}
+
+// Far-wing profile and its gamma and alpha derivatives from the asymptotic series, in the
+// scaled variable u = sqrt(s)/(D + i gamma) (|u| <= 1), x = u^2, c_k = a_k (alpha^2/s)^k:
+//   V        = S/(pi sqrt(s))       (-Im sum_k c_k u^(2k+1))
+//   dV/dgamma = S/(pi s)             ( Re sum_k (2k+1) c_k u^(2k+2))
+//   dV/dalpha = S/(pi alpha sqrt(s)) (-Im sum_k 2k c_k u^(2k+1))
+// (term by term derivatives of V = (S/pi) sum_k a_k alpha^2k (-Im (D + i gamma)^-(2k+1))).
+template <int KD>
+__device__ __forceinline__ void wing_adj(float ur, float ui, const float* cv, float& v, float& dg, float& da) {
+  const float xr = ur * ur - ui * ui, xi = 2.0f * ur * ui;
+  float pr = cv[KD - 1], pi = 0.0f;                                        // sum c_k x^k
+  float ar = 2.0f * (KD - 1) * cv[KD - 1], ai = 0.0f;                      // sum 2k c_k x^k
+  float gr = (2.0f * (KD - 1) + 1.0f) * cv[KD - 1], gi = 0.0f;             // sum (2k+1) c_k x^k
+#pragma unroll
+  for (int k = KD - 2; k >= 0; --k) {
+    float t = __builtin_fmaf(pr, xr, __builtin_fmaf(-pi, xi, cv[k]));
+    pi = __builtin_fmaf(pr, xi, pi * xr);
+    pr = t;
+    t = __builtin_fmaf(ar, xr, __builtin_fmaf(-ai, xi, 2.0f * k * cv[k]));
+    ai = __builtin_fmaf(ar, xi, ai * xr);
+    ar = t;
+    t = __builtin_fmaf(gr, xr, __builtin_fmaf(-gi, xi, (2.0f * k + 1.0f) * cv[k]));
+    gi = __builtin_fmaf(gr, xi, gi * xr);
+    gr = t;
+  }
+  v = -(ur * pi + ui * pr);   // -Im(u P)
+  da = -(ur * ai + ui * ar);  // -Im(u P_A)
+  dg = xr * gr - xi * gi;     //  Re(x P_G)
+}
+
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// One wave per line (static assignment), lanes over its grid points inside the cut.
+__global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
+  __shared__ double sW[kWeidN + 1];
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid < kWeidN) sW[tid] = c_weid[tid];
+  if (tid == kWeidN) sW[kWeidN] = c_weidL;
+  __syncthreads();
+  const int64_t nw = (int64_t)gridDim.x * kWavesPerWG;
+  const PrepArgs& pa = a.pa;
+  for (int64_t i = (int64_t)blockIdx.x * kWavesPerWG + (tid >> 6); i < pa.N; i += nw) {
+    // per-line FP64 quantities (as the prep kernel), with optional overrides
+    const int32_t c = pa.perm[i];
+    const double Sref = pa.ovr_S ? pa.ovr_S[c] : pa.Sref[i];
+    const double gref = pa.ovr_g ? pa.ovr_g[c] : pa.gref[i];
+    const double nexp = pa.ovr_n ? pa.ovr_n[c] : pa.nexp[i];
+    const double nu0 = pa.nu[i];
+    const double E = pa.E[i];
+    const double Rs = pa.q_ratio * exp(pa.c2E_coef * E) * (expm1(-pa.c2_over_T * nu0) / expm1(-pa.c2_over_Tref * nu0));
+    const double S = Rs * Sref;
+    const double gfac = exp(nexp * pa.log_tr) * pa.pfac;  // gamma / gamma_ref
+    const double gam = gref * gfac;
+    const double alpha = nu0 * pa.beta;
+    const int4 gr = a.grec[i];
+    const int jref = gr.y, jlo = gr.z, jhi = gr.w;
+    double SVw = 0.0, SGw = 0.0, SAw = 0.0, SVc = 0.0, SGc = 0.0, SAc = 0.0;
+    const double a2d = alpha * alpha, g2d = gam * gam;
+    const double scd = a2d > g2d ? a2d : g2d;
+    if (jlo <= jhi && scd > 0.0) {
+      const float rs = (float)(1.0 / sqrt(scd));
+      const float dh = __int_as_float(gr.x) * rs, dnh = (float)a.dnu * rs, gh = (float)gam * rs;
+      const float ah = (float)(a2d / scd);
+      float cv[kKmax + 1];
+      cv[0] = 1.0f;
+      float ak = 1.0f, ap = 1.0f;
+#pragma unroll
+      for (int k = 1; k <= kKmax; ++k) {
+        ak *= (2.0f * k - 1.0f) * 0.5f;
+        ap *= ah;
+        cv[k] = ak * ap;
+      }
+      // zones in grid points around the centre
+      const double cpos = (double)jref - (double)__int_as_float(gr.x) / a.dnu;
+      int zlo[kKmax], zhi[kKmax];
+#pragma unroll
+      for (int K = 0; K < kKmax; ++K) {
+        const double zz = (double)a.zK[K] * alpha;
+        const double h2 = zz * zz - g2d;
+        zlo[K] = 2000000000;  // empty zone: no chunk intersects it
+        zhi[K] = -2000000000;
+        if (h2 > 0.0) {
+          const double h = sqrt(h2) / a.dnu * 1.00001 + 1e-3;
+          const double lo = ceil(cpos - h), hi = floor(cpos + h);
+          zlo[K] = lo < -1.0 ? -1 : (lo > 2.0e9 ? 2000000000 : (int)lo);
+          zhi[K] = hi < -1.0 ? -1 : (hi > 2.0e9 ? 2000000000 : (int)hi);
+        }
+      }
+      const double d64 = __dsub_rn(grid_nu(a.nu_start, a.dnu, (int64_t)jref), nu0);
+      const double ia = 1.0 / alpha, y = gam / alpha;
+      const double zc2 = (double)a.zK[kKmax - 1] * (double)a.zK[kKmax - 1];
+      float bV = 0.f, bG = 0.f, bA = 0.f;
+      int nb = 0;
+      for (int jc = jlo; jc <= jhi; jc += kWave) {
+        const int j = jc + lane;
+        const bool valid = j <= jhi;
+        const float gv = valid ? a.g[j] : 0.0f;
+        const int je = jc + kWave - 1;
+        // terms of the series for this chunk: one more than the profile needs, for dV/dalpha
+        int KD = 2;
+#pragma unroll
+        for (int z = 0; z < kKmax - 1; ++z) KD += (je >= zlo[z] && jc <= zhi[z]) ? 1 : 0;
+        bool core = false;
+        if (je >= zlo[kKmax - 1] && jc <= zhi[kKmax - 1]) {
+          // chunk touches the core: lanes with |z| below the last threshold take the FP64
+          // rational approximation, the others the longest series
+          KD = kKmax + 1;
+          const double x = ((double)(j - jref) * a.dnu + d64) * ia;
+          core = x * x + y * y < zc2;
+          if (core) {
+            double K, L;
+            weideman_w(x, y, sW, K, L);
+            const double Kx = -2.0 * (x * K - y * L);
+            const double Ky = 2.0 * (x * L + y * K) - 1.1283791670955125739;
+            const double gd = (double)gv;
+            SVc += gd * K;
+            SGc += gd * Ky;
+            SAc += gd * (-(K + x * Kx + y * Ky));
+          }
+        }
+        if (!core) {
+          const float kf = (float)(j - jref);
+          const float D = __builtin_fmaf(kf, dnh, dh);
+          const float R = __builtin_fmaf(D, D, gh * gh);
+          const float q = __builtin_amdgcn_rcpf(R);
+          const float ur = D * q, ui = -gh * q;
+          float v, dg, da;
+          switch (KD) {
+            case 2: wing_adj<2>(ur, ui, cv, v, dg, da); break;
+            case 3: wing_adj<3>(ur, ui, cv, v, dg, da); break;
+            case 4: wing_adj<4>(ur, ui, cv, v, dg, da); break;
+            case 5: wing_adj<5>(ur, ui, cv, v, dg, da); break;
+            default: wing_adj<6>(ur, ui, cv, v, dg, da); break;
+          }
+          bV = __builtin_fmaf(gv, v, bV);
+          bG = __builtin_fmaf(gv, dg, bG);
+          bA = __builtin_fmaf(gv, da, bA);
+        }
+        if (++nb == 8) {
+          SVw += (double)bV; SGw += (double)bG; SAw += (double)bA;
+          bV = bG = bA = 0.f;
+          nb = 0;
+        }
+      }
+      SVw += (double)bV; SGw += (double)bG; SAw += (double)bA;
+      // per-lane sums to per-wave sums (fixed butterfly order)
+      SVw = wave_sum64(SVw); SGw = wave_sum64(SGw); SAw = wave_sum64(SAw);
+      SVc = wave_sum64(SVc); SGc = wave_sum64(SGc); SAc = wave_sum64(SAc);
+      const double sq = sqrt(scd);
+      const double isp = 0.56418958354775628695;  // 1/sqrt(pi)
+      const double GV = SVw / (M_PI * sq) + SVc * isp * ia;               // sum g V
+      const double GGs = SGw / (M_PI * scd) + SGc * isp * ia * ia;        // sum g dV/dgamma
+      const double GAs = SAw / (M_PI * alpha * sq) + SAc * isp * ia * ia; // sum g dV/dalpha
+      SVw = GV; SGw = S * GGs; SAw = S * GAs;
+    }
+    if (lane == 0) {
+      // SVw, SGw, SAw now hold sum_j g_j V_ij, dL/dgamma_i, dL/dalpha_i (zero without points)
+      const double GS = SVw, Gg = SGw, Ga = SAw;
+      const double T = a.T;
+      const double c2nu = pa.c2_over_T * nu0;
+      const double dlnS_dT = -a.q_b / T + pa.c2_over_T * E / T - (c2nu / T) / expm1(c2nu);
+      if (a.dSref) a.dSref[c] = Rs * GS;
+      if (a.dgref) a.dgref[c] = (float)(gfac * Gg);
+      if (a.dn) a.dn[c] = (float)(gam * pa.log_tr * Gg);
+      a.contrib[2 * i] = GS * S * dlnS_dT + Ga * alpha / (2.0 * T) - Gg * nexp * gam / T;
+      a.contrib[2 * i + 1] = gam * Gg;
+    }
+  }
+}
+
+// Fixed-order sums of the per-line (dL/dT, dL/dlnP) terms: per-block tree sums, then one block.
+__global__ __launch_bounds__(1024) void k_reduce2(const double* __restrict__ in, int64_t N, double* __restrict__ out) {
+  __shared__ double s0[1024], s1[1024];
+  const int64_t per = (N + gridDim.x - 1) / gridDim.x;
+  const int64_t b0 = (int64_t)blockIdx.x * per, b1 = b0 + per < N ? b0 + per : N;
+  double a0 = 0.0, a1 = 0.0;
+  for (int64_t i = b0 + threadIdx.x; i < b1; i += 1024) { a0 += in[2 * i]; a1 += in[2 * i + 1]; }
+  s0[threadIdx.x] = a0;
+  s1[threadIdx.x] = a1;
+  __syncthreads();
+  for (int st = 512; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) { s0[threadIdx.x] += s0[threadIdx.x + st]; s1[threadIdx.x] += s1[threadIdx.x + st]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { out[2 * blockIdx.x] = s0[0]; out[2 * blockIdx.x + 1] = s1[0]; }
+}
+
 // Fixed-order (chunk 0, 1, ...) FP64 sum of the partial tiles of multi-chunk tiles;
 // one workgroup per tile.
 template <int P>
@@ -1062,6 +1274,18 @@ hipError_t launch_cut_bounds(const double* nu, const int32_t* perm, int64_t N, d
                              int64_t n, double cut, int32_t* jlo, int32_t* jhi, hipStream_t st) {
   hipLaunchKernelGGL(k_cut_bounds, dim3(blocks_for(N, kThreads)), dim3(kThreads), 0, st, nu, perm, N, nu_start,
                      dnu, n, cut, jlo, jhi);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(const AdjArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_adjoint, dim3(grid), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce2(const double* contrib, int64_t N, double* partial, int n_partial, double* out,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce2, dim3(n_partial), dim3(1024), 0, st, contrib, N, partial);
+  hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(1024), 0, st, (const double*)partial, (int64_t)n_partial, out);
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@ import linegen
 import oracle
 
 TOL_K = 1e-5  # max |k_gpu - k_oracle| <= TOL_K * max k_oracle over the compared points
+TOL_G = 1e-4  # per-line gradients: max |gpu - oracle| <= TOL_G * max |oracle|; scalars: <= TOL_G * |oracle|
 
 
 def to_device(L):
@@ -37,3 +38,21 @@ def rel_err(k, ko):
 def workload_lines(name, **kw):
     w = linegen.workload(name, **kw)
     return w, linegen.generate(w.recipe(), w.seed, w.N)
+
+
+def _lines(nu, S=1e-20, E=500.0, g=0.05, n=0.5):
+    """A small hand-made line list (constant fields unless arrays are given)."""
+    nu = np.atleast_1d(np.asarray(nu, dtype=np.float64))
+    N = nu.size
+    f = lambda v: np.full(N, v, dtype=np.float64) if np.isscalar(v) else np.asarray(v, dtype=np.float64)
+    return {"nu": nu, "S_ref": f(S), "E": f(E), "gamma_ref": f(g), "n": f(n)}
+
+
+def upstream(n, seed):
+    """Seeded dL/dk ~ N(0, 1) in float32 (the upstream gradient of the differentiation workload)."""
+    return np.random.default_rng(seed).standard_normal(n).astype(np.float32)
+
+
+def vec_err(a, ao):
+    m = np.max(np.abs(ao))
+    return float(np.max(np.abs(a - ao)) / m) if m > 0 else float(np.max(np.abs(a)))

@@ -5,7 +5,7 @@ import pytest
 
 import linegen
 import oracle
-from gpu_util import TOL_K, gpu_k, oracle_k, prepare, rel_err, to_device, workload_lines
+from gpu_util import TOL_K, _lines, gpu_k, oracle_k, prepare, rel_err, to_device, workload_lines
 
 pytestmark = pytest.mark.gpu
 
@@ -80,13 +80,6 @@ def test_small_config_all_points(reading):
     print("c1 reading %d: max rel err %.3e" % (reading, rel_err(k, ko)))
     assert rel_err(k, ko) <= TOL_K
     lines.release()
-
-
-def _lines(nu, S=1e-20, E=500.0, g=0.05, n=0.5):
-    nu = np.atleast_1d(np.asarray(nu, dtype=np.float64))
-    N = nu.size
-    f = lambda v: np.full(N, v, dtype=np.float64) if np.isscalar(v) else np.asarray(v, dtype=np.float64)
-    return {"nu": nu, "S_ref": f(S), "E": f(E), "gamma_ref": f(g), "n": f(n)}
 
 
 EDGE = [
