@@ -21,7 +21,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = "lines/s + Voigt evals/s at 0.01 cm^-1; %FP32 VALU peak; batched vs plain"
 PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (256 CU x 2.4 GHz x 256 flop/clk)
-FLOPS_PER_EVAL = 8           # algorithmic FP32 work per wing evaluation
+FLOPS_PER_EVAL = 8           # algorithmic FP32 work per far-wing evaluation: offset FMA, D^2+gamma^2 FMA,
+                             # reciprocal, amplitude multiply, accumulate
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_voigt_c2_5e8_cut25_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2101_02005_amd", "csrc", "hk_kernels.hip")
+
+
+def k_voigt_traffic(lines, cut, dnu):
+    """HBM bytes per k_voigt launch from the committed FETCH_SIZE / WRITE_SIZE counter runs,
+    scaled by the same counters on a plain copy; None when absent, taken on another workload,
+    or taken on a different kernel source."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_FILE) as f:
+        for ln in f:
+            if ":" in ln and not ln.startswith("#"):
+                k, v = ln.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        with open(KERNEL_SRC, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        if kv.get("kernel_src_sha256") != sha:
+            return None
+        if (float(kv["lines"]), float(kv["cut"]), float(kv["dnu"])) != (float(lines), float(cut), float(dnu)):
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError, OSError):
+        return None
 
 
 def parse():
@@ -33,8 +61,27 @@ def parse():
     ap.add_argument("--cut", type=float, default=25.0)
     ap.add_argument("--dnu", type=float, default=0.01)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--extras", default="cut100,dnu0.1", help="comma list: cut100, dnu0.1, or none")
+    ap.add_argument("--extras", default="cut100,dnu0.1,batched,backward",
+                    help="comma list of cut100, dnu0.1, batched, backward; or none")
+    ap.add_argument("--batched-lines", type=float, default=1e7, help="line count of the batched/backward list")
+    ap.add_argument("--copy-calibration", type=float, default=0,
+                    help="bytes of a plain device copy run after the steps (HBM counter calibration)")
     return ap.parse_args()
+
+
+PEAK_HBM_GBS = 8000.0
+BIN_BYTES_PER_LINE = 88      # read 5 FP64 fields; write them sorted, the permutation and the bin keys
+PREP_BYTES_PER_LINE = 72     # strengths/widths: read 40 B, write 8 B; grid records: read 8 B, write 16 B
+
+
+def hbm_phases(N, bin_ms, prep_ms):
+    """Algorithmic HBM rates of the bandwidth-bound phases (binning once per list, per-T prep)."""
+    out = {}
+    for name, bpl, ms in (("bin", BIN_BYTES_PER_LINE, bin_ms), ("prep", PREP_BYTES_PER_LINE, prep_ms)):
+        gbs = N * bpl / (ms * 1e-3) / 1e9
+        out[name] = {"bytes_per_line": bpl, "ms": ms, "achieved_GBs": gbs, "peak_GBs": PEAK_HBM_GBS,
+                     "frac": gbs / PEAK_HBM_GBS}
+    return out
 
 
 def count_evals(hk, lines, grd, cut):
@@ -77,6 +124,125 @@ def cpu_baseline(w, n_total_evals):
                       "(%.3g evals/s; line selection %.1f s not timed); scaled to the whole job by its %.4g evals"
                       % (npts, nu_a, nu_a + npts * w.dnu, len(L["nu"]), evals, t, eps, t_sel, n_total_evals),
             "evals_per_s": eps}
+
+
+def _device_list(w, N):
+    import torch
+
+    import linegen
+    dev = [torch.empty(N, dtype=torch.float64, device="cuda") for _ in range(5)]
+    linegen.generate_device(w.recipe(), w.seed, N, [t.data_ptr() for t in dev],
+                            stream=torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return dev
+
+
+def _oracle_windows(w, N, T, P, grd, k_host, starts, width=16):
+    """Max |k - k_oracle| / max k_oracle over oracle windows (lines selected around each window)."""
+    import numpy as np
+
+    import linegen
+    import oracle
+    sp = oracle.species(*w.species_tuple())
+    worst = 0.0
+    for s0 in starts:
+        s0 = int(min(max(s0, 0), grd.n - width))
+        lo = grd.nu_start + s0 * grd.dnu - w.cut - 0.5
+        hi = grd.nu_start + (s0 + width) * grd.dnu + w.cut + 0.5
+        _, L = linegen.select(w.recipe(), w.seed, N, max(lo, 0.0), hi, cap=1 << 24)
+        pts = np.arange(s0, s0 + width)
+        ko = oracle.opacity(L, sp, T, P, grd.nu_start, grd.dnu, w.cut, pts)
+        if ko.max() > 0:
+            worst = max(worst, float(np.max(np.abs(k_host[pts].astype(np.float64) - ko)) / ko.max()))
+    return worst
+
+
+def bench_batched(hk, n_lines):
+    """300 (T, P) pairs of the batched workload: one hk_opacity_batched call (graph replay)
+    against 300 hk_opacity calls on the same device-resident list."""
+    import numpy as np
+    import torch
+
+    import linegen
+    w = linegen.workload("c3", N=int(n_lines))
+    dev = _device_list(w, w.N)
+    lines = hk.hk_prepare_lines(*dev, hk.species(*w.species_tuple()))
+    del dev
+    T = [t for t in w.T for _ in w.P]
+    P = [p for _ in w.T for p in w.P]
+    n_pairs = len(T)
+    grd = hk.grid(w.nu_start, w.dnu, w.n_grid)
+    kb = torch.empty(n_pairs * w.n_grid, dtype=torch.float32, device="cuda")
+    kp = torch.empty_like(kb)
+    wsb = hk._lib._workspace(hk.hk_workspace_size(lines, 1, [grd] * n_pairs, w.cut, n_temps=len(w.T)))
+    wsp = hk._lib._workspace(hk.hk_workspace_size(lines, 0, [grd], w.cut))
+    # first batched call records the graph (untimed), then one timed replay
+    hk.hk_opacity_batched(lines, T, P, [grd] * n_pairs, w.cut, k=kb, ws=wsb)
+    torch.cuda.synchronize()
+    print("bench: batched graph recorded", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    hk.hk_opacity_batched(lines, T, P, [grd] * n_pairs, w.cut, k=kb, ws=wsb)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    print("bench: batched %.2f s" % t_b, file=sys.stderr, flush=True)
+    hk.hk_opacity(lines, T[0], P[0], grd, w.cut, k=kp[:w.n_grid], ws=wsp)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in range(n_pairs):
+        hk.hk_opacity(lines, T[p], P[p], grd, w.cut, k=kp[p * w.n_grid:(p + 1) * w.n_grid], ws=wsp)
+    torch.cuda.synchronize()
+    t_p = time.perf_counter() - t0
+    print("bench: 300 plain calls %.2f s" % t_p, file=sys.stderr, flush=True)
+    kb2, kp2 = kb.view(n_pairs, -1), kp.view(n_pairs, -1)
+    diff = ((kb2 - kp2).abs().amax(dim=1).double() / kp2.amax(dim=1).double().clamp_min(1e-300)).max().item()
+    evals_pair = count_evals(hk, lines, grd, w.cut)
+    lines.release()
+    # oracle windows for two extreme pairs (lowest T and P, highest T and P)
+    orc = {}
+    for p in (0, n_pairs - 1):
+        kh = kb2[p].cpu().numpy()
+        starts = [int(np.argmax(kh)) - 8, w.n_grid // 3, w.n_grid - 16]
+        orc["T=%g,P=%g" % (T[p], P[p])] = _oracle_windows(w, w.N, T[p], P[p], grd, kh, starts)
+    del kb, kp, kb2, kp2, wsb, wsp
+    torch.cuda.empty_cache()
+    return {"workload": "%d lines (nu = 10000 u^2), %d T x %d P = %d pairs, grid %g-%g cm^-1 at %g (%d points), "
+                        "cut %g" % (w.N, len(w.T), len(w.P), n_pairs, w.nu_start, w.nu_end, w.dnu, w.n_grid, w.cut),
+            "batched_s": t_b, "plain_300_s": t_p, "speedup": t_p / t_b,
+            "evals_per_s_batched": evals_pair * n_pairs / t_b, "lines_pairs_per_s_batched": w.N * n_pairs / t_b,
+            "max_rel_diff_batched_vs_plain": diff, "oracle_window_max_rel_err": orc}
+
+
+def bench_backward(hk, n_lines):
+    """The adjoint at the differentiation workload (T = 800 K, P = 0.1 atm, cut 100)."""
+    import torch
+
+    import linegen
+    w = linegen.workload("c4", N=int(n_lines))
+    dev = _device_list(w, w.N)
+    lines = hk.hk_prepare_lines(*dev, hk.species(*w.species_tuple()))
+    del dev
+    grd = hk.grid(w.nu_start, w.dnu, w.n_grid)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(w.extra["g_seed"])
+    g = torch.randn(w.n_grid, generator=gen, device="cuda", dtype=torch.float32)
+    ws = hk._lib._workspace(hk.hk_workspace_size(lines, 2, [grd], w.cut))
+    hk.hk_opacity_backward(lines, w.T[0], w.P[0], grd, w.cut, g, ws=ws)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out2, dS, dg, dn = hk.hk_opacity_backward(lines, w.T[0], w.P[0], grd, w.cut, g, ws=ws)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    tb = hk.hk_get_timings().backward_ms
+    t1 = time.perf_counter()
+    hk.hk_opacity(lines, w.T[0], w.P[0], grd, w.cut)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t1
+    ne = count_evals(hk, lines, grd, w.cut)
+    lines.release()
+    return {"workload": "%d lines, grid %g-%g cm^-1 at %g (%d points), cut %g, T=%g K, P=%g atm, dL/dk ~ N(0,1)"
+                        % (w.N, w.nu_start, w.nu_end, w.dnu, w.n_grid, w.cut, w.T[0], w.P[0]),
+            "backward_s": t, "backward_kernel_ms": tb, "forward_s": tf, "evals": ne,
+            "evals_per_s_backward": ne / t, "dL_dT": out2[0].item(), "dL_dlnP": out2[1].item()}
 
 
 def main():
@@ -131,8 +297,11 @@ def main():
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
     voigt_ms = sum(t.voigt_ms for _, t in per) / len(per)
+    core_ms = sum(t.core_ms for _, t in per) / len(per)
     tm = per[-1][1]
-    achieved = FLOPS_PER_EVAL * n_evals / (voigt_ms * 1e-3) / 1e12
+    core_evals = tm.core_evals
+    wing_evals = n_evals - core_evals
+    achieved = FLOPS_PER_EVAL * wing_evals / (voigt_ms * 1e-3) / 1e12
     out = {
         "metric": METRIC, "value": N / dt, "unit": "lines/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -142,20 +311,31 @@ def main():
                                % (N, w.nu_start, w.nu_end, w.dnu, w.n_grid, w.cut, w.T[0], w.P[0]),
                    "lines": N, "grid_points": w.n_grid, "dnu": w.dnu, "cut": w.cut},
         "evals_per_s": n_evals / dt,
-        "voigt_evals_per_s": n_evals / (voigt_ms * 1e-3),
+        "voigt_evals_per_s": n_evals / ((voigt_ms + core_ms) * 1e-3),
+        "evals": n_evals, "core_evals": core_evals,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
-                     "kernel": "k_voigt", "flops_per_eval": FLOPS_PER_EVAL, "evals_per_launch": n_evals,
-                     "avg_launch_ms": voigt_ms},
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": k_voigt_traffic(N, w.cut, w.dnu),
+                     "kernel": "k_voigt (far-wing pass)", "flops_per_eval": FLOPS_PER_EVAL,
+                     "evals_per_launch": wing_evals, "avg_launch_ms": voigt_ms},
         "phases_ms": {"bin": sum(b for b, _ in per) / len(per), "prep": tm.prep_ms, "worklist": tm.worklist_ms,
-                      "voigt": voigt_ms, "combine": tm.combine_ms},
+                      "voigt_wing": voigt_ms, "voigt_core": core_ms, "combine": tm.combine_ms},
+        "hbm": hbm_phases(N, sum(b for b, _ in per) / len(per), tm.prep_ms),
         "tuning": {"tile_width": tm.tile_width, "lines_per_batch": tm.lines_per_batch,
                    "chunk_lines": tm.chunk_lines, "items_bound": tm.n_items},
         "paper_context": "HELIOS-K 2.0: BT2 water (~4.5e8 lines, data read from RAM) 45 s at 0.01 cm^-1 / cut 25 "
                          "(~1e7 lines/s) and 12.5 s at 0.1 cm^-1 on an RTX 2080 Ti",
     }
+    if args.copy_calibration > 0:
+        nf = int(args.copy_calibration) // 4
+        src = torch.ones(nf, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read": 4 * nf, "bytes_written": 4 * nf}
+        del src, dst
     extras = {}
-    for ex in [e for e in args.extras.split(",") if e and e != "none"]:
+    for ex in [e for e in args.extras.split(",") if e and e != "none" and e in ("cut100", "dnu0.1")]:
         cut, dnu = (100.0, w.dnu) if ex == "cut100" else (w.cut, 0.1)
         g2 = hk.grid(w.nu_start, dnu, int(round((w.nu_end - w.nu_start) / dnu)))
         ln = hk.hk_prepare_lines(*dev, sp)
@@ -167,15 +347,24 @@ def main():
         hk.hk_opacity(ln, w.T[0], w.P[0], g2, cut, k=kk)
         torch.cuda.synchronize()
         te = time.perf_counter() - t1
-        tv = hk.hk_get_timings().voigt_ms
+        t2 = hk.hk_get_timings()
+        tv, tc = t2.voigt_ms, t2.core_ms
         ln.release()
-        extras[ex] = {"dnu": dnu, "cut": cut, "evals": ne, "opacity_s": te, "voigt_ms": tv,
-                      "voigt_evals_per_s": ne / (tv * 1e-3), "frac_fp32": FLOPS_PER_EVAL * ne / (tv * 1e-3) / 1e12
+        extras[ex] = {"dnu": dnu, "cut": cut, "evals": ne, "core_evals": t2.core_evals, "opacity_s": te,
+                      "voigt_wing_ms": tv, "voigt_core_ms": tc, "voigt_evals_per_s": ne / ((tv + tc) * 1e-3),
+                      "frac_fp32_k_voigt": FLOPS_PER_EVAL * (ne - t2.core_evals) / (tv * 1e-3) / 1e12
                       / PEAK_FP32_TFLOPS}
         print("bench: extra %s done" % ex, file=sys.stderr, flush=True)
     out["extra"] = extras
     del dev
     torch.cuda.empty_cache()
+    wanted = args.extras.split(",")
+    if "batched" in wanted:
+        out["batched"] = bench_batched(hk, args.batched_lines)
+        print("bench: batched done", file=sys.stderr, flush=True)
+    if "backward" in wanted:
+        out["backward"] = bench_backward(hk, args.batched_lines)
+        print("bench: backward done", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(w, n_evals)

@@ -34,7 +34,8 @@ class Timings(ctypes.Structure):
     _fields_ = [("prep_ms", ctypes.c_double), ("worklist_ms", ctypes.c_double), ("voigt_ms", ctypes.c_double),
                 ("combine_ms", ctypes.c_double), ("backward_ms", ctypes.c_double), ("bin_ms", ctypes.c_double),
                 ("tile_width", ctypes.c_int32), ("lines_per_batch", ctypes.c_int32),
-                ("chunk_lines", ctypes.c_int32), ("n_items", ctypes.c_int32)]
+                ("chunk_lines", ctypes.c_int32), ("n_items", ctypes.c_int32), ("core_ms", ctypes.c_double),
+                ("core_evals", ctypes.c_int64)]
 
 
 _lib = None

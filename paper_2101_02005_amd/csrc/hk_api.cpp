@@ -159,7 +159,7 @@ struct Plan {
   int64_t items_bound = 0;
   int grid = 0;
   size_t off_S = 0, off_g = 0, off_gr = 0, off_pairs = 0, off_lo = 0, off_hi = 0, off_nc = 0, off_ib = 0,
-         off_cnt = 0, off_part = 0, total = 0;
+         off_cnt = 0, off_part = 0, off_stats = 0, total = 0;
   int n_grids = 0;
   std::vector<hk::PairDesc> pairs;
   std::vector<double> temps;
@@ -260,6 +260,7 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   pl->off_ib = take(sizeof(int32_t) * (tiles + 1));
   pl->off_cnt = take(sizeof(int) * 64);
   pl->off_part = take(sizeof(float) * (size_t)pl->items_bound * pl->W);
+  pl->off_stats = take(sizeof(long long) * (size_t)(pl->grid > 0 ? pl->grid : 1));
   pl->total = off;
   return HK_OK;
 }
@@ -373,7 +374,10 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   va.n_pairs = pl.n_pairs;
   va.n_tiles_total = pl.n_tiles_total;
   va.chunk = pl.chunk;
+  long long* stats = reinterpret_cast<long long*>(ws + pl.off_stats);
+  va.stats = tm.on ? stats : nullptr;
   HK_HIP(hk::launch_voigt(va, pl.slots, pl.grid, st));
+  tm.mark();
   HK_HIP(hk::launch_core(va, pl.slots, pl.grid, st));
   tm.mark();
   HK_HIP(hk::launch_combine(va, pl.slots, st));
@@ -382,8 +386,17 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   g_tim.prep_ms = tm.ms(0);
   g_tim.worklist_ms = tm.ms(1);
   g_tim.voigt_ms = tm.ms(2);
-  g_tim.combine_ms = tm.ms(3);
+  g_tim.core_ms = tm.ms(3);
+  g_tim.combine_ms = tm.ms(4);
   g_tim.backward_ms = -1;
+  g_tim.core_evals = -1;
+  if (tm.on) {
+    std::vector<long long> h((size_t)pl.grid);
+    HK_HIP(hipMemcpy(h.data(), stats, sizeof(long long) * h.size(), hipMemcpyDeviceToHost));
+    long long t = 0;
+    for (long long v : h) t += v;
+    g_tim.core_evals = t;
+  }
   g_tim.tile_width = pl.W;
   g_tim.lines_per_batch = hk::kLB;
   g_tim.chunk_lines = pl.chunk;
@@ -670,6 +683,8 @@ hk_status hk_opacity_batched(const hk_lines* lines, int32_t n_pairs, const doubl
   tm.finish();
   g_tim.prep_ms = g_tim.worklist_ms = g_tim.combine_ms = -1;
   g_tim.voigt_ms = tm.ms(0);  // whole graph
+  g_tim.core_ms = -1;
+  g_tim.core_evals = -1;
   g_tim.tile_width = pl.W;
   g_tim.lines_per_batch = hk::kLB;
   g_tim.chunk_lines = pl.chunk;
@@ -724,7 +739,8 @@ hk_status hk_opacity_backward(const hk_lines* lines, const hk_line_override* ovr
   HK_HIP(hk::launch_reduce2(contrib, lines->N, part, kBwdPartials, dL_dT_lnP, stream));
   tm.mark();
   tm.finish();
-  g_tim.prep_ms = g_tim.worklist_ms = g_tim.voigt_ms = g_tim.combine_ms = -1;
+  g_tim.prep_ms = g_tim.worklist_ms = g_tim.voigt_ms = g_tim.combine_ms = g_tim.core_ms = -1;
+  g_tim.core_evals = -1;
   g_tim.backward_ms = tm.ms(0);
   return HK_OK;
 }

@@ -52,6 +52,7 @@ struct VoigtArgs {
   float* k;
   float* partial;          // [item][tile width]: chunk sums of multi-chunk tiles
   int* counter;            // work-item dispenser (scheduling only)
+  long long* stats;        // nullable: per-block count of core evaluations (k_core)
   int64_t N;
   double cut;              // > 0; +inf: no cut
   float zK[kKmax];         // |z| above which the series of order K (1..kKmax) is used

@@ -778,6 +778,7 @@ __global__ __launch_bounds__(kThreads) void k_core(VoigtArgs a) {
   const int total = a.item_base[a.n_tiles_total];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const float zc = a.zK[kKmax - 1];
+  long long ncore = 0;  // core evaluations done by this wave (statistics only)
 
   for (;;) {
     if (tid == 0) {
@@ -905,6 +906,7 @@ __global__ __launch_bounds__(kThreads) void k_core(VoigtArgs a) {
               L.acc[wv][p * kWave + lane] = 0.0f;
             }
             kahan_flush<P>(part, s, cc);
+            ncore += qn;
             qn = 0;
             any = true;
           }
@@ -930,6 +932,16 @@ __global__ __launch_bounds__(kThreads) void k_core(VoigtArgs a) {
       }
     }
     __syncthreads();
+  }
+  if (a.stats) {
+    __shared__ long long sc[kWavesPerWG];
+    if (lane == 0) sc[wv] = ncore;
+    __syncthreads();
+    if (tid == 0) {
+      long long t = 0;
+      for (int w = 0; w < kWavesPerWG; ++w) t += sc[w];
+      a.stats[blockIdx.x] = t;
+    }
   }
 }
 
