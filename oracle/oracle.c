@@ -26,8 +26,11 @@
  *   opacity         k_j     : sum over lines with |nu_j - nu_i| <= cut of
  *                             S_i V(nu_j - nu_i) (Sec. 2.4.3 step 4, fixed
  *                             cutting length), grid nu_j = nu_start + j dnu.
- *   gradient                : analytic adjoint of k (no counterpart in the paper)
- *                             from w'(z) = -2 z w(z) + 2i/sqrt(pi).
+ *   gradient                : analytic adjoint of k (no counterpart in the paper):
+ *                             profile derivatives from w'(z) = -2 z w(z) + 2i/sqrt(pi)
+ *                             for |z| < 10, and by Gauss-Hermite quadrature of the
+ *                             Gaussian-Lorentzian convolution, differentiated under
+ *                             the integral, for |z| >= 10 (see or_voigt_derivs).
  *
  * The Faddeeva function w(z) = exp(-z^2) erfc(-iz) is this file's own FP64
  * implementation of a published method: W. Gautschi, "Efficient computation of
