@@ -76,6 +76,7 @@ int env_int(const char* name, int dflt) {
 struct DevInfo {
   int cus = 0;
   int wg_per_cu[2] = {1, 1};  // Voigt kernel occupancy for 4 and 8 slots
+  int core_per_cu[2] = {1, 1};  // core kernel (one-wave workgroups) occupancy
 };
 
 std::mutex g_mu;
@@ -128,6 +129,8 @@ hk_status device_init(int* dev_out, DevInfo* info) {
     di.cus = prop.multiProcessorCount;
     di.wg_per_cu[0] = hk::voigt_max_blocks_per_cu(4);
     di.wg_per_cu[1] = hk::voigt_max_blocks_per_cu(8);
+    di.core_per_cu[0] = hk::core_max_blocks_per_cu(4);
+    di.core_per_cu[1] = hk::core_max_blocks_per_cu(8);
     it = g_dev.emplace(dev, di).first;
   }
   *dev_out = dev;
@@ -160,6 +163,11 @@ struct Plan {
   int grid = 0;
   size_t off_S = 0, off_g = 0, off_gr = 0, off_pairs = 0, off_lo = 0, off_hi = 0, off_nc = 0, off_ib = 0,
          off_cnt = 0, off_part = 0, off_stats = 0, total = 0;
+  // the line-core pass's own work list and partial tiles
+  size_t off_pairs_c = 0, off_lo_c = 0, off_hi_c = 0, off_nc_c = 0, off_ib_c = 0, off_cnt_c = 0, off_part_c = 0;
+  int64_t items_bound_c = 0;
+  int W_c = 256, n_tiles_c = 0, grid_c = 0;
+  std::vector<hk::PairDesc> pairs_c;  // the pairs with the core pass's (one-wave) tiling
   int n_grids = 0;
   std::vector<hk::PairDesc> pairs;
   std::vector<double> temps;
@@ -213,10 +221,12 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
     gidx[p] = found;
   }
   pl->n_grids = (int)pl->grids.size();
-  // tiles and the bound on line visits
-  int64_t tiles = 0;
-  double visits = 0.0;
+  // tiles and the bound on line visits (wing pass, and the narrower windows of the core pass)
+  int64_t tiles = 0, tiles_c = 0;
+  double visits = 0.0, visits_c = 0.0;
+  pl->W_c = hk::kWave * pl->slots;
   pl->pairs.assign(n_pairs, hk::PairDesc{});
+  pl->pairs_c.assign(n_pairs, hk::PairDesc{});
   for (int p = 0; p < n_pairs; ++p) {
     const int64_t nt = (grids[p].n + pl->W - 1) / pl->W;
     if (tiles + nt >= (int64_t(1) << 30)) return fail(HK_ENOMEM, "too many grid tiles");
@@ -233,8 +243,21 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
     d.n_tiles = (int32_t)nt;
     tiles += nt;
     visits += (double)N * (double)visits_per_line(L, grids[p], cut, pl->W, nt);
+    const double gend = std::max(std::fabs(grids[p].nu_start),
+                                 std::fabs(grids[p].nu_start + (double)grids[p].n * grids[p].dnu));
+    const double vmax = std::min(L->numax, gend + (std::isinf(cut) ? L->numax : cut));
+    const double hc = std::min(cut, kZK[hk::kKmax - 1] * d.beta * vmax * 1.0001 + 0.01 * grids[p].dnu);
+    const int64_t nt_c = (grids[p].n + pl->W_c - 1) / pl->W_c;
+    if (tiles_c + nt_c >= (int64_t(1) << 30)) return fail(HK_ENOMEM, "too many grid tiles");
+    hk::PairDesc& dc = pl->pairs_c[p];
+    dc = d;
+    dc.tile_base = (int32_t)tiles_c;
+    dc.n_tiles = (int32_t)nt_c;
+    tiles_c += nt_c;
+    visits_c += (double)N * (double)visits_per_line(L, grids[p], T ? hc : cut, pl->W_c, nt_c);
   }
   pl->n_tiles_total = (int)tiles;
+  pl->n_tiles_c = (int)tiles_c;
   // work-item size: enough items to balance the persistent grid
   const int wgs = di.cus * di.wg_per_cu[pl->slots == 8 ? 1 : 0];
   double c = std::ceil(visits / (64.0 * (wgs > 0 ? wgs : 1024)));
@@ -246,7 +269,12 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   const double items = (double)tiles + std::ceil(visits / pl->chunk);
   if (items >= 2.0e9) return fail(HK_ENOMEM, "work list too large (%.3g items)", items);
   pl->items_bound = (int64_t)items;
+  const double items_c = (double)tiles_c + std::ceil(visits_c / pl->chunk);
+  if (items_c >= 2.0e9) return fail(HK_ENOMEM, "core work list too large (%.3g items)", items_c);
+  pl->items_bound_c = (int64_t)items_c;
   pl->grid = (int)std::min<int64_t>(pl->items_bound, (int64_t)(wgs > 0 ? wgs : 1024));
+  const int wgs_c = di.cus * di.core_per_cu[pl->slots == 8 ? 1 : 0];
+  pl->grid_c = (int)std::max<int64_t>(1, std::min<int64_t>(pl->items_bound_c, (int64_t)(wgs_c > 0 ? wgs_c : 4096)));
   // workspace layout (256-byte aligned sections)
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
@@ -260,7 +288,14 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   pl->off_ib = take(sizeof(int32_t) * (tiles + 1));
   pl->off_cnt = take(sizeof(int) * 64);
   pl->off_part = take(sizeof(float) * (size_t)pl->items_bound * pl->W);
-  pl->off_stats = take(sizeof(long long) * (size_t)(pl->grid > 0 ? pl->grid : 1));
+  pl->off_stats = take(sizeof(long long) * (size_t)std::max(pl->grid, pl->grid_c));
+  pl->off_pairs_c = take(sizeof(hk::PairDesc) * n_pairs);
+  pl->off_lo_c = take(sizeof(int32_t) * tiles_c);
+  pl->off_hi_c = take(sizeof(int32_t) * tiles_c);
+  pl->off_nc_c = take(sizeof(int32_t) * tiles_c);
+  pl->off_ib_c = take(sizeof(int32_t) * (tiles_c + 1));
+  pl->off_cnt_c = take(sizeof(int) * 64);
+  pl->off_part_c = take(sizeof(float) * (size_t)pl->items_bound_c * pl->W_c);
   pl->total = off;
   return HK_OK;
 }
@@ -351,8 +386,18 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   int* cnt = reinterpret_cast<int*>(ws + pl.off_cnt);
   HK_HIP(hk::launch_fill_pairs(pl.pairs.data(), pl.n_pairs, dpairs, st));
   HK_HIP(hk::launch_worklist(L->keys, L->N, L->km, L->numin, L->numax, dpairs, pl.n_pairs, pl.n_tiles_total,
-                             pl.W, cut, pl.chunk, lo, hi, nc, st));
+                             pl.W, cut, 0.0, pl.chunk, lo, hi, nc, st));
   HK_HIP(hk::launch_item_scan(nc, pl.n_tiles_total, ib, cnt, st));
+  int32_t* lo_c = reinterpret_cast<int32_t*>(ws + pl.off_lo_c);
+  int32_t* hi_c = reinterpret_cast<int32_t*>(ws + pl.off_hi_c);
+  int32_t* nc_c = reinterpret_cast<int32_t*>(ws + pl.off_nc_c);
+  int32_t* ib_c = reinterpret_cast<int32_t*>(ws + pl.off_ib_c);
+  int* cnt_c = reinterpret_cast<int*>(ws + pl.off_cnt_c);
+  hk::PairDesc* dpairs_c = reinterpret_cast<hk::PairDesc*>(ws + pl.off_pairs_c);
+  HK_HIP(hk::launch_fill_pairs(pl.pairs_c.data(), pl.n_pairs, dpairs_c, st));
+  HK_HIP(hk::launch_worklist(L->keys, L->N, L->km, L->numin, L->numax, dpairs_c, pl.n_pairs, pl.n_tiles_c,
+                             pl.W_c, cut, kZK[hk::kKmax - 1], pl.chunk, lo_c, hi_c, nc_c, st));
+  HK_HIP(hk::launch_item_scan(nc_c, pl.n_tiles_c, ib_c, cnt_c, st));
   tm.mark();
   hk::VoigtArgs va;
   memset(&va, 0, sizeof va);
@@ -374,24 +419,38 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   va.n_pairs = pl.n_pairs;
   va.n_tiles_total = pl.n_tiles_total;
   va.chunk = pl.chunk;
+  va.items_cap = (int32_t)std::min<int64_t>(pl.items_bound, INT32_MAX);
   long long* stats = reinterpret_cast<long long*>(ws + pl.off_stats);
   va.stats = tm.on ? stats : nullptr;
   HK_HIP(hk::launch_voigt(va, pl.slots, pl.grid, st));
   tm.mark();
-  HK_HIP(hk::launch_core(va, pl.slots, pl.grid, st));
-  tm.mark();
   HK_HIP(hk::launch_combine(va, pl.slots, st));
+  tm.mark();
+  // line-core pass over its own (narrower) work list, after the wing sums are final
+  hk::VoigtArgs vc = va;
+  vc.pairs = dpairs_c;
+  vc.n_tiles_total = pl.n_tiles_c;
+  vc.tile_lo = lo_c;
+  vc.tile_hi = hi_c;
+  vc.tile_nc = nc_c;
+  vc.item_base = ib_c;
+  vc.counter = cnt_c;
+  vc.partial = reinterpret_cast<float*>(ws + pl.off_part_c);
+  vc.items_cap = (int32_t)std::min<int64_t>(pl.items_bound_c, INT32_MAX);
+  const int grid_c = pl.grid_c;
+  HK_HIP(hk::launch_core(vc, pl.slots, grid_c, st));
+  HK_HIP(hk::launch_combine_core(vc, pl.slots, st));
   tm.mark();
   tm.finish();
   g_tim.prep_ms = tm.ms(0);
   g_tim.worklist_ms = tm.ms(1);
   g_tim.voigt_ms = tm.ms(2);
-  g_tim.core_ms = tm.ms(3);
-  g_tim.combine_ms = tm.ms(4);
+  g_tim.combine_ms = tm.ms(3);
+  g_tim.core_ms = tm.ms(4);
   g_tim.backward_ms = -1;
   g_tim.core_evals = -1;
   if (tm.on) {
-    std::vector<long long> h((size_t)pl.grid);
+    std::vector<long long> h((size_t)grid_c);
     HK_HIP(hipMemcpy(h.data(), stats, sizeof(long long) * h.size(), hipMemcpyDeviceToHost));
     long long t = 0;
     for (long long v : h) t += v;

@@ -50,7 +50,7 @@ struct VoigtArgs {
   const int32_t* tile_nc;  // per global tile: chunks (work items)
   const int32_t* item_base;// per global tile: first item; [n_tiles_total] = total items
   float* k;
-  float* partial;          // [item][tile width]: chunk sums of multi-chunk tiles
+  float* partial;          // [item][tile width]: chunk sums of multi-chunk tiles (each pass its own)
   int* counter;            // work-item dispenser (scheduling only)
   long long* stats;        // nullable: per-block count of core evaluations (k_core)
   int64_t N;
@@ -59,7 +59,7 @@ struct VoigtArgs {
   int32_t n_pairs;
   int32_t n_tiles_total;
   int32_t chunk;           // lines per work item
-  int32_t pad;
+  int32_t items_cap;       // rows of `partial` (work items beyond it are never written)
 };
 
 struct PrepArgs {
@@ -113,7 +113,7 @@ hipError_t launch_prep(const PrepArgs& a, float* S_T, float* gT, double* S64, do
 hipError_t launch_fill_pairs(const PairDesc* host_pairs, int count, PairDesc* dst, hipStream_t st);
 hipError_t launch_worklist(const uint32_t* keys, int64_t N, KeyMap km, double numin, double numax,
                            const PairDesc* pairs,
-                           int n_pairs, int n_tiles_total, int tile_w, double cut, int chunk,
+                           int n_pairs, int n_tiles_total, int tile_w, double cut, double core_z, int chunk,
                            int32_t* lo, int32_t* hi, int32_t* nc, hipStream_t st);
 hipError_t launch_item_scan(const int32_t* nc, int n_tiles_total, int32_t* item_base, int* counter,
                             hipStream_t st);
@@ -122,6 +122,7 @@ hipError_t launch_gridrec(const double* nu, int64_t N, double nu_start, double d
 hipError_t launch_voigt(const VoigtArgs& a, int slots, int grid, hipStream_t st);
 hipError_t launch_core(const VoigtArgs& a, int slots, int grid, hipStream_t st);
 hipError_t launch_combine(const VoigtArgs& a, int slots, hipStream_t st);
+hipError_t launch_combine_core(const VoigtArgs& a, int slots, hipStream_t st);
 hipError_t launch_cut_bounds(const double* nu, const int32_t* perm, int64_t N, double nu_start,
                              double dnu, int64_t n, double cut, int32_t* jlo, int32_t* jhi,
                              hipStream_t st);
@@ -129,6 +130,7 @@ hipError_t launch_adjoint(const AdjArgs& a, int grid, hipStream_t st);
 hipError_t launch_reduce2(const double* contrib, int64_t N, double* partial, int n_partial, double* out,
                           hipStream_t st);
 int voigt_max_blocks_per_cu(int slots);
+int core_max_blocks_per_cu(int slots);
 hipError_t upload_weideman(const double* coef, double L);
 
 }  // namespace hk

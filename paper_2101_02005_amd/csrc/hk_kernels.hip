@@ -277,9 +277,12 @@ __device__ __forceinline__ int find_pair(const PairDesc* pairs, int n_pairs, int
   return lo;
 }
 
+// core_z > 0: the list for the line-core pass. A line reaches a tile point with |z| < core_z
+// only if its centre lies within core_z alpha of it, and alpha = beta nu <= beta (nu_j1 + cut),
+// so the window shrinks to that half-width (with slack for the FP32 zone test of the core pass).
 __global__ void k_worklist(const uint32_t* __restrict__ keys, int64_t N, KeyMap km, double numin, double numax,
                            const PairDesc* __restrict__ pairs, int n_pairs, int n_tiles_total,
-                           int tile_w, double cut, int chunk, int32_t* __restrict__ lo_out,
+                           int tile_w, double cut, double core_z, int chunk, int32_t* __restrict__ lo_out,
                            int32_t* __restrict__ hi_out, int32_t* __restrict__ nc_out) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n_tiles_total) return;
@@ -288,9 +291,15 @@ __global__ void k_worklist(const uint32_t* __restrict__ keys, int64_t N, KeyMap 
   const int64_t j0 = t * tile_w;
   const int64_t j1 = (j0 + tile_w < pd.n ? j0 + tile_w : pd.n) - 1;
   int64_t lo = 0, hi = N;
-  if (!isinf(cut)) {
-    const double va = __dsub_rn(grid_nu(pd.nu_start, pd.dnu, j0), cut);
-    const double vb = __dadd_rn(grid_nu(pd.nu_start, pd.dnu, j1), cut);
+  double hw = cut;
+  if (core_z > 0.0) {
+    const double vmax = fabs(grid_nu(pd.nu_start, pd.dnu, j1)) + (isinf(cut) ? numax : cut);
+    const double hc = core_z * pd.beta * (vmax > numax ? numax : vmax) * 1.0001 + 0.01 * pd.dnu + 1e-300;
+    hw = hc < cut ? hc : cut;
+  }
+  if (!isinf(hw)) {
+    const double va = __dsub_rn(grid_nu(pd.nu_start, pd.dnu, j0), hw);
+    const double vb = __dadd_rn(grid_nu(pd.nu_start, pd.dnu, j1), hw);
     if (vb < numin || va > numax) { lo_out[g] = 0; hi_out[g] = 0; nc_out[g] = 1; return; }
     uint32_t ka = bin_key(va, km), kb = bin_key(vb, km);
     ka = ka > 0 ? ka - 1 : 0;
@@ -349,17 +358,20 @@ __device__ __forceinline__ double rcp64(double d) {
   return fma(r, e, r);
 }
 
-__device__ __forceinline__ double weideman_re(double x, double y, const double* __restrict__ wc) {
-  const double L = wc[kWeidN];
+// Re w(x + iy) by Weideman's rational series: w = 2 p(Z)/(L - iz)^2 + 1/(sqrt(pi)(L - iz)),
+// Z = (L + iz)/(L - iz), p(Z) = sum_n a_n Z^(n-1). The coefficients live in constant memory
+// and are read with scalar loads into SGPRs (the loop is fully unrolled).
+__device__ __forceinline__ double weideman_re(double x, double y) {
+  const double L = c_weidL;
   const double dr = L + y, di = -x;  // L - iz
   const double nr = L - y, ni = x;   // L + iz
   const double inv = rcp64(dr * dr + di * di);
   const double Zr = (nr * dr + ni * di) * inv;
   const double Zi = (ni * dr - nr * di) * inv;
-  double pr = wc[kWeidN - 1], pi = 0.0;
-#pragma unroll 4
+  double pr = c_weid[kWeidN - 1], pi = 0.0;
+#pragma unroll
   for (int m = kWeidN - 2; m >= 0; --m) {
-    const double t = fma(pr, Zr, fma(-pi, Zi, wc[m]));
+    const double t = fma(pr, Zr, fma(-pi, Zi, c_weid[m]));
     pi = fma(pr, Zi, pi * Zr);
     pr = t;
   }
@@ -449,6 +461,24 @@ __device__ __forceinline__ void kahan_flush(float (&part)[P], float (&s)[P], flo
   }
 }
 
+// Core points of a line relative to its reference point j_ref: the integers r with
+// |r - c| < h, where c = -delta/dnu is the centre in grid units and h = sqrt(zc^2 alpha^2 -
+// gamma^2)/dnu (with a little slack). Evaluated in FP32 from the same inputs in the wing and
+// the core pass, so both classify every (line, point) pair identically whatever their tiling.
+__device__ __forceinline__ bool core_rel(float alpha, float gam, float delta, float inv_dnu, float zc, int& rlo,
+                                         int& rhi) {
+  const float af = alpha * inv_dnu, gf = gam * inv_dnu;
+  const float zz = zc * af;
+  const float h2 = zz * zz - gf * gf;
+  if (!(h2 > 0.0f)) return false;
+  const float h = sqrtf(h2) * 1.00001f + 1e-3f;
+  const float c = -delta * inv_dnu;
+  const float fl = floorf(c - h) + 1.0f, fh = ceilf(c + h) - 1.0f;
+  rlo = fl < -2.0e9f ? -2000000000 : (int)fl;
+  rhi = fh > 2.0e9f ? 2000000000 : (int)fh;
+  return rlo <= rhi;
+}
+
 // Stage one line for a tile from its grid record and its strength/width at T: the FP32
 // quantities the waves need, and for each wave its code word. Lines that do not reach the
 // tile keep code 0 for every wave. Every decision that needs FP64 (cut bounds, reference
@@ -491,11 +521,11 @@ __device__ __forceinline__ void stage_line(LineLDS<P>& L, int tid, const int4 gr
   const int clo = (int)((int64_t)jlo - tile0 < -1 ? -1 : (int64_t)jlo - tile0);
   const int chi = (int)((int64_t)jhi - tile0 > W ? W : (int64_t)jhi - tile0);
   // core points: strictly inside the last zone, and within the cut range
-  int czl = 1, czh = 0;
-  if (zh[kKmax - 1] > zl[kKmax - 1]) {
-    const float fl = floorf(zl[kKmax - 1]) + 1.0f, fh = ceilf(zh[kKmax - 1]) - 1.0f;
-    czl = fl < (float)clo ? clo : (fl > (float)(W + 1) ? W + 1 : (int)fl);
-    czh = fh > (float)chi ? chi : (fh < -2.0f ? -2 : (int)fh);
+  int czl = 1, czh = 0, rlo, rhi;
+  if (core_rel(alpha, gam, delta, inv_dnu, zK[kKmax - 1], rlo, rhi)) {
+    const int64_t gl = (int64_t)jref + rlo - tile0, gh = (int64_t)jref + rhi - tile0;
+    czl = (int)(gl < clo ? clo : (gl > W + 1 ? W + 1 : gl));
+    czh = (int)(gh > chi ? chi : (gh < -2 ? -2 : gh));
   }
   L.CZ[tid] = make_int2(czl, czh);
 #pragma unroll
@@ -579,22 +609,44 @@ __device__ __forceinline__ int line_group(uint32_t code) {
   return ((code & 24u) || (code & 7u) > 4u) ? 5 : (int)(code & 7u);
 }
 
-// Per-wave wing loop over the lines of one group (all unmasked, no core slots).
+// Per-wave wing loop over the lines of one group (all unmasked, no core slots). Lines go in
+// blocks of 16 with a compensated flush after each block (and after a partial last block);
+// the list is read four entries at a time into a scalar register.
+template <int P, int K>
+__device__ __forceinline__ void wing_line(const LineLDS<P>& L, int l, float jl0, float (&part)[P]) {
+  const float4 f0 = L.F0[l];
+  const float4 f1 = L.F1[l];
+  float4 ka = make_float4(0.f, 0.f, 0.f, 0.f), kb = ka;
+  float kc = 0.f;
+  if (K >= 2) ka = L.KA[l];
+  if (K >= 3) kb = L.KB[l];
+  if (K >= 4) kc = L.KC[l];
+  wing_slots<P, K, false, false>(part, jl0 - f0.y, f0, f1, ka, kb, kc);
+}
+
 template <int P, int K>
 __device__ __forceinline__ void group_loop(const LineLDS<P>& L, int wv, int i0, int i1, float jl0, float (&part)[P],
-                                           float (&s)[P], float (&cc)[P], int& nproc) {
-  for (int i = i0; i < i1; ++i) {
-    const int l = __builtin_amdgcn_readfirstlane((int)L.list[wv][i]);
-    const float4 f0 = L.F0[l];
-    const float4 f1 = L.F1[l];
-    float4 ka = make_float4(0.f, 0.f, 0.f, 0.f), kb = ka;
-    float kc = 0.f;
-    if (K >= 2) ka = L.KA[l];
-    if (K >= 3) kb = L.KB[l];
-    if (K >= 4) kc = L.KC[l];
-    wing_slots<P, K, false, false>(part, jl0 - f0.y, f0, f1, ka, kb, kc);
-    if ((++nproc & 15) == 0) kahan_flush<P>(part, s, cc);
+                                           float (&s)[P], float (&cc)[P]) {
+  if (i0 >= i1) return;
+  int i = i0;
+  // unaligned head: single entries up to a multiple of 4
+  for (; i < i1 && (i & 3); ++i) wing_line<P, K>(L, __builtin_amdgcn_readfirstlane((int)L.list[wv][i]), jl0, part);
+  int since = 0;
+  for (; i + 4 <= i1; i += 4) {
+    const uint32_t w4 = (uint32_t)__builtin_amdgcn_readfirstlane(
+        (int)*reinterpret_cast<const uint32_t*>(&L.list[wv][i]));
+    wing_line<P, K>(L, (int)(w4 & 255u), jl0, part);
+    wing_line<P, K>(L, (int)((w4 >> 8) & 255u), jl0, part);
+    wing_line<P, K>(L, (int)((w4 >> 16) & 255u), jl0, part);
+    wing_line<P, K>(L, (int)(w4 >> 24), jl0, part);
+    since += 4;
+    if (since == 16) {
+      kahan_flush<P>(part, s, cc);
+      since = 0;
+    }
   }
+  for (; i < i1; ++i) wing_line<P, K>(L, __builtin_amdgcn_readfirstlane((int)L.list[wv][i]), jl0, part);
+  kahan_flush<P>(part, s, cc);
 }
 
 template <int P>
@@ -646,8 +698,6 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
       cc[p] = 0.0f;
       part[p] = 0.0f;
     }
-    int nproc = 0;
-
     for (int64_t b = line_lo; b < line_hi; b += kLB) {
       // ---- stage one batch of lines: one thread per line
       {
@@ -689,10 +739,10 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
 
       // ---- accumulate: fast groups, then the general group
       {
-        group_loop<P, 1>(L, wv, o[1], o[2], jl0, part, s, cc, nproc);
-        group_loop<P, 2>(L, wv, o[2], o[3], jl0, part, s, cc, nproc);
-        group_loop<P, 3>(L, wv, o[3], o[4], jl0, part, s, cc, nproc);
-        group_loop<P, 4>(L, wv, o[4], o[5], jl0, part, s, cc, nproc);
+        group_loop<P, 1>(L, wv, o[1], o[2], jl0, part, s, cc);
+        group_loop<P, 2>(L, wv, o[2], o[3], jl0, part, s, cc);
+        group_loop<P, 3>(L, wv, o[3], o[4], jl0, part, s, cc);
+        group_loop<P, 4>(L, wv, o[4], o[5], jl0, part, s, cc);
         for (int i = o[5]; i < o[6]; ++i) {
           const int l = __builtin_amdgcn_readfirstlane((int)L.list[wv][i]);
           const uint32_t code = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t*>(L.code)[4 * l + wv]);
@@ -725,8 +775,9 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
           else if (K == 2u) wing_slots<P, 2, true, false>(part, kf0, f0, f1, ka, kb, kc);
           else if (K == 3u) wing_slots<P, 3, true, false>(part, kf0, f0, f1, ka, kb, kc);
           else wing_slots<P, 4, true, false>(part, kf0, f0, f1, ka, kb, kc);
-          if ((++nproc & 15) == 0) kahan_flush<P>(part, s, cc);
+          if (((i - o[5]) & 15) == 15) kahan_flush<P>(part, s, cc);
         }
+        kahan_flush<P>(part, s, cc);
       }
       __syncthreads();
     }
@@ -739,7 +790,7 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
       const float v = s[p] - cc[p];
       if (nc == 1) {
         if (tile0 + local < pd.n) a.k[pd.out_off + tile0 + local] = v;
-      } else {
+      } else if (it < a.items_cap) {
         a.partial[((int64_t)it) * W + local] = v;
       }
     }
@@ -749,61 +800,63 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
 
 // ------------------------------------------------------------------- core pass
 // The core points of every line (|z| below the last series threshold, within the cut) are
-// evaluated here, after the wing pass, over the same work items: each wave queues the
-// (line, point) pairs that fall on its points, evaluates 64 at a time with the FP64 rational
-// approximation (from the line's FP64 centre and widths) and adds them to its points in line
-// order (one round of LDS updates per line; a line's pairs have distinct points), then adds
-// the Kahan-summed result to the tile. Deterministic for a fixed tuning.
+// evaluated here, after the wing pass and its combine. A workgroup is one wave and owns a
+// core tile of 64 P grid points; its work list holds the lines whose centre lies within the
+// largest core half-width of the tile. The wave stages 64 lines at a time (one per lane; the
+// next batch is loaded while the current one is queued), appends the (line, point) pairs of
+// lines with core points on the tile to a queue held in registers (one pair per lane, with
+// the line's FP64 constants), evaluates 64 pairs at a time with the FP64 rational
+// approximation, and adds them to its LDS accumulator one line segment at a time (a line's
+// pairs are contiguous in the queue and have distinct points, so each segment is one
+// conflict-free update, applied in line order). Every 8 rounds the accumulator goes into
+// compensated per-lane sums. No workgroup barrier couples waves with unequal work.
 template <int P>
 struct CoreLDS {
-  int4 C[kLB];                  // (core lo, core hi, jt, ampc bits); lo > hi: no core in the tile
-  uint8_t list[kWavesPerWG][kLB];
-  uint32_t queue[kWavesPerWG][kWave];
-  float acc[kWavesPerWG][kWave * P];
+  float acc[kWave * P];
 };
 
 template <int P>
-__global__ __launch_bounds__(kThreads) void k_core(VoigtArgs a) {
-  constexpr int W = kWavesPerWG * kWave * P;
+__device__ __forceinline__ void core_round(CoreLDS<P>& L, int lane, int qn, uint64_t segs, double qx, double qy,
+                                           float qa, int qj) {
+  float v = 0.0f;
+  if (lane < qn) v = qa * (float)weideman_re(qx, qy);
+  // one conflict-free LDS update per line segment, in queue (line) order
+  uint64_t rem = segs & ((qn >= 64) ? ~0ull : ((1ull << qn) - 1ull));
+  while (rem) {
+    const int s0 = (int)__builtin_ctzll(rem);
+    rem &= rem - 1ull;
+    const int s1 = rem ? (int)__builtin_ctzll(rem) : qn;
+    if (lane >= s0 && lane < s1) L.acc[qj] += v;  // LDS operations of a wave stay in order
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(kWave) void k_core(VoigtArgs a) {
+  constexpr int W = kWave * P;  // core tile width in grid points
   __shared__ CoreLDS<P> L;
-  __shared__ double sW[kWeidN + 1];
-  __shared__ int sItem, sTile, sPair;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int w0 = wv * kWave * P, w1 = w0 + kWave * P - 1;
-  if (tid < kWeidN) sW[tid] = c_weid[tid];
-  if (tid == kWeidN) sW[kWeidN] = c_weidL;
+  const int lane = threadIdx.x;
 #pragma unroll
-  for (int p = 0; p < P; ++p) L.acc[wv][p * kWave + lane] = 0.0f;
+  for (int p = 0; p < P; ++p) L.acc[p * kWave + lane] = 0.0f;
   const int total = a.item_base[a.n_tiles_total];
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const float zc = a.zK[kKmax - 1];
-  long long ncore = 0;  // core evaluations done by this wave (statistics only)
+  long long ncore = 0;  // core evaluations of this wave (statistics only)
 
   for (;;) {
-    if (tid == 0) {
-      const int it = atomicAdd(a.counter + 1, 1);
-      sItem = it;
-      if (it < total) {
-        int lo = 0, hi = a.n_tiles_total - 1;
-        while (lo < hi) {
-          const int m = (lo + hi + 1) >> 1;
-          if (a.item_base[m] <= it) lo = m; else hi = m - 1;
-        }
-        sTile = lo;
-        sPair = find_pair(a.pairs, a.n_pairs, lo);
-      }
-    }
-    __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(sItem);
+    int itv = 0;
+    if (lane == 0) itv = atomicAdd(a.counter + 1, 1);
+    const int it = __builtin_amdgcn_readfirstlane(__shfl(itv, 0));
     if (it >= total) break;
-    const int g = __builtin_amdgcn_readfirstlane(sTile);
-    const PairDesc pd = wave_uniform(a.pairs[__builtin_amdgcn_readfirstlane(sPair)]);
+    int lo = 0, hi = a.n_tiles_total - 1;  // last tile with item_base <= it
+    while (lo < hi) {
+      const int m = (lo + hi + 1) >> 1;
+      if (__builtin_amdgcn_readfirstlane(a.item_base[m]) <= it) lo = m; else hi = m - 1;
+    }
+    const int g = lo;
+    const PairDesc pd = wave_uniform(a.pairs[find_pair(a.pairs, a.n_pairs, g)]);
     const int ibase = __builtin_amdgcn_readfirstlane(a.item_base[g]);
-    const int chunk_idx = it - ibase;
     const int nc = __builtin_amdgcn_readfirstlane(a.tile_nc[g]);
     const int64_t tile0 = (int64_t)(g - pd.tile_base) * W;
-    const int64_t line_lo = (int64_t)__builtin_amdgcn_readfirstlane(a.tile_lo[g]) + (int64_t)chunk_idx * a.chunk;
+    const int64_t line_lo = (int64_t)__builtin_amdgcn_readfirstlane(a.tile_lo[g]) + (int64_t)(it - ibase) * a.chunk;
     int64_t line_hi = line_lo + a.chunk;
     const int64_t thi = __builtin_amdgcn_readfirstlane(a.tile_hi[g]);
     if (line_hi > thi) line_hi = thi;
@@ -816,148 +869,146 @@ __global__ __launch_bounds__(kThreads) void k_core(VoigtArgs a) {
 #pragma unroll
     for (int p = 0; p < P; ++p) { s[p] = 0.0f; cc[p] = 0.0f; part[p] = 0.0f; }
     bool any = false;
+    int rounds = 0;
+    // the queue: lane k < qn holds one pair (x, y, amplitude, tile-local point)
+    int qn = 0;
+    uint64_t segs = 0ull;  // lanes where a line's segment starts
+    double qx = 0.0, qy = 0.0;
+    float qa = 0.0f;
+    int qj = 0;
 
-    for (int64_t b = line_lo; b < line_hi; b += kLB) {
-      // stage: each line's core points in this tile (tile-local, within the cut range)
-      int czl = 1, czh = 0, jt = 0;
-      float ampc = 0.0f;
-      {
-        const int64_t li = b + tid;
-        if (li < line_hi) {
-          const int4 gr = grec[li];
-          const float S = S_T[li];
-          const int jref = gr.y, jlo = gr.z, jhi = gr.w;
-          if (S > 0.0f && jlo <= jhi && (int64_t)jhi >= tile0 && (int64_t)jlo <= tile0 + (W - 1)) {
-            const double nu0 = a.nu[li];
-            const float alpha = (float)(nu0 * pd.beta);
-            const float gam = gT[li] * (float)pd.pfac;
-            jt = (int)((int64_t)jref - tile0);
-            const float af = alpha * inv_dnu, gf = gam * inv_dnu;
-            const float zz = zc * af;
-            const float h2 = zz * zz - gf * gf;
-            if (h2 > 0.0f) {
-              const float h = sqrtf(h2) * 1.00001f + 1e-3f;
-              const float c = (float)jt - __int_as_float(gr.x) * inv_dnu;
-              const int clo = (int)((int64_t)jlo - tile0 < -1 ? -1 : (int64_t)jlo - tile0);
-              const int chi = (int)((int64_t)jhi - tile0 > W ? W : (int64_t)jhi - tile0);
-              const float fl = floorf(c - h) + 1.0f, fh = ceilf(c + h) - 1.0f;
-              czl = fl < (float)clo ? clo : (fl > (float)(W + 1) ? W + 1 : (int)fl);
-              czh = fh > (float)chi ? chi : (fh < -2.0f ? -2 : (int)fh);
-              ampc = S / (1.7724538509055160273f * alpha);
-            }
-          }
-        }
-        L.C[tid] = make_int4(czl, czh, jt, __float_as_int(ampc));
-      }
-      __syncthreads();
-      // this wave's list of lines with core points on its span, in staging order
-      int nl = 0;
-      {
-#pragma unroll
-        for (int r = 0; r < kLB / kWave; ++r) {
-          const int4 c = L.C[r * kWave + lane];
-          const int lo = c.x > w0 ? c.x : w0, hi = c.y < w1 ? c.y : w1;
-          const bool has = lo <= hi;
-          const uint64_t m = __ballot(has);
-          if (has) L.list[wv][nl + (int)__popcll(m & lt)] = (uint8_t)(r * kWave + lane);
-          nl += (int)__popcll(m);
-        }
-      }
-      // queue, evaluate, accumulate
-      int qn = 0;
-      for (int i = 0; i <= nl; ++i) {
-        int j0 = 1, j1 = 0, l = 0;
-        if (i < nl) {
-          l = __builtin_amdgcn_readfirstlane((int)L.list[wv][i]);
-          const int cl = __builtin_amdgcn_readfirstlane(L.C[l].x), ch = __builtin_amdgcn_readfirstlane(L.C[l].y);
-          j0 = cl > w0 ? cl : w0;
-          j1 = ch < w1 ? ch : w1;
-        }
-        while (j0 <= j1 || (i == nl && qn > 0)) {
-          const int take = j0 <= j1 ? ((j1 - j0 + 1) < (kWave - qn) ? (j1 - j0 + 1) : (kWave - qn)) : 0;
-          if (lane < take) L.queue[wv][qn + lane] = ((uint32_t)l << 16) | (uint32_t)(j0 + lane - w0);
-          qn += take;
-          j0 += take;
-          if (qn == kWave || (i == nl && qn > 0)) {
-            const bool valid = lane < qn;
-            const uint32_t e = valid ? L.queue[wv][lane] : 0u;
-            const int el = (int)(e >> 16), jw = (int)(e & 0xFFFFu);
-            float v = 0.0f;
-            if (valid) {
-              const int4 c = L.C[el];
-              const int64_t li = b + el;
-              const double nu0 = a.nu[li];
-              const double alpha = nu0 * pd.beta;
-              const double y = (double)gT[li] * pd.pfac * rcp64(alpha);
-              const double d64 = __dsub_rn(grid_nu(pd.nu_start, pd.dnu, (int64_t)c.z + tile0), nu0);
-              const double D = (double)(w0 + jw - c.z) * pd.dnu + d64;
-              v = __int_as_float(c.w) * (float)weideman_re(D * rcp64(alpha), y, sW);
-            }
-            uint64_t rem = __ballot(valid);
-            while (rem) {
-              const int lf = __builtin_amdgcn_readlane(el, (int)__builtin_ctzll(rem));
-              const bool mine = valid && el == lf && ((rem >> lane) & 1ull);
-              if (mine) L.acc[wv][jw] += v;
-              rem &= ~__ballot(mine);
-            }
-#pragma unroll
-            for (int p = 0; p < P; ++p) {
-              part[p] += L.acc[wv][p * kWave + lane];
-              L.acc[wv][p * kWave + lane] = 0.0f;
-            }
-            kahan_flush<P>(part, s, cc);
-            ncore += qn;
-            qn = 0;
-            any = true;
-          }
-        }
-      }
-      __syncthreads();
-    }
-    // add the core sums to the wing pass's tile (or partial tile)
-    if (__builtin_amdgcn_readfirstlane((int)any)) {
+    auto flush_acc = [&]() {
 #pragma unroll
       for (int p = 0; p < P; ++p) {
-        const int local = w0 + p * kWave + lane;
-        const float v = s[p] - cc[p];
-        if (nc == 1) {
-          if (tile0 + local < pd.n) {
-            float* dst = a.k + pd.out_off + tile0 + local;
-            *dst = *dst + v;
+        part[p] += L.acc[p * kWave + lane];
+        L.acc[p * kWave + lane] = 0.0f;
+      }
+      kahan_flush<P>(part, s, cc);
+    };
+    auto run_round = [&]() {
+      core_round<P>(L, lane, qn, segs, qx, qy, qa, qj);
+      ncore += qn;
+      qn = 0;
+      segs = 0ull;
+      any = true;
+      if (++rounds == 8) {
+        flush_acc();
+        rounds = 0;
+      }
+    };
+
+    // software pipeline: the next batch's line data is loaded before the current one is queued
+    int4 nx_gr = make_int4(0, 0, 1, 0);
+    float nx_S = 0.0f, nx_g = 0.0f;
+    double nx_nu = 1.0;
+    if (line_lo + lane < line_hi) {
+      const int64_t li = line_lo + lane;
+      nx_gr = grec[li]; nx_S = S_T[li]; nx_g = gT[li]; nx_nu = a.nu[li];
+    }
+    for (int64_t b = line_lo; b < line_hi; b += kWave) {
+      const int4 gr = nx_gr;
+      const float S = nx_S, gTv = nx_g;
+      const double nu0 = nx_nu;
+      const bool valid = b + lane < line_hi;
+      if (b + kWave + lane < line_hi) {
+        const int64_t li = b + kWave + lane;
+        nx_gr = grec[li]; nx_S = S_T[li]; nx_g = gT[li]; nx_nu = a.nu[li];
+      }
+      // this lane's line: its core points on the tile (tile-local, inclusive)
+      int czl = 1, czh = 0;
+      double lia = 0.0, ld64 = 0.0, ly = 0.0;
+      float lamp = 0.0f;
+      const int jref = gr.y, jlo = gr.z, jhi = gr.w;
+      if (valid && S > 0.0f && jlo <= jhi) {
+        const float alpha = (float)(nu0 * pd.beta);
+        const float gam = gTv * (float)pd.pfac;
+        int rlo, rhi;
+        if (core_rel(alpha, gam, __int_as_float(gr.x), inv_dnu, zc, rlo, rhi)) {
+          int64_t gl = (int64_t)jref + rlo, gh = (int64_t)jref + rhi;
+          if (gl < jlo) gl = jlo;
+          if (gh > jhi) gh = jhi;
+          if (gl < tile0) gl = tile0;
+          if (gh > tile0 + W - 1) gh = tile0 + W - 1;
+          if (gh > pd.n - 1) gh = pd.n - 1;
+          if (gl <= gh) {
+            czl = (int)(gl - tile0);
+            czh = (int)(gh - tile0);
+            lamp = S / (1.7724538509055160273f * alpha);
+            lia = rcp64(nu0 * pd.beta);
+            ld64 = __dsub_rn(grid_nu(pd.nu_start, pd.dnu, (int64_t)jref), nu0);
+            ly = (double)gTv * pd.pfac * lia;
           }
-        } else {
-          float* dst = a.partial + (int64_t)it * W + local;
-          *dst = *dst + v;
+        }
+      }
+      const int jrl = (int)((int64_t)jref - tile0);
+      // append each line's pairs in staging order
+      uint64_t m = __ballot(czl <= czh);
+      while (m) {
+        const int l = (int)__builtin_ctzll(m);
+        m &= m - 1ull;
+        int j0 = __builtin_amdgcn_readlane(czl, l);
+        const int j1 = __builtin_amdgcn_readlane(czh, l);
+        const int jr = __builtin_amdgcn_readlane(jrl, l);
+        const float amp = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lamp), l));
+        const double ia = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(lia), l),
+                                           __builtin_amdgcn_readlane(__double2loint(lia), l));
+        const double d64 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(ld64), l),
+                                            __builtin_amdgcn_readlane(__double2loint(ld64), l));
+        const double yv = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(ly), l),
+                                           __builtin_amdgcn_readlane(__double2loint(ly), l));
+        while (j0 <= j1) {
+          const int take = (j1 - j0 + 1) < (kWave - qn) ? (j1 - j0 + 1) : (kWave - qn);
+          segs |= 1ull << qn;
+          if (lane >= qn && lane < qn + take) {
+            const int j = j0 + (lane - qn);
+            qj = j;
+            qx = ((double)(j - jr) * pd.dnu + d64) * ia;
+            qy = yv;
+            qa = amp;
+          }
+          qn += take;
+          j0 += take;
+          if (qn == kWave) run_round();
         }
       }
     }
-    __syncthreads();
-  }
-  if (a.stats) {
-    __shared__ long long sc[kWavesPerWG];
-    if (lane == 0) sc[wv] = ncore;
-    __syncthreads();
-    if (tid == 0) {
-      long long t = 0;
-      for (int w = 0; w < kWavesPerWG; ++w) t += sc[w];
-      a.stats[blockIdx.x] = t;
+    if (qn > 0) run_round();
+    flush_acc();
+
+    // single-item tiles add their core sums to k (the wing pass and its combine are done);
+    // items of split tiles store theirs for the fixed-order core combine
+    if (nc == 1) {
+      if (any) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+          const int local = p * kWave + lane;
+          if (tile0 + local < pd.n) {
+            float* dst = a.k + pd.out_off + tile0 + local;
+            *dst = *dst + (s[p] - cc[p]);
+          }
+        }
+      }
+    } else if (it < a.items_cap) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) a.partial[(int64_t)it * W + p * kWave + lane] = s[p] - cc[p];
     }
   }
+  if (a.stats && lane == 0) a.stats[blockIdx.x] = ncore;
 }
 
 // ------------------------------------------------------------------------ adjoint
 // w(x + iy) = K + iL in FP64 by the same rational approximation (both parts).
-__device__ __forceinline__ void weideman_w(double x, double y, const double* __restrict__ wc, double& K, double& L) {
-  const double Lw = wc[kWeidN];
+__device__ __forceinline__ void weideman_w(double x, double y, double& K, double& L) {
+  const double Lw = c_weidL;
   const double dr = Lw + y, di = -x;
   const double nr = Lw - y, ni = x;
   const double inv = rcp64(dr * dr + di * di);
   const double Zr = (nr * dr + ni * di) * inv;
   const double Zi = (ni * dr - nr * di) * inv;
-  double pr = wc[kWeidN - 1], pi = 0.0;
-#pragma unroll 4
+  double pr = c_weid[kWeidN - 1], pi = 0.0;
+#pragma unroll
   for (int m = kWeidN - 2; m >= 0; --m) {
-    const double t = fma(pr, Zr, fma(-pi, Zi, wc[m]));
+    const double t = fma(pr, Zr, fma(-pi, Zi, c_weid[m]));
     pi = fma(pr, Zi, pi * Zr);
     pr = t;
   }
@@ -1004,11 +1055,7 @@ __device__ __forceinline__ double wave_sum64(double v) {
 
 // One wave per line (static assignment), lanes over its grid points inside the cut.
 __global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
-  __shared__ double sW[kWeidN + 1];
   const int tid = threadIdx.x, lane = tid & 63;
-  if (tid < kWeidN) sW[tid] = c_weid[tid];
-  if (tid == kWeidN) sW[kWeidN] = c_weidL;
-  __syncthreads();
   const int64_t nw = (int64_t)gridDim.x * kWavesPerWG;
   const PrepArgs& pa = a.pa;
   for (int64_t i = (int64_t)blockIdx.x * kWavesPerWG + (tid >> 6); i < pa.N; i += nw) {
@@ -1081,7 +1128,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
           core = x * x + y * y < zc2;
           if (core) {
             double K, L;
-            weideman_w(x, y, sW, K, L);
+            weideman_w(x, y, K, L);
             const double Kx = -2.0 * (x * K - y * L);
             const double Ky = 2.0 * (x * L + y * K) - 1.1283791670955125739;
             const double gd = (double)gv;
@@ -1171,8 +1218,27 @@ __global__ __launch_bounds__(kThreads) void k_combine(VoigtArgs a) {
   for (int local = threadIdx.x; local < W; local += kThreads) {
     if (tile0 + local >= pd.n) continue;
     double acc = 0.0;
-    for (int c = 0; c < nc; ++c) acc += (double)a.partial[(int64_t)(base + c) * W + local];
+    for (int c = 0; c < nc && base + c < a.items_cap; ++c) acc += (double)a.partial[(int64_t)(base + c) * W + local];
     a.k[pd.out_off + tile0 + local] = (float)acc;
+  }
+}
+
+// k += fixed-order (chunk 0, 1, ...) sum of the core pass's partial tiles of split tiles.
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_combine_core(VoigtArgs a) {
+  constexpr int W = kWave * P;  // core tiles are one wave wide
+  const int g = blockIdx.x;
+  const int nc = a.tile_nc[g];
+  if (nc <= 1) return;
+  const PairDesc pd = a.pairs[find_pair(a.pairs, a.n_pairs, g)];
+  const int64_t tile0 = (int64_t)(g - pd.tile_base) * W;
+  const int base = a.item_base[g];
+  for (int local = threadIdx.x; local < W; local += kThreads) {
+    if (tile0 + local >= pd.n) continue;
+    double acc = 0.0;
+    for (int c = 0; c < nc && base + c < a.items_cap; ++c) acc += (double)a.partial[(int64_t)(base + c) * W + local];
+    float* dst = a.k + pd.out_off + tile0 + local;
+    *dst = *dst + (float)acc;
   }
 }
 
@@ -1240,10 +1306,10 @@ hipError_t launch_fill_pairs(const PairDesc* host_pairs, int count, PairDesc* ds
 
 hipError_t launch_worklist(const uint32_t* keys, int64_t N, KeyMap km, double numin, double numax,
                            const PairDesc* pairs, int n_pairs,
-                           int n_tiles_total, int tile_w, double cut, int chunk, int32_t* lo, int32_t* hi,
-                           int32_t* nc, hipStream_t st) {
+                           int n_tiles_total, int tile_w, double cut, double core_z, int chunk, int32_t* lo,
+                           int32_t* hi, int32_t* nc, hipStream_t st) {
   hipLaunchKernelGGL(k_worklist, dim3(blocks_for(n_tiles_total, kThreads)), dim3(kThreads), 0, st, keys, N, km,
-                     numin, numax, pairs, n_pairs, n_tiles_total, tile_w, cut, chunk, lo, hi, nc);
+                     numin, numax, pairs, n_pairs, n_tiles_total, tile_w, cut, core_z, chunk, lo, hi, nc);
   return hipGetLastError();
 }
 
@@ -1268,8 +1334,8 @@ hipError_t launch_voigt(const VoigtArgs& a, int slots, int grid, hipStream_t st)
 }
 
 hipError_t launch_core(const VoigtArgs& a, int slots, int grid, hipStream_t st) {
-  if (slots == 8) hipLaunchKernelGGL(k_core<8>, dim3(grid), dim3(kThreads), 0, st, a);
-  else if (slots == 4) hipLaunchKernelGGL(k_core<4>, dim3(grid), dim3(kThreads), 0, st, a);
+  if (slots == 8) hipLaunchKernelGGL(k_core<8>, dim3(grid), dim3(kWave), 0, st, a);
+  else if (slots == 4) hipLaunchKernelGGL(k_core<4>, dim3(grid), dim3(kWave), 0, st, a);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -1278,6 +1344,14 @@ hipError_t launch_combine(const VoigtArgs& a, int slots, hipStream_t st) {
   dim3 grid((unsigned)a.n_tiles_total);
   if (slots == 8) hipLaunchKernelGGL(k_combine<8>, grid, dim3(kThreads), 0, st, a);
   else if (slots == 4) hipLaunchKernelGGL(k_combine<4>, grid, dim3(kThreads), 0, st, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_combine_core(const VoigtArgs& a, int slots, hipStream_t st) {
+  dim3 grid((unsigned)a.n_tiles_total);
+  if (slots == 8) hipLaunchKernelGGL(k_combine_core<8>, grid, dim3(kThreads), 0, st, a);
+  else if (slots == 4) hipLaunchKernelGGL(k_combine_core<4>, grid, dim3(kThreads), 0, st, a);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
@@ -1299,6 +1373,13 @@ hipError_t launch_reduce2(const double* contrib, int64_t N, double* partial, int
   hipLaunchKernelGGL(k_reduce2, dim3(n_partial), dim3(1024), 0, st, contrib, N, partial);
   hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(1024), 0, st, (const double*)partial, (int64_t)n_partial, out);
   return hipGetLastError();
+}
+
+int core_max_blocks_per_cu(int slots) {
+  int nb = 0;
+  if (slots == 8) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_core<8>, kWave, 0);
+  else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_core<4>, kWave, 0);
+  return nb > 0 ? nb : 1;
 }
 
 int voigt_max_blocks_per_cu(int slots) {
