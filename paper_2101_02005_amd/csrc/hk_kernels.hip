@@ -591,28 +591,36 @@ __device__ __forceinline__ void wing_slots(float (&part)[P], float kf0, const fl
       t = __builtin_fmaf(t, q, ka.x);
       t = __builtin_fmaf(t, q, f1.x);
     }
-    if (MASK || EXCL) {
-      bool in = true;
-      if (MASK) in = (kf >= f1.y) && (kf <= f1.z);
-      if (EXCL) in = in && ((kf < xl) || (kf > xh));
+    if (EXCL) {
+      // excluded core points may have R = 0 (q infinite): select the sum, not the term
+      bool in = (kf < xl) || (kf > xh);
+      if (MASK) in = in && (kf >= f1.y) && (kf <= f1.z);
       part[p] = in ? __builtin_fmaf(t, q, part[p]) : part[p];
+    } else if (MASK) {
+      // points outside the cut are far from the centre (q finite): zero the term
+      const float tm = (kf >= f1.y && kf <= f1.z) ? t : 0.0f;
+      part[p] = __builtin_fmaf(tm, q, part[p]);
     } else {
       part[p] = __builtin_fmaf(t, q, part[p]);
     }
   }
 }
 
-// Group of a staged line for one wave: 0 does not reach the wave, 1..4 unmasked line of
-// series order K without core points, 5 general (order 5, lanes outside the cut, or core points).
+// Group of a staged line for one wave: 0 does not reach the wave; 1..4 series order K, all
+// lanes inside the cut, no core points; 6..9 the same with lanes outside the cut (order
+// K = group - 5); 5 general (order 5 or core points on the wave).
+constexpr int kGroups = 9;
 __device__ __forceinline__ int line_group(uint32_t code) {
   if (code == 0u) return 0;
-  return ((code & 24u) || (code & 7u) > 4u) ? 5 : (int)(code & 7u);
+  const int K = (int)(code & 7u);
+  if ((code & 16u) || K > 4) return 5;
+  return (code & 8u) ? 5 + K : K;
 }
 
 // Per-wave wing loop over the lines of one group (all unmasked, no core slots). Lines go in
 // blocks of 16 with a compensated flush after each block (and after a partial last block);
 // the list is read four entries at a time into a scalar register.
-template <int P, int K>
+template <int P, int K, bool MASK>
 __device__ __forceinline__ void wing_line(const LineLDS<P>& L, int l, float jl0, float (&part)[P]) {
   const float4 f0 = L.F0[l];
   const float4 f1 = L.F1[l];
@@ -621,31 +629,32 @@ __device__ __forceinline__ void wing_line(const LineLDS<P>& L, int l, float jl0,
   if (K >= 2) ka = L.KA[l];
   if (K >= 3) kb = L.KB[l];
   if (K >= 4) kc = L.KC[l];
-  wing_slots<P, K, false, false>(part, jl0 - f0.y, f0, f1, ka, kb, kc);
+  wing_slots<P, K, MASK, false>(part, jl0 - f0.y, f0, f1, ka, kb, kc);
 }
 
-template <int P, int K>
+template <int P, int K, bool MASK>
 __device__ __forceinline__ void group_loop(const LineLDS<P>& L, int wv, int i0, int i1, float jl0, float (&part)[P],
                                            float (&s)[P], float (&cc)[P]) {
   if (i0 >= i1) return;
   int i = i0;
   // unaligned head: single entries up to a multiple of 4
-  for (; i < i1 && (i & 3); ++i) wing_line<P, K>(L, __builtin_amdgcn_readfirstlane((int)L.list[wv][i]), jl0, part);
+  for (; i < i1 && (i & 3); ++i)
+    wing_line<P, K, MASK>(L, __builtin_amdgcn_readfirstlane((int)L.list[wv][i]), jl0, part);
   int since = 0;
   for (; i + 4 <= i1; i += 4) {
     const uint32_t w4 = (uint32_t)__builtin_amdgcn_readfirstlane(
         (int)*reinterpret_cast<const uint32_t*>(&L.list[wv][i]));
-    wing_line<P, K>(L, (int)(w4 & 255u), jl0, part);
-    wing_line<P, K>(L, (int)((w4 >> 8) & 255u), jl0, part);
-    wing_line<P, K>(L, (int)((w4 >> 16) & 255u), jl0, part);
-    wing_line<P, K>(L, (int)(w4 >> 24), jl0, part);
+    wing_line<P, K, MASK>(L, (int)(w4 & 255u), jl0, part);
+    wing_line<P, K, MASK>(L, (int)((w4 >> 8) & 255u), jl0, part);
+    wing_line<P, K, MASK>(L, (int)((w4 >> 16) & 255u), jl0, part);
+    wing_line<P, K, MASK>(L, (int)(w4 >> 24), jl0, part);
     since += 4;
     if (since == 16) {
       kahan_flush<P>(part, s, cc);
       since = 0;
     }
   }
-  for (; i < i1; ++i) wing_line<P, K>(L, __builtin_amdgcn_readfirstlane((int)L.list[wv][i]), jl0, part);
+  for (; i < i1; ++i) wing_line<P, K, MASK>(L, __builtin_amdgcn_readfirstlane((int)L.list[wv][i]), jl0, part);
   kahan_flush<P>(part, s, cc);
 }
 
@@ -709,27 +718,29 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
       __syncthreads();
       // ---- this wave's list of the staged lines that reach it, grouped by series order and in
       //      staging order within a group (wave ballots; deterministic)
-      int o[7];
+      int o[kGroups + 2];
       {
         const uint32_t* code_w = reinterpret_cast<const uint32_t*>(L.code) + wv;
         int grp[kLB / kWave];
-        int cnt[6] = {0, 0, 0, 0, 0, 0};
+        int cnt[kGroups + 1];
+#pragma unroll
+        for (int gg = 0; gg <= kGroups; ++gg) cnt[gg] = 0;
 #pragma unroll
         for (int r = 0; r < kLB / kWave; ++r) {
           grp[r] = line_group(code_w[4 * (r * kWave + lane)]);
 #pragma unroll
-          for (int gg = 1; gg <= 5; ++gg) cnt[gg] += (int)__popcll(__ballot(grp[r] == gg));
+          for (int gg = 1; gg <= kGroups; ++gg) cnt[gg] += (int)__popcll(__ballot(grp[r] == gg));
         }
         o[1] = 0;
 #pragma unroll
-        for (int gg = 1; gg <= 5; ++gg) o[gg + 1] = o[gg] + cnt[gg];
-        int st[6];
+        for (int gg = 1; gg <= kGroups; ++gg) o[gg + 1] = o[gg] + cnt[gg];
+        int st[kGroups + 1];
 #pragma unroll
-        for (int gg = 1; gg <= 5; ++gg) st[gg] = o[gg];
+        for (int gg = 1; gg <= kGroups; ++gg) st[gg] = o[gg];
 #pragma unroll
         for (int r = 0; r < kLB / kWave; ++r) {
 #pragma unroll
-          for (int gg = 1; gg <= 5; ++gg) {
+          for (int gg = 1; gg <= kGroups; ++gg) {
             const uint64_t m = __ballot(grp[r] == gg);
             if (grp[r] == gg) L.list[wv][st[gg] + (int)__popcll(m & lt)] = (uint8_t)(r * kWave + lane);
             st[gg] += (int)__popcll(m);
@@ -739,42 +750,38 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
 
       // ---- accumulate: fast groups, then the general group
       {
-        group_loop<P, 1>(L, wv, o[1], o[2], jl0, part, s, cc);
-        group_loop<P, 2>(L, wv, o[2], o[3], jl0, part, s, cc);
-        group_loop<P, 3>(L, wv, o[3], o[4], jl0, part, s, cc);
-        group_loop<P, 4>(L, wv, o[4], o[5], jl0, part, s, cc);
+        group_loop<P, 1, false>(L, wv, o[1], o[2], jl0, part, s, cc);
+        group_loop<P, 2, false>(L, wv, o[2], o[3], jl0, part, s, cc);
+        group_loop<P, 3, false>(L, wv, o[3], o[4], jl0, part, s, cc);
+        group_loop<P, 4, false>(L, wv, o[4], o[5], jl0, part, s, cc);
+        group_loop<P, 1, true>(L, wv, o[6], o[7], jl0, part, s, cc);
+        group_loop<P, 2, true>(L, wv, o[7], o[8], jl0, part, s, cc);
+        group_loop<P, 3, true>(L, wv, o[8], o[9], jl0, part, s, cc);
+        group_loop<P, 4, true>(L, wv, o[9], o[10], jl0, part, s, cc);
+        // general group: order 5, possibly lanes outside the cut and core points to skip
         for (int i = o[5]; i < o[6]; ++i) {
           const int l = __builtin_amdgcn_readfirstlane((int)L.list[wv][i]);
           const uint32_t code = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t*>(L.code)[4 * l + wv]);
           const float4 f0 = L.F0[l];
           const float4 f1 = L.F1[l];
-          const float4 ka = L.KA[l];
-          const float4 kb = L.KB[l];
-          const float kc = L.KC[l];
           const float kf0 = jl0 - f0.y;
-          const uint32_t K = code & 7u;
-          if (K == 5u) {
-            // order-5 coefficients from a = alpha^2/s, g = gamma^2/s, times Ah
-            const float av = f1.w, gv = f0.w, A = f1.x;
-            const float a2 = av * av, a3 = a2 * av, a4 = a2 * a2, g2 = gv * gv, g3 = g2 * gv;
-            const float4 k5a = make_float4(A * (1.5f * av), A * (-2.0f * av * gv + 3.75f * a2),
-                                           A * (-15.0f * a2 * gv + 13.125f * a3),
-                                           A * (12.0f * a2 * g2 - 105.0f * a3 * gv + 59.0625f * a4));
-            const float4 k5b = make_float4(A * (210.0f * a3 * g2 - 787.5f * a4 * gv),
-                                           A * (-120.0f * a3 * g3 + 2835.0f * a4 * g2), A * (-3780.0f * a4 * g3),
-                                           A * (1680.0f * a4 * g2 * g2));
-            if (code & 16u) {
-              const int czl = __builtin_amdgcn_readfirstlane(L.CZ[l].x);
-              const int czh = __builtin_amdgcn_readfirstlane(L.CZ[l].y);
-              const float jt = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(f0.y)));
-              wing_slots<P, 5, true, true>(part, kf0, f0, f1, k5a, k5b, 0.f, (float)czl - jt, (float)czh - jt);
-            } else {
-              wing_slots<P, 5, true, false>(part, kf0, f0, f1, k5a, k5b, 0.f);
-            }
-          } else if (K == 1u) wing_slots<P, 1, true, false>(part, kf0, f0, f1, ka, kb, kc);
-          else if (K == 2u) wing_slots<P, 2, true, false>(part, kf0, f0, f1, ka, kb, kc);
-          else if (K == 3u) wing_slots<P, 3, true, false>(part, kf0, f0, f1, ka, kb, kc);
-          else wing_slots<P, 4, true, false>(part, kf0, f0, f1, ka, kb, kc);
+          // order-5 coefficients from a = alpha^2/s, g = gamma^2/s, times Ah
+          const float av = f1.w, gv = f0.w, A = f1.x;
+          const float a2 = av * av, a3 = a2 * av, a4 = a2 * a2, g2 = gv * gv, g3 = g2 * gv;
+          const float4 k5a = make_float4(A * (1.5f * av), A * (-2.0f * av * gv + 3.75f * a2),
+                                         A * (-15.0f * a2 * gv + 13.125f * a3),
+                                         A * (12.0f * a2 * g2 - 105.0f * a3 * gv + 59.0625f * a4));
+          const float4 k5b = make_float4(A * (210.0f * a3 * g2 - 787.5f * a4 * gv),
+                                         A * (-120.0f * a3 * g3 + 2835.0f * a4 * g2), A * (-3780.0f * a4 * g3),
+                                         A * (1680.0f * a4 * g2 * g2));
+          if (code & 16u) {
+            const int czl = __builtin_amdgcn_readfirstlane(L.CZ[l].x);
+            const int czh = __builtin_amdgcn_readfirstlane(L.CZ[l].y);
+            const float jt = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(f0.y)));
+            wing_slots<P, 5, true, true>(part, kf0, f0, f1, k5a, k5b, 0.f, (float)czl - jt, (float)czh - jt);
+          } else {
+            wing_slots<P, 5, true, false>(part, kf0, f0, f1, k5a, k5b, 0.f);
+          }
           if (((i - o[5]) & 15) == 15) kahan_flush<P>(part, s, cc);
         }
         kahan_flush<P>(part, s, cc);
