@@ -251,6 +251,7 @@ def main():
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus)
         sys.exit(2)
     os.environ.setdefault("HK_TIMING", "1")
+    os.environ.setdefault("HK_AUTOTUNE", "1")  # tile width and LDS line batch timed on the first call
     import torch
 
     import linegen
@@ -351,6 +352,7 @@ def main():
         tv, tc = t2.voigt_ms, t2.core_ms
         ln.release()
         extras[ex] = {"dnu": dnu, "cut": cut, "evals": ne, "core_evals": t2.core_evals, "opacity_s": te,
+                      "tile_width": t2.tile_width, "lines_per_batch": t2.lines_per_batch,
                       "voigt_wing_ms": tv, "voigt_core_ms": tc, "voigt_evals_per_s": ne / ((tv + tc) * 1e-3),
                       "frac_fp32_k_voigt": FLOPS_PER_EVAL * (ne - t2.core_evals) / (tv * 1e-3) / 1e12
                       / PEAK_FP32_TFLOPS}

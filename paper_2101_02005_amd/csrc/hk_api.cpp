@@ -75,8 +75,8 @@ int env_int(const char* name, int dflt) {
 
 struct DevInfo {
   int cus = 0;
-  int wg_per_cu[2] = {1, 1};  // Voigt kernel occupancy for 4 and 8 slots
-  int core_per_cu[2] = {1, 1};  // core kernel (one-wave workgroups) occupancy
+  int wg_per_cu[4][2] = {};   // wing kernel occupancy per (slots 1/2/4/8, line batch 128/256)
+  int core_per_cu[4] = {};    // core kernel (one-wave workgroups) occupancy per slots
 };
 
 std::mutex g_mu;
@@ -127,10 +127,11 @@ hk_status device_init(int* dev_out, DevInfo* info) {
     HK_HIP(hk::upload_weideman(a, L));
     DevInfo di;
     di.cus = prop.multiProcessorCount;
-    di.wg_per_cu[0] = hk::voigt_max_blocks_per_cu(4);
-    di.wg_per_cu[1] = hk::voigt_max_blocks_per_cu(8);
-    di.core_per_cu[0] = hk::core_max_blocks_per_cu(4);
-    di.core_per_cu[1] = hk::core_max_blocks_per_cu(8);
+    for (int si = 0; si < 4; ++si) {
+      di.wg_per_cu[si][0] = hk::voigt_max_blocks_per_cu(1 << si, 128);
+      di.wg_per_cu[si][1] = hk::voigt_max_blocks_per_cu(1 << si, 256);
+      di.core_per_cu[si] = hk::core_max_blocks_per_cu(1 << si);
+    }
     it = g_dev.emplace(dev, di).first;
   }
   *dev_out = dev;
@@ -155,7 +156,7 @@ bool cut_ok(double c) { return c > 0 && (std::isfinite(c) || std::isinf(c)); }
 
 // ------------------------------------------------------------------ forward plan
 struct Plan {
-  int slots = 8, W = 2048;
+  int slots = 4, lb = 256, W = 1024;
   int chunk = 0;
   int n_pairs = 0, n_temps = 0;
   int n_tiles_total = 0;
@@ -174,9 +175,21 @@ struct Plan {
   std::vector<hk_grid> grids;  // distinct grids
 };
 
-int pick_slots() {
-  const int s = env_int("HK_SLOTS", 4);
-  return (s == 4) ? 4 : 8;
+// A tuning of the Voigt passes: slots P (wing tile width 256 P points, core tile 64 P) and
+// the wing pass's LDS line batch.
+struct Tuning {
+  int slots = 4, lb = 256;
+};
+inline int slot_index(int slots) { return slots == 1 ? 0 : slots == 2 ? 1 : slots == 4 ? 2 : 3; }
+const Tuning kCandidates[] = {{1, 256}, {2, 256}, {4, 256}, {8, 256}, {2, 128}, {4, 128}};
+
+// The tuning forced by HK_SLOTS / HK_LB, if any.
+bool env_tuning(Tuning* t) {
+  const int sl = env_int("HK_SLOTS", 0), lb = env_int("HK_LB", 0);
+  if (sl == 0 && lb == 0) return false;
+  t->slots = (sl == 1 || sl == 2 || sl == 4 || sl == 8) ? sl : 4;
+  t->lb = (lb == 128) ? 128 : 256;
+  return true;
 }
 
 // Tiles a line can be counted in: windows [nu_j0 - cut, nu_j1 + cut] widened by two bins.
@@ -189,8 +202,10 @@ int64_t visits_per_line(const hk_lines* L, const hk_grid& g, double cut, int W, 
 }
 
 hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const double* T, const double* P,
-                    const hk_grid* grids, const int64_t* out_off, double cut, const DevInfo& di, Plan* pl) {
-  pl->slots = pick_slots();
+                    const hk_grid* grids, const int64_t* out_off, double cut, const DevInfo& di, Tuning tu,
+                    Plan* pl) {
+  pl->slots = tu.slots;
+  pl->lb = tu.lb;
   pl->W = hk::kWavesPerWG * hk::kWave * pl->slots;
   pl->n_pairs = n_pairs;
   const int64_t N = L->N;
@@ -259,7 +274,7 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   pl->n_tiles_total = (int)tiles;
   pl->n_tiles_c = (int)tiles_c;
   // work-item size: enough items to balance the persistent grid
-  const int wgs = di.cus * di.wg_per_cu[pl->slots == 8 ? 1 : 0];
+  const int wgs = di.cus * di.wg_per_cu[slot_index(pl->slots)][pl->lb == 256 ? 1 : 0];
   double c = std::ceil(visits / (64.0 * (wgs > 0 ? wgs : 1024)));
   const int env_chunk = env_int("HK_CHUNK", 0);
   if (env_chunk > 0) c = env_chunk;
@@ -273,7 +288,7 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   if (items_c >= 2.0e9) return fail(HK_ENOMEM, "core work list too large (%.3g items)", items_c);
   pl->items_bound_c = (int64_t)items_c;
   pl->grid = (int)std::min<int64_t>(pl->items_bound, (int64_t)(wgs > 0 ? wgs : 1024));
-  const int wgs_c = di.cus * di.core_per_cu[pl->slots == 8 ? 1 : 0];
+  const int wgs_c = di.cus * di.core_per_cu[slot_index(pl->slots)];
   pl->grid_c = (int)std::max<int64_t>(1, std::min<int64_t>(pl->items_bound_c, (int64_t)(wgs_c > 0 ? wgs_c : 4096)));
   // workspace layout (256-byte aligned sections)
   size_t off = 0;
@@ -422,7 +437,7 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   va.items_cap = (int32_t)std::min<int64_t>(pl.items_bound, INT32_MAX);
   long long* stats = reinterpret_cast<long long*>(ws + pl.off_stats);
   va.stats = tm.on ? stats : nullptr;
-  HK_HIP(hk::launch_voigt(va, pl.slots, pl.grid, st));
+  HK_HIP(hk::launch_voigt(va, pl.slots, pl.lb, pl.grid, st));
   tm.mark();
   HK_HIP(hk::launch_combine(va, pl.slots, st));
   tm.mark();
@@ -457,7 +472,7 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
     g_tim.core_evals = t;
   }
   g_tim.tile_width = pl.W;
-  g_tim.lines_per_batch = hk::kLB;
+  g_tim.lines_per_batch = pl.lb;
   g_tim.chunk_lines = pl.chunk;
   g_tim.n_items = (int32_t)pl.items_bound;
   return HK_OK;
@@ -468,6 +483,64 @@ hk_status check_lines(const hk_lines* L) {
   int dev = -1;
   HK_HIP(hipGetDevice(&dev));
   if (dev != L->device) return fail(HK_EINVAL, "current device %d differs from the handle's device %d", dev, L->device);
+  return HK_OK;
+}
+
+// Tuning for a call: forced by the environment, else the cached autotuner choice for this
+// key, else (HK_AUTOTUNE=1) timed now over the candidates on the caller's data, else default.
+// Autotuning runs the forward path once per candidate on `stream` and synchronizes.
+std::mutex g_tune_mu;
+std::map<std::string, Tuning> g_tune;
+
+std::string tune_key(const hk_lines* L, int n_pairs, const double* T, const hk_grid* grids, double cut) {
+  std::string key;
+  auto put = [&](const void* p, size_t n) { key.append(static_cast<const char*>(p), n); };
+  put(&L->N, sizeof L->N);
+  put(&L->device, sizeof L->device);
+  put(&n_pairs, sizeof n_pairs);
+  put(&cut, sizeof cut);
+  int64_t pts = 0;
+  for (int p = 0; p < n_pairs; ++p) pts += grids[p].n;
+  put(&pts, sizeof pts);
+  put(&grids[0].dnu, sizeof(double));
+  (void)T;  // the choice depends on the list, the grids and the cut, not on the exact (T, P)
+  return key;
+}
+
+hk_status choose_tuning(const hk_lines* L, const hk_line_override* ovr, int n_pairs, const double* T,
+                        const double* P, const hk_grid* grids, const int64_t* out_off, double cut, float* k,
+                        char* ws, size_t ws_bytes, hipStream_t st, const DevInfo& di, Tuning* out) {
+  if (env_tuning(out)) return HK_OK;
+  const std::string key = tune_key(L, n_pairs, T, grids, cut);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) { *out = it->second; return HK_OK; }
+  }
+  *out = Tuning{};
+  if (!env_flag("HK_AUTOTUNE", false)) return HK_OK;
+  float best_ms = 0.0f;
+  bool have = false;
+  hipEvent_t e0, e1;
+  HK_HIP(hipEventCreate(&e0));
+  HK_HIP(hipEventCreate(&e1));
+  for (const Tuning& tu : kCandidates) {
+    Plan pl;
+    hk_status s = make_plan(L, n_pairs, n_pairs, T, P, grids, out_off, cut, di, tu, &pl);
+    if (s != HK_OK || pl.total > ws_bytes) continue;
+    HK_HIP(hipEventRecord(e0, st));
+    s = run_forward(L, ovr, pl, cut, k, ws, st, false);
+    if (s != HK_OK) return s;
+    HK_HIP(hipEventRecord(e1, st));
+    HK_HIP(hipEventSynchronize(e1));
+    float ms = 0.0f;
+    HK_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (!have || ms < best_ms) { best_ms = ms; *out = tu; have = true; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = *out;
   return HK_OK;
 }
 
@@ -629,10 +702,15 @@ hk_status hk_workspace_size(const hk_lines* lines, int mode, int32_t n_pairs, in
     *bytes = backward_layout(lines->N).total;
     return HK_OK;
   }
-  Plan pl;
-  s = make_plan(lines, n_pairs, n_temps, nullptr, nullptr, grids, nullptr, cutoff, di, &pl);
-  if (s != HK_OK) return s;
-  *bytes = pl.total;
+  // enough for every tuning the autotuner may pick
+  size_t best = 0;
+  for (const Tuning& tu : kCandidates) {
+    Plan pl;
+    s = make_plan(lines, n_pairs, n_temps, nullptr, nullptr, grids, nullptr, cutoff, di, tu, &pl);
+    if (s != HK_OK) return s;
+    best = std::max(best, pl.total);
+  }
+  *bytes = best;
   return HK_OK;
 }
 
@@ -650,9 +728,13 @@ hk_status hk_opacity(const hk_lines* lines, const hk_line_override* ovr, double 
   DevInfo di;
   s = device_init(&dev, &di);
   if (s != HK_OK) return s;
-  Plan pl;
   const int64_t zero = 0;
-  s = make_plan(lines, 1, 1, &T, &P_atm, &grid, &zero, cutoff, di, &pl);
+  Tuning tu;
+  s = choose_tuning(lines, ovr, 1, &T, &P_atm, &grid, &zero, cutoff, k, static_cast<char*>(ws), ws_bytes, stream, di,
+                    &tu);
+  if (s != HK_OK) return s;
+  Plan pl;
+  s = make_plan(lines, 1, 1, &T, &P_atm, &grid, &zero, cutoff, di, tu, &pl);
   if (s != HK_OK) return s;
   if (ws_bytes < pl.total) return fail(HK_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, pl.total);
   return run_forward(lines, ovr, pl, cutoff, k, static_cast<char*>(ws), stream);
@@ -686,8 +768,12 @@ hk_status hk_opacity_batched(const hk_lines* lines, int32_t n_pairs, const doubl
   DevInfo di;
   s = device_init(&dev, &di);
   if (s != HK_OK) return s;
+  Tuning tu;
+  s = choose_tuning(lines, nullptr, n_pairs, T, P_atm, grids, out_offset, cutoff, k, static_cast<char*>(ws), ws_bytes,
+                    stream, di, &tu);
+  if (s != HK_OK) return s;
   Plan pl;
-  s = make_plan(lines, n_pairs, n_pairs, T, P_atm, grids, out_offset, cutoff, di, &pl);
+  s = make_plan(lines, n_pairs, n_pairs, T, P_atm, grids, out_offset, cutoff, di, tu, &pl);
   if (s != HK_OK) return s;
   if (ws_bytes < pl.total) return fail(HK_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, pl.total);
   if (!env_flag("HK_GRAPH", true))
@@ -701,6 +787,7 @@ hk_status hk_opacity_batched(const hk_lines* lines, int32_t n_pairs, const doubl
   put(&cutoff, sizeof cutoff);
   put(&n_pairs, sizeof n_pairs);
   put(&pl.slots, sizeof pl.slots);
+  put(&pl.lb, sizeof pl.lb);
   put(&pl.chunk, sizeof pl.chunk);
   put(T, sizeof(double) * n_pairs);
   put(P_atm, sizeof(double) * n_pairs);
@@ -745,7 +832,7 @@ hk_status hk_opacity_batched(const hk_lines* lines, int32_t n_pairs, const doubl
   g_tim.core_ms = -1;
   g_tim.core_evals = -1;
   g_tim.tile_width = pl.W;
-  g_tim.lines_per_batch = hk::kLB;
+  g_tim.lines_per_batch = pl.lb;
   g_tim.chunk_lines = pl.chunk;
   g_tim.n_items = (int32_t)pl.items_bound;
   return HK_OK;

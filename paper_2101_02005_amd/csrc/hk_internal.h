@@ -9,7 +9,7 @@ namespace hk {
 constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kThreads = 256;    // threads per workgroup of the Voigt and sort kernels
 constexpr int kWavesPerWG = kThreads / kWave;
-constexpr int kLB = 256;         // lines staged in LDS per batch (one per thread)
+constexpr int kLB = 256;         // largest LDS line batch of the wing pass (one line per thread)
 constexpr int kKmax = 5;         // highest order of the far-wing series
 constexpr int kWeidN = 20;       // terms of the FP64 core rational approximation
 constexpr int kKeyBits = 24;     // linear wavenumber-bin key width
@@ -119,7 +119,7 @@ hipError_t launch_item_scan(const int32_t* nc, int n_tiles_total, int32_t* item_
                             hipStream_t st);
 hipError_t launch_gridrec(const double* nu, int64_t N, double nu_start, double dnu, int64_t n, double cut,
                           int4* grec, hipStream_t st);
-hipError_t launch_voigt(const VoigtArgs& a, int slots, int grid, hipStream_t st);
+hipError_t launch_voigt(const VoigtArgs& a, int slots, int lb, int grid, hipStream_t st);
 hipError_t launch_core(const VoigtArgs& a, int slots, int grid, hipStream_t st);
 hipError_t launch_combine(const VoigtArgs& a, int slots, hipStream_t st);
 hipError_t launch_combine_core(const VoigtArgs& a, int slots, hipStream_t st);
@@ -129,7 +129,7 @@ hipError_t launch_cut_bounds(const double* nu, const int32_t* perm, int64_t N, d
 hipError_t launch_adjoint(const AdjArgs& a, int grid, hipStream_t st);
 hipError_t launch_reduce2(const double* contrib, int64_t N, double* partial, int n_partial, double* out,
                           hipStream_t st);
-int voigt_max_blocks_per_cu(int slots);
+int voigt_max_blocks_per_cu(int slots, int lb);
 int core_max_blocks_per_cu(int slots);
 hipError_t upload_weideman(const double* coef, double L);
 

@@ -412,16 +412,16 @@ __global__ __launch_bounds__(kThreads) void k_gridrec(const double* __restrict__
 //            not reach the wave), bit 3 some lanes fall outside the cut range, bit 4 some of
 //            its points are core points
 //   list[w]: the staged lines reaching wave w, grouped by series order (see line_group)
-template <int P>
+template <int LB>
 struct LineLDS {
-  float4 F0[kLB];
-  float4 F1[kLB];
-  float4 KA[kLB];   // c1, c2(K=2), c2(K>=3), c3(K=3)
-  float4 KB[kLB];   // c4(K=3), c3(K=4), c4(K=4), c5(K=4)
-  float KC[kLB];    // c6(K=4)
-  int2 CZ[kLB];
-  uint4 code[kLB];  // component w: the code word of wave w
-  uint8_t list[kWavesPerWG][kLB];
+  float4 F0[LB];
+  float4 F1[LB];
+  float4 KA[LB];   // c1, c2(K=2), c2(K>=3), c3(K=3)
+  float4 KB[LB];   // c4(K=3), c3(K=4), c4(K=4), c5(K=4)
+  float KC[LB];    // c6(K=4)
+  int2 CZ[LB];
+  uint4 code[LB];  // component w: the code word of wave w
+  uint8_t list[kWavesPerWG][LB];
 };
 
 // Far-wing series of the Voigt profile in q = 1/(D^2 + gamma^2), from the asymptotic
@@ -484,8 +484,8 @@ __device__ __forceinline__ bool core_rel(float alpha, float gam, float delta, fl
 // tile keep code 0 for every wave. Every decision that needs FP64 (cut bounds, reference
 // point, offset) is already in the grid record; the rest needs ~1e-7 and is done in FP32
 // (products ordered so that no intermediate underflows for relevant lines).
-template <int P>
-__device__ __forceinline__ void stage_line(LineLDS<P>& L, int tid, const int4 gr, double nu0, float S, float gTv,
+template <int P, int LB>
+__device__ __forceinline__ void stage_line(LineLDS<LB>& L, int tid, const int4 gr, double nu0, float S, float gTv,
                                            const PairDesc& pd, const float* zK, int64_t tile0,
                                            uint32_t (&codes)[kWavesPerWG]) {
   constexpr int W = kWavesPerWG * kWave * P;
@@ -620,8 +620,8 @@ __device__ __forceinline__ int line_group(uint32_t code) {
 // Per-wave wing loop over the lines of one group (all unmasked, no core slots). Lines go in
 // blocks of 16 with a compensated flush after each block (and after a partial last block);
 // the list is read four entries at a time into a scalar register.
-template <int P, int K, bool MASK>
-__device__ __forceinline__ void wing_line(const LineLDS<P>& L, int l, float jl0, float (&part)[P]) {
+template <int P, int LB, int K, bool MASK>
+__device__ __forceinline__ void wing_line(const LineLDS<LB>& L, int l, float jl0, float (&part)[P]) {
   const float4 f0 = L.F0[l];
   const float4 f1 = L.F1[l];
   float4 ka = make_float4(0.f, 0.f, 0.f, 0.f), kb = ka;
@@ -632,36 +632,36 @@ __device__ __forceinline__ void wing_line(const LineLDS<P>& L, int l, float jl0,
   wing_slots<P, K, MASK, false>(part, jl0 - f0.y, f0, f1, ka, kb, kc);
 }
 
-template <int P, int K, bool MASK>
-__device__ __forceinline__ void group_loop(const LineLDS<P>& L, int wv, int i0, int i1, float jl0, float (&part)[P],
+template <int P, int LB, int K, bool MASK>
+__device__ __forceinline__ void group_loop(const LineLDS<LB>& L, int wv, int i0, int i1, float jl0, float (&part)[P],
                                            float (&s)[P], float (&cc)[P]) {
   if (i0 >= i1) return;
   int i = i0;
   // unaligned head: single entries up to a multiple of 4
   for (; i < i1 && (i & 3); ++i)
-    wing_line<P, K, MASK>(L, __builtin_amdgcn_readfirstlane((int)L.list[wv][i]), jl0, part);
+    wing_line<P, LB, K, MASK>(L, __builtin_amdgcn_readfirstlane((int)L.list[wv][i]), jl0, part);
   int since = 0;
   for (; i + 4 <= i1; i += 4) {
     const uint32_t w4 = (uint32_t)__builtin_amdgcn_readfirstlane(
         (int)*reinterpret_cast<const uint32_t*>(&L.list[wv][i]));
-    wing_line<P, K, MASK>(L, (int)(w4 & 255u), jl0, part);
-    wing_line<P, K, MASK>(L, (int)((w4 >> 8) & 255u), jl0, part);
-    wing_line<P, K, MASK>(L, (int)((w4 >> 16) & 255u), jl0, part);
-    wing_line<P, K, MASK>(L, (int)(w4 >> 24), jl0, part);
+    wing_line<P, LB, K, MASK>(L, (int)(w4 & 255u), jl0, part);
+    wing_line<P, LB, K, MASK>(L, (int)((w4 >> 8) & 255u), jl0, part);
+    wing_line<P, LB, K, MASK>(L, (int)((w4 >> 16) & 255u), jl0, part);
+    wing_line<P, LB, K, MASK>(L, (int)(w4 >> 24), jl0, part);
     since += 4;
     if (since == 16) {
       kahan_flush<P>(part, s, cc);
       since = 0;
     }
   }
-  for (; i < i1; ++i) wing_line<P, K, MASK>(L, __builtin_amdgcn_readfirstlane((int)L.list[wv][i]), jl0, part);
+  for (; i < i1; ++i) wing_line<P, LB, K, MASK>(L, __builtin_amdgcn_readfirstlane((int)L.list[wv][i]), jl0, part);
   kahan_flush<P>(part, s, cc);
 }
 
-template <int P>
+template <int P, int LB>
 __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
   constexpr int W = kWavesPerWG * kWave * P;  // tile width in grid points
-  __shared__ LineLDS<P> L;
+  __shared__ LineLDS<LB> L;
   __shared__ int sItem, sTile, sPair;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
@@ -707,13 +707,14 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
       cc[p] = 0.0f;
       part[p] = 0.0f;
     }
-    for (int64_t b = line_lo; b < line_hi; b += kLB) {
+    for (int64_t b = line_lo; b < line_hi; b += LB) {
       // ---- stage one batch of lines: one thread per line
       {
         const int64_t li = b + tid;
         uint32_t codes[kWavesPerWG] = {0u, 0u, 0u, 0u};
-        if (li < line_hi) stage_line<P>(L, tid, grec[li], a.nu[li], S_T[li], gT[li], pd, a.zK, tile0, codes);
-        L.code[tid] = make_uint4(codes[0], codes[1], codes[2], codes[3]);
+        if (tid < LB && li < line_hi)
+          stage_line<P, LB>(L, tid, grec[li], a.nu[li], S_T[li], gT[li], pd, a.zK, tile0, codes);
+        if (tid < LB) L.code[tid] = make_uint4(codes[0], codes[1], codes[2], codes[3]);
       }
       __syncthreads();
       // ---- this wave's list of the staged lines that reach it, grouped by series order and in
@@ -721,12 +722,12 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
       int o[kGroups + 2];
       {
         const uint32_t* code_w = reinterpret_cast<const uint32_t*>(L.code) + wv;
-        int grp[kLB / kWave];
+        int grp[LB / kWave];
         int cnt[kGroups + 1];
 #pragma unroll
         for (int gg = 0; gg <= kGroups; ++gg) cnt[gg] = 0;
 #pragma unroll
-        for (int r = 0; r < kLB / kWave; ++r) {
+        for (int r = 0; r < LB / kWave; ++r) {
           grp[r] = line_group(code_w[4 * (r * kWave + lane)]);
 #pragma unroll
           for (int gg = 1; gg <= kGroups; ++gg) cnt[gg] += (int)__popcll(__ballot(grp[r] == gg));
@@ -738,7 +739,7 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
 #pragma unroll
         for (int gg = 1; gg <= kGroups; ++gg) st[gg] = o[gg];
 #pragma unroll
-        for (int r = 0; r < kLB / kWave; ++r) {
+        for (int r = 0; r < LB / kWave; ++r) {
 #pragma unroll
           for (int gg = 1; gg <= kGroups; ++gg) {
             const uint64_t m = __ballot(grp[r] == gg);
@@ -750,14 +751,14 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
 
       // ---- accumulate: fast groups, then the general group
       {
-        group_loop<P, 1, false>(L, wv, o[1], o[2], jl0, part, s, cc);
-        group_loop<P, 2, false>(L, wv, o[2], o[3], jl0, part, s, cc);
-        group_loop<P, 3, false>(L, wv, o[3], o[4], jl0, part, s, cc);
-        group_loop<P, 4, false>(L, wv, o[4], o[5], jl0, part, s, cc);
-        group_loop<P, 1, true>(L, wv, o[6], o[7], jl0, part, s, cc);
-        group_loop<P, 2, true>(L, wv, o[7], o[8], jl0, part, s, cc);
-        group_loop<P, 3, true>(L, wv, o[8], o[9], jl0, part, s, cc);
-        group_loop<P, 4, true>(L, wv, o[9], o[10], jl0, part, s, cc);
+        group_loop<P, LB, 1, false>(L, wv, o[1], o[2], jl0, part, s, cc);
+        group_loop<P, LB, 2, false>(L, wv, o[2], o[3], jl0, part, s, cc);
+        group_loop<P, LB, 3, false>(L, wv, o[3], o[4], jl0, part, s, cc);
+        group_loop<P, LB, 4, false>(L, wv, o[4], o[5], jl0, part, s, cc);
+        group_loop<P, LB, 1, true>(L, wv, o[6], o[7], jl0, part, s, cc);
+        group_loop<P, LB, 2, true>(L, wv, o[7], o[8], jl0, part, s, cc);
+        group_loop<P, LB, 3, true>(L, wv, o[8], o[9], jl0, part, s, cc);
+        group_loop<P, LB, 4, true>(L, wv, o[9], o[10], jl0, part, s, cc);
         // general group: order 5, possibly lanes outside the cut and core points to skip
         for (int i = o[5]; i < o[6]; ++i) {
           const int l = __builtin_amdgcn_readfirstlane((int)L.list[wv][i]);
@@ -1333,34 +1334,73 @@ hipError_t launch_gridrec(const double* nu, int64_t N, double nu_start, double d
   return hipGetLastError();
 }
 
-hipError_t launch_voigt(const VoigtArgs& a, int slots, int grid, hipStream_t st) {
-  if (slots == 8) hipLaunchKernelGGL(k_voigt<8>, dim3(grid), dim3(kThreads), 0, st, a);
-  else if (slots == 4) hipLaunchKernelGGL(k_voigt<4>, dim3(grid), dim3(kThreads), 0, st, a);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
+// Tunings: P (64-point slots per lane group; tile width 256 P) in {1, 2, 4, 8} and the LDS
+// line batch LB in {128, 256} of the wing pass.
+template <template <int> class F, typename... A>
+static hipError_t by_slots(int slots, A... args) {
+  switch (slots) {
+    case 1: return F<1>::run(args...);
+    case 2: return F<2>::run(args...);
+    case 4: return F<4>::run(args...);
+    case 8: return F<8>::run(args...);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int P>
+struct VoigtL {
+  static hipError_t run(const VoigtArgs& a, int lb, int grid, hipStream_t st) {
+    if (lb == 256) hipLaunchKernelGGL((k_voigt<P, 256>), dim3(grid), dim3(kThreads), 0, st, a);
+    else if (lb == 128) hipLaunchKernelGGL((k_voigt<P, 128>), dim3(grid), dim3(kThreads), 0, st, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+  }
+};
+template <int P>
+struct CoreL {
+  static hipError_t run(const VoigtArgs& a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_core<P>, dim3(grid), dim3(kWave), 0, st, a);
+    return hipGetLastError();
+  }
+};
+template <int P>
+struct CombineL {
+  static hipError_t run(const VoigtArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_combine<P>, dim3((unsigned)a.n_tiles_total), dim3(kThreads), 0, st, a);
+    return hipGetLastError();
+  }
+};
+template <int P>
+struct CombineCoreL {
+  static hipError_t run(const VoigtArgs& a, hipStream_t st) {
+    hipLaunchKernelGGL(k_combine_core<P>, dim3((unsigned)a.n_tiles_total), dim3(kThreads), 0, st, a);
+    return hipGetLastError();
+  }
+};
+template <int P>
+struct VoigtOcc {
+  static hipError_t run(int lb, int* nb) {
+    if (lb == 256) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_voigt<P, 256>, kThreads, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_voigt<P, 128>, kThreads, 0);
+  }
+};
+template <int P>
+struct CoreOcc {
+  static hipError_t run(int* nb) { return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_core<P>, kWave, 0); }
+};
+
+hipError_t launch_voigt(const VoigtArgs& a, int slots, int lb, int grid, hipStream_t st) {
+  return by_slots<VoigtL>(slots, a, lb, grid, st);
 }
 
 hipError_t launch_core(const VoigtArgs& a, int slots, int grid, hipStream_t st) {
-  if (slots == 8) hipLaunchKernelGGL(k_core<8>, dim3(grid), dim3(kWave), 0, st, a);
-  else if (slots == 4) hipLaunchKernelGGL(k_core<4>, dim3(grid), dim3(kWave), 0, st, a);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
+  return by_slots<CoreL>(slots, a, grid, st);
 }
 
-hipError_t launch_combine(const VoigtArgs& a, int slots, hipStream_t st) {
-  dim3 grid((unsigned)a.n_tiles_total);
-  if (slots == 8) hipLaunchKernelGGL(k_combine<8>, grid, dim3(kThreads), 0, st, a);
-  else if (slots == 4) hipLaunchKernelGGL(k_combine<4>, grid, dim3(kThreads), 0, st, a);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
-}
+hipError_t launch_combine(const VoigtArgs& a, int slots, hipStream_t st) { return by_slots<CombineL>(slots, a, st); }
 
 hipError_t launch_combine_core(const VoigtArgs& a, int slots, hipStream_t st) {
-  dim3 grid((unsigned)a.n_tiles_total);
-  if (slots == 8) hipLaunchKernelGGL(k_combine_core<8>, grid, dim3(kThreads), 0, st, a);
-  else if (slots == 4) hipLaunchKernelGGL(k_combine_core<4>, grid, dim3(kThreads), 0, st, a);
-  else return hipErrorInvalidValue;
-  return hipGetLastError();
+  return by_slots<CombineCoreL>(slots, a, st);
 }
 
 hipError_t launch_cut_bounds(const double* nu, const int32_t* perm, int64_t N, double nu_start, double dnu,
@@ -1384,15 +1424,13 @@ hipError_t launch_reduce2(const double* contrib, int64_t N, double* partial, int
 
 int core_max_blocks_per_cu(int slots) {
   int nb = 0;
-  if (slots == 8) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_core<8>, kWave, 0);
-  else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_core<4>, kWave, 0);
+  (void)by_slots<CoreOcc>(slots, &nb);
   return nb > 0 ? nb : 1;
 }
 
-int voigt_max_blocks_per_cu(int slots) {
+int voigt_max_blocks_per_cu(int slots, int lb) {
   int nb = 0;
-  if (slots == 8) (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_voigt<8>, kThreads, 0);
-  else (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_voigt<4>, kThreads, 0);
+  (void)by_slots<VoigtOcc>(slots, lb, &nb);
   return nb > 0 ? nb : 1;
 }
 
