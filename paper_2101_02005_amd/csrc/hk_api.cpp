@@ -583,7 +583,7 @@ hk_status hk_prepare_lines(const double* nu, const double* S_ref, const double* 
   const int64_t G = (N + hk::kSortBlock - 1) / hk::kSortBlock;
   off = 0;
   const size_t t_k = take(4 * N), t_v = take(4 * N), t_h = take(4 * 256 * (size_t)G), t_d = take(4 * 256),
-               t_mm = take(16), t_f = take(16);
+               t_mm = take(16), t_f = take(16), t_r = take(40 * N);
   const size_t tbytes = off;
   std::unique_ptr<hk_lines> L(new hk_lines());
   L->device = dev;
@@ -611,6 +611,7 @@ hk_status hk_prepare_lines(const double* nu, const double* S_ref, const double* 
   uint32_t* dtot = reinterpret_cast<uint32_t*>(tmp + t_d);
   unsigned long long* mm = reinterpret_cast<unsigned long long*>(tmp + t_mm);
   int* flags = reinterpret_cast<int*>(tmp + t_f);
+  double* rec = reinterpret_cast<double*>(tmp + t_r);
   auto cleanup_fail = [&](hk_status st, const char* what, hipError_t e) {
     (void)hipStreamSynchronize(stream);
     (void)hipFree(tmp);
@@ -640,12 +641,12 @@ hk_status hk_prepare_lines(const double* nu, const double* S_ref, const double* 
   L->km.scale = vmax > vmin ? (double)L->km.kmax / (vmax - vmin) : 0.0;
   L->km.pad = 0;
   // keys -> stable LSD radix sort (3 passes of 8 bits; ping-pong ends in the handle arrays)
-  e = hk::launch_keys(nu, N, L->km, kA, vA, stream);
+  e = hk::launch_keys(nu, S_ref, E_low, gamma_ref, n_exp, N, L->km, kA, vA, rec, stream);
   if (e == hipSuccess) e = hk::launch_radix_pass(kA, vA, L->keys, L->perm, N, 0, hist, dtot, stream);
   if (e == hipSuccess) e = hk::launch_radix_pass(L->keys, L->perm, kA, vA, N, 8, hist, dtot, stream);
   if (e == hipSuccess) e = hk::launch_radix_pass(kA, vA, L->keys, L->perm, N, 16, hist, dtot, stream);
   if (e == hipSuccess)
-    e = hk::launch_gather(L->perm, N, nu, S_ref, E_low, gamma_ref, n_exp, L->nu, L->Sref, L->E, L->gref, L->nexp, stream);
+    e = hk::launch_gather(L->perm, N, rec, L->nu, L->Sref, L->E, L->gref, L->nexp, stream);
   tm.mark();
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return cleanup_fail(HK_EDEVICE, "binning", e);

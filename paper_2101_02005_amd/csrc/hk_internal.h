@@ -101,13 +101,12 @@ struct AdjArgs {
 hipError_t launch_validate(const double* nu, const double* S, const double* E, const double* g,
                            const double* n, int64_t N, unsigned long long* mm, int* flags,
                            hipStream_t st);
-hipError_t launch_keys(const double* nu, int64_t N, KeyMap km, uint32_t* keys, int32_t* vals,
-                       hipStream_t st);
+hipError_t launch_keys(const double* nu, const double* S, const double* E, const double* g, const double* n,
+                       int64_t N, KeyMap km, uint32_t* keys, int32_t* vals, double* rec, hipStream_t st);
 hipError_t launch_radix_pass(const uint32_t* kin, const int32_t* vin, uint32_t* kout, int32_t* vout,
                              int64_t N, int shift, uint32_t* hist, uint32_t* dig_tot, hipStream_t st);
-hipError_t launch_gather(const int32_t* perm, int64_t N, const double* nu, const double* S,
-                         const double* E, const double* g, const double* n, double* onu, double* oS,
-                         double* oE, double* og, double* on, hipStream_t st);
+hipError_t launch_gather(const int32_t* perm, int64_t N, const double* rec, double* onu, double* oS, double* oE,
+                         double* og, double* on, hipStream_t st);
 hipError_t launch_prep(const PrepArgs& a, float* S_T, float* gT, double* S64, double* a64, double* g64,
                        hipStream_t st);
 hipError_t launch_fill_pairs(const PairDesc* host_pairs, int count, PairDesc* dst, hipStream_t st);

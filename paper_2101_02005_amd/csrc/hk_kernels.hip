@@ -98,12 +98,22 @@ __global__ __launch_bounds__(kThreads) void k_validate(const double* __restrict_
   }
 }
 
-__global__ void k_keys(const double* __restrict__ nu, int64_t N, KeyMap km, uint32_t* __restrict__ keys,
-                       int32_t* __restrict__ vals) {
+// Bin keys, identity values, and a record-per-line copy of the five fields (so that the
+// gather after the sort reads one record, not five scattered words, per line).
+__global__ void k_keys(const double* __restrict__ nu, const double* __restrict__ S, const double* __restrict__ E,
+                       const double* __restrict__ g, const double* __restrict__ n, int64_t N, KeyMap km,
+                       uint32_t* __restrict__ keys, int32_t* __restrict__ vals, double* __restrict__ rec) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  keys[i] = bin_key(nu[i], km);
+  const double v = nu[i];
+  keys[i] = bin_key(v, km);
   vals[i] = (int32_t)i;
+  double* r = rec + 5 * i;
+  r[0] = v;
+  r[1] = S[i];
+  r[2] = E[i];
+  r[3] = g[i];
+  r[4] = n[i];
 }
 
 // Per-block digit histogram: hist[d * G + b].
@@ -150,24 +160,48 @@ __global__ __launch_bounds__(1024) void k_radix_scan(uint32_t* __restrict__ hist
 }
 
 // Stable scatter: keys of block b keep their order within each digit.
+// Stable scatter of one 8-bit digit: each block orders its keys by digit in LDS (ranks from
+// wave ballots, waves and rounds in index order), then writes every digit's run to its global
+// place with consecutive threads on consecutive addresses.
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __restrict__ kin,
     const int32_t* __restrict__ vin, uint32_t* __restrict__ kout, int32_t* __restrict__ vout, int64_t N,
     int shift, const uint32_t* __restrict__ hist, const uint32_t* __restrict__ dig_tot) {
-  __shared__ uint32_t base[256];
+  __shared__ uint32_t sk[kSortBlock];
+  __shared__ int32_t sv[kSortBlock];
+  __shared__ uint32_t gbase[256];   // global start of this block's run of digit d
+  __shared__ uint32_t lstart[256];  // start of digit d in the block's ordered keys
+  __shared__ uint32_t run[256];     // keys of digit d placed so far
   __shared__ uint32_t wcnt[kWavesPerWG][256];
   __shared__ uint32_t scan[256];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  // digit start = (sum of smaller digits' totals) + (this block's offset inside the digit)
+  // hist holds, per digit, the exclusive scan of the blocks' counts (this block's offset inside
+  // the digit); this block's own count is the difference to the next block's offset
+  const int64_t hb = (int64_t)tid * gridDim.x + blockIdx.x;
+  const uint32_t boff = hist[hb];
+  const uint32_t mine = (blockIdx.x + 1 < gridDim.x ? hist[hb + 1] : dig_tot[tid]) - boff;
+  // global digit starts: scan over digit totals, plus this block's offset inside the digit
   scan[tid] = dig_tot[tid];
-  for (int i = 0; i < kWavesPerWG; ++i) wcnt[i][tid] = 0;
   __syncthreads();
   for (int off = 1; off < 256; off <<= 1) {
-    uint32_t t = tid >= off ? scan[tid - off] : 0u;
+    const uint32_t t = tid >= off ? scan[tid - off] : 0u;
     __syncthreads();
     scan[tid] += t;
     __syncthreads();
   }
-  base[tid] = scan[tid] - dig_tot[tid] + hist[(int64_t)tid * gridDim.x + blockIdx.x];
+  gbase[tid] = scan[tid] - dig_tot[tid] + boff;
+  __syncthreads();
+  // local digit starts: scan of this block's counts
+  scan[tid] = mine;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t t = tid >= off ? scan[tid - off] : 0u;
+    __syncthreads();
+    scan[tid] += t;
+    __syncthreads();
+  }
+  lstart[tid] = scan[tid] - mine;
+  run[tid] = 0;
+  for (int i = 0; i < kWavesPerWG; ++i) wcnt[i][tid] = 0;
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t b0 = (int64_t)blockIdx.x * kSortBlock;
@@ -175,6 +209,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
     const int64_t i = b0 + (int64_t)r * kThreads + tid;
     const bool valid = i < N;
     const uint32_t key = valid ? kin[i] : 0u;
+    const int32_t val = valid ? vin[i] : 0;
     const uint32_t d = (key >> shift) & 255u;
     uint64_t peers = __ballot(valid);
     for (int bit = 0; bit < 8; ++bit) {
@@ -186,33 +221,39 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
     if (valid && rank == 0) wcnt[wv][d] = (uint32_t)__popcll(peers);
     __syncthreads();
     if (valid) {
-      uint32_t o = base[d] + rank;
+      uint32_t o = lstart[d] + run[d] + rank;
       for (int w = 0; w < wv; ++w) o += wcnt[w][d];
-      kout[o] = key;
-      vout[o] = vin[i];
+      sk[o] = key;
+      sv[o] = val;
     }
     uint32_t add = 0;
     for (int w = 0; w < kWavesPerWG; ++w) add += wcnt[w][tid];
     __syncthreads();
-    base[tid] += add;
+    run[tid] += add;
     for (int w = 0; w < kWavesPerWG; ++w) wcnt[w][tid] = 0;
     __syncthreads();
   }
+  const int nvalid = (int)((N - b0) < kSortBlock ? (N - b0) : kSortBlock);
+  for (int j = tid; j < nvalid; j += kThreads) {
+    const uint32_t key = sk[j];
+    const uint32_t d = (key >> shift) & 255u;
+    const uint32_t o = gbase[d] + ((uint32_t)j - lstart[d]);
+    kout[o] = key;
+    vout[o] = sv[j];
+  }
 }
 
-__global__ void k_gather(const int32_t* __restrict__ perm, int64_t N, const double* __restrict__ nu,
-                         const double* __restrict__ S, const double* __restrict__ E,
-                         const double* __restrict__ g, const double* __restrict__ n,
+__global__ void k_gather(const int32_t* __restrict__ perm, int64_t N, const double* __restrict__ rec,
                          double* __restrict__ onu, double* __restrict__ oS, double* __restrict__ oE,
                          double* __restrict__ og, double* __restrict__ on) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  const int32_t s = perm[i];
-  onu[i] = nu[s];
-  oS[i] = S[s];
-  oE[i] = E[s];
-  og[i] = g[s];
-  on[i] = n[s];
+  const double* r = rec + 5 * (int64_t)perm[i];
+  onu[i] = r[0];
+  oS[i] = r[1];
+  oE[i] = r[2];
+  og[i] = r[3];
+  on[i] = r[4];
 }
 
 // ---------------------------------------------------------------------------- prep
@@ -1273,8 +1314,10 @@ hipError_t launch_validate(const double* nu, const double* S, const double* E, c
   return hipGetLastError();
 }
 
-hipError_t launch_keys(const double* nu, int64_t N, KeyMap km, uint32_t* keys, int32_t* vals, hipStream_t st) {
-  hipLaunchKernelGGL(k_keys, dim3(blocks_for(N, kThreads)), dim3(kThreads), 0, st, nu, N, km, keys, vals);
+hipError_t launch_keys(const double* nu, const double* S, const double* E, const double* g, const double* n,
+                       int64_t N, KeyMap km, uint32_t* keys, int32_t* vals, double* rec, hipStream_t st) {
+  hipLaunchKernelGGL(k_keys, dim3(blocks_for(N, kThreads)), dim3(kThreads), 0, st, nu, S, E, g, n, N, km, keys,
+                     vals, rec);
   return hipGetLastError();
 }
 
@@ -1288,11 +1331,10 @@ hipError_t launch_radix_pass(const uint32_t* kin, const int32_t* vin, uint32_t* 
   return hipGetLastError();
 }
 
-hipError_t launch_gather(const int32_t* perm, int64_t N, const double* nu, const double* S, const double* E,
-                         const double* g, const double* n, double* onu, double* oS, double* oE, double* og,
-                         double* on, hipStream_t st) {
-  hipLaunchKernelGGL(k_gather, dim3(blocks_for(N, kThreads)), dim3(kThreads), 0, st, perm, N, nu, S, E, g, n,
-                     onu, oS, oE, og, on);
+hipError_t launch_gather(const int32_t* perm, int64_t N, const double* rec, double* onu, double* oS, double* oE,
+                         double* og, double* on, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather, dim3(blocks_for(N, kThreads)), dim3(kThreads), 0, st, perm, N, rec, onu, oS, oE, og,
+                     on);
   return hipGetLastError();
 }
 
