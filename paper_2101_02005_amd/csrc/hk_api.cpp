@@ -318,7 +318,7 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
 // Backward workspace: grid records, per-line (dL/dT, dL/dlnP) terms, reduction partials.
 constexpr int kBwdPartials = 256;
 struct BwdLayout {
-  size_t off_gr = 0, off_contrib = 0, off_part = 0, total = 0;
+  size_t off_gr = 0, off_contrib = 0, off_part = 0, off_lrec = 0, total = 0;
 };
 BwdLayout backward_layout(int64_t N) {
   BwdLayout b;
@@ -327,6 +327,7 @@ BwdLayout backward_layout(int64_t N) {
   b.off_gr = take(sizeof(int4) * (size_t)N);
   b.off_contrib = take(2 * sizeof(double) * (size_t)N);
   b.off_part = take(2 * sizeof(double) * kBwdPartials);
+  b.off_lrec = take(6 * sizeof(double) * (size_t)N);
   b.total = off;
   return b;
 }
@@ -879,6 +880,7 @@ hk_status hk_opacity_backward(const hk_lines* lines, const hk_line_override* ovr
   a.dgref = dL_dgref;
   a.dn = dL_dn;
   a.contrib = contrib;
+  a.lrec = reinterpret_cast<double*>(w + bl.off_lrec);
   const int64_t want = (lines->N + hk::kWavesPerWG - 1) / hk::kWavesPerWG;
   const int64_t cap = (int64_t)di.cus * 8;
   const int blocks = (int)std::max<int64_t>(1, std::min(want, cap));

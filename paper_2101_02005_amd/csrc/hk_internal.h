@@ -95,6 +95,7 @@ struct AdjArgs {
   float* dgref;            // caller order, nullable
   float* dn;               // caller order, nullable
   double* contrib;         // [N][2], sorted order: per-line dL/dT and dL/dlnP terms
+  double* lrec;            // [N][6], sorted order: per-line FP64 quantities (k_adj_lines)
 };
 
 // Launch wrappers (hk_kernels.hip); each returns the launch status.

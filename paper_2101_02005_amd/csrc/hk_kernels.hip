@@ -1067,33 +1067,83 @@ __device__ __forceinline__ void weideman_w(double x, double y, double& K, double
   L = 2.0 * (pr * vi + pi * vr) + 0.56418958354775628695 * ui;
 }
 
-// Far-wing profile and its gamma and alpha derivatives from the asymptotic series, in the
-// scaled variable u = sqrt(s)/(D + i gamma) (|u| <= 1), x = u^2, c_k = a_k (alpha^2/s)^k:
-//   V        = S/(pi sqrt(s))       (-Im sum_k c_k u^(2k+1))
-//   dV/dgamma = S/(pi s)             ( Re sum_k (2k+1) c_k u^(2k+2))
-//   dV/dalpha = S/(pi alpha sqrt(s)) (-Im sum_k 2k c_k u^(2k+1))
-// (term by term derivatives of V = (S/pi) sum_k a_k alpha^2k (-Im (D + i gamma)^-(2k+1))).
+// Far-wing profile and its gamma and alpha derivatives as real polynomials in q = s/(D^2 +
+// gamma^2) (s = max(alpha^2, gamma^2)), from the asymptotic series of w truncated after KD terms:
+// with a = alpha^2/s, g = gamma^2/s, u = g q, c = sqrt(1 - u), a_k = (2k-1)!!/2^k,
+//   V         = gamma/(pi s)       sum_k a_k a^k q^(k+1) U_2k(c)
+//   dV/dalpha = gamma/(pi s alpha) sum_k 2k a_k a^k q^(k+1) U_2k(c)
+//   dV/dgamma = 1/(pi s)           sum_k (2k+1) a_k a^k q^(k+1) T_(2k+2)(c)
+// (V per unit strength; term by term derivatives of -Im (D + i gamma)^-(2k+1) alpha^2k/pi).
+// U and T are Chebyshev polynomials written in powers of u (c^2 = 1 - u).
+constexpr int kAdjDeg = 2 * (kKmax + 1) + 1;  // highest power of q + 1
+struct AdjPoly {
+  float v[kAdjDeg], da[kAdjDeg], dg[kAdjDeg];  // coefficient of q^M at [M]
+};
+
+// Chebyshev polynomials in powers of u (c^2 = 1 - u): U_2k (k = 0..5) and T_(2k+2).
+__constant__ float c_adjU[6][8] = {{1, 0, 0, 0, 0, 0, 0, 0},          {3, -4, 0, 0, 0, 0, 0, 0},
+                                   {5, -20, 16, 0, 0, 0, 0, 0},       {7, -56, 112, -64, 0, 0, 0, 0},
+                                   {9, -120, 432, -576, 256, 0, 0, 0}, {11, -220, 1232, -2816, 2816, -1024, 0, 0}};
+__constant__ float c_adjT[6][8] = {{1, -2, 0, 0, 0, 0, 0, 0},           {1, -8, 8, 0, 0, 0, 0, 0},
+                                   {1, -18, 48, -32, 0, 0, 0, 0},       {1, -32, 160, -256, 128, 0, 0, 0},
+                                   {1, -50, 400, -1120, 1280, -512, 0, 0}, {1, -72, 840, -3584, 6912, -6144, 2048, 0}};
+
+// Coefficients of q^M (one M per lane) of the three polynomials, series truncated after KD terms.
 template <int KD>
-__device__ __forceinline__ void wing_adj(float ur, float ui, const float* cv, float& v, float& dg, float& da) {
-  const float xr = ur * ur - ui * ui, xi = 2.0f * ur * ui;
-  float pr = cv[KD - 1], pi = 0.0f;                                        // sum c_k x^k
-  float ar = 2.0f * (KD - 1) * cv[KD - 1], ai = 0.0f;                      // sum 2k c_k x^k
-  float gr = (2.0f * (KD - 1) + 1.0f) * cv[KD - 1], gi = 0.0f;             // sum (2k+1) c_k x^k
+__device__ __forceinline__ void adj_coef(int M, float a, float g, float& v, float& da, float& dg) {
+  constexpr float ak[6] = {1.0f, 0.5f, 0.75f, 1.875f, 6.5625f, 29.53125f};
+  v = da = dg = 0.0f;
+  float ap = 1.0f;
 #pragma unroll
-  for (int k = KD - 2; k >= 0; --k) {
-    float t = __builtin_fmaf(pr, xr, __builtin_fmaf(-pi, xi, cv[k]));
-    pi = __builtin_fmaf(pr, xi, pi * xr);
-    pr = t;
-    t = __builtin_fmaf(ar, xr, __builtin_fmaf(-ai, xi, 2.0f * k * cv[k]));
-    ai = __builtin_fmaf(ar, xi, ai * xr);
-    ar = t;
-    t = __builtin_fmaf(gr, xr, __builtin_fmaf(-gi, xi, (2.0f * k + 1.0f) * cv[k]));
-    gi = __builtin_fmaf(gr, xi, gi * xr);
-    gr = t;
+  for (int k = 0; k < KD; ++k) {
+    const int j = M - k - 1;  // power of u
+    if (j >= 0 && j <= k + 1) {
+      float gp = 1.0f;
+      for (int r = 0; r < j; ++r) gp *= g;
+      const float w = ak[k] * ap * gp;
+      if (j <= k) {
+        v += w * c_adjU[k][j];
+        da += 2.0f * k * w * c_adjU[k][j];
+      }
+      dg += (2.0f * k + 1.0f) * w * c_adjT[k][j];
+    }
+    ap *= a;
   }
-  v = -(ur * pi + ui * pr);   // -Im(u P)
-  da = -(ur * ai + ui * ar);  // -Im(u P_A)
-  dg = xr * gr - xi * gi;     //  Re(x P_G)
+}
+
+// sum_M c[M] q^M for M = 1 .. DEG (Horner)
+template <int DEG>
+__device__ __forceinline__ float adj_horner(const float* c, float q) {
+  float t = c[DEG];
+#pragma unroll
+  for (int M = DEG - 1; M >= 1; --M) t = __builtin_fmaf(t, q, c[M]);
+  return t * q;
+}
+
+// sum_M c[M] q^(M-1) for M = 1 .. DEG
+template <int DEG>
+__device__ __forceinline__ float adj_horner1(const float* c, float q) {
+  float t = c[DEG];
+#pragma unroll
+  for (int M = DEG - 1; M >= 1; --M) t = __builtin_fmaf(t, q, c[M]);
+  return t;
+}
+
+// One step of NP x 64 far-wing points: accumulate g V, g dV/dalpha, g dV/dgamma (per unit
+// strength, up to the line's constant factors) with polynomials of the given degrees.
+template <int NP, int DV, int DA, int DG>
+__device__ __forceinline__ void adj_step(const AdjPoly& P, int jc, int lane, int jref, float dnh, float dh, float gh,
+                                         const float (&gcur)[NP], float& bV, float& bA, float& bG) {
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int j = jc + p * kWave + lane;
+    const float D = __builtin_fmaf((float)(j - jref), dnh, dh);
+    const float q = __builtin_amdgcn_rcpf(__builtin_fmaf(D, D, gh * gh));  // q = s/(D^2 + gamma^2) <= 1
+    const float gq = gcur[p] * q;
+    bV = __builtin_fmaf(gq, adj_horner1<DV>(P.v, q), bV);
+    bA = __builtin_fmaf(gq, adj_horner1<DA>(P.da, q), bA);
+    bG = __builtin_fmaf(gq, adj_horner1<DG>(P.dg, q), bG);
+  }
 }
 
 __device__ __forceinline__ double wave_sum64(double v) {
@@ -1103,22 +1153,45 @@ __device__ __forceinline__ double wave_sum64(double v) {
 }
 
 // One wave per line (static assignment), lanes over its grid points inside the cut.
+// Per-line FP64 quantities of the adjoint, one thread per line (sorted order), kept apart from
+// the point loop so that the transcendental functions do not hold registers there:
+// rec[6 i ..] = (S, gamma, S/S_ref, gamma/gamma_ref, S dlnS/dT, n gamma / T).
+__global__ __launch_bounds__(kThreads) void k_adj_lines(AdjArgs a) {
+  const PrepArgs& pa = a.pa;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= pa.N) return;
+  const int32_t c = pa.perm[i];
+  const double Sref = pa.ovr_S ? pa.ovr_S[c] : pa.Sref[i];
+  const double gref = pa.ovr_g ? pa.ovr_g[c] : pa.gref[i];
+  const double nexp = pa.ovr_n ? pa.ovr_n[c] : pa.nexp[i];
+  const double nu0 = pa.nu[i];
+  const double E = pa.E[i];
+  const double Rs = pa.q_ratio * exp(pa.c2E_coef * E) * (expm1(-pa.c2_over_T * nu0) / expm1(-pa.c2_over_Tref * nu0));
+  const double S = Rs * Sref;
+  const double gfac = exp(nexp * pa.log_tr) * pa.pfac;  // gamma / gamma_ref
+  const double gam = gref * gfac;
+  const double T = a.T;
+  const double c2nu = pa.c2_over_T * nu0;
+  const double dlnS_dT = -a.q_b / T + pa.c2_over_T * E / T - (c2nu / T) / expm1(c2nu);
+  double* r = a.lrec + 6 * i;
+  r[0] = S;
+  r[1] = gam;
+  r[2] = Rs;
+  r[3] = gfac;
+  r[4] = S * dlnS_dT;
+  r[5] = nexp * gam / T;
+}
+
 __global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
+  __shared__ AdjPoly sP[kWavesPerWG][3];
   const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t nw = (int64_t)gridDim.x * kWavesPerWG;
   const PrepArgs& pa = a.pa;
-  for (int64_t i = (int64_t)blockIdx.x * kWavesPerWG + (tid >> 6); i < pa.N; i += nw) {
-    // per-line FP64 quantities (as the prep kernel), with optional overrides
-    const int32_t c = pa.perm[i];
-    const double Sref = pa.ovr_S ? pa.ovr_S[c] : pa.Sref[i];
-    const double gref = pa.ovr_g ? pa.ovr_g[c] : pa.gref[i];
-    const double nexp = pa.ovr_n ? pa.ovr_n[c] : pa.nexp[i];
+  for (int64_t i = (int64_t)blockIdx.x * kWavesPerWG + wv; i < pa.N; i += nw) {
+    const double* lr = a.lrec + 6 * i;
+    const double gam = lr[1];
     const double nu0 = pa.nu[i];
-    const double E = pa.E[i];
-    const double Rs = pa.q_ratio * exp(pa.c2E_coef * E) * (expm1(-pa.c2_over_T * nu0) / expm1(-pa.c2_over_Tref * nu0));
-    const double S = Rs * Sref;
-    const double gfac = exp(nexp * pa.log_tr) * pa.pfac;  // gamma / gamma_ref
-    const double gam = gref * gfac;
     const double alpha = nu0 * pa.beta;
     const int4 gr = a.grec[i];
     const int jref = gr.y, jlo = gr.z, jhi = gr.w;
@@ -1128,15 +1201,18 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
     if (jlo <= jhi && scd > 0.0) {
       const float rs = (float)(1.0 / sqrt(scd));
       const float dh = __int_as_float(gr.x) * rs, dnh = (float)a.dnu * rs, gh = (float)gam * rs;
-      const float ah = (float)(a2d / scd);
-      float cv[kKmax + 1];
-      cv[0] = 1.0f;
-      float ak = 1.0f, ap = 1.0f;
-#pragma unroll
-      for (int k = 1; k <= kKmax; ++k) {
-        ak *= (2.0f * k - 1.0f) * 0.5f;
-        ap *= ah;
-        cv[k] = ak * ap;
+      // coefficient sets of this line: 3 terms (chunks of series order <= 2) and 6 terms
+      {
+        const float ah = (float)(a2d / scd), gh2 = (float)(g2d / scd);
+        if (lane < kAdjDeg) {
+          float v, da, dg;
+          adj_coef<2>(lane, ah, gh2, v, da, dg);
+          sP[wv][0].v[lane] = v; sP[wv][0].da[lane] = da; sP[wv][0].dg[lane] = dg;
+          adj_coef<3>(lane, ah, gh2, v, da, dg);
+          sP[wv][1].v[lane] = v; sP[wv][1].da[lane] = da; sP[wv][1].dg[lane] = dg;
+          adj_coef<kKmax + 1>(lane, ah, gh2, v, da, dg);
+          sP[wv][2].v[lane] = v; sP[wv][2].da[lane] = da; sP[wv][2].dg[lane] = dg;
+        }
       }
       // zones in grid points around the centre
       const double cpos = (double)jref - (double)__int_as_float(gr.x) / a.dnu;
@@ -1153,85 +1229,113 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
           zlo[K] = lo < -1.0 ? -1 : (lo > 2.0e9 ? 2000000000 : (int)lo);
           zhi[K] = hi < -1.0 ? -1 : (hi > 2.0e9 ? 2000000000 : (int)hi);
         }
+        zlo[K] = __builtin_amdgcn_readfirstlane(zlo[K]);  // uniform: scalar registers
+        zhi[K] = __builtin_amdgcn_readfirstlane(zhi[K]);
       }
       const double d64 = __dsub_rn(grid_nu(a.nu_start, a.dnu, (int64_t)jref), nu0);
       const double ia = 1.0 / alpha, y = gam / alpha;
       const double zc2 = (double)a.zK[kKmax - 1] * (double)a.zK[kKmax - 1];
       float bV = 0.f, bG = 0.f, bA = 0.f;
-      int nb = 0;
-      for (int jc = jlo; jc <= jhi; jc += kWave) {
-        const int j = jc + lane;
-        const bool valid = j <= jhi;
-        const float gv = valid ? a.g[j] : 0.0f;
-        const int je = jc + kWave - 1;
-        // terms of the series for this chunk: one more than the profile needs, for dV/dalpha
+      // steps of kAdjP x 64 points (kAdjP per lane); the next step's dL/dk is loaded ahead
+      constexpr int kAdjP = 4, kStep = kAdjP * kWave;
+      float gcur[kAdjP];
+#pragma unroll
+      for (int p = 0; p < kAdjP; ++p) {
+        const int j = jlo + p * kWave + lane;
+        gcur[p] = j <= jhi ? a.g[j] : 0.0f;
+      }
+      int nstep = 0;
+      for (int jc = jlo; jc <= jhi; jc += kStep) {
+        // the coefficient sets are read from LDS in every step rather than held in registers
+        asm volatile("" ::: "memory");
+        float gnx[kAdjP];
+#pragma unroll
+        for (int p = 0; p < kAdjP; ++p) {
+          const int j = jc + kStep + p * kWave + lane;
+          gnx[p] = j <= jhi ? a.g[j] : 0.0f;
+        }
+        const int je = jc + kStep - 1;
+        // terms of the series for this step: one more than the profile needs, for dV/dalpha
         int KD = 2;
 #pragma unroll
         for (int z = 0; z < kKmax - 1; ++z) KD += (je >= zlo[z] && jc <= zhi[z]) ? 1 : 0;
-        bool core = false;
-        if (je >= zlo[kKmax - 1] && jc <= zhi[kKmax - 1]) {
-          // chunk touches the core: lanes with |z| below the last threshold take the FP64
-          // rational approximation, the others the longest series
-          KD = kKmax + 1;
-          const double x = ((double)(j - jref) * a.dnu + d64) * ia;
-          core = x * x + y * y < zc2;
-          if (core) {
-            double K, L;
-            weideman_w(x, y, K, L);
-            const double Kx = -2.0 * (x * K - y * L);
-            const double Ky = 2.0 * (x * L + y * K) - 1.1283791670955125739;
-            const double gd = (double)gv;
-            SVc += gd * K;
-            SGc += gd * Ky;
-            SAc += gd * (-(K + x * Kx + y * Ky));
+        const bool core_step = je >= zlo[kKmax - 1] && jc <= zhi[kKmax - 1];
+        if (core_step) {
+          // lanes with |z| below the last threshold take the FP64 rational approximation, the
+          // others the longest series
+          const AdjPoly& PP = sP[wv][2];
+#pragma unroll 1
+          for (int p = 0; p < kAdjP; ++p) {
+            asm volatile("" ::: "memory");
+            const int j = jc + p * kWave + lane;
+            const float gv = gcur[p];
+            const double x = ((double)(j - jref) * a.dnu + d64) * ia;
+            if (x * x + y * y < zc2) {
+              double K, L;
+              weideman_w(x, y, K, L);
+              const double Kx = -2.0 * (x * K - y * L);
+              const double Ky = 2.0 * (x * L + y * K) - 1.1283791670955125739;
+              const double gd = (double)gv;
+              SVc += gd * K;
+              SGc += gd * Ky;
+              SAc += gd * (-(K + x * Kx + y * Ky));
+            } else {
+              const float D = __builtin_fmaf((float)(j - jref), dnh, dh);
+              const float q = __builtin_amdgcn_rcpf(__builtin_fmaf(D, D, gh * gh));
+              const float gq = gv * q;
+              bV = __builtin_fmaf(gq, adj_horner1<kAdjDeg - 2>(PP.v, q), bV);
+              bA = __builtin_fmaf(gq, adj_horner1<kAdjDeg - 2>(PP.da, q), bA);
+              bG = __builtin_fmaf(gq, adj_horner1<kAdjDeg - 1>(PP.dg, q), bG);
+            }
+          }
+        } else if (KD == 2) {
+          adj_step<kAdjP, 3, 3, 4>(sP[wv][0], jc, lane, jref, dnh, dh, gh, gcur, bV, bA, bG);
+        } else if (KD == 3) {
+          adj_step<kAdjP, 5, 5, 6>(sP[wv][1], jc, lane, jref, dnh, dh, gh, gcur, bV, bA, bG);
+        } else {
+          // rare steps near the core: one point at a time, coefficients re-read from LDS
+#pragma unroll 1
+          for (int p = 0; p < kAdjP; ++p) {
+            asm volatile("" ::: "memory");
+            float g1[1] = {gcur[0]};
+            if (p == 1) g1[0] = gcur[1];
+            if (p == 2) g1[0] = gcur[2];
+            if (p == 3) g1[0] = gcur[3];
+            adj_step<1, kAdjDeg - 2, kAdjDeg - 2, kAdjDeg - 1>(sP[wv][2], jc + p * kWave, lane, jref, dnh, dh, gh, g1,
+                                                             bV, bA, bG);
           }
         }
-        if (!core) {
-          const float kf = (float)(j - jref);
-          const float D = __builtin_fmaf(kf, dnh, dh);
-          const float R = __builtin_fmaf(D, D, gh * gh);
-          const float q = __builtin_amdgcn_rcpf(R);
-          const float ur = D * q, ui = -gh * q;
-          float v, dg, da;
-          switch (KD) {
-            case 2: wing_adj<2>(ur, ui, cv, v, dg, da); break;
-            case 3: wing_adj<3>(ur, ui, cv, v, dg, da); break;
-            case 4: wing_adj<4>(ur, ui, cv, v, dg, da); break;
-            case 5: wing_adj<5>(ur, ui, cv, v, dg, da); break;
-            default: wing_adj<6>(ur, ui, cv, v, dg, da); break;
-          }
-          bV = __builtin_fmaf(gv, v, bV);
-          bG = __builtin_fmaf(gv, dg, bG);
-          bA = __builtin_fmaf(gv, da, bA);
-        }
-        if (++nb == 8) {
+        if (++nstep == 2) {
           SVw += (double)bV; SGw += (double)bG; SAw += (double)bA;
           bV = bG = bA = 0.f;
-          nb = 0;
+          nstep = 0;
         }
+#pragma unroll
+        for (int p = 0; p < kAdjP; ++p) gcur[p] = gnx[p];
       }
       SVw += (double)bV; SGw += (double)bG; SAw += (double)bA;
       // per-lane sums to per-wave sums (fixed butterfly order)
       SVw = wave_sum64(SVw); SGw = wave_sum64(SGw); SAw = wave_sum64(SAw);
       SVc = wave_sum64(SVc); SGc = wave_sum64(SGc); SAc = wave_sum64(SAc);
-      const double sq = sqrt(scd);
       const double isp = 0.56418958354775628695;  // 1/sqrt(pi)
-      const double GV = SVw / (M_PI * sq) + SVc * isp * ia;               // sum g V
-      const double GGs = SGw / (M_PI * scd) + SGc * isp * ia * ia;        // sum g dV/dgamma
-      const double GAs = SAw / (M_PI * alpha * sq) + SAc * isp * ia * ia; // sum g dV/dalpha
-      SVw = GV; SGw = S * GGs; SAw = S * GAs;
+      const double gL = lr[1], aL = pa.nu[i] * pa.beta, SL = lr[0];
+      const double iaL = 1.0 / aL;
+      const double sL2 = aL * aL > gL * gL ? aL * aL : gL * gL;
+      const double GV = gL / (M_PI * sL2) * SVw + SVc * isp * iaL;               // sum g V
+      const double GGs = SGw / (M_PI * sL2) + SGc * isp * iaL * iaL;             // sum g dV/dgamma
+      const double GAs = gL / (M_PI * sL2 * aL) * SAw + SAc * isp * iaL * iaL;   // sum g dV/dalpha
+      SVw = GV; SGw = SL * GGs; SAw = SL * GAs;
     }
     if (lane == 0) {
       // SVw, SGw, SAw now hold sum_j g_j V_ij, dL/dgamma_i, dL/dalpha_i (zero without points)
       const double GS = SVw, Gg = SGw, Ga = SAw;
-      const double T = a.T;
-      const double c2nu = pa.c2_over_T * nu0;
-      const double dlnS_dT = -a.q_b / T + pa.c2_over_T * E / T - (c2nu / T) / expm1(c2nu);
-      if (a.dSref) a.dSref[c] = Rs * GS;
-      if (a.dgref) a.dgref[c] = (float)(gfac * Gg);
-      if (a.dn) a.dn[c] = (float)(gam * pa.log_tr * Gg);
-      a.contrib[2 * i] = GS * S * dlnS_dT + Ga * alpha / (2.0 * T) - Gg * nexp * gam / T;
-      a.contrib[2 * i + 1] = gam * Gg;
+      const int32_t c = pa.perm[i];
+      const double aL = pa.nu[i] * pa.beta;
+      if (a.dSref) a.dSref[c] = lr[2] * GS;
+      if (a.dgref) a.dgref[c] = (float)(lr[3] * Gg);
+      if (a.dn) a.dn[c] = (float)(lr[1] * pa.log_tr * Gg);
+      a.contrib[2 * i] = GS * lr[4] + Ga * aL / (2.0 * a.T) - Gg * lr[5];
+      a.contrib[2 * i + 1] = lr[1] * Gg;
     }
   }
 }
@@ -1453,6 +1557,7 @@ hipError_t launch_cut_bounds(const double* nu, const int32_t* perm, int64_t N, d
 }
 
 hipError_t launch_adjoint(const AdjArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_lines, dim3(blocks_for(a.pa.N, kThreads)), dim3(kThreads), 0, st, a);
   hipLaunchKernelGGL(k_adjoint, dim3(grid), dim3(kThreads), 0, st, a);
   return hipGetLastError();
 }

@@ -199,3 +199,40 @@ def test_override_changes_gradient_like_oracle():
     assert vec_err(dg.cpu().numpy().astype(np.float64), go["dgamma_ref"]) <= TOL_G
     assert vec_err(dn.cpu().numpy().astype(np.float64), go["dn"]) <= TOL_G
     assert abs(out2[0].item() - go["dT_part"].sum()) <= TOL_G * abs(go["dT_part"].sum())
+
+
+def test_c4_full_list_sampled_lines_and_identities():
+    """The full differentiation list (1e7 lines, 0-10000 cm^-1 at 0.01, cut 100): per-line
+    gradients of 300 sampled lines against the oracle, and the chain-rule identities
+    sum S_ref dL/dS_ref = L = sum_j g_j k_j and dL/dlnP = sum gamma_ref dL/dgamma_ref."""
+    import torch
+
+    import paper_2101_02005_amd as hk
+    w = linegen.workload("c4")
+    dev = [torch.empty(w.N, dtype=torch.float64, device="cuda") for _ in range(5)]
+    linegen.generate_device(w.recipe(), w.seed, w.N, [t.data_ptr() for t in dev],
+                            stream=torch.cuda.current_stream().cuda_stream)
+    lines = hk.hk_prepare_lines(*dev, hk.species(*w.species_tuple()))
+    grd = hk.grid(w.nu_start, w.dnu, w.n_grid)
+    g = upstream(w.n_grid, w.extra["g_seed"])
+    gd = torch.from_numpy(g).cuda()
+    out2, dS, dg, dn = hk.hk_opacity_backward(lines, w.T[0], w.P[0], grd, w.cut, gd)
+    k = hk.hk_opacity(lines, w.T[0], w.P[0], grd, w.cut)
+    torch.cuda.synchronize()
+    Lk = float((k.double() * gd.double()).sum())
+    LS = float((dev[1] * dS).sum())
+    lnP = float((dev[3] * dg.double()).sum())
+    print("L %.6e  sum S dL/dS %.6e  dL/dlnP %.6e  sum g dL/dg %.6e  dL/dT %.6e" % (Lk, LS, out2[1].item(), lnP,
+                                                                                 out2[0].item()))
+    assert abs(LS - Lk) <= 1e-4 * abs(Lk)
+    assert abs(lnP - out2[1].item()) <= 1e-4 * abs(out2[1].item())
+    rng = np.random.default_rng(44)
+    sel = np.sort(rng.choice(w.N, 300, replace=False))
+    L = {kk: t.cpu().numpy()[sel] for kk, t in zip(linegen.FIELDS, dev)}
+    lines.release()
+    go = _oracle_grad(L, w.T[0], w.P[0], w.nu_start, w.dnu, w.n_grid, w.cut, g)
+    for name, gpu in (("dS_ref", dS.cpu().numpy()[sel]), ("dgamma_ref", dg.cpu().numpy()[sel].astype(np.float64)),
+                      ("dn", dn.cpu().numpy()[sel].astype(np.float64))):
+        e = vec_err(gpu, go[name])
+        print("c4 full list, 300 sampled lines, %s: rel err %.2e" % (name, e))
+        assert e <= TOL_G, name
