@@ -27,7 +27,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_voigt_c2_5e8_cut25_traffic.txt"
 KERNEL_SRC = os.path.join(ROOT, "paper_2101_02005_amd", "csrc", "hk_kernels.hip")
 
 
-def k_voigt_traffic(lines, cut, dnu):
+def k_voigt_traffic(lines, cut, dnu, tile_width):
     """HBM bytes per k_voigt launch from the committed FETCH_SIZE / WRITE_SIZE counter runs,
     scaled by the same counters on a plain copy; None when absent, taken on another workload,
     or taken on a different kernel source."""
@@ -46,6 +46,8 @@ def k_voigt_traffic(lines, cut, dnu):
         if kv.get("kernel_src_sha256") != sha:
             return None
         if (float(kv["lines"]), float(kv["cut"]), float(kv["dnu"])) != (float(lines), float(cut), float(dnu)):
+            return None
+        if int(kv["tile_width"]) != int(tile_width):
             return None
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError, OSError):
@@ -315,8 +317,9 @@ def main():
         "voigt_evals_per_s": n_evals / ((voigt_ms + core_ms) * 1e-3),
         "evals": n_evals, "core_evals": core_evals,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": k_voigt_traffic(N, w.cut, w.dnu),
-                     "kernel": "k_voigt (far-wing pass)", "flops_per_eval": FLOPS_PER_EVAL,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": k_voigt_traffic(N, w.cut, w.dnu, tm.tile_width),
+                     "kernel": "k_voigt<%d, %d> (far-wing pass)" % (tm.tile_width // 256, tm.lines_per_batch),
+                     "flops_per_eval": FLOPS_PER_EVAL,
                      "evals_per_launch": wing_evals, "avg_launch_ms": voigt_ms},
         "phases_ms": {"bin": sum(b for b, _ in per) / len(per), "prep": tm.prep_ms, "worklist": tm.worklist_ms,
                       "voigt_wing": voigt_ms, "voigt_core": core_ms, "combine": tm.combine_ms},
