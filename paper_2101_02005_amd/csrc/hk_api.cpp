@@ -520,7 +520,7 @@ hk_status choose_tuning(const hk_lines* L, const hk_line_override* ovr, int n_pa
   }
   *out = Tuning{};
   if (!env_flag("HK_AUTOTUNE", false)) return HK_OK;
-  float best_ms = 0.0f;
+  float best_ms = 0.0f, default_ms = -1.0f;
   bool have = false;
   hipEvent_t e0, e1;
   HK_HIP(hipEventCreate(&e0));
@@ -536,8 +536,11 @@ hk_status choose_tuning(const hk_lines* L, const hk_line_override* ovr, int n_pa
     HK_HIP(hipEventSynchronize(e1));
     float ms = 0.0f;
     HK_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (tu.slots == Tuning{}.slots && tu.lb == Tuning{}.lb) default_ms = ms;
     if (!have || ms < best_ms) { best_ms = ms; *out = tu; have = true; }
   }
+  // keep the default unless another tuning is clearly faster (timing noise must not flip it)
+  if (default_ms > 0.0f && default_ms <= 1.03f * best_ms) *out = Tuning{};
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   std::lock_guard<std::mutex> lk(g_tune_mu);
