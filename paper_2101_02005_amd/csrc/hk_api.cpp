@@ -77,6 +77,8 @@ struct DevInfo {
   int cus = 0;
   int wg_per_cu[4][2] = {};   // wing kernel occupancy per (slots 1/2/4/8, line batch 128/256)
   int core_per_cu[4] = {};    // core kernel (one-wave workgroups) occupancy per slots
+  double* cheb_w[4] = {};     // device: Lagrange weights of the span nodes, per slots 1/2/4/8
+  float cheb_x[4][hk::kNodes] = {};  // node positions relative to the span's first point
 };
 
 std::mutex g_mu;
@@ -112,6 +114,32 @@ void weideman_coeffs(int N, double* a_out, double* L_out) {
   *L_out = L;
 }
 
+// Chebyshev points of the first kind on a span of S grid points [0, S-1] and, for every grid
+// point of the span, the Lagrange weights of the nodes (barycentric form). weights[k * S + j].
+void span_nodes(int S, float* x_out, std::vector<double>& weights) {
+  const int m = hk::kNodes;
+  const double h = 0.5 * (S - 1);
+  std::vector<double> x(m), bw(m);
+  for (int k = 0; k < m; ++k) {
+    const double th = (2.0 * k + 1.0) * M_PI / (2.0 * m);
+    x[k] = h + h * std::cos(th);
+    bw[k] = ((k & 1) ? -1.0 : 1.0) * std::sin(th);
+    x_out[k] = (float)x[k];
+  }
+  weights.assign((size_t)m * S, 0.0);
+  for (int j = 0; j < S; ++j) {
+    int hit = -1;
+    double den = 0.0;
+    for (int k = 0; k < m; ++k) {
+      const double d = j - x[k];
+      if (d == 0.0) { hit = k; break; }
+      den += bw[k] / d;
+    }
+    for (int k = 0; k < m; ++k)
+      weights[(size_t)k * S + j] = hit >= 0 ? (k == hit ? 1.0 : 0.0) : (bw[k] / (j - x[k])) / den;
+  }
+}
+
 hk_status device_init(int* dev_out, DevInfo* info) {
   int dev = -1;
   HK_HIP(hipGetDevice(&dev));
@@ -131,6 +159,11 @@ hk_status device_init(int* dev_out, DevInfo* info) {
       di.wg_per_cu[si][0] = hk::voigt_max_blocks_per_cu(1 << si, 128);
       di.wg_per_cu[si][1] = hk::voigt_max_blocks_per_cu(1 << si, 256);
       di.core_per_cu[si] = hk::core_max_blocks_per_cu(1 << si);
+      const int S = hk::kWave << si;
+      std::vector<double> wts;
+      span_nodes(S, di.cheb_x[si], wts);
+      HK_HIP(hipMalloc(&di.cheb_w[si], sizeof(double) * wts.size()));  // held for the process lifetime
+      HK_HIP(hipMemcpy(di.cheb_w[si], wts.data(), sizeof(double) * wts.size(), hipMemcpyHostToDevice));
     }
     it = g_dev.emplace(dev, di).first;
   }
@@ -436,6 +469,15 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   va.n_tiles_total = pl.n_tiles_total;
   va.chunk = pl.chunk;
   va.items_cap = (int32_t)std::min<int64_t>(pl.items_bound, INT32_MAX);
+  {
+    int dev = 0;
+    DevInfo di;
+    hk_status ds = device_init(&dev, &di);
+    if (ds != HK_OK) return ds;
+    const int si = slot_index(pl.slots);
+    va.cheb_w = di.cheb_w[si];
+    for (int k = 0; k < hk::kNodes; ++k) va.cheb_x[k] = di.cheb_x[si][k];
+  }
   long long* stats = reinterpret_cast<long long*>(ws + pl.off_stats);
   va.stats = tm.on ? stats : nullptr;
   HK_HIP(hk::launch_voigt(va, pl.slots, pl.lb, pl.grid, st));

@@ -17,6 +17,8 @@ constexpr int kRadixBits = 8;
 constexpr int kSortItems = 16;   // keys per thread per sort block
 constexpr int kSortBlock = kThreads * kSortItems;
 constexpr int kFillPairs = 48;   // pair descriptors per fill launch (kernel-argument space)
+constexpr int kNodes = 16;       // Chebyshev nodes per wave span for lines far from the span
+constexpr float kFarSpans = 1.5f;  // far: centre at least 1.5 spans (3 half-spans) from the span centre
 
 // Wavenumber -> bin key: clamp(floor((v - numin) * scale), 0, kmax), evaluated in FP64.
 struct KeyMap {
@@ -60,6 +62,8 @@ struct VoigtArgs {
   int32_t n_tiles_total;
   int32_t chunk;           // lines per work item
   int32_t items_cap;       // rows of `partial` (work items beyond it are never written)
+  const double* cheb_w;    // [kNodes][64 P] Lagrange weights of the span's Chebyshev nodes
+  float cheb_x[kNodes];    // node positions relative to the span's first point
 };
 
 struct PrepArgs {

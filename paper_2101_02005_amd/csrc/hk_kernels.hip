@@ -586,7 +586,12 @@ __device__ __forceinline__ void stage_line(LineLDS<LB>& L, int tid, const int4 g
       }
       const bool core = (czl > w0 ? czl : w0) <= (czh < w1 ? czh : w1);
       if (core) K = kKmax;  // the wing points next to the core need the highest order
-      code = K | ((w0 >= clo && w1 <= chi) ? 0u : 8u) | (core ? 16u : 0u);
+      const bool masked = !(w0 >= clo && w1 <= chi);
+      // far: the whole span inside the cut, and the centre at least 3 half-spans away, so the
+      // line is smooth on the span and is evaluated at the span's Chebyshev nodes only
+      const float dc = c - (float)w0 - 0.5f * (float)(kWave * P - 1);
+      const bool far = !masked && !core && K < (uint32_t)kKmax && fabsf(dc) >= kFarSpans * (float)(kWave * P);
+      code = K | (masked ? 8u : 0u) | (core ? 16u : 0u) | (far ? 32u : 0u);
     }
     codes[w] = code;
   }
@@ -647,14 +652,16 @@ __device__ __forceinline__ void wing_slots(float (&part)[P], float kf0, const fl
   }
 }
 
-// Group of a staged line for one wave: 0 does not reach the wave; 1..4 series order K, all
-// lanes inside the cut, no core points; 6..9 the same with lanes outside the cut (order
-// K = group - 5); 5 general (order 5 or core points on the wave).
-constexpr int kGroups = 9;
+// Group of a staged line for one wave: 0 does not reach the wave; 1-4 all lanes inside the cut,
+// no core points, series order K = 1-4; 5 general (order 5 or core points on the wave); 6-9 the
+// same as 1-4 with some lanes outside the cut; 10-13 far from the wave's span, order 1-4
+// (evaluated at the span's Chebyshev nodes).
+constexpr int kGroups = 13;
 __device__ __forceinline__ int line_group(uint32_t code) {
   if (code == 0u) return 0;
   const int K = (int)(code & 7u);
   if ((code & 16u) || K > 4) return 5;
+  if (code & 32u) return 9 + K;
   return (code & 8u) ? 5 + K : K;
 }
 
@@ -671,6 +678,64 @@ __device__ __forceinline__ void wing_line(const LineLDS<LB>& L, int l, float jl0
   if (K >= 3) kb = L.KB[l];
   if (K >= 4) kc = L.KC[l];
   wing_slots<P, K, MASK, false>(part, jl0 - f0.y, f0, f1, ka, kb, kc);
+}
+
+// Far lines of one group: four lines per step, lane = 16 (line in step) + node; each lane adds
+// the line's profile at its node to its node sum (lines are assigned to lanes in a fixed way).
+template <int LB, int K>
+__device__ __forceinline__ void far_loop(const LineLDS<LB>& L, int wv, int i0, int i1, int lane, float xnode,
+                                         float& fpart, float& fs, float& fc) {
+  int n = 0;
+  for (int i = i0; i < i1; i += 4) {
+    const int li = i + (lane >> 4);
+    float t = 0.0f, q = 0.0f;
+    if (li < i1) {
+      const int l = (int)L.list[wv][li];
+      const float4 f0 = L.F0[l];
+      const float4 f1 = L.F1[l];
+      const float D = __builtin_fmaf(xnode - f0.y, f0.z, f0.x);
+      const float R = __builtin_fmaf(D, D, f0.w);
+      q = __builtin_amdgcn_rcpf(R);
+      if (K == 1) {
+        t = f1.x;
+      } else if (K == 2) {
+        const float4 ka = L.KA[l];
+        t = __builtin_fmaf(ka.y, q, ka.x);
+        t = __builtin_fmaf(t, q, f1.x);
+      } else if (K == 3) {
+        const float4 ka = L.KA[l];
+        const float4 kb = L.KB[l];
+        t = __builtin_fmaf(kb.x, q, ka.w);
+        t = __builtin_fmaf(t, q, ka.z);
+        t = __builtin_fmaf(t, q, ka.x);
+        t = __builtin_fmaf(t, q, f1.x);
+      } else {
+        const float4 ka = L.KA[l];
+        const float4 kb = L.KB[l];
+        const float kc = L.KC[l];
+        t = __builtin_fmaf(kc, q, kb.w);
+        t = __builtin_fmaf(t, q, kb.z);
+        t = __builtin_fmaf(t, q, kb.y);
+        t = __builtin_fmaf(t, q, ka.z);
+        t = __builtin_fmaf(t, q, ka.x);
+        t = __builtin_fmaf(t, q, f1.x);
+      }
+    }
+    fpart = __builtin_fmaf(t, q, fpart);
+    if (++n == 16) {
+      const float y = fpart - fc;
+      const float tt = fs + y;
+      fc = (tt - fs) - y;
+      fs = tt;
+      fpart = 0.0f;
+      n = 0;
+    }
+  }
+  const float y = fpart - fc;
+  const float tt = fs + y;
+  fc = (tt - fs) - y;
+  fs = tt;
+  fpart = 0.0f;
 }
 
 template <int P, int LB, int K, bool MASK>
@@ -703,6 +768,8 @@ template <int P, int LB>
 __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
   constexpr int W = kWavesPerWG * kWave * P;  // tile width in grid points
   __shared__ LineLDS<LB> L;
+  __shared__ float sNode[kWavesPerWG][kWave];
+  __shared__ double sNodeSum[kWavesPerWG][kNodes];
   __shared__ int sItem, sTile, sPair;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
@@ -748,6 +815,9 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
       cc[p] = 0.0f;
       part[p] = 0.0f;
     }
+    // far lines: this lane's node and its compensated node sum
+    const float xnode = (float)(wv * kWave * P) + a.cheb_x[lane & (kNodes - 1)];
+    float fpart = 0.0f, fs = 0.0f, fc = 0.0f;
     for (int64_t b = line_lo; b < line_hi; b += LB) {
       // ---- stage one batch of lines: one thread per line
       {
@@ -800,6 +870,10 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
         group_loop<P, LB, 2, true>(L, wv, o[7], o[8], jl0, part, s, cc);
         group_loop<P, LB, 3, true>(L, wv, o[8], o[9], jl0, part, s, cc);
         group_loop<P, LB, 4, true>(L, wv, o[9], o[10], jl0, part, s, cc);
+        far_loop<LB, 1>(L, wv, o[10], o[11], lane, xnode, fpart, fs, fc);
+        far_loop<LB, 2>(L, wv, o[11], o[12], lane, xnode, fpart, fs, fc);
+        far_loop<LB, 3>(L, wv, o[12], o[13], lane, xnode, fpart, fs, fc);
+        far_loop<LB, 4>(L, wv, o[13], o[14], lane, xnode, fpart, fs, fc);
         // general group: order 5, possibly lanes outside the cut and core points to skip
         for (int i = o[5]; i < o[6]; ++i) {
           const int l = __builtin_amdgcn_readfirstlane((int)L.list[wv][i]);
@@ -829,6 +903,33 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
         kahan_flush<P>(part, s, cc);
       }
       __syncthreads();
+    }
+    // ---- far lines: node sums (the four line groups of lanes in a fixed order), then their
+    //      interpolation to this wave's points with the span's Lagrange weights, in FP64
+    sNode[wv][lane] = fs - fc;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    if (lane < kNodes) {
+      double t = 0.0;
+#pragma unroll
+      for (int gq = 0; gq < kWave / kNodes; ++gq) t += (double)sNode[wv][gq * kNodes + lane];
+      sNodeSum[wv][lane] = t;
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    {
+      double v[P];
+#pragma unroll
+      for (int p = 0; p < P; ++p) v[p] = 0.0;
+#pragma unroll 1
+      for (int k = 0; k < kNodes; ++k) {
+        const double ns = sNodeSum[wv][k];
+        const double* __restrict__ wk = a.cheb_w + k * (kWave * P) + lane;
+#pragma unroll
+        for (int p = 0; p < P; ++p) v[p] = fma(ns, wk[p * kWave], v[p]);
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p) part[p] += (float)v[p];
     }
     kahan_flush<P>(part, s, cc);
 
