@@ -85,8 +85,9 @@ typedef struct hk_lines hk_lines;
 
 /* Timings and tuning of the last completed call on this thread (milliseconds, filled only
  * when HK_TIMING=1 is set in the environment; otherwise the times are negative).
- * hk_opacity: voigt_ms is the wing kernel, core_ms the line-core kernel, core_evals the
- * number of (line, point) evaluations the core kernel made. hk_opacity_batched: voigt_ms is
+ * hk_opacity: voigt_ms is the wing kernel, far_ms the tile-far pass (lines far from a whole
+ * tile, evaluated at its Chebyshev nodes and interpolated), core_ms the line-core kernel,
+ * core_evals the number of (line, point) evaluations the core kernel made. hk_opacity_batched: voigt_ms is
  * the whole graph. hk_opacity_backward: backward_ms. */
 typedef struct hk_timings {
   double prep_ms, worklist_ms, voigt_ms, combine_ms, backward_ms, bin_ms;
@@ -96,6 +97,10 @@ typedef struct hk_timings {
   int32_t n_items;         /* upper bound of work items of the last call */
   double core_ms;
   int64_t core_evals;
+  double far_ms;           /* tile-far pass (node evaluation and interpolation) */
+  int64_t wing_evals;      /* profile evaluations the wing and tile-far passes made: every
+                              point of a wave for a line evaluated directly, 16 per line
+                              evaluated at the Chebyshev nodes of a wave span or a tile */
 } hk_timings;
 
 /*

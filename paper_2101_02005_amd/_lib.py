@@ -35,7 +35,8 @@ class Timings(ctypes.Structure):
                 ("combine_ms", ctypes.c_double), ("backward_ms", ctypes.c_double), ("bin_ms", ctypes.c_double),
                 ("tile_width", ctypes.c_int32), ("lines_per_batch", ctypes.c_int32),
                 ("chunk_lines", ctypes.c_int32), ("n_items", ctypes.c_int32), ("core_ms", ctypes.c_double),
-                ("core_evals", ctypes.c_int64)]
+                ("core_evals", ctypes.c_int64), ("far_ms", ctypes.c_double),
+                ("wing_evals", ctypes.c_int64)]
 
 
 _lib = None

@@ -79,6 +79,9 @@ struct DevInfo {
   int core_per_cu[4] = {};    // core kernel (one-wave workgroups) occupancy per slots
   double* cheb_w[4] = {};     // device: Lagrange weights of the span nodes, per slots 1/2/4/8
   float cheb_x[4][hk::kNodes] = {};  // node positions relative to the span's first point
+  double* tile_w[4] = {};     // device: the same for the wing tile (4 spans), per slots
+  float tile_x[4][hk::kNodes] = {};
+  int far_per_cu = 1;         // tile-far kernel occupancy
 };
 
 std::mutex g_mu;
@@ -164,7 +167,11 @@ hk_status device_init(int* dev_out, DevInfo* info) {
       span_nodes(S, di.cheb_x[si], wts);
       HK_HIP(hipMalloc(&di.cheb_w[si], sizeof(double) * wts.size()));  // held for the process lifetime
       HK_HIP(hipMemcpy(di.cheb_w[si], wts.data(), sizeof(double) * wts.size(), hipMemcpyHostToDevice));
+      span_nodes(hk::kWavesPerWG * S, di.tile_x[si], wts);
+      HK_HIP(hipMalloc(&di.tile_w[si], sizeof(double) * wts.size()));  // held for the process lifetime
+      HK_HIP(hipMemcpy(di.tile_w[si], wts.data(), sizeof(double) * wts.size(), hipMemcpyHostToDevice));
     }
+    di.far_per_cu = hk::far_max_blocks_per_cu();
     it = g_dev.emplace(dev, di).first;
   }
   *dev_out = dev;
@@ -201,6 +208,10 @@ struct Plan {
   size_t off_pairs_c = 0, off_lo_c = 0, off_hi_c = 0, off_nc_c = 0, off_ib_c = 0, off_cnt_c = 0, off_part_c = 0;
   int64_t items_bound_c = 0;
   int W_c = 256, n_tiles_c = 0, grid_c = 0;
+  // the tile-far pass: per-tile line ranges, its work items and their node sums
+  size_t off_far = 0, off_nf = 0, off_ibf = 0, off_partf = 0;
+  int64_t items_bound_f = 0;
+  int chunk_f = 0, grid_f = 0;
   std::vector<hk::PairDesc> pairs_c;  // the pairs with the core pass's (one-wave) tiling
   int n_grids = 0;
   std::vector<hk::PairDesc> pairs;
@@ -320,6 +331,16 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   const double items_c = (double)tiles_c + std::ceil(visits_c / pl->chunk);
   if (items_c >= 2.0e9) return fail(HK_ENOMEM, "core work list too large (%.3g items)", items_c);
   pl->items_bound_c = (int64_t)items_c;
+  // tile-far items: large chunks (a line costs kNodes evaluations), still enough to balance
+  const int wgs_f = di.cus * di.far_per_cu;
+  double cf = std::ceil(visits / (16.0 * (wgs_f > 0 ? wgs_f : 1024)));
+  if (cf < 4096) cf = 4096;
+  if (cf > (1 << 22)) cf = 1 << 22;
+  pl->chunk_f = (int)(std::ceil(cf / hk::kThreads) * hk::kThreads);
+  const double items_f = (double)tiles + std::ceil(visits / pl->chunk_f);
+  if (items_f >= 2.0e9) return fail(HK_ENOMEM, "tile-far work list too large (%.3g items)", items_f);
+  pl->items_bound_f = (int64_t)items_f;
+  pl->grid_f = (int)std::max<int64_t>(1, std::min<int64_t>(pl->items_bound_f, (int64_t)(wgs_f > 0 ? wgs_f : 1024)));
   pl->grid = (int)std::min<int64_t>(pl->items_bound, (int64_t)(wgs > 0 ? wgs : 1024));
   const int wgs_c = di.cus * di.core_per_cu[slot_index(pl->slots)];
   pl->grid_c = (int)std::max<int64_t>(1, std::min<int64_t>(pl->items_bound_c, (int64_t)(wgs_c > 0 ? wgs_c : 4096)));
@@ -336,7 +357,7 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   pl->off_ib = take(sizeof(int32_t) * (tiles + 1));
   pl->off_cnt = take(sizeof(int) * 64);
   pl->off_part = take(sizeof(float) * (size_t)pl->items_bound * pl->W);
-  pl->off_stats = take(sizeof(long long) * (size_t)std::max(pl->grid, pl->grid_c));
+  pl->off_stats = take(sizeof(long long) * ((size_t)hk::kWavesPerWG * pl->grid + pl->grid_c + pl->grid_f));
   pl->off_pairs_c = take(sizeof(hk::PairDesc) * n_pairs);
   pl->off_lo_c = take(sizeof(int32_t) * tiles_c);
   pl->off_hi_c = take(sizeof(int32_t) * tiles_c);
@@ -344,6 +365,10 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   pl->off_ib_c = take(sizeof(int32_t) * (tiles_c + 1));
   pl->off_cnt_c = take(sizeof(int) * 64);
   pl->off_part_c = take(sizeof(float) * (size_t)pl->items_bound_c * pl->W_c);
+  pl->off_far = take(sizeof(int4) * tiles);
+  pl->off_nf = take(sizeof(int32_t) * tiles);
+  pl->off_ibf = take(sizeof(int32_t) * (tiles + 1));
+  pl->off_partf = take(sizeof(double) * hk::kNodes * (size_t)pl->items_bound_f);
   pl->total = off;
   return HK_OK;
 }
@@ -434,9 +459,14 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   int32_t* ib = reinterpret_cast<int32_t*>(ws + pl.off_ib);
   int* cnt = reinterpret_cast<int*>(ws + pl.off_cnt);
   HK_HIP(hk::launch_fill_pairs(pl.pairs.data(), pl.n_pairs, dpairs, st));
+  int4* tfar = reinterpret_cast<int4*>(ws + pl.off_far);
+  int32_t* nf = reinterpret_cast<int32_t*>(ws + pl.off_nf);
+  int32_t* ibf = reinterpret_cast<int32_t*>(ws + pl.off_ibf);
+  int* cnt_f = cnt + 16;
   HK_HIP(hk::launch_worklist(L->keys, L->N, L->km, L->numin, L->numax, dpairs, pl.n_pairs, pl.n_tiles_total,
-                             pl.W, cut, 0.0, pl.chunk, lo, hi, nc, st));
+                             pl.W, cut, 0.0, pl.chunk, lo, hi, nc, tfar, nf, pl.chunk_f, kZK[hk::kKmax - 2], st));
   HK_HIP(hk::launch_item_scan(nc, pl.n_tiles_total, ib, cnt, st));
+  HK_HIP(hk::launch_item_scan(nf, pl.n_tiles_total, ibf, cnt_f, st));
   int32_t* lo_c = reinterpret_cast<int32_t*>(ws + pl.off_lo_c);
   int32_t* hi_c = reinterpret_cast<int32_t*>(ws + pl.off_hi_c);
   int32_t* nc_c = reinterpret_cast<int32_t*>(ws + pl.off_nc_c);
@@ -445,7 +475,8 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   hk::PairDesc* dpairs_c = reinterpret_cast<hk::PairDesc*>(ws + pl.off_pairs_c);
   HK_HIP(hk::launch_fill_pairs(pl.pairs_c.data(), pl.n_pairs, dpairs_c, st));
   HK_HIP(hk::launch_worklist(L->keys, L->N, L->km, L->numin, L->numax, dpairs_c, pl.n_pairs, pl.n_tiles_c,
-                             pl.W_c, cut, kZK[hk::kKmax - 1], pl.chunk, lo_c, hi_c, nc_c, st));
+                             pl.W_c, cut, kZK[hk::kKmax - 1], pl.chunk, lo_c, hi_c, nc_c, nullptr, nullptr, 1,
+                             0.0, st));
   HK_HIP(hk::launch_item_scan(nc_c, pl.n_tiles_c, ib_c, cnt_c, st));
   tm.mark();
   hk::VoigtArgs va;
@@ -457,6 +488,7 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   va.pairs = dpairs;
   va.tile_lo = lo;
   va.tile_hi = hi;
+  va.tile_far = tfar;
   va.tile_nc = nc;
   va.item_base = ib;
   va.k = k;
@@ -469,6 +501,8 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   va.n_tiles_total = pl.n_tiles_total;
   va.chunk = pl.chunk;
   va.items_cap = (int32_t)std::min<int64_t>(pl.items_bound, INT32_MAX);
+  hk::FarArgs fa;
+  memset(&fa, 0, sizeof fa);
   {
     int dev = 0;
     DevInfo di;
@@ -477,12 +511,37 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
     const int si = slot_index(pl.slots);
     va.cheb_w = di.cheb_w[si];
     for (int k = 0; k < hk::kNodes; ++k) va.cheb_x[k] = di.cheb_x[si][k];
+    fa.tile_w = di.tile_w[si];
+    for (int k = 0; k < hk::kNodes; ++k) fa.tile_x[k] = di.tile_x[si][k];
   }
+  fa.nu = L->nu;
+  fa.S_T = S_T;
+  fa.gT = gT;
+  fa.pairs = dpairs;
+  fa.tile_far = tfar;
+  fa.item_base = ibf;
+  fa.node_part = reinterpret_cast<double*>(ws + pl.off_partf);
+  fa.counter = cnt_f;
+  fa.k = k;
+  fa.N = L->N;
+  for (int i = 0; i < hk::kKmax; ++i) fa.zK[i] = (float)kZK[i];
+  fa.n_pairs = pl.n_pairs;
+  fa.n_tiles_total = pl.n_tiles_total;
+  fa.chunk = pl.chunk_f;
+  fa.items_cap = (int32_t)std::min<int64_t>(pl.items_bound_f, INT32_MAX);
+  fa.W = pl.W;
+  // evaluation counts (timed calls only): k_voigt per wave, then k_core and k_far per block
   long long* stats = reinterpret_cast<long long*>(ws + pl.off_stats);
+  long long* stats_c = stats + (size_t)hk::kWavesPerWG * pl.grid;
+  long long* stats_f = stats_c + pl.grid_c;
   va.stats = tm.on ? stats : nullptr;
+  fa.stats = tm.on ? stats_f : nullptr;
   HK_HIP(hk::launch_voigt(va, pl.slots, pl.lb, pl.grid, st));
   tm.mark();
   HK_HIP(hk::launch_combine(va, pl.slots, st));
+  tm.mark();
+  HK_HIP(hk::launch_far(fa, pl.grid_f, st));
+  HK_HIP(hk::launch_combine_far(fa, st));
   tm.mark();
   // line-core pass over its own (narrower) work list, after the wing sums are final
   hk::VoigtArgs vc = va;
@@ -495,6 +554,7 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   vc.counter = cnt_c;
   vc.partial = reinterpret_cast<float*>(ws + pl.off_part_c);
   vc.items_cap = (int32_t)std::min<int64_t>(pl.items_bound_c, INT32_MAX);
+  vc.stats = tm.on ? stats_c : nullptr;
   const int grid_c = pl.grid_c;
   HK_HIP(hk::launch_core(vc, pl.slots, grid_c, st));
   HK_HIP(hk::launch_combine_core(vc, pl.slots, st));
@@ -504,15 +564,19 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   g_tim.worklist_ms = tm.ms(1);
   g_tim.voigt_ms = tm.ms(2);
   g_tim.combine_ms = tm.ms(3);
-  g_tim.core_ms = tm.ms(4);
+  g_tim.far_ms = tm.ms(4);
+  g_tim.core_ms = tm.ms(5);
   g_tim.backward_ms = -1;
   g_tim.core_evals = -1;
+  g_tim.wing_evals = -1;
   if (tm.on) {
-    std::vector<long long> h((size_t)grid_c);
+    const size_t nw = (size_t)hk::kWavesPerWG * pl.grid;
+    std::vector<long long> h(nw + grid_c + pl.grid_f);
     HK_HIP(hipMemcpy(h.data(), stats, sizeof(long long) * h.size(), hipMemcpyDeviceToHost));
-    long long t = 0;
-    for (long long v : h) t += v;
-    g_tim.core_evals = t;
+    long long tw = 0, tc = 0;
+    for (size_t i = 0; i < h.size(); ++i) (i >= nw && i < nw + grid_c ? tc : tw) += h[i];
+    g_tim.core_evals = tc;
+    g_tim.wing_evals = tw;
   }
   g_tim.tile_width = pl.W;
   g_tim.lines_per_batch = pl.lb;
@@ -876,8 +940,8 @@ hk_status hk_opacity_batched(const hk_lines* lines, int32_t n_pairs, const doubl
   tm.finish();
   g_tim.prep_ms = g_tim.worklist_ms = g_tim.combine_ms = -1;
   g_tim.voigt_ms = tm.ms(0);  // whole graph
-  g_tim.core_ms = -1;
-  g_tim.core_evals = -1;
+  g_tim.core_ms = g_tim.far_ms = -1;
+  g_tim.core_evals = g_tim.wing_evals = -1;
   g_tim.tile_width = pl.W;
   g_tim.lines_per_batch = pl.lb;
   g_tim.chunk_lines = pl.chunk;
@@ -933,8 +997,8 @@ hk_status hk_opacity_backward(const hk_lines* lines, const hk_line_override* ovr
   HK_HIP(hk::launch_reduce2(contrib, lines->N, part, kBwdPartials, dL_dT_lnP, stream));
   tm.mark();
   tm.finish();
-  g_tim.prep_ms = g_tim.worklist_ms = g_tim.voigt_ms = g_tim.combine_ms = g_tim.core_ms = -1;
-  g_tim.core_evals = -1;
+  g_tim.prep_ms = g_tim.worklist_ms = g_tim.voigt_ms = g_tim.combine_ms = g_tim.core_ms = g_tim.far_ms = -1;
+  g_tim.core_evals = g_tim.wing_evals = -1;
   g_tim.backward_ms = tm.ms(0);
   return HK_OK;
 }

@@ -19,6 +19,7 @@ constexpr int kSortBlock = kThreads * kSortItems;
 constexpr int kFillPairs = 48;   // pair descriptors per fill launch (kernel-argument space)
 constexpr int kNodes = 16;       // Chebyshev nodes per wave span for lines far from the span
 constexpr float kFarSpans = 1.5f;  // far: centre at least 1.5 spans (3 half-spans) from the span centre
+constexpr double kTileFar = 1.5;   // tile-far: centre at least 1.5 tile widths from the tile centre
 
 // Wavenumber -> bin key: clamp(floor((v - numin) * scale), 0, kmax), evaluated in FP64.
 struct KeyMap {
@@ -49,12 +50,15 @@ struct VoigtArgs {
   const PairDesc* pairs;
   const int32_t* tile_lo;  // per global tile: first line
   const int32_t* tile_hi;  // per global tile: one past the last line
+  const int4* tile_far;    // per global tile: tile-far line ranges [x, y) and [z, w) (not processed here)
   const int32_t* tile_nc;  // per global tile: chunks (work items)
   const int32_t* item_base;// per global tile: first item; [n_tiles_total] = total items
   float* k;
   float* partial;          // [item][tile width]: chunk sums of multi-chunk tiles (each pass its own)
   int* counter;            // work-item dispenser (scheduling only)
-  long long* stats;        // nullable: per-block count of core evaluations (k_core)
+  long long* stats;        // nullable: per-block count of core evaluations (k_core), or per wave of
+                           // evaluations made (k_voigt: 64 P per line evaluated directly, kNodes
+                           // per line evaluated at the span's nodes)
   int64_t N;
   double cut;              // > 0; +inf: no cut
   float zK[kKmax];         // |z| above which the series of order K (1..kKmax) is used
@@ -64,6 +68,29 @@ struct VoigtArgs {
   int32_t items_cap;       // rows of `partial` (work items beyond it are never written)
   const double* cheb_w;    // [kNodes][64 P] Lagrange weights of the span's Chebyshev nodes
   float cheb_x[kNodes];    // node positions relative to the span's first point
+};
+
+// Arguments of the tile-far pass (lines evaluated at the tile's Chebyshev nodes) and its combine.
+struct FarArgs {
+  const double* nu;        // sorted, N
+  const float* S_T;        // [n_temps][N]
+  const float* gT;         // [n_temps][N]
+  const PairDesc* pairs;
+  const int4* tile_far;    // per global tile: [x, y) and [z, w), the tile-far line ranges
+  const int32_t* item_base;// per global tile: first far item; [n_tiles_total] = total far items
+  double* node_part;       // [item][kNodes]: node sums of one work item
+  int* counter;            // work-item dispenser (scheduling only)
+  long long* stats;        // nullable: per-block count of node evaluations
+  const double* tile_w;    // [kNodes][tile width] Lagrange weights of the tile's nodes
+  float* k;
+  int64_t N;
+  float zK[kKmax];
+  int32_t n_pairs;
+  int32_t n_tiles_total;
+  int32_t chunk;           // tile-far lines per work item
+  int32_t items_cap;       // rows of node_part
+  int32_t W;               // tile width in grid points
+  float tile_x[kNodes];    // node positions relative to the tile's first point
 };
 
 struct PrepArgs {
@@ -118,7 +145,8 @@ hipError_t launch_fill_pairs(const PairDesc* host_pairs, int count, PairDesc* ds
 hipError_t launch_worklist(const uint32_t* keys, int64_t N, KeyMap km, double numin, double numax,
                            const PairDesc* pairs,
                            int n_pairs, int n_tiles_total, int tile_w, double cut, double core_z, int chunk,
-                           int32_t* lo, int32_t* hi, int32_t* nc, hipStream_t st);
+                           int32_t* lo, int32_t* hi, int32_t* nc, int4* far, int32_t* nf, int far_chunk,
+                           double far_z, hipStream_t st);
 hipError_t launch_item_scan(const int32_t* nc, int n_tiles_total, int32_t* item_base, int* counter,
                             hipStream_t st);
 hipError_t launch_gridrec(const double* nu, int64_t N, double nu_start, double dnu, int64_t n, double cut,
@@ -130,6 +158,9 @@ hipError_t launch_combine_core(const VoigtArgs& a, int slots, hipStream_t st);
 hipError_t launch_cut_bounds(const double* nu, const int32_t* perm, int64_t N, double nu_start,
                              double dnu, int64_t n, double cut, int32_t* jlo, int32_t* jhi,
                              hipStream_t st);
+hipError_t launch_far(const FarArgs& a, int grid, hipStream_t st);
+hipError_t launch_combine_far(const FarArgs& a, hipStream_t st);
+int far_max_blocks_per_cu();
 hipError_t launch_adjoint(const AdjArgs& a, int grid, hipStream_t st);
 hipError_t launch_reduce2(const double* contrib, int64_t N, double* partial, int n_partial, double* out,
                           hipStream_t st);

@@ -318,13 +318,41 @@ __device__ __forceinline__ int find_pair(const PairDesc* pairs, int n_pairs, int
   return lo;
 }
 
+// Index range [a, b) within [lo, hi) of the lines whose key lies strictly between the keys of
+// v0 and v1 (v0 = -inf / v1 = +inf: unbounded). Keys are monotone in nu, so every such line has
+// v0 < nu < v1 whatever the rounding of the key map; the range may miss a few lines near the
+// bounds, never include one outside.
+__device__ __forceinline__ void key_range(const uint32_t* __restrict__ keys, int64_t lo, int64_t hi, double v0,
+                                          double v1, const KeyMap& km, int64_t& ra, int64_t& rb) {
+  ra = rb = lo;
+  if (!(v0 < v1)) return;
+  const uint32_t kl = isinf(v0) ? 0u : bin_key(v0, km) + 1u;
+  const uint32_t k1 = isinf(v1) ? km.kmax + 1u : bin_key(v1, km);
+  if (k1 == 0u || kl > k1 - 1u) return;
+  const uint32_t kr = k1 - 1u;
+  int64_t a = lo, b = hi;  // first key >= kl
+  while (a < b) { int64_t m = (a + b) >> 1; if (keys[m] < kl) a = m + 1; else b = m; }
+  ra = a;
+  b = hi;                  // first key > kr
+  while (a < b) { int64_t m = (a + b) >> 1; if (keys[m] <= kr) a = m + 1; else b = m; }
+  rb = a;
+}
+
 // core_z > 0: the list for the line-core pass. A line reaches a tile point with |z| < core_z
 // only if its centre lies within core_z alpha of it, and alpha = beta nu <= beta (nu_j1 + cut),
 // so the window shrinks to that half-width (with slack for the FP32 zone test of the core pass).
+// far != null (wing pass): also the tile-far ranges of full tiles, the lines that (1) keep the
+// whole tile inside their cut (with half a grid step to spare), (2) lie at least kTileFar tile
+// widths from the tile centre, and (3) lie farther from the tile than far_z alpha_max, the
+// largest reach of the order-5 zone |z| < far_z (zone half-widths are at most far_z alpha),
+// so that they have no core point and a series order below 5 on the tile. These three facts
+// follow from the bounds alone, so the tile-far pass needs no per-line test and the wing
+// pass skips the ranges; every other line of [lo, hi) stays in the wing pass.
 __global__ void k_worklist(const uint32_t* __restrict__ keys, int64_t N, KeyMap km, double numin, double numax,
                            const PairDesc* __restrict__ pairs, int n_pairs, int n_tiles_total,
                            int tile_w, double cut, double core_z, int chunk, int32_t* __restrict__ lo_out,
-                           int32_t* __restrict__ hi_out, int32_t* __restrict__ nc_out) {
+                           int32_t* __restrict__ hi_out, int32_t* __restrict__ nc_out, int4* __restrict__ far_out,
+                           int32_t* __restrict__ nf_out, int far_chunk, double far_z) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n_tiles_total) return;
   const PairDesc pd = pairs[find_pair(pairs, n_pairs, g)];
@@ -341,7 +369,11 @@ __global__ void k_worklist(const uint32_t* __restrict__ keys, int64_t N, KeyMap 
   if (!isinf(hw)) {
     const double va = __dsub_rn(grid_nu(pd.nu_start, pd.dnu, j0), hw);
     const double vb = __dadd_rn(grid_nu(pd.nu_start, pd.dnu, j1), hw);
-    if (vb < numin || va > numax) { lo_out[g] = 0; hi_out[g] = 0; nc_out[g] = 1; return; }
+    if (vb < numin || va > numax) {
+      lo_out[g] = 0; hi_out[g] = 0; nc_out[g] = 1;
+      if (far_out) { far_out[g] = make_int4(0, 0, 0, 0); nf_out[g] = 0; }
+      return;
+    }
     uint32_t ka = bin_key(va, km), kb = bin_key(vb, km);
     ka = ka > 0 ? ka - 1 : 0;
     kb = kb < km.kmax ? kb + 1 : km.kmax;
@@ -352,11 +384,31 @@ __global__ void k_worklist(const uint32_t* __restrict__ keys, int64_t N, KeyMap 
     while (a < b) { int64_t m = (a + b) >> 1; if (keys[m] <= kb) a = m + 1; else b = m; }
     hi = a;
   }
-  const int64_t cnt = hi - lo;
+  int64_t a1 = lo, b1 = lo, a2 = hi, b2 = hi;
+  if (far_out && j0 + tile_w <= pd.n && hi > lo) {
+    const double nA = grid_nu(pd.nu_start, pd.dnu, j0), nB = grid_nu(pd.nu_start, pd.dnu, j0 + tile_w - 1);
+    const double nc = 0.5 * (nA + nB), half = 0.5 * (nB - nA);
+    const double wlo = isinf(cut) ? numin : fmax(numin, nA - cut);
+    const double whi = isinf(cut) ? numax : fmin(numax, nB + cut);
+    const double amax = pd.beta * fmax(fabs(wlo), fabs(whi));
+    const double dfar = fmax(kTileFar * tile_w * pd.dnu, half + far_z * amax * 1.001 + 2.0 * pd.dnu);
+    const double m = 0.5 * pd.dnu;
+    key_range(keys, lo, hi, isinf(cut) ? -INFINITY : nB - cut + m, nc - dfar, km, a1, b1);
+    key_range(keys, lo, hi, nc + dfar, isinf(cut) ? INFINITY : nA + cut - m, km, a2, b2);
+    if (a1 == b1) a1 = b1 = lo;
+    if (a2 == b2) a2 = b2 = hi;
+    if (b1 > a2) { a1 = b1 = lo; a2 = b2 = hi; }  // cannot happen (disjoint key ranges); kept safe
+  }
+  const int64_t cnt = (a1 - lo) + (a2 - b1) + (hi - b2);
   int64_t nc = (cnt + chunk - 1) / chunk;
   lo_out[g] = (int32_t)lo;
   hi_out[g] = (int32_t)hi;
   nc_out[g] = (int32_t)(nc > 0 ? nc : 1);
+  if (far_out) {
+    far_out[g] = make_int4((int)a1, (int)b1, (int)a2, (int)b2);
+    const int64_t nfl = (b1 - a1) + (b2 - a2);
+    nf_out[g] = (int32_t)((nfl + far_chunk - 1) / far_chunk);
+  }
 }
 
 // item_base = exclusive scan of nc; item_base[n] = total; also resets the item dispenser.
@@ -776,6 +828,7 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
   const int total = a.item_base[a.n_tiles_total];
   const float jl0 = (float)(wv * kWave * P + lane);  // this lane's first tile point
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  long long n_direct = 0, n_node = 0;  // lines this wave evaluated directly / at the span's nodes
 
   for (;;) {
     if (tid == 0) {
@@ -800,10 +853,16 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
     const int chunk_idx = it - ibase;
     const int nc = __builtin_amdgcn_readfirstlane(a.tile_nc[g]);
     const int64_t tile0 = (int64_t)(g - pd.tile_base) * W;
-    const int64_t line_lo = (int64_t)__builtin_amdgcn_readfirstlane(a.tile_lo[g]) + (int64_t)chunk_idx * a.chunk;
-    int64_t line_hi = line_lo + a.chunk;
-    const int64_t thi = __builtin_amdgcn_readfirstlane(a.tile_hi[g]);
-    if (line_hi > thi) line_hi = thi;
+    // this item's lines: positions [v_lo, v_hi) of the tile's lines outside its tile-far ranges,
+    // i.e. of the concatenation [lo, x) + [y, z) + [w, hi)
+    const int tlo = __builtin_amdgcn_readfirstlane(a.tile_lo[g]);
+    const int thi = __builtin_amdgcn_readfirstlane(a.tile_hi[g]);
+    const int4 tf = wave_uniform(a.tile_far[g]);
+    const int n0 = tf.x - tlo, n01 = n0 + (tf.z - tf.y);
+    const int sh1 = tf.y - n0, sh2 = tf.w - n01;  // line = position + shift, per segment
+    const int nv = n01 + (thi - tf.w);
+    const int v_lo = chunk_idx * a.chunk;
+    const int v_hi = v_lo + a.chunk < nv ? v_lo + a.chunk : nv;
     const float* __restrict__ S_T = a.S_T + (int64_t)pd.tidx * a.N;
     const float* __restrict__ gT = a.gT + (int64_t)pd.tidx * a.N;
     const int4* __restrict__ grec = a.grec + (int64_t)pd.gidx * a.N;
@@ -818,12 +877,13 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
     // far lines: this lane's node and its compensated node sum
     const float xnode = (float)(wv * kWave * P) + a.cheb_x[lane & (kNodes - 1)];
     float fpart = 0.0f, fs = 0.0f, fc = 0.0f;
-    for (int64_t b = line_lo; b < line_hi; b += LB) {
+    for (int b = v_lo; b < v_hi; b += LB) {
       // ---- stage one batch of lines: one thread per line
       {
-        const int64_t li = b + tid;
+        const int v = b + tid;
+        const int64_t li = v + (v < n0 ? tlo : (v < n01 ? sh1 : sh2));
         uint32_t codes[kWavesPerWG] = {0u, 0u, 0u, 0u};
-        if (tid < LB && li < line_hi)
+        if (tid < LB && v < v_hi)
           stage_line<P, LB>(L, tid, grec[li], a.nu[li], S_T[li], gT[li], pd, a.zK, tile0, codes);
         if (tid < LB) L.code[tid] = make_uint4(codes[0], codes[1], codes[2], codes[3]);
       }
@@ -860,6 +920,8 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
         }
       }
 
+      n_direct += o[kGroups - 3] - o[1];
+      n_node += o[kGroups + 1] - o[kGroups - 3];
       // ---- accumulate: fast groups, then the general group
       {
         group_loop<P, LB, 1, false>(L, wv, o[1], o[2], jl0, part, s, cc);
@@ -945,6 +1007,182 @@ __global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
       }
     }
     __syncthreads();
+  }
+  if (a.stats && lane == 0) a.stats[blockIdx.x * kWavesPerWG + wv] = n_direct * (kWave * P) + n_node * kNodes;
+}
+
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// --------------------------------------------------------------- tile-far pass
+// The lines of a tile's tile-far ranges (see k_worklist) are smooth on the whole tile: each is
+// evaluated at the tile's kNodes Chebyshev nodes only, one line per lane, with the far-wing
+// series of the order that its nearest tile point needs (the largest over the wave's lines;
+// the ranges' bounds keep it below 5). A work item is a tile and a chunk of its tile-far lines;
+// it writes its kNodes node sums (per lane in FP32 over 16 lines, then FP64; over the
+// workgroup in a fixed order), and k_combine_far adds their interpolation to the tile.
+template <int K>
+__device__ __forceinline__ void far_nodes(const FarArgs& a, float h, float e, float gq, float A, const float4& ka,
+                                          const float4& kb, float kc, float (&acc)[kNodes]) {
+#pragma unroll
+  for (int k = 0; k < kNodes; ++k) {
+    const float D = __builtin_fmaf(a.tile_x[k], h, e);
+    const float R = __builtin_fmaf(D, D, gq);
+    const float q = __builtin_amdgcn_rcpf(R);
+    float t;
+    if (K == 1) {
+      t = A;
+    } else if (K == 2) {
+      t = __builtin_fmaf(ka.y, q, ka.x);
+      t = __builtin_fmaf(t, q, A);
+    } else if (K == 3) {
+      t = __builtin_fmaf(kb.x, q, ka.w);
+      t = __builtin_fmaf(t, q, ka.z);
+      t = __builtin_fmaf(t, q, ka.x);
+      t = __builtin_fmaf(t, q, A);
+    } else {
+      t = __builtin_fmaf(kc, q, kb.w);
+      t = __builtin_fmaf(t, q, kb.z);
+      t = __builtin_fmaf(t, q, kb.y);
+      t = __builtin_fmaf(t, q, ka.z);
+      t = __builtin_fmaf(t, q, ka.x);
+      t = __builtin_fmaf(t, q, A);
+    }
+    acc[k] = __builtin_fmaf(t, q, acc[k]);
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_far(FarArgs a) {
+  __shared__ double sRed[kWavesPerWG][kNodes];
+  __shared__ int sItem, sTile, sPair;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int total = a.item_base[a.n_tiles_total];
+  long long n_lines = 0;
+  for (;;) {
+    if (tid == 0) {
+      const int it = atomicAdd(a.counter, 1);
+      sItem = it;
+      if (it < total) {
+        int lo = 0, hi = a.n_tiles_total - 1;  // last tile with item_base <= it
+        while (lo < hi) {
+          const int m = (lo + hi + 1) >> 1;
+          if (a.item_base[m] <= it) lo = m; else hi = m - 1;
+        }
+        sTile = lo;
+        sPair = find_pair(a.pairs, a.n_pairs, lo);
+      }
+    }
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(sItem);
+    if (it >= total) break;
+    const int g = __builtin_amdgcn_readfirstlane(sTile);
+    const PairDesc pd = wave_uniform(a.pairs[__builtin_amdgcn_readfirstlane(sPair)]);
+    const int ibase = __builtin_amdgcn_readfirstlane(a.item_base[g]);
+    const int4 tf = wave_uniform(a.tile_far[g]);
+    const int nl = tf.y - tf.x, nv = nl + (tf.w - tf.z);
+    const int v_lo = (it - ibase) * a.chunk;
+    const int v_hi = v_lo + a.chunk < nv ? v_lo + a.chunk : nv;
+    n_lines += v_hi > v_lo ? v_hi - v_lo : 0;
+    const int64_t tile0 = (int64_t)(g - pd.tile_base) * a.W;
+    const double nu0 = grid_nu(pd.nu_start, pd.dnu, tile0);
+    const double nu1 = grid_nu(pd.nu_start, pd.dnu, tile0 + a.W - 1);
+    const float dnu_f = (float)pd.dnu, inv_dnu = (float)(1.0 / pd.dnu), pfac = (float)pd.pfac;
+    const float* __restrict__ S_T = a.S_T + (int64_t)pd.tidx * a.N;
+    const float* __restrict__ gT = a.gT + (int64_t)pd.tidx * a.N;
+
+    double acc64[kNodes];
+    float acc[kNodes];
+#pragma unroll
+    for (int k = 0; k < kNodes; ++k) {
+      acc64[k] = 0.0;
+      acc[k] = 0.0f;
+    }
+    int n = 0;
+    for (int b = v_lo; b < v_hi; b += kThreads) {
+      const int v = b + tid;
+      // an idle lane evaluates A = 0 at D = 1 (adds zero)
+      float h = 0.0f, e = 1.0f, gq = 1.0f, A = 0.0f, kc = 0.0f;
+      float4 ka = make_float4(0.f, 0.f, 0.f, 0.f), kb = ka;
+      int K = 1;
+      if (v < v_hi) {
+        const int64_t li = v < nl ? (int64_t)tf.x + v : (int64_t)tf.z + (v - nl);
+        const double nu = a.nu[li];
+        const float S = S_T[li];
+        const float alpha = (float)(nu * pd.beta);
+        const float gam = gT[li] * pfac;
+        const float a2 = alpha * alpha, g2 = gam * gam;
+        const float sc = a2 > g2 ? a2 : g2;
+        if (S > 0.0f && sc > 0.0f) {
+          const float rs = __frsqrt_rn(sc);
+          const float isc = rs * rs;
+          A = S * (gam * isc) * 0.318309886183790672f;  // S gamma / (pi s)
+          gq = g2 * isc;
+          wing_coeffs(a2 * isc, gq, A, ka, kb, kc);
+          h = dnu_f * rs;                                // one grid step in units of sqrt(s)
+          e = -((float)(nu - nu0) * inv_dnu) * h;        // minus the line's position, same units
+          const float dmin = (float)(nu < nu0 ? nu0 - nu : nu - nu1);  // to the nearest tile point
+          const float r2 = dmin * dmin + g2;
+#pragma unroll
+          for (int z = 0; z < kKmax - 1; ++z) K += (a.zK[z] * a.zK[z] * a2 > r2) ? 1 : 0;
+        }
+      }
+      const int Kw = 1 + (__ballot(K >= 2) != 0ull ? 1 : 0) + (__ballot(K >= 3) != 0ull ? 1 : 0) +
+                     (__ballot(K >= 4) != 0ull ? 1 : 0);
+      if (Kw == 1) far_nodes<1>(a, h, e, gq, A, ka, kb, kc, acc);
+      else if (Kw == 2) far_nodes<2>(a, h, e, gq, A, ka, kb, kc, acc);
+      else if (Kw == 3) far_nodes<3>(a, h, e, gq, A, ka, kb, kc, acc);
+      else far_nodes<4>(a, h, e, gq, A, ka, kb, kc, acc);
+      if (++n == 16) {
+#pragma unroll
+        for (int k = 0; k < kNodes; ++k) {
+          acc64[k] += (double)acc[k];
+          acc[k] = 0.0f;
+        }
+        n = 0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kNodes; ++k) {
+      const double t = wave_sum64(acc64[k] + (double)acc[k]);
+      if (lane == 0) sRed[wv][k] = t;
+    }
+    __syncthreads();
+    if (tid < kNodes) {
+      double t = 0.0;
+#pragma unroll
+      for (int w = 0; w < kWavesPerWG; ++w) t += sRed[w][tid];
+      if (it < a.items_cap) a.node_part[(int64_t)it * kNodes + tid] = t;
+    }
+    __syncthreads();
+  }
+  if (a.stats && tid == 0) a.stats[blockIdx.x] = n_lines * kNodes;
+}
+
+// k += interpolation onto the tile of the fixed-order (item 0, 1, ...) sum of its node sums.
+__global__ __launch_bounds__(kThreads) void k_combine_far(FarArgs a) {
+  __shared__ double ns[kNodes];
+  const int g = blockIdx.x;
+  const int base = a.item_base[g], nf = a.item_base[g + 1] - base;
+  if (nf <= 0) return;
+  const PairDesc pd = a.pairs[find_pair(a.pairs, a.n_pairs, g)];
+  if (threadIdx.x < kNodes) {
+    double t = 0.0;
+    for (int c = 0; c < nf && base + c < a.items_cap; ++c) t += a.node_part[(int64_t)(base + c) * kNodes + threadIdx.x];
+    ns[threadIdx.x] = t;
+  }
+  __syncthreads();
+  const int64_t tile0 = (int64_t)(g - pd.tile_base) * a.W;
+  for (int local = threadIdx.x; local < a.W; local += kThreads) {
+    if (tile0 + local >= pd.n) continue;
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < kNodes; ++k) v = fma(ns[k], a.tile_w[k * a.W + local], v);
+    float* dst = a.k + pd.out_off + tile0 + local;
+    *dst = (float)((double)*dst + v);
   }
 }
 
@@ -1247,11 +1485,6 @@ __device__ __forceinline__ void adj_step(const AdjPoly& P, int jc, int lane, int
   }
 }
 
-__device__ __forceinline__ double wave_sum64(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
 
 // One wave per line (static assignment), lanes over its grid points inside the cut.
 // Per-line FP64 quantities of the adjoint, one thread per line (sorted order), kept apart from
@@ -1562,9 +1795,11 @@ hipError_t launch_fill_pairs(const PairDesc* host_pairs, int count, PairDesc* ds
 hipError_t launch_worklist(const uint32_t* keys, int64_t N, KeyMap km, double numin, double numax,
                            const PairDesc* pairs, int n_pairs,
                            int n_tiles_total, int tile_w, double cut, double core_z, int chunk, int32_t* lo,
-                           int32_t* hi, int32_t* nc, hipStream_t st) {
+                           int32_t* hi, int32_t* nc, int4* far, int32_t* nf, int far_chunk, double far_z,
+                           hipStream_t st) {
   hipLaunchKernelGGL(k_worklist, dim3(blocks_for(n_tiles_total, kThreads)), dim3(kThreads), 0, st, keys, N, km,
-                     numin, numax, pairs, n_pairs, n_tiles_total, tile_w, cut, core_z, chunk, lo, hi, nc);
+                     numin, numax, pairs, n_pairs, n_tiles_total, tile_w, cut, core_z, chunk, lo, hi, nc, far, nf,
+                     far_chunk, far_z);
   return hipGetLastError();
 }
 
@@ -1655,6 +1890,23 @@ hipError_t launch_cut_bounds(const double* nu, const int32_t* perm, int64_t N, d
   hipLaunchKernelGGL(k_cut_bounds, dim3(blocks_for(N, kThreads)), dim3(kThreads), 0, st, nu, perm, N, nu_start,
                      dnu, n, cut, jlo, jhi);
   return hipGetLastError();
+}
+
+hipError_t launch_far(const FarArgs& a, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_far, dim3(grid), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine_far(const FarArgs& a, hipStream_t st) {
+  if (a.n_tiles_total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_combine_far, dim3(a.n_tiles_total), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+int far_max_blocks_per_cu() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_far, kThreads, 0) != hipSuccess) return 1;
+  return n > 0 ? n : 1;
 }
 
 hipError_t launch_adjoint(const AdjArgs& a, int grid, hipStream_t st) {
