@@ -303,7 +303,7 @@ def main():
     dt = (time.perf_counter() - t0) / args.steps
     kv_ms = sum(t.voigt_ms for _, t in per) / len(per)
     far_ms = sum(t.far_ms for _, t in per) / len(per)
-    voigt_ms = kv_ms + far_ms  # the wing pass: k_voigt, then the tile-far pass
+    voigt_ms = kv_ms + far_ms  # the wing pass: k_wing, then the tile-far pass
     core_ms = sum(t.core_ms for _, t in per) / len(per)
     tm = per[-1][1]
     core_evals = tm.core_evals
@@ -323,11 +323,10 @@ def main():
         "evals": n_evals, "core_evals": core_evals,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": k_voigt_traffic(N, w.cut, w.dnu, tm.tile_width),
-                     "kernel": "wing pass: k_voigt<%d, %d> + k_far + k_combine_far"
-                               % (tm.tile_width // 256, tm.lines_per_batch),
+                     "kernel": "wing pass: k_wing<%d> + k_far + k_combine_far" % (tm.tile_width // 64),
                      "flops_per_eval": FLOPS_PER_EVAL,
                      "evals_per_launch": made, "avg_launch_ms": voigt_ms,
-                     "k_voigt_ms": kv_ms, "k_far_ms": far_ms,
+                     "k_wing_ms": kv_ms, "k_far_ms": far_ms,
                      "algorithmic_wing_evals": wing_evals,
                      "algorithmic_equivalent_TFLOPs": FLOPS_PER_EVAL * wing_evals / (voigt_ms * 1e-3) / 1e12},
         "phases_ms": {"bin": sum(b for b, _ in per) / len(per), "prep": tm.prep_ms, "worklist": tm.worklist_ms,

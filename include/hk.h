@@ -85,14 +85,14 @@ typedef struct hk_lines hk_lines;
 
 /* Timings and tuning of the last completed call on this thread (milliseconds, filled only
  * when HK_TIMING=1 is set in the environment; otherwise the times are negative).
- * hk_opacity: voigt_ms is the wing kernel, far_ms the tile-far pass (lines far from a whole
+ * hk_opacity: voigt_ms is the wing kernel (spans), far_ms the tile-far pass (lines far from a whole
  * tile, evaluated at its Chebyshev nodes and interpolated), core_ms the line-core kernel,
  * core_evals the number of (line, point) evaluations the core kernel made. hk_opacity_batched: voigt_ms is
  * the whole graph. hk_opacity_backward: backward_ms. */
 typedef struct hk_timings {
   double prep_ms, worklist_ms, voigt_ms, combine_ms, backward_ms, bin_ms;
-  int32_t tile_width;      /* grid points per tile (workgroup) */
-  int32_t lines_per_batch; /* lines staged in LDS per batch */
+  int32_t tile_width;      /* grid points per span (one wave of the wing pass; 64 slots) */
+  int32_t lines_per_batch; /* lines a wave stages in LDS per batch */
   int32_t chunk_lines;     /* lines per work item of a heavy tile */
   int32_t n_items;         /* upper bound of work items of the last call */
   double core_ms;

@@ -75,7 +75,7 @@ int env_int(const char* name, int dflt) {
 
 struct DevInfo {
   int cus = 0;
-  int wg_per_cu[4][2] = {};   // wing kernel occupancy per (slots 1/2/4/8, line batch 128/256)
+  int wing_per_cu[4] = {};    // wing kernel (one-wave workgroups) occupancy per slots 1/2/4/8
   int core_per_cu[4] = {};    // core kernel (one-wave workgroups) occupancy per slots
   double* cheb_w[4] = {};     // device: Lagrange weights of the span nodes, per slots 1/2/4/8
   float cheb_x[4][hk::kNodes] = {};  // node positions relative to the span's first point
@@ -159,8 +159,7 @@ hk_status device_init(int* dev_out, DevInfo* info) {
     DevInfo di;
     di.cus = prop.multiProcessorCount;
     for (int si = 0; si < 4; ++si) {
-      di.wg_per_cu[si][0] = hk::voigt_max_blocks_per_cu(1 << si, 128);
-      di.wg_per_cu[si][1] = hk::voigt_max_blocks_per_cu(1 << si, 256);
+      di.wing_per_cu[si] = hk::wing_max_blocks_per_cu(1 << si);
       di.core_per_cu[si] = hk::core_max_blocks_per_cu(1 << si);
       const int S = hk::kWave << si;
       std::vector<double> wts;
@@ -196,43 +195,45 @@ bool cut_ok(double c) { return c > 0 && (std::isfinite(c) || std::isinf(c)); }
 
 // ------------------------------------------------------------------ forward plan
 struct Plan {
-  int slots = 4, lb = 256, W = 1024;
-  int chunk = 0;
+  int slots = 4;
+  int W = 1024;    // tile width of the tile-far pass (4 spans)
+  int W_c = 256;   // span width of the wing and line-core passes (one wave, 64 slots)
+  int chunk = 0;   // lines per work item of the wing and line-core passes
   int n_pairs = 0, n_temps = 0;
-  int n_tiles_total = 0;
-  int64_t items_bound = 0;
-  int grid = 0;
-  size_t off_S = 0, off_g = 0, off_gr = 0, off_pairs = 0, off_lo = 0, off_hi = 0, off_nc = 0, off_ib = 0,
-         off_cnt = 0, off_part = 0, off_stats = 0, total = 0;
-  // the line-core pass's own work list and partial tiles
-  size_t off_pairs_c = 0, off_lo_c = 0, off_hi_c = 0, off_nc_c = 0, off_ib_c = 0, off_cnt_c = 0, off_part_c = 0;
-  int64_t items_bound_c = 0;
-  int W_c = 256, n_tiles_c = 0, grid_c = 0;
-  // the tile-far pass: per-tile line ranges, its work items and their node sums
-  size_t off_far = 0, off_nf = 0, off_ibf = 0, off_partf = 0;
+  int n_tiles_total = 0;  // tiles
+  int n_tiles_c = 0;      // spans
+  size_t off_S = 0, off_g = 0, off_gr = 0, off_pairs = 0, off_pairs_c = 0, off_cnt = 0, off_stats = 0, total = 0;
+  // the tile-far pass: per-tile window and tile-far ranges, its work items and their node sums
+  size_t off_lo = 0, off_hi = 0, off_nc = 0, off_far = 0, off_nf = 0, off_ibf = 0, off_partf = 0;
   int64_t items_bound_f = 0;
   int chunk_f = 0, grid_f = 0;
-  std::vector<hk::PairDesc> pairs_c;  // the pairs with the core pass's (one-wave) tiling
+  // the wing pass: per-span line segments, work items and partial spans
+  size_t off_segs = 0, off_nc_w = 0, off_ib_w = 0, off_part_w = 0;
+  int64_t items_bound_w = 0;
+  int grid_w = 0;
+  // the line-core pass: per-span line window, work items and partial spans
+  size_t off_lo_c = 0, off_hi_c = 0, off_nc_c = 0, off_ib_c = 0, off_part_c = 0;
+  int64_t items_bound_c = 0;
+  int grid_c = 0;
+  std::vector<hk::PairDesc> pairs;    // the pairs with the tile-far pass's tiling
+  std::vector<hk::PairDesc> pairs_c;  // the pairs with the span tiling (wing and line-core passes)
   int n_grids = 0;
-  std::vector<hk::PairDesc> pairs;
   std::vector<double> temps;
   std::vector<hk_grid> grids;  // distinct grids
 };
 
-// A tuning of the Voigt passes: slots P (wing tile width 256 P points, core tile 64 P) and
-// the wing pass's LDS line batch.
+// A tuning of the Voigt passes: slots P (span width 64 P points, tile width 256 P).
 struct Tuning {
-  int slots = 4, lb = 256;
+  int slots = 4;
 };
 inline int slot_index(int slots) { return slots == 1 ? 0 : slots == 2 ? 1 : slots == 4 ? 2 : 3; }
-const Tuning kCandidates[] = {{1, 256}, {2, 256}, {4, 256}, {8, 256}, {2, 128}, {4, 128}};
+const Tuning kCandidates[] = {{1}, {2}, {4}, {8}};
 
-// The tuning forced by HK_SLOTS / HK_LB, if any.
+// The tuning forced by HK_SLOTS, if any.
 bool env_tuning(Tuning* t) {
-  const int sl = env_int("HK_SLOTS", 0), lb = env_int("HK_LB", 0);
-  if (sl == 0 && lb == 0) return false;
+  const int sl = env_int("HK_SLOTS", 0);
+  if (sl == 0) return false;
   t->slots = (sl == 1 || sl == 2 || sl == 4 || sl == 8) ? sl : 4;
-  t->lb = (lb == 128) ? 128 : 256;
   return true;
 }
 
@@ -249,7 +250,6 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
                     const hk_grid* grids, const int64_t* out_off, double cut, const DevInfo& di, Tuning tu,
                     Plan* pl) {
   pl->slots = tu.slots;
-  pl->lb = tu.lb;
   pl->W = hk::kWavesPerWG * hk::kWave * pl->slots;
   pl->n_pairs = n_pairs;
   const int64_t N = L->N;
@@ -280,9 +280,10 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
     gidx[p] = found;
   }
   pl->n_grids = (int)pl->grids.size();
-  // tiles and the bound on line visits (wing pass, and the narrower windows of the core pass)
+  // tiles, spans and the bounds on line visits (tile windows, span windows, and the narrower
+  // windows of the core pass)
   int64_t tiles = 0, tiles_c = 0;
-  double visits = 0.0, visits_c = 0.0;
+  double visits = 0.0, visits_w = 0.0, visits_c = 0.0;
   pl->W_c = hk::kWave * pl->slots;
   pl->pairs.assign(n_pairs, hk::PairDesc{});
   pl->pairs_c.assign(n_pairs, hk::PairDesc{});
@@ -313,21 +314,22 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
     dc.tile_base = (int32_t)tiles_c;
     dc.n_tiles = (int32_t)nt_c;
     tiles_c += nt_c;
+    visits_w += (double)N * (double)visits_per_line(L, grids[p], cut, pl->W_c, nt_c);
     visits_c += (double)N * (double)visits_per_line(L, grids[p], T ? hc : cut, pl->W_c, nt_c);
   }
   pl->n_tiles_total = (int)tiles;
   pl->n_tiles_c = (int)tiles_c;
-  // work-item size: enough items to balance the persistent grid
-  const int wgs = di.cus * di.wg_per_cu[slot_index(pl->slots)][pl->lb == 256 ? 1 : 0];
-  double c = std::ceil(visits / (64.0 * (wgs > 0 ? wgs : 1024)));
+  // work-item size: enough items to balance the persistent grid of the wing pass
+  const int wgs_w = di.cus * di.wing_per_cu[slot_index(pl->slots)];
+  double c = std::ceil(visits_w / (16.0 * (wgs_w > 0 ? wgs_w : 4096)));
   const int env_chunk = env_int("HK_CHUNK", 0);
   if (env_chunk > 0) c = env_chunk;
-  if (c < hk::kLB) c = hk::kLB;
+  if (c < 256) c = 256;
   if (c > (1 << 22)) c = 1 << 22;
-  pl->chunk = (int)(std::ceil(c / hk::kLB) * hk::kLB);
-  const double items = (double)tiles + std::ceil(visits / pl->chunk);
-  if (items >= 2.0e9) return fail(HK_ENOMEM, "work list too large (%.3g items)", items);
-  pl->items_bound = (int64_t)items;
+  pl->chunk = (int)(std::ceil(c / hk::kWave) * hk::kWave);
+  const double items_w = (double)tiles_c + std::ceil(visits_w / pl->chunk);
+  if (items_w >= 2.0e9) return fail(HK_ENOMEM, "work list too large (%.3g items)", items_w);
+  pl->items_bound_w = (int64_t)items_w;
   const double items_c = (double)tiles_c + std::ceil(visits_c / pl->chunk);
   if (items_c >= 2.0e9) return fail(HK_ENOMEM, "core work list too large (%.3g items)", items_c);
   pl->items_bound_c = (int64_t)items_c;
@@ -340,8 +342,8 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   const double items_f = (double)tiles + std::ceil(visits / pl->chunk_f);
   if (items_f >= 2.0e9) return fail(HK_ENOMEM, "tile-far work list too large (%.3g items)", items_f);
   pl->items_bound_f = (int64_t)items_f;
+  pl->grid_w = (int)std::max<int64_t>(1, std::min<int64_t>(pl->items_bound_w, (int64_t)(wgs_w > 0 ? wgs_w : 4096)));
   pl->grid_f = (int)std::max<int64_t>(1, std::min<int64_t>(pl->items_bound_f, (int64_t)(wgs_f > 0 ? wgs_f : 1024)));
-  pl->grid = (int)std::min<int64_t>(pl->items_bound, (int64_t)(wgs > 0 ? wgs : 1024));
   const int wgs_c = di.cus * di.core_per_cu[slot_index(pl->slots)];
   pl->grid_c = (int)std::max<int64_t>(1, std::min<int64_t>(pl->items_bound_c, (int64_t)(wgs_c > 0 ? wgs_c : 4096)));
   // workspace layout (256-byte aligned sections)
@@ -351,24 +353,25 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   pl->off_g = take(sizeof(float) * (size_t)N * pl->n_temps);
   pl->off_gr = take(sizeof(int4) * (size_t)N * pl->n_grids);
   pl->off_pairs = take(sizeof(hk::PairDesc) * n_pairs);
+  pl->off_pairs_c = take(sizeof(hk::PairDesc) * n_pairs);
+  pl->off_cnt = take(sizeof(int) * 64);
+  pl->off_stats = take(sizeof(long long) * ((size_t)pl->grid_w + pl->grid_c + pl->grid_f));
   pl->off_lo = take(sizeof(int32_t) * tiles);
   pl->off_hi = take(sizeof(int32_t) * tiles);
   pl->off_nc = take(sizeof(int32_t) * tiles);
-  pl->off_ib = take(sizeof(int32_t) * (tiles + 1));
-  pl->off_cnt = take(sizeof(int) * 64);
-  pl->off_part = take(sizeof(float) * (size_t)pl->items_bound * pl->W);
-  pl->off_stats = take(sizeof(long long) * ((size_t)hk::kWavesPerWG * pl->grid + pl->grid_c + pl->grid_f));
-  pl->off_pairs_c = take(sizeof(hk::PairDesc) * n_pairs);
-  pl->off_lo_c = take(sizeof(int32_t) * tiles_c);
-  pl->off_hi_c = take(sizeof(int32_t) * tiles_c);
-  pl->off_nc_c = take(sizeof(int32_t) * tiles_c);
-  pl->off_ib_c = take(sizeof(int32_t) * (tiles_c + 1));
-  pl->off_cnt_c = take(sizeof(int) * 64);
-  pl->off_part_c = take(sizeof(float) * (size_t)pl->items_bound_c * pl->W_c);
   pl->off_far = take(sizeof(int4) * tiles);
   pl->off_nf = take(sizeof(int32_t) * tiles);
   pl->off_ibf = take(sizeof(int32_t) * (tiles + 1));
   pl->off_partf = take(sizeof(double) * hk::kNodes * (size_t)pl->items_bound_f);
+  pl->off_segs = take(sizeof(hk::SpanSeg) * tiles_c);
+  pl->off_nc_w = take(sizeof(int32_t) * tiles_c);
+  pl->off_ib_w = take(sizeof(int32_t) * (tiles_c + 1));
+  pl->off_part_w = take(sizeof(float) * (size_t)pl->items_bound_w * pl->W_c);
+  pl->off_lo_c = take(sizeof(int32_t) * tiles_c);
+  pl->off_hi_c = take(sizeof(int32_t) * tiles_c);
+  pl->off_nc_c = take(sizeof(int32_t) * tiles_c);
+  pl->off_ib_c = take(sizeof(int32_t) * (tiles_c + 1));
+  pl->off_part_c = take(sizeof(float) * (size_t)pl->items_bound_c * pl->W_c);
   pl->total = off;
   return HK_OK;
 }
@@ -452,68 +455,76 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
     HK_HIP(hk::launch_gridrec(L->nu, L->N, pl.grids[q].nu_start, pl.grids[q].dnu, pl.grids[q].n, cut,
                               grec + (size_t)q * L->N, st));
   tm.mark();
+  // work lists: tile windows and tile-far ranges, span segments, span core windows
+  const double far_z = kZK[hk::kKmax - 2], core_z = kZK[hk::kKmax - 1];
   hk::PairDesc* dpairs = reinterpret_cast<hk::PairDesc*>(ws + pl.off_pairs);
+  hk::PairDesc* dpairs_c = reinterpret_cast<hk::PairDesc*>(ws + pl.off_pairs_c);
+  int* cnt = reinterpret_cast<int*>(ws + pl.off_cnt);  // dispensers: wing [0], core [8], tile-far [16]
   int32_t* lo = reinterpret_cast<int32_t*>(ws + pl.off_lo);
   int32_t* hi = reinterpret_cast<int32_t*>(ws + pl.off_hi);
   int32_t* nc = reinterpret_cast<int32_t*>(ws + pl.off_nc);
-  int32_t* ib = reinterpret_cast<int32_t*>(ws + pl.off_ib);
-  int* cnt = reinterpret_cast<int*>(ws + pl.off_cnt);
-  HK_HIP(hk::launch_fill_pairs(pl.pairs.data(), pl.n_pairs, dpairs, st));
   int4* tfar = reinterpret_cast<int4*>(ws + pl.off_far);
   int32_t* nf = reinterpret_cast<int32_t*>(ws + pl.off_nf);
   int32_t* ibf = reinterpret_cast<int32_t*>(ws + pl.off_ibf);
-  int* cnt_f = cnt + 16;
-  HK_HIP(hk::launch_worklist(L->keys, L->N, L->km, L->numin, L->numax, dpairs, pl.n_pairs, pl.n_tiles_total,
-                             pl.W, cut, 0.0, pl.chunk, lo, hi, nc, tfar, nf, pl.chunk_f, kZK[hk::kKmax - 2], st));
-  HK_HIP(hk::launch_item_scan(nc, pl.n_tiles_total, ib, cnt, st));
-  HK_HIP(hk::launch_item_scan(nf, pl.n_tiles_total, ibf, cnt_f, st));
+  hk::SpanSeg* segs = reinterpret_cast<hk::SpanSeg*>(ws + pl.off_segs);
+  int32_t* nc_w = reinterpret_cast<int32_t*>(ws + pl.off_nc_w);
+  int32_t* ib_w = reinterpret_cast<int32_t*>(ws + pl.off_ib_w);
   int32_t* lo_c = reinterpret_cast<int32_t*>(ws + pl.off_lo_c);
   int32_t* hi_c = reinterpret_cast<int32_t*>(ws + pl.off_hi_c);
   int32_t* nc_c = reinterpret_cast<int32_t*>(ws + pl.off_nc_c);
   int32_t* ib_c = reinterpret_cast<int32_t*>(ws + pl.off_ib_c);
-  int* cnt_c = reinterpret_cast<int*>(ws + pl.off_cnt_c);
-  hk::PairDesc* dpairs_c = reinterpret_cast<hk::PairDesc*>(ws + pl.off_pairs_c);
+  HK_HIP(hk::launch_fill_pairs(pl.pairs.data(), pl.n_pairs, dpairs, st));
   HK_HIP(hk::launch_fill_pairs(pl.pairs_c.data(), pl.n_pairs, dpairs_c, st));
+  HK_HIP(hk::launch_worklist(L->keys, L->N, L->km, L->numin, L->numax, dpairs, pl.n_pairs, pl.n_tiles_total,
+                             pl.W, cut, 0.0, pl.chunk, lo, hi, nc, tfar, nf, pl.chunk_f, far_z, st));
+  HK_HIP(hk::launch_item_scan(nf, pl.n_tiles_total, ibf, cnt + 16, st));
+  HK_HIP(hk::launch_span_segments(L->keys, L->N, L->km, L->numin, L->numax, dpairs_c, dpairs, pl.n_pairs,
+                                  pl.n_tiles_c, pl.W_c, cut, far_z, tfar, pl.chunk, segs, nc_w, st));
+  HK_HIP(hk::launch_item_scan(nc_w, pl.n_tiles_c, ib_w, cnt, st));
   HK_HIP(hk::launch_worklist(L->keys, L->N, L->km, L->numin, L->numax, dpairs_c, pl.n_pairs, pl.n_tiles_c,
-                             pl.W_c, cut, kZK[hk::kKmax - 1], pl.chunk, lo_c, hi_c, nc_c, nullptr, nullptr, 1,
-                             0.0, st));
-  HK_HIP(hk::launch_item_scan(nc_c, pl.n_tiles_c, ib_c, cnt_c, st));
+                             pl.W_c, cut, core_z, pl.chunk, lo_c, hi_c, nc_c, nullptr, nullptr, 1, 0.0, st));
+  HK_HIP(hk::launch_item_scan(nc_c, pl.n_tiles_c, ib_c, cnt + 8, st));
   tm.mark();
+  int dev = 0;
+  DevInfo di;
+  hk_status ds = device_init(&dev, &di);
+  if (ds != HK_OK) return ds;
+  const int si = slot_index(pl.slots);
+  // evaluation counts (timed calls only): per workgroup of the wing, core and tile-far kernels
+  long long* stats = reinterpret_cast<long long*>(ws + pl.off_stats);
+  long long* stats_c = stats + pl.grid_w;
+  long long* stats_f = stats_c + pl.grid_c;
+  // wing pass over spans
   hk::VoigtArgs va;
   memset(&va, 0, sizeof va);
   va.nu = L->nu;
   va.S_T = S_T;
   va.gT = gT;
   va.grec = grec;
-  va.pairs = dpairs;
-  va.tile_lo = lo;
-  va.tile_hi = hi;
-  va.tile_far = tfar;
-  va.tile_nc = nc;
-  va.item_base = ib;
+  va.pairs = dpairs_c;
+  va.segs = segs;
+  va.tile_nc = nc_w;
+  va.item_base = ib_w;
   va.k = k;
-  va.partial = reinterpret_cast<float*>(ws + pl.off_part);
+  va.partial = reinterpret_cast<float*>(ws + pl.off_part_w);
   va.counter = cnt;
+  va.stats = tm.on ? stats : nullptr;
   va.N = L->N;
   va.cut = cut;
   for (int i = 0; i < hk::kKmax; ++i) va.zK[i] = (float)kZK[i];
   va.n_pairs = pl.n_pairs;
-  va.n_tiles_total = pl.n_tiles_total;
+  va.n_tiles_total = pl.n_tiles_c;
   va.chunk = pl.chunk;
-  va.items_cap = (int32_t)std::min<int64_t>(pl.items_bound, INT32_MAX);
+  va.items_cap = (int32_t)std::min<int64_t>(pl.items_bound_w, INT32_MAX);
+  va.cheb_w = di.cheb_w[si];
+  for (int q = 0; q < hk::kNodes; ++q) va.cheb_x[q] = di.cheb_x[si][q];
+  HK_HIP(hk::launch_wing(va, pl.slots, pl.grid_w, st));
+  tm.mark();
+  HK_HIP(hk::launch_combine(va, pl.slots, false, st));
+  tm.mark();
+  // tile-far pass
   hk::FarArgs fa;
   memset(&fa, 0, sizeof fa);
-  {
-    int dev = 0;
-    DevInfo di;
-    hk_status ds = device_init(&dev, &di);
-    if (ds != HK_OK) return ds;
-    const int si = slot_index(pl.slots);
-    va.cheb_w = di.cheb_w[si];
-    for (int k = 0; k < hk::kNodes; ++k) va.cheb_x[k] = di.cheb_x[si][k];
-    fa.tile_w = di.tile_w[si];
-    for (int k = 0; k < hk::kNodes; ++k) fa.tile_x[k] = di.tile_x[si][k];
-  }
   fa.nu = L->nu;
   fa.S_T = S_T;
   fa.gT = gT;
@@ -521,7 +532,9 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   fa.tile_far = tfar;
   fa.item_base = ibf;
   fa.node_part = reinterpret_cast<double*>(ws + pl.off_partf);
-  fa.counter = cnt_f;
+  fa.counter = cnt + 16;
+  fa.stats = tm.on ? stats_f : nullptr;
+  fa.tile_w = di.tile_w[si];
   fa.k = k;
   fa.N = L->N;
   for (int i = 0; i < hk::kKmax; ++i) fa.zK[i] = (float)kZK[i];
@@ -530,34 +543,23 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   fa.chunk = pl.chunk_f;
   fa.items_cap = (int32_t)std::min<int64_t>(pl.items_bound_f, INT32_MAX);
   fa.W = pl.W;
-  // evaluation counts (timed calls only): k_voigt per wave, then k_core and k_far per block
-  long long* stats = reinterpret_cast<long long*>(ws + pl.off_stats);
-  long long* stats_c = stats + (size_t)hk::kWavesPerWG * pl.grid;
-  long long* stats_f = stats_c + pl.grid_c;
-  va.stats = tm.on ? stats : nullptr;
-  fa.stats = tm.on ? stats_f : nullptr;
-  HK_HIP(hk::launch_voigt(va, pl.slots, pl.lb, pl.grid, st));
-  tm.mark();
-  HK_HIP(hk::launch_combine(va, pl.slots, st));
-  tm.mark();
+  for (int q = 0; q < hk::kNodes; ++q) fa.tile_x[q] = di.tile_x[si][q];
   HK_HIP(hk::launch_far(fa, pl.grid_f, st));
   HK_HIP(hk::launch_combine_far(fa, st));
   tm.mark();
   // line-core pass over its own (narrower) work list, after the wing sums are final
   hk::VoigtArgs vc = va;
-  vc.pairs = dpairs_c;
-  vc.n_tiles_total = pl.n_tiles_c;
+  vc.segs = nullptr;
   vc.tile_lo = lo_c;
   vc.tile_hi = hi_c;
   vc.tile_nc = nc_c;
   vc.item_base = ib_c;
-  vc.counter = cnt_c;
+  vc.counter = cnt + 8;
   vc.partial = reinterpret_cast<float*>(ws + pl.off_part_c);
   vc.items_cap = (int32_t)std::min<int64_t>(pl.items_bound_c, INT32_MAX);
   vc.stats = tm.on ? stats_c : nullptr;
-  const int grid_c = pl.grid_c;
-  HK_HIP(hk::launch_core(vc, pl.slots, grid_c, st));
-  HK_HIP(hk::launch_combine_core(vc, pl.slots, st));
+  HK_HIP(hk::launch_core(vc, pl.slots, pl.grid_c, st));
+  HK_HIP(hk::launch_combine(vc, pl.slots, true, st));
   tm.mark();
   tm.finish();
   g_tim.prep_ms = tm.ms(0);
@@ -570,18 +572,18 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   g_tim.core_evals = -1;
   g_tim.wing_evals = -1;
   if (tm.on) {
-    const size_t nw = (size_t)hk::kWavesPerWG * pl.grid;
-    std::vector<long long> h(nw + grid_c + pl.grid_f);
+    std::vector<long long> h((size_t)pl.grid_w + pl.grid_c + pl.grid_f);
     HK_HIP(hipMemcpy(h.data(), stats, sizeof(long long) * h.size(), hipMemcpyDeviceToHost));
     long long tw = 0, tc = 0;
-    for (size_t i = 0; i < h.size(); ++i) (i >= nw && i < nw + grid_c ? tc : tw) += h[i];
+    for (size_t i = 0; i < h.size(); ++i)
+      (i >= (size_t)pl.grid_w && i < (size_t)pl.grid_w + pl.grid_c ? tc : tw) += h[i];
     g_tim.core_evals = tc;
     g_tim.wing_evals = tw;
   }
-  g_tim.tile_width = pl.W;
-  g_tim.lines_per_batch = pl.lb;
+  g_tim.tile_width = pl.W_c;
+  g_tim.lines_per_batch = hk::kWave;
   g_tim.chunk_lines = pl.chunk;
-  g_tim.n_items = (int32_t)pl.items_bound;
+  g_tim.n_items = (int32_t)pl.items_bound_w;
   return HK_OK;
 }
 
@@ -642,7 +644,7 @@ hk_status choose_tuning(const hk_lines* L, const hk_line_override* ovr, int n_pa
     HK_HIP(hipEventSynchronize(e1));
     float ms = 0.0f;
     HK_HIP(hipEventElapsedTime(&ms, e0, e1));
-    if (tu.slots == Tuning{}.slots && tu.lb == Tuning{}.lb) default_ms = ms;
+    if (tu.slots == Tuning{}.slots) default_ms = ms;
     if (!have || ms < best_ms) { best_ms = ms; *out = tu; have = true; }
   }
   // keep the default unless another tuning is clearly faster (timing noise must not flip it)
@@ -898,7 +900,6 @@ hk_status hk_opacity_batched(const hk_lines* lines, int32_t n_pairs, const doubl
   put(&cutoff, sizeof cutoff);
   put(&n_pairs, sizeof n_pairs);
   put(&pl.slots, sizeof pl.slots);
-  put(&pl.lb, sizeof pl.lb);
   put(&pl.chunk, sizeof pl.chunk);
   put(T, sizeof(double) * n_pairs);
   put(P_atm, sizeof(double) * n_pairs);
@@ -942,10 +943,10 @@ hk_status hk_opacity_batched(const hk_lines* lines, int32_t n_pairs, const doubl
   g_tim.voigt_ms = tm.ms(0);  // whole graph
   g_tim.core_ms = g_tim.far_ms = -1;
   g_tim.core_evals = g_tim.wing_evals = -1;
-  g_tim.tile_width = pl.W;
-  g_tim.lines_per_batch = pl.lb;
+  g_tim.tile_width = pl.W_c;
+  g_tim.lines_per_batch = hk::kWave;
   g_tim.chunk_lines = pl.chunk;
-  g_tim.n_items = (int32_t)pl.items_bound;
+  g_tim.n_items = (int32_t)pl.items_bound_w;
   return HK_OK;
 }
 

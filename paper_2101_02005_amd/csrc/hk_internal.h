@@ -7,9 +7,8 @@
 namespace hk {
 
 constexpr int kWave = 64;        // CDNA wavefront width
-constexpr int kThreads = 256;    // threads per workgroup of the Voigt and sort kernels
-constexpr int kWavesPerWG = kThreads / kWave;
-constexpr int kLB = 256;         // largest LDS line batch of the wing pass (one line per thread)
+constexpr int kThreads = 256;    // threads per workgroup of the tile-far and sort kernels
+constexpr int kWavesPerWG = kThreads / kWave;  // spans per tile of the tile-far pass
 constexpr int kKmax = 5;         // highest order of the far-wing series
 constexpr int kWeidN = 20;       // terms of the FP64 core rational approximation
 constexpr int kKeyBits = 24;     // linear wavenumber-bin key width
@@ -41,29 +40,39 @@ struct PairDesc {
   int32_t gidx;       // which grid-record array (pairs with equal grids share one)
 };
 
-// Arguments of the persistent Voigt kernel.
+// The lines of one span (64 P grid points, one wave of the wing pass) as segments of the
+// sorted list, in list order; the tile-far ranges of its tile are left out.
+constexpr int kMaxSeg = 9;
+struct SpanSeg {
+  int32_t lo[kMaxSeg];   // first line of segment q
+  int32_t len[kMaxSeg];  // its line count
+  int32_t far_mask;      // bit q: segment q is far from the span (evaluated at the span's nodes)
+  int32_t n;             // segment count
+};
+
+// Arguments of the persistent Voigt kernels (wing pass over spans, line-core pass).
 struct VoigtArgs {
   const double* nu;        // sorted, N
   const float* S_T;        // [n_temps][N] strength at T
   const float* gT;         // [n_temps][N] gamma_ref (T_ref/T)^n
   const int4* grec;        // [n_grids][N] (offset bits, reference index, cut lo, cut hi)
   const PairDesc* pairs;
-  const int32_t* tile_lo;  // per global tile: first line
-  const int32_t* tile_hi;  // per global tile: one past the last line
-  const int4* tile_far;    // per global tile: tile-far line ranges [x, y) and [z, w) (not processed here)
-  const int32_t* tile_nc;  // per global tile: chunks (work items)
-  const int32_t* item_base;// per global tile: first item; [n_tiles_total] = total items
+  const int32_t* tile_lo;  // core pass, per span: first line
+  const int32_t* tile_hi;  // core pass, per span: one past the last line
+  const SpanSeg* segs;     // wing pass, per span: its line segments
+  const int32_t* tile_nc;  // per span: chunks (work items)
+  const int32_t* item_base;// per span: first item; [n_tiles_total] = total items
   float* k;
-  float* partial;          // [item][tile width]: chunk sums of multi-chunk tiles (each pass its own)
+  float* partial;          // [item][64 P]: chunk sums of multi-chunk spans (each pass its own)
   int* counter;            // work-item dispenser (scheduling only)
-  long long* stats;        // nullable: per-block count of core evaluations (k_core), or per wave of
-                           // evaluations made (k_voigt: 64 P per line evaluated directly, kNodes
-                           // per line evaluated at the span's nodes)
+  long long* stats;        // nullable: per-wave count of the evaluations made: core evaluations
+                           // (k_core), or 64 P per line evaluated directly plus kNodes per line
+                           // evaluated at the span's nodes (k_wing)
   int64_t N;
   double cut;              // > 0; +inf: no cut
   float zK[kKmax];         // |z| above which the series of order K (1..kKmax) is used
   int32_t n_pairs;
-  int32_t n_tiles_total;
+  int32_t n_tiles_total;   // spans
   int32_t chunk;           // lines per work item
   int32_t items_cap;       // rows of `partial` (work items beyond it are never written)
   const double* cheb_w;    // [kNodes][64 P] Lagrange weights of the span's Chebyshev nodes
@@ -151,10 +160,14 @@ hipError_t launch_item_scan(const int32_t* nc, int n_tiles_total, int32_t* item_
                             hipStream_t st);
 hipError_t launch_gridrec(const double* nu, int64_t N, double nu_start, double dnu, int64_t n, double cut,
                           int4* grec, hipStream_t st);
-hipError_t launch_voigt(const VoigtArgs& a, int slots, int lb, int grid, hipStream_t st);
+hipError_t launch_span_segments(const uint32_t* keys, int64_t N, KeyMap km, double numin, double numax,
+                                const PairDesc* spairs, const PairDesc* tpairs, int n_pairs, int n_spans,
+                                int span_w, double cut, double far_z, const int4* tile_far, int chunk,
+                                SpanSeg* segs, int32_t* nc, hipStream_t st);
+hipError_t launch_wing(const VoigtArgs& a, int slots, int grid, hipStream_t st);
 hipError_t launch_core(const VoigtArgs& a, int slots, int grid, hipStream_t st);
-hipError_t launch_combine(const VoigtArgs& a, int slots, hipStream_t st);
-hipError_t launch_combine_core(const VoigtArgs& a, int slots, hipStream_t st);
+// k = (add ? k : 0) + fixed-order sum of the partial spans of multi-item spans
+hipError_t launch_combine(const VoigtArgs& a, int slots, bool add, hipStream_t st);
 hipError_t launch_cut_bounds(const double* nu, const int32_t* perm, int64_t N, double nu_start,
                              double dnu, int64_t n, double cut, int32_t* jlo, int32_t* jhi,
                              hipStream_t st);
@@ -164,7 +177,7 @@ int far_max_blocks_per_cu();
 hipError_t launch_adjoint(const AdjArgs& a, int grid, hipStream_t st);
 hipError_t launch_reduce2(const double* contrib, int64_t N, double* partial, int n_partial, double* out,
                           hipStream_t st);
-int voigt_max_blocks_per_cu(int slots, int lb);
+int wing_max_blocks_per_cu(int slots);
 int core_max_blocks_per_cu(int slots);
 hipError_t upload_weideman(const double* coef, double L);
 

@@ -411,6 +411,87 @@ __global__ void k_worklist(const uint32_t* __restrict__ keys, int64_t N, KeyMap 
   }
 }
 
+// Line segments of each span of the wing pass: the span's window of lines (as in k_worklist),
+// minus the tile-far ranges of its tile (evaluated by the tile-far pass), split into far
+// segments -- lines that keep the whole span inside their cut (half a grid step to spare), lie
+// at least kFarSpans spans from the span centre and farther from the span than the reach of the
+// order-5 zone (far_z alpha_max), so that they have no core point and an order below 5 there,
+// all from the bounds alone -- and direct segments (every other line), in list order.
+__global__ void k_span_segments(const uint32_t* __restrict__ keys, int64_t N, KeyMap km, double numin,
+                                double numax, const PairDesc* __restrict__ spairs,
+                                const PairDesc* __restrict__ tpairs, int n_pairs, int n_spans, int span_w,
+                                double cut, double far_z, const int4* __restrict__ tile_far, int chunk,
+                                SpanSeg* __restrict__ segs, int32_t* __restrict__ nc_out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_spans) return;
+  const int p = find_pair(spairs, n_pairs, g);
+  const PairDesc pd = spairs[p];
+  const int64_t t = g - pd.tile_base;
+  const int64_t j0 = t * span_w;
+  const int64_t j1 = (j0 + span_w < pd.n ? j0 + span_w : pd.n) - 1;
+  const double nA = grid_nu(pd.nu_start, pd.dnu, j0), nB = grid_nu(pd.nu_start, pd.dnu, j1);
+  SpanSeg sg;
+  sg.n = 0;
+  sg.far_mask = 0;
+  int64_t lo = 0, hi = N;
+  if (!isinf(cut)) {
+    const double va = __dsub_rn(nA, cut), vb = __dadd_rn(nB, cut);
+    if (vb < numin || va > numax) { segs[g] = sg; nc_out[g] = 1; return; }
+    uint32_t ka = bin_key(va, km), kb = bin_key(vb, km);
+    ka = ka > 0 ? ka - 1 : 0;
+    kb = kb < km.kmax ? kb + 1 : km.kmax;
+    int64_t a = 0, b = N;  // first key >= ka
+    while (a < b) { int64_t m = (a + b) >> 1; if (keys[m] < ka) a = m + 1; else b = m; }
+    lo = a;
+    b = N;                 // first key > kb
+    while (a < b) { int64_t m = (a + b) >> 1; if (keys[m] <= kb) a = m + 1; else b = m; }
+    hi = a;
+  }
+  // tile-far ranges of the span's tile
+  int64_t ta1 = lo, tb1 = lo, ta2 = hi, tb2 = hi;
+  if (tile_far) {
+    const int4 tf = tile_far[tpairs[p].tile_base + (int)(t / kWavesPerWG)];
+    ta1 = tf.x; tb1 = tf.y; ta2 = tf.z; tb2 = tf.w;
+  }
+  // far ranges of the span (full spans only)
+  int64_t fa1 = lo, fb1 = lo, fa2 = hi, fb2 = hi;
+  if (j0 + span_w <= pd.n && hi > lo) {
+    const double c = 0.5 * (nA + nB), half = 0.5 * (nB - nA);
+    const double wlo = isinf(cut) ? numin : fmax(numin, nA - cut);
+    const double whi = isinf(cut) ? numax : fmin(numax, nB + cut);
+    const double amax = pd.beta * fmax(fabs(wlo), fabs(whi));
+    const double d = fmax((double)kFarSpans * span_w * pd.dnu, half + far_z * amax * 1.001 + 2.0 * pd.dnu);
+    const double m = 0.5 * pd.dnu;
+    key_range(keys, lo, hi, isinf(cut) ? -INFINITY : nB - cut + m, c - d, km, fa1, fb1);
+    key_range(keys, lo, hi, c + d, isinf(cut) ? INFINITY : nA + cut - m, km, fa2, fb2);
+  }
+  // elementary intervals between all range ends, in order; tile-far ones are left out
+  int64_t bp[10] = {lo, hi, fa1, fb1, fa2, fb2, ta1, tb1, ta2, tb2};
+  for (int i = 0; i < 10; ++i) bp[i] = bp[i] < lo ? lo : (bp[i] > hi ? hi : bp[i]);
+  for (int i = 1; i < 10; ++i)
+    for (int j = i; j > 0 && bp[j - 1] > bp[j]; --j) { const int64_t x = bp[j]; bp[j] = bp[j - 1]; bp[j - 1] = x; }
+  int64_t total = 0;
+  for (int i = 0; i + 1 < 10; ++i) {
+    const int64_t x = bp[i], y = bp[i + 1];
+    if (x >= y) continue;
+    if ((x >= ta1 && y <= tb1) || (x >= ta2 && y <= tb2)) continue;
+    const int far = ((x >= fa1 && y <= fb1) || (x >= fa2 && y <= fb2)) ? 1 : 0;
+    const int q = sg.n - 1;
+    if (q >= 0 && (int64_t)sg.lo[q] + sg.len[q] == x && ((sg.far_mask >> q) & 1) == far) {
+      sg.len[q] += (int32_t)(y - x);
+    } else if (sg.n < kMaxSeg) {
+      sg.lo[sg.n] = (int32_t)x;
+      sg.len[sg.n] = (int32_t)(y - x);
+      sg.far_mask |= far << sg.n;
+      ++sg.n;
+    }
+    total += y - x;
+  }
+  segs[g] = sg;
+  const int64_t nc = (total + chunk - 1) / chunk;
+  nc_out[g] = (int32_t)(nc > 0 ? nc : 1);
+}
+
 // item_base = exclusive scan of nc; item_base[n] = total; also resets the item dispenser.
 __global__ __launch_bounds__(1024) void k_item_scan(const int32_t* __restrict__ nc, int n,
                                                     int32_t* __restrict__ item_base, int* counter) {
@@ -492,31 +573,42 @@ __global__ __launch_bounds__(kThreads) void k_gridrec(const double* __restrict__
   grec[i] = make_int4(__float_as_int((float)delta), (int)jref, (int)jlo, (int)jhi);
 }
 
-// Line record layout in LDS (structure of arrays, one entry per staged line):
-//   F0 = (dh, jt, dnh, gh): offset delta/sqrt(s), reference index - tile start, dnu/sqrt(s),
+// Per-wave record of the lines of a direct segment staged in LDS (structure of arrays, one
+// entry per lane):
+//   F0 = (dh, jt, dnh, gh): offset delta/sqrt(s), reference index - span start, dnu/sqrt(s),
 //        gamma^2/s, with s = max(alpha^2, gamma^2)
 //   F1 = (Ah, lo_rel, hi_rel, a): S gamma/(pi s), cut bounds relative to the reference
 //        index, alpha^2/s
-//   KA, KB, KC: Ah times the far-wing series coefficients of orders 2-4 (see wing_coeffs);
-//        order 5 is formed on the fly from a = alpha^2/s and g = gamma^2/s
+//   KA, KB, KC: Ah times the far-wing series coefficients of orders 2-4 (see wing_coeffs)
+//   K5, K5C: c4-c7 and c8 of order 5 (c1-c3 as order 4), for lines that need it
 //   CZ: the line's core points (|z| below the last series threshold) within its cut range,
-//       as an inclusive tile-local range (empty: x > y)
-//   code[w]: for wave w, bits 0-2 series order K used for its wing points (0: the line does
-//            not reach the wave), bit 3 some lanes fall outside the cut range, bit 4 some of
-//            its points are core points
-//   list[w]: the staged lines reaching wave w, grouped by series order (see line_group)
-template <int LB>
-struct LineLDS {
-  float4 F0[LB];
-  float4 F1[LB];
-  float4 KA[LB];   // c1, c2(K=2), c2(K>=3), c3(K=3)
-  float4 KB[LB];   // c4(K=3), c3(K=4), c4(K=4), c5(K=4)
-  float KC[LB];    // c6(K=4)
-  int2 CZ[LB];
-  uint4 code[LB];  // component w: the code word of wave w
-  uint8_t list[kWavesPerWG][LB];
+//       as an inclusive span-local range (empty: x > y)
+//   list: the staged lines that reach the span, grouped by how they are evaluated (see
+//         direct_group), in staging order within a group
+//   node: the span's node sums of the item's far lines
+struct WaveLDS {
+  float4 F0[kWave];
+  float4 F1[kWave];
+  float4 KA[kWave];  // c1, c2(K=2), c2(K>=3), c3(K=3)
+  float4 KB[kWave];  // c4(K=3), c3(K=4), c4(K=4), c5(K=4)
+  float KC[kWave];   // c6(K=4)
+  float4 K5[kWave];  // c4-c7(K=5)
+  float K5C[kWave];  // c8(K=5)
+  int2 CZ[kWave];
+  uint8_t list[kWave];
+  double node[kNodes];
 };
 
+// Evaluation group of a staged line: 0 does not reach the span; 1-4 all points inside the cut,
+// no core points, series order 1-4; 5-8 the same with some points outside the cut; 9 general
+// (order 5 or core points on the span).
+constexpr int kDirectGroups = 9;
+__device__ __forceinline__ int direct_group(uint32_t code) {
+  if (code == 0u) return 0;
+  const int K = (int)(code & 7u);
+  if ((code & 16u) || K > 4) return 9;
+  return (code & 8u) ? 4 + K : K;
+}
 // Far-wing series of the Voigt profile in q = 1/(D^2 + gamma^2), from the asymptotic
 // expansion w(z) ~ (i/sqrt(pi)) sum_k (2k-1)!!/(2^k z^(2k+1)): with t = alpha^2 q and
 // u = gamma^2 q,  V = (S gamma/pi) q sum_{k<K} a_k t^k P_k(u), a_k = (2k-1)!!/2^k,
@@ -572,81 +664,74 @@ __device__ __forceinline__ bool core_rel(float alpha, float gam, float delta, fl
   return rlo <= rhi;
 }
 
-// Stage one line for a tile from its grid record and its strength/width at T: the FP32
-// quantities the waves need, and for each wave its code word. Lines that do not reach the
-// tile keep code 0 for every wave. Every decision that needs FP64 (cut bounds, reference
-// point, offset) is already in the grid record; the rest needs ~1e-7 and is done in FP32
-// (products ordered so that no intermediate underflows for relevant lines).
-template <int P, int LB>
-__device__ __forceinline__ void stage_line(LineLDS<LB>& L, int tid, const int4 gr, double nu0, float S, float gTv,
-                                           const PairDesc& pd, const float* zK, int64_t tile0,
-                                           uint32_t (&codes)[kWavesPerWG]) {
-  constexpr int W = kWavesPerWG * kWave * P;
+// Stage one line for a span (64 P points from global point span0) from its grid record and its
+// strength/width at T: the FP32 quantities of the evaluation, and the code word: bits 0-2 the
+// series order K its span points need (0: the line does not reach the span), bit 3 some
+// points fall outside its cut range, bit 4 some of its points are core points. Every decision
+// that needs FP64 (cut bounds, reference point, offset) is already in the grid record; the
+// rest needs ~1e-7 and is done in FP32 (products ordered so that no intermediate underflows
+// for relevant lines).
+template <int P>
+__device__ __forceinline__ uint32_t stage_span_line(WaveLDS& L, int lane, const int4 gr, double nu0, float S,
+                                                    float gTv, const PairDesc& pd, const float* zK, int64_t span0) {
+  constexpr int W = kWave * P;
   const int jref = gr.y, jlo = gr.z, jhi = gr.w;
-  if (!(S > 0.0f) || jlo > jhi || (int64_t)jhi < tile0 || (int64_t)jlo > tile0 + (W - 1)) return;
+  if (!(S > 0.0f) || jlo > jhi || (int64_t)jhi < span0 || (int64_t)jlo > span0 + (W - 1)) return 0u;
   const float alpha = (float)(nu0 * pd.beta);
   const float gam = gTv * (float)pd.pfac;
   const float a2 = alpha * alpha, g2 = gam * gam;
   const float sc = a2 > g2 ? a2 : g2;
-  if (!(sc > 0.0f)) return;
+  if (!(sc > 0.0f)) return 0u;
   const float rs = __frsqrt_rn(sc);
   const float isc = rs * rs;
   const float delta = __int_as_float(gr.x);
-  const int jt = (int)((int64_t)jref - tile0);
+  const int jt = (int)((int64_t)jref - span0);
   const float Ah = S * (gam * isc) * 0.318309886183790672f;  // S gamma / (pi s)
-  L.F0[tid] = make_float4(delta * rs, (float)jt, (float)pd.dnu * rs, g2 * isc);
-  L.F1[tid] = make_float4(Ah, (float)(jlo - jref), (float)(jhi - jref), a2 * isc);
-  wing_coeffs(a2 * isc, g2 * isc, Ah, L.KA[tid], L.KB[tid], L.KC[tid]);
+  L.F0[lane] = make_float4(delta * rs, (float)jt, (float)pd.dnu * rs, g2 * isc);
+  L.F1[lane] = make_float4(Ah, (float)(jlo - jref), (float)(jhi - jref), a2 * isc);
+  wing_coeffs(a2 * isc, g2 * isc, Ah, L.KA[lane], L.KB[lane], L.KC[lane]);
   // zone K: points with |z| < zK[K], i.e. |j - c| < sqrt(zK^2 alpha^2 - gamma^2)/dnu around the
-  // centre c (tile-local points); a slot [s0, s1] meets it when s0 < c + h and s1 > c - h
+  // centre c (span-local points); a slot [s0, s1] meets it when s0 < c + h and s1 > c - h
   const float inv_dnu = (float)(1.0 / pd.dnu);
   const float af = alpha * inv_dnu, gf = gam * inv_dnu;
   const float c = (float)jt - delta * inv_dnu;
-  float zl[kKmax], zh[kKmax];
+  const int clo = (int)((int64_t)jlo - span0 < -1 ? -1 : (int64_t)jlo - span0);
+  const int chi = (int)((int64_t)jhi - span0 > W ? W : (int64_t)jhi - span0);
+  uint32_t K = 1u;
 #pragma unroll
-  for (int K = 0; K < kKmax; ++K) {
-    const float zz = zK[K] * af;
-    const float h2 = zz * zz - gf * gf;
-    const float h = h2 > 0.0f ? sqrtf(h2) * 1.00001f + 1e-3f : -1.0f;
-    zl[K] = c - h;
-    zh[K] = c + h;
+  for (int p = 0; p < P; ++p) {
+    const int s0 = p * kWave, s1 = s0 + kWave - 1;
+    if (s1 < clo || s0 > chi) continue;
+    uint32_t path = 1u;
+#pragma unroll
+    for (int z = 0; z < kKmax - 1; ++z) {
+      const float zz = zK[z] * af;
+      const float h2 = zz * zz - gf * gf;
+      const float h = h2 > 0.0f ? sqrtf(h2) * 1.00001f + 1e-3f : -1.0f;
+      path += ((float)s0 < c + h && (float)s1 > c - h) ? 1u : 0u;
+    }
+    K = path > K ? path : K;
   }
-  const int clo = (int)((int64_t)jlo - tile0 < -1 ? -1 : (int64_t)jlo - tile0);
-  const int chi = (int)((int64_t)jhi - tile0 > W ? W : (int64_t)jhi - tile0);
   // core points: strictly inside the last zone, and within the cut range
   int czl = 1, czh = 0, rlo, rhi;
   if (core_rel(alpha, gam, delta, inv_dnu, zK[kKmax - 1], rlo, rhi)) {
-    const int64_t gl = (int64_t)jref + rlo - tile0, gh = (int64_t)jref + rhi - tile0;
+    const int64_t gl = (int64_t)jref + rlo - span0, gh = (int64_t)jref + rhi - span0;
     czl = (int)(gl < clo ? clo : (gl > W + 1 ? W + 1 : gl));
     czh = (int)(gh > chi ? chi : (gh < -2 ? -2 : gh));
   }
-  L.CZ[tid] = make_int2(czl, czh);
-#pragma unroll
-  for (int w = 0; w < kWavesPerWG; ++w) {
-    const int w0 = w * kWave * P, w1 = w0 + kWave * P - 1;
-    uint32_t code = 0u;
-    if (!(chi < w0 || clo > w1)) {
-      uint32_t K = 1u;
-#pragma unroll
-      for (int p = 0; p < P; ++p) {
-        const int s0 = w0 + p * kWave, s1 = s0 + kWave - 1;
-        if (s1 < clo || s0 > chi) continue;
-        uint32_t path = 1u;
-#pragma unroll
-        for (int z = 0; z < kKmax - 1; ++z) path += ((float)s0 < zh[z] && (float)s1 > zl[z]) ? 1u : 0u;
-        K = path > K ? path : K;
-      }
-      const bool core = (czl > w0 ? czl : w0) <= (czh < w1 ? czh : w1);
-      if (core) K = kKmax;  // the wing points next to the core need the highest order
-      const bool masked = !(w0 >= clo && w1 <= chi);
-      // far: the whole span inside the cut, and the centre at least 3 half-spans away, so the
-      // line is smooth on the span and is evaluated at the span's Chebyshev nodes only
-      const float dc = c - (float)w0 - 0.5f * (float)(kWave * P - 1);
-      const bool far = !masked && !core && K < (uint32_t)kKmax && fabsf(dc) >= kFarSpans * (float)(kWave * P);
-      code = K | (masked ? 8u : 0u) | (core ? 16u : 0u) | (far ? 32u : 0u);
-    }
-    codes[w] = code;
+  L.CZ[lane] = make_int2(czl, czh);
+  const bool core = (czl > 0 ? czl : 0) <= (czh < W - 1 ? czh : W - 1);
+  if (core) K = kKmax;  // the wing points next to the core need the highest order
+  if (K == (uint32_t)kKmax) {
+    const float av = a2 * isc, gv = g2 * isc;
+    const float a3 = av * av * av, a4 = a3 * av, g2v = gv * gv, g3v = g2v * gv;
+    L.K5[lane] = make_float4(Ah * (12.0f * av * av * g2v - 105.0f * a3 * gv + 59.0625f * a4),
+                             Ah * (210.0f * a3 * g2v - 787.5f * a4 * gv), Ah * (-120.0f * a3 * g3v + 2835.0f * a4 * g2v),
+                             Ah * (-3780.0f * a4 * g3v));
+    L.K5C[lane] = Ah * (1680.0f * a4 * g2v * g2v);
   }
+  const bool masked = !(clo <= 0 && chi >= W - 1);
+  return K | (masked ? 8u : 0u) | (core ? 16u : 0u);
 }
 
 // One line, all slots of this wave, series order K. MASK: lanes outside the cut range add
@@ -704,24 +789,9 @@ __device__ __forceinline__ void wing_slots(float (&part)[P], float kf0, const fl
   }
 }
 
-// Group of a staged line for one wave: 0 does not reach the wave; 1-4 all lanes inside the cut,
-// no core points, series order K = 1-4; 5 general (order 5 or core points on the wave); 6-9 the
-// same as 1-4 with some lanes outside the cut; 10-13 far from the wave's span, order 1-4
-// (evaluated at the span's Chebyshev nodes).
-constexpr int kGroups = 13;
-__device__ __forceinline__ int line_group(uint32_t code) {
-  if (code == 0u) return 0;
-  const int K = (int)(code & 7u);
-  if ((code & 16u) || K > 4) return 5;
-  if (code & 32u) return 9 + K;
-  return (code & 8u) ? 5 + K : K;
-}
-
-// Per-wave wing loop over the lines of one group (all unmasked, no core slots). Lines go in
-// blocks of 16 with a compensated flush after each block (and after a partial last block);
-// the list is read four entries at a time into a scalar register.
-template <int P, int LB, int K, bool MASK>
-__device__ __forceinline__ void wing_line(const LineLDS<LB>& L, int l, float jl0, float (&part)[P]) {
+// One staged line (uniform index l), all slots of this wave, series order K 1-4, no core points.
+template <int P, int K, bool MASK>
+__device__ __forceinline__ void wing_line(const WaveLDS& L, int l, float jl0, float (&part)[P]) {
   const float4 f0 = L.F0[l];
   const float4 f1 = L.F1[l];
   float4 ka = make_float4(0.f, 0.f, 0.f, 0.f), kb = ka;
@@ -732,283 +802,51 @@ __device__ __forceinline__ void wing_line(const LineLDS<LB>& L, int l, float jl0
   wing_slots<P, K, MASK, false>(part, jl0 - f0.y, f0, f1, ka, kb, kc);
 }
 
-// Far lines of one group: four lines per step, lane = 16 (line in step) + node; each lane adds
-// the line's profile at its node to its node sum (lines are assigned to lanes in a fixed way).
-template <int LB, int K>
-__device__ __forceinline__ void far_loop(const LineLDS<LB>& L, int wv, int i0, int i1, int lane, float xnode,
-                                         float& fpart, float& fs, float& fc) {
-  int n = 0;
-  for (int i = i0; i < i1; i += 4) {
-    const int li = i + (lane >> 4);
-    float t = 0.0f, q = 0.0f;
-    if (li < i1) {
-      const int l = (int)L.list[wv][li];
-      const float4 f0 = L.F0[l];
-      const float4 f1 = L.F1[l];
-      const float D = __builtin_fmaf(xnode - f0.y, f0.z, f0.x);
-      const float R = __builtin_fmaf(D, D, f0.w);
-      q = __builtin_amdgcn_rcpf(R);
-      if (K == 1) {
-        t = f1.x;
-      } else if (K == 2) {
-        const float4 ka = L.KA[l];
-        t = __builtin_fmaf(ka.y, q, ka.x);
-        t = __builtin_fmaf(t, q, f1.x);
-      } else if (K == 3) {
-        const float4 ka = L.KA[l];
-        const float4 kb = L.KB[l];
-        t = __builtin_fmaf(kb.x, q, ka.w);
-        t = __builtin_fmaf(t, q, ka.z);
-        t = __builtin_fmaf(t, q, ka.x);
-        t = __builtin_fmaf(t, q, f1.x);
-      } else {
-        const float4 ka = L.KA[l];
-        const float4 kb = L.KB[l];
-        const float kc = L.KC[l];
-        t = __builtin_fmaf(kc, q, kb.w);
-        t = __builtin_fmaf(t, q, kb.z);
-        t = __builtin_fmaf(t, q, kb.y);
-        t = __builtin_fmaf(t, q, ka.z);
-        t = __builtin_fmaf(t, q, ka.x);
-        t = __builtin_fmaf(t, q, f1.x);
-      }
-    }
-    fpart = __builtin_fmaf(t, q, fpart);
-    if (++n == 16) {
-      const float y = fpart - fc;
-      const float tt = fs + y;
-      fc = (tt - fs) - y;
-      fs = tt;
-      fpart = 0.0f;
-      n = 0;
-    }
+// One staged line of order 5 or with core points on the span (those add nothing here).
+template <int P>
+__device__ __forceinline__ void wing_line_general(const WaveLDS& L, int l, uint32_t code, float jl0,
+                                                  float (&part)[P]) {
+  const float4 f0 = L.F0[l];
+  const float4 f1 = L.F1[l];
+  const float4 ka = L.KA[l], kb = L.KB[l], k5 = L.K5[l];
+  const float kf0 = jl0 - f0.y;
+  // order 5 as wing_slots takes it: ka = (c1, c2, c3, c4), kb = (c5, c6, c7, c8)
+  const float4 k5a = make_float4(ka.x, ka.z, kb.y, k5.x);
+  const float4 k5b = make_float4(k5.y, k5.z, k5.w, L.K5C[l]);
+  if (code & 16u) {
+    const int czl = __builtin_amdgcn_readfirstlane(L.CZ[l].x);
+    const int czh = __builtin_amdgcn_readfirstlane(L.CZ[l].y);
+    const float jt = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(f0.y)));
+    wing_slots<P, 5, true, true>(part, kf0, f0, f1, k5a, k5b, 0.f, (float)czl - jt, (float)czh - jt);
+  } else {
+    wing_slots<P, 5, true, false>(part, kf0, f0, f1, k5a, k5b, 0.f);
   }
-  const float y = fpart - fc;
-  const float tt = fs + y;
-  fc = (tt - fs) - y;
-  fs = tt;
-  fpart = 0.0f;
 }
 
-template <int P, int LB, int K, bool MASK>
-__device__ __forceinline__ void group_loop(const LineLDS<LB>& L, int wv, int i0, int i1, float jl0, float (&part)[P],
-                                           float (&s)[P], float (&cc)[P]) {
+// The lines of one group (list entries [i0, i1)): blocks of four lines (the list read four
+// entries at a time into a scalar register), a compensated flush after every 16 lines.
+template <int P, int K, bool MASK>
+__device__ __forceinline__ void direct_loop(const WaveLDS& L, int i0, int i1, float jl0, float (&part)[P],
+                                            float (&s)[P], float (&cc)[P]) {
   if (i0 >= i1) return;
   int i = i0;
-  // unaligned head: single entries up to a multiple of 4
-  for (; i < i1 && (i & 3); ++i)
-    wing_line<P, LB, K, MASK>(L, __builtin_amdgcn_readfirstlane((int)L.list[wv][i]), jl0, part);
+  for (; i < i1 && (i & 3); ++i)  // unaligned head
+    wing_line<P, K, MASK>(L, __builtin_amdgcn_readfirstlane((int)L.list[i]), jl0, part);
   int since = 0;
   for (; i + 4 <= i1; i += 4) {
-    const uint32_t w4 = (uint32_t)__builtin_amdgcn_readfirstlane(
-        (int)*reinterpret_cast<const uint32_t*>(&L.list[wv][i]));
-    wing_line<P, LB, K, MASK>(L, (int)(w4 & 255u), jl0, part);
-    wing_line<P, LB, K, MASK>(L, (int)((w4 >> 8) & 255u), jl0, part);
-    wing_line<P, LB, K, MASK>(L, (int)((w4 >> 16) & 255u), jl0, part);
-    wing_line<P, LB, K, MASK>(L, (int)(w4 >> 24), jl0, part);
+    const uint32_t w4 = (uint32_t)__builtin_amdgcn_readfirstlane((int)*reinterpret_cast<const uint32_t*>(&L.list[i]));
+    wing_line<P, K, MASK>(L, (int)(w4 & 255u), jl0, part);
+    wing_line<P, K, MASK>(L, (int)((w4 >> 8) & 255u), jl0, part);
+    wing_line<P, K, MASK>(L, (int)((w4 >> 16) & 255u), jl0, part);
+    wing_line<P, K, MASK>(L, (int)(w4 >> 24), jl0, part);
     since += 4;
     if (since == 16) {
       kahan_flush<P>(part, s, cc);
       since = 0;
     }
   }
-  for (; i < i1; ++i) wing_line<P, LB, K, MASK>(L, __builtin_amdgcn_readfirstlane((int)L.list[wv][i]), jl0, part);
+  for (; i < i1; ++i) wing_line<P, K, MASK>(L, __builtin_amdgcn_readfirstlane((int)L.list[i]), jl0, part);
   kahan_flush<P>(part, s, cc);
-}
-
-template <int P, int LB>
-__global__ __launch_bounds__(kThreads) void k_voigt(VoigtArgs a) {
-  constexpr int W = kWavesPerWG * kWave * P;  // tile width in grid points
-  __shared__ LineLDS<LB> L;
-  __shared__ float sNode[kWavesPerWG][kWave];
-  __shared__ double sNodeSum[kWavesPerWG][kNodes];
-  __shared__ int sItem, sTile, sPair;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave index (uniform)
-  const int total = a.item_base[a.n_tiles_total];
-  const float jl0 = (float)(wv * kWave * P + lane);  // this lane's first tile point
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  long long n_direct = 0, n_node = 0;  // lines this wave evaluated directly / at the span's nodes
-
-  for (;;) {
-    if (tid == 0) {
-      const int it = atomicAdd(a.counter, 1);
-      sItem = it;
-      if (it < total) {
-        int lo = 0, hi = a.n_tiles_total - 1;  // last tile with item_base <= it
-        while (lo < hi) {
-          const int m = (lo + hi + 1) >> 1;
-          if (a.item_base[m] <= it) lo = m; else hi = m - 1;
-        }
-        sTile = lo;
-        sPair = find_pair(a.pairs, a.n_pairs, lo);
-      }
-    }
-    __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(sItem);
-    if (it >= total) break;
-    const int g = __builtin_amdgcn_readfirstlane(sTile);
-    const PairDesc pd = wave_uniform(a.pairs[__builtin_amdgcn_readfirstlane(sPair)]);
-    const int ibase = __builtin_amdgcn_readfirstlane(a.item_base[g]);
-    const int chunk_idx = it - ibase;
-    const int nc = __builtin_amdgcn_readfirstlane(a.tile_nc[g]);
-    const int64_t tile0 = (int64_t)(g - pd.tile_base) * W;
-    // this item's lines: positions [v_lo, v_hi) of the tile's lines outside its tile-far ranges,
-    // i.e. of the concatenation [lo, x) + [y, z) + [w, hi)
-    const int tlo = __builtin_amdgcn_readfirstlane(a.tile_lo[g]);
-    const int thi = __builtin_amdgcn_readfirstlane(a.tile_hi[g]);
-    const int4 tf = wave_uniform(a.tile_far[g]);
-    const int n0 = tf.x - tlo, n01 = n0 + (tf.z - tf.y);
-    const int sh1 = tf.y - n0, sh2 = tf.w - n01;  // line = position + shift, per segment
-    const int nv = n01 + (thi - tf.w);
-    const int v_lo = chunk_idx * a.chunk;
-    const int v_hi = v_lo + a.chunk < nv ? v_lo + a.chunk : nv;
-    const float* __restrict__ S_T = a.S_T + (int64_t)pd.tidx * a.N;
-    const float* __restrict__ gT = a.gT + (int64_t)pd.tidx * a.N;
-    const int4* __restrict__ grec = a.grec + (int64_t)pd.gidx * a.N;
-
-    float s[P], cc[P], part[P];
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      s[p] = 0.0f;
-      cc[p] = 0.0f;
-      part[p] = 0.0f;
-    }
-    // far lines: this lane's node and its compensated node sum
-    const float xnode = (float)(wv * kWave * P) + a.cheb_x[lane & (kNodes - 1)];
-    float fpart = 0.0f, fs = 0.0f, fc = 0.0f;
-    for (int b = v_lo; b < v_hi; b += LB) {
-      // ---- stage one batch of lines: one thread per line
-      {
-        const int v = b + tid;
-        const int64_t li = v + (v < n0 ? tlo : (v < n01 ? sh1 : sh2));
-        uint32_t codes[kWavesPerWG] = {0u, 0u, 0u, 0u};
-        if (tid < LB && v < v_hi)
-          stage_line<P, LB>(L, tid, grec[li], a.nu[li], S_T[li], gT[li], pd, a.zK, tile0, codes);
-        if (tid < LB) L.code[tid] = make_uint4(codes[0], codes[1], codes[2], codes[3]);
-      }
-      __syncthreads();
-      // ---- this wave's list of the staged lines that reach it, grouped by series order and in
-      //      staging order within a group (wave ballots; deterministic)
-      int o[kGroups + 2];
-      {
-        const uint32_t* code_w = reinterpret_cast<const uint32_t*>(L.code) + wv;
-        int grp[LB / kWave];
-        int cnt[kGroups + 1];
-#pragma unroll
-        for (int gg = 0; gg <= kGroups; ++gg) cnt[gg] = 0;
-#pragma unroll
-        for (int r = 0; r < LB / kWave; ++r) {
-          grp[r] = line_group(code_w[4 * (r * kWave + lane)]);
-#pragma unroll
-          for (int gg = 1; gg <= kGroups; ++gg) cnt[gg] += (int)__popcll(__ballot(grp[r] == gg));
-        }
-        o[1] = 0;
-#pragma unroll
-        for (int gg = 1; gg <= kGroups; ++gg) o[gg + 1] = o[gg] + cnt[gg];
-        int st[kGroups + 1];
-#pragma unroll
-        for (int gg = 1; gg <= kGroups; ++gg) st[gg] = o[gg];
-#pragma unroll
-        for (int r = 0; r < LB / kWave; ++r) {
-#pragma unroll
-          for (int gg = 1; gg <= kGroups; ++gg) {
-            const uint64_t m = __ballot(grp[r] == gg);
-            if (grp[r] == gg) L.list[wv][st[gg] + (int)__popcll(m & lt)] = (uint8_t)(r * kWave + lane);
-            st[gg] += (int)__popcll(m);
-          }
-        }
-      }
-
-      n_direct += o[kGroups - 3] - o[1];
-      n_node += o[kGroups + 1] - o[kGroups - 3];
-      // ---- accumulate: fast groups, then the general group
-      {
-        group_loop<P, LB, 1, false>(L, wv, o[1], o[2], jl0, part, s, cc);
-        group_loop<P, LB, 2, false>(L, wv, o[2], o[3], jl0, part, s, cc);
-        group_loop<P, LB, 3, false>(L, wv, o[3], o[4], jl0, part, s, cc);
-        group_loop<P, LB, 4, false>(L, wv, o[4], o[5], jl0, part, s, cc);
-        group_loop<P, LB, 1, true>(L, wv, o[6], o[7], jl0, part, s, cc);
-        group_loop<P, LB, 2, true>(L, wv, o[7], o[8], jl0, part, s, cc);
-        group_loop<P, LB, 3, true>(L, wv, o[8], o[9], jl0, part, s, cc);
-        group_loop<P, LB, 4, true>(L, wv, o[9], o[10], jl0, part, s, cc);
-        far_loop<LB, 1>(L, wv, o[10], o[11], lane, xnode, fpart, fs, fc);
-        far_loop<LB, 2>(L, wv, o[11], o[12], lane, xnode, fpart, fs, fc);
-        far_loop<LB, 3>(L, wv, o[12], o[13], lane, xnode, fpart, fs, fc);
-        far_loop<LB, 4>(L, wv, o[13], o[14], lane, xnode, fpart, fs, fc);
-        // general group: order 5, possibly lanes outside the cut and core points to skip
-        for (int i = o[5]; i < o[6]; ++i) {
-          const int l = __builtin_amdgcn_readfirstlane((int)L.list[wv][i]);
-          const uint32_t code = __builtin_amdgcn_readfirstlane(reinterpret_cast<const uint32_t*>(L.code)[4 * l + wv]);
-          const float4 f0 = L.F0[l];
-          const float4 f1 = L.F1[l];
-          const float kf0 = jl0 - f0.y;
-          // order-5 coefficients from a = alpha^2/s, g = gamma^2/s, times Ah
-          const float av = f1.w, gv = f0.w, A = f1.x;
-          const float a2 = av * av, a3 = a2 * av, a4 = a2 * a2, g2 = gv * gv, g3 = g2 * gv;
-          const float4 k5a = make_float4(A * (1.5f * av), A * (-2.0f * av * gv + 3.75f * a2),
-                                         A * (-15.0f * a2 * gv + 13.125f * a3),
-                                         A * (12.0f * a2 * g2 - 105.0f * a3 * gv + 59.0625f * a4));
-          const float4 k5b = make_float4(A * (210.0f * a3 * g2 - 787.5f * a4 * gv),
-                                         A * (-120.0f * a3 * g3 + 2835.0f * a4 * g2), A * (-3780.0f * a4 * g3),
-                                         A * (1680.0f * a4 * g2 * g2));
-          if (code & 16u) {
-            const int czl = __builtin_amdgcn_readfirstlane(L.CZ[l].x);
-            const int czh = __builtin_amdgcn_readfirstlane(L.CZ[l].y);
-            const float jt = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(f0.y)));
-            wing_slots<P, 5, true, true>(part, kf0, f0, f1, k5a, k5b, 0.f, (float)czl - jt, (float)czh - jt);
-          } else {
-            wing_slots<P, 5, true, false>(part, kf0, f0, f1, k5a, k5b, 0.f);
-          }
-          if (((i - o[5]) & 15) == 15) kahan_flush<P>(part, s, cc);
-        }
-        kahan_flush<P>(part, s, cc);
-      }
-      __syncthreads();
-    }
-    // ---- far lines: node sums (the four line groups of lanes in a fixed order), then their
-    //      interpolation to this wave's points with the span's Lagrange weights, in FP64
-    sNode[wv][lane] = fs - fc;
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    if (lane < kNodes) {
-      double t = 0.0;
-#pragma unroll
-      for (int gq = 0; gq < kWave / kNodes; ++gq) t += (double)sNode[wv][gq * kNodes + lane];
-      sNodeSum[wv][lane] = t;
-    }
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    {
-      double v[P];
-#pragma unroll
-      for (int p = 0; p < P; ++p) v[p] = 0.0;
-#pragma unroll 1
-      for (int k = 0; k < kNodes; ++k) {
-        const double ns = sNodeSum[wv][k];
-        const double* __restrict__ wk = a.cheb_w + k * (kWave * P) + lane;
-#pragma unroll
-        for (int p = 0; p < P; ++p) v[p] = fma(ns, wk[p * kWave], v[p]);
-      }
-#pragma unroll
-      for (int p = 0; p < P; ++p) part[p] += (float)v[p];
-    }
-    kahan_flush<P>(part, s, cc);
-
-    // ---- output: the tile directly, or this chunk's partial tile
-#pragma unroll
-    for (int p = 0; p < P; ++p) {
-      const int local = wv * kWave * P + p * kWave + lane;
-      const float v = s[p] - cc[p];
-      if (nc == 1) {
-        if (tile0 + local < pd.n) a.k[pd.out_off + tile0 + local] = v;
-      } else if (it < a.items_cap) {
-        a.partial[((int64_t)it) * W + local] = v;
-      }
-    }
-    __syncthreads();
-  }
-  if (a.stats && lane == 0) a.stats[blockIdx.x * kWavesPerWG + wv] = n_direct * (kWave * P) + n_node * kNodes;
 }
 
 __device__ __forceinline__ double wave_sum64(double v) {
@@ -1017,44 +855,281 @@ __device__ __forceinline__ double wave_sum64(double v) {
   return v;
 }
 
-// --------------------------------------------------------------- tile-far pass
-// The lines of a tile's tile-far ranges (see k_worklist) are smooth on the whole tile: each is
-// evaluated at the tile's kNodes Chebyshev nodes only, one line per lane, with the far-wing
-// series of the order that its nearest tile point needs (the largest over the wave's lines;
-// the ranges' bounds keep it below 5). A work item is a tile and a chunk of its tile-far lines;
-// it writes its kNodes node sums (per lane in FP32 over 16 lines, then FP64; over the
-// workgroup in a fixed order), and k_combine_far adds their interpolation to the tile.
+// ------------------------------------------------------- lines far from a span or a tile
+// A line whose centre lies far outside an interval of grid points (a span or a tile; see
+// k_span_segments and k_worklist for the bounds that make it so) is smooth on it: it is
+// evaluated at the interval's kNodes Chebyshev nodes only, one line per lane, with the
+// far-wing series of the order its nearest point of the interval needs (the largest over the
+// wave's lines; the bounds keep it below 5). The node sums are later interpolated to the
+// interval's points with the nodes' Lagrange weights.
+struct FarLine {
+  float h, e, gq, A, kc;  // node offset D = x h + e (x: node position in grid steps), gamma^2/s
+  float4 ka, kb;          // Ah times the series coefficients (see wing_coeffs)
+  int K;
+};
+
+// The constants of one line for the interval of grid points [nu_a, nu_b] (an idle lane, or a
+// line with S = 0, evaluates A = 0 at D = 1 and adds zero).
+__device__ __forceinline__ FarLine far_line(bool valid, double nu, float S, float gTv, const PairDesc& pd,
+                                            double nu_a, double nu_b, float inv_dnu, const float* zK) {
+  FarLine f;
+  f.h = 0.0f; f.e = 1.0f; f.gq = 1.0f; f.A = 0.0f; f.kc = 0.0f;
+  f.ka = make_float4(0.f, 0.f, 0.f, 0.f);
+  f.kb = f.ka;
+  f.K = 1;
+  if (!valid) return f;
+  const float alpha = (float)(nu * pd.beta);
+  const float gam = gTv * (float)pd.pfac;
+  const float a2 = alpha * alpha, g2 = gam * gam;
+  const float sc = a2 > g2 ? a2 : g2;
+  if (!(S > 0.0f && sc > 0.0f)) return f;
+  const float rs = __frsqrt_rn(sc);
+  const float isc = rs * rs;
+  f.A = S * (gam * isc) * 0.318309886183790672f;  // S gamma / (pi s)
+  f.gq = g2 * isc;
+  wing_coeffs(a2 * isc, f.gq, f.A, f.ka, f.kb, f.kc);
+  f.h = (float)pd.dnu * rs;                       // one grid step in units of sqrt(s)
+  f.e = -((float)(nu - nu_a) * inv_dnu) * f.h;    // minus the line's position, same units
+  const float dmin = (float)(nu < nu_a ? nu_a - nu : nu - nu_b);  // to the nearest point
+  const float r2 = dmin * dmin + g2;
+#pragma unroll
+  for (int z = 0; z < kKmax - 1; ++z) f.K += (zK[z] * zK[z] * a2 > r2) ? 1 : 0;
+  return f;
+}
+
 template <int K>
-__device__ __forceinline__ void far_nodes(const FarArgs& a, float h, float e, float gq, float A, const float4& ka,
-                                          const float4& kb, float kc, float (&acc)[kNodes]) {
+__device__ __forceinline__ void far_nodes(const float (&xn)[kNodes], const FarLine& f, float (&acc)[kNodes]) {
 #pragma unroll
   for (int k = 0; k < kNodes; ++k) {
-    const float D = __builtin_fmaf(a.tile_x[k], h, e);
-    const float R = __builtin_fmaf(D, D, gq);
+    const float D = __builtin_fmaf(xn[k], f.h, f.e);
+    const float R = __builtin_fmaf(D, D, f.gq);
     const float q = __builtin_amdgcn_rcpf(R);
     float t;
     if (K == 1) {
-      t = A;
+      t = f.A;
     } else if (K == 2) {
-      t = __builtin_fmaf(ka.y, q, ka.x);
-      t = __builtin_fmaf(t, q, A);
+      t = __builtin_fmaf(f.ka.y, q, f.ka.x);
+      t = __builtin_fmaf(t, q, f.A);
     } else if (K == 3) {
-      t = __builtin_fmaf(kb.x, q, ka.w);
-      t = __builtin_fmaf(t, q, ka.z);
-      t = __builtin_fmaf(t, q, ka.x);
-      t = __builtin_fmaf(t, q, A);
+      t = __builtin_fmaf(f.kb.x, q, f.ka.w);
+      t = __builtin_fmaf(t, q, f.ka.z);
+      t = __builtin_fmaf(t, q, f.ka.x);
+      t = __builtin_fmaf(t, q, f.A);
     } else {
-      t = __builtin_fmaf(kc, q, kb.w);
-      t = __builtin_fmaf(t, q, kb.z);
-      t = __builtin_fmaf(t, q, kb.y);
-      t = __builtin_fmaf(t, q, ka.z);
-      t = __builtin_fmaf(t, q, ka.x);
-      t = __builtin_fmaf(t, q, A);
+      t = __builtin_fmaf(f.kc, q, f.kb.w);
+      t = __builtin_fmaf(t, q, f.kb.z);
+      t = __builtin_fmaf(t, q, f.kb.y);
+      t = __builtin_fmaf(t, q, f.ka.z);
+      t = __builtin_fmaf(t, q, f.ka.x);
+      t = __builtin_fmaf(t, q, f.A);
     }
     acc[k] = __builtin_fmaf(t, q, acc[k]);
   }
 }
 
+// Adds each lane's line at the nodes to its node sums, with the wave's largest order.
+__device__ __forceinline__ void far_accumulate(const float (&xn)[kNodes], const FarLine& f, float (&acc)[kNodes]) {
+  const int Kw = 1 + (__ballot(f.K >= 2) != 0ull ? 1 : 0) + (__ballot(f.K >= 3) != 0ull ? 1 : 0) +
+                 (__ballot(f.K >= 4) != 0ull ? 1 : 0);
+  if (Kw == 1) far_nodes<1>(xn, f, acc);
+  else if (Kw == 2) far_nodes<2>(xn, f, acc);
+  else if (Kw == 3) far_nodes<3>(xn, f, acc);
+  else far_nodes<4>(xn, f, acc);
+}
+
+// Adds the wave's node sums (a butterfly over the lanes in FP64, the same on every lane) to
+// node[k] (lane k) and clears the lanes' FP32 sums; every 16 lines per lane at most, so that
+// the FP32 sums stay short.
+__device__ __forceinline__ void far_flush(float (&acc)[kNodes], int lane, double* node) {
+  double mine = 0.0;
+#pragma unroll
+  for (int k = 0; k < kNodes; ++k) {
+    const double t = wave_sum64((double)acc[k]);
+    mine = lane == k ? t : mine;
+    acc[k] = 0.0f;
+  }
+  if (lane < kNodes) node[lane] += mine;
+}
+
+// ------------------------------------------------------------------- wing pass
+// One wave per span of 64 P grid points (lane + 64 p, p < P). A work item is a span and a
+// chunk of its line segments (k_span_segments), taken in list order:
+//  * a direct segment is staged 64 lines at a time in the wave's LDS (one line per lane),
+//    and every staged line that reaches the span is evaluated at all its points with the
+//    series order it needs there (lanes outside its cut range and its core points add
+//    nothing; the core points are the line-core pass's), in staging order, into per-lane
+//    FP32 sums with a compensated flush every 16 lines;
+//  * a far segment is evaluated at the span's Chebyshev nodes, one line per lane (per lane
+//    in FP32 over 16 lines, then FP64; over the wave by a butterfly, the same on every lane),
+//    and the node sums are interpolated to the span's points in FP64 at the end of the item.
+// A span with one item writes k; otherwise each item writes its partial span and k_combine
+// sums them in item order. No workgroup barrier: waves run independently.
+template <int P>
+__global__ __launch_bounds__(kWave) void k_wing(VoigtArgs a) {
+  constexpr int W = kWave * P;  // span width in grid points
+  __shared__ WaveLDS L;
+  const int lane = threadIdx.x;
+  const int total = a.item_base[a.n_tiles_total];
+  const float jl0 = (float)lane;  // this lane's first span point
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  long long n_direct = 0, n_node = 0;
+
+  for (;;) {
+    int mine = 0;
+    if (lane == 0) mine = atomicAdd(a.counter, 1);
+    const int it = __builtin_amdgcn_readfirstlane(mine);
+    if (it >= total) break;
+    int g = 0;
+    {
+      int lo = 0, hi = a.n_tiles_total - 1;  // last span with item_base <= it
+      while (lo < hi) {
+        const int m = (lo + hi + 1) >> 1;
+        if (a.item_base[m] <= it) lo = m; else hi = m - 1;
+      }
+      g = lo;
+    }
+    const PairDesc pd = wave_uniform(a.pairs[find_pair(a.pairs, a.n_pairs, g)]);
+    const int nc = a.tile_nc[g];
+    const int v_lo = (it - a.item_base[g]) * a.chunk;
+    const int64_t span0 = (int64_t)(g - pd.tile_base) * W;
+    const float* __restrict__ S_T = a.S_T + (int64_t)pd.tidx * a.N;
+    const float* __restrict__ gT = a.gT + (int64_t)pd.tidx * a.N;
+    const int4* __restrict__ grec = a.grec + (int64_t)pd.gidx * a.N;
+    const SpanSeg* __restrict__ sg = a.segs + g;
+    const int nseg = sg->n, fmask = sg->far_mask;
+
+    float s[P], cc[P], part[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      s[p] = 0.0f;
+      cc[p] = 0.0f;
+      part[p] = 0.0f;
+    }
+    if (lane < kNodes) L.node[lane] = 0.0;
+    bool any_far = false;
+    int cum = 0, v_hi = v_lo;
+    for (int q = 0; q < nseg; ++q) {
+      const int len = sg->len[q];
+      const int x0 = v_lo > cum ? v_lo : cum;
+      const int x1 = (v_lo + a.chunk < cum + len) ? v_lo + a.chunk : cum + len;
+      if (x0 < x1) {
+        const int i0 = sg->lo[q] + (x0 - cum), i1 = i0 + (x1 - x0);
+        v_hi = x1;
+        if ((fmask >> q) & 1) {
+          // ---- far segment: node sums, one line per lane
+          any_far = true;
+          n_node += i1 - i0;
+          const double nu_a = grid_nu(pd.nu_start, pd.dnu, span0);
+          const double nu_b = grid_nu(pd.nu_start, pd.dnu, span0 + W - 1);
+          const float inv_dnu = (float)(1.0 / pd.dnu);
+          float acc[kNodes];
+#pragma unroll
+          for (int k = 0; k < kNodes; ++k) acc[k] = 0.0f;
+          int n = 0;
+          for (int b = i0; b < i1; b += kWave) {
+            const int li = b + lane;
+            const bool valid = li < i1;
+            const FarLine f = far_line(valid, valid ? a.nu[li] : 0.0, valid ? S_T[li] : 0.0f,
+                                       valid ? gT[li] : 0.0f, pd, nu_a, nu_b, inv_dnu, a.zK);
+            far_accumulate(a.cheb_x, f, acc);
+            if (++n == 16 || b + kWave >= i1) {
+              far_flush(acc, lane, L.node);
+              n = 0;
+            }
+          }
+        } else {
+          // ---- direct segment: 64 lines per stage
+          for (int b = i0; b < i1; b += kWave) {
+            const int li = b + lane;
+            uint32_t code = 0u;
+            if (li < i1) code = stage_span_line<P>(L, lane, grec[li], a.nu[li], S_T[li], gT[li], pd, a.zK, span0);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            // group the staged lines (wave ballots; staging order within a group)
+            int o[kDirectGroups + 2];
+            {
+              const int grp = direct_group(code);
+              o[1] = 0;
+#pragma unroll
+              for (int gg = 1; gg <= kDirectGroups; ++gg) {
+                const uint64_t m = __ballot(grp == gg);
+                if (grp == gg) L.list[o[gg] + (int)__popcll(m & lt)] = (uint8_t)lane;
+                o[gg + 1] = o[gg] + (int)__popcll(m);
+              }
+            }
+            n_direct += o[kDirectGroups + 1] - o[1];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            direct_loop<P, 1, false>(L, o[1], o[2], jl0, part, s, cc);
+            direct_loop<P, 2, false>(L, o[2], o[3], jl0, part, s, cc);
+            direct_loop<P, 3, false>(L, o[3], o[4], jl0, part, s, cc);
+            direct_loop<P, 4, false>(L, o[4], o[5], jl0, part, s, cc);
+            direct_loop<P, 1, true>(L, o[5], o[6], jl0, part, s, cc);
+            direct_loop<P, 2, true>(L, o[6], o[7], jl0, part, s, cc);
+            direct_loop<P, 3, true>(L, o[7], o[8], jl0, part, s, cc);
+            direct_loop<P, 4, true>(L, o[8], o[9], jl0, part, s, cc);
+            for (int i = o[9]; i < o[10]; ++i) {
+              const int l = __builtin_amdgcn_readfirstlane((int)L.list[i]);
+              wing_line_general<P>(L, l, (uint32_t)__builtin_amdgcn_readlane((int)code, l), jl0, part);
+              if (((i - o[9]) & 15) == 15) kahan_flush<P>(part, s, cc);
+            }
+            kahan_flush<P>(part, s, cc);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          }
+          kahan_flush<P>(part, s, cc);
+        }
+      }
+      cum += len;
+    }
+    (void)v_hi;
+    // ---- far lines: interpolation of the node sums to the span's points, in FP64
+    if (any_far) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      double v[P];
+#pragma unroll
+      for (int p = 0; p < P; ++p) v[p] = 0.0;
+#pragma unroll 1
+      for (int k = 0; k < kNodes; ++k) {
+        const double ns = L.node[k];
+        const double* __restrict__ wk = a.cheb_w + k * W + lane;
+#pragma unroll
+        for (int p = 0; p < P; ++p) v[p] = fma(ns, wk[p * kWave], v[p]);
+      }
+#pragma unroll
+      for (int p = 0; p < P; ++p) part[p] += (float)v[p];
+      kahan_flush<P>(part, s, cc);
+    }
+    // ---- output: the span directly, or this item's partial span
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int local = p * kWave + lane;
+      const float v = s[p] - cc[p];
+      if (nc == 1) {
+        if (span0 + local < pd.n) a.k[pd.out_off + span0 + local] = v;
+      } else if (it < a.items_cap) {
+        a.partial[((int64_t)it) * W + local] = v;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  if (a.stats && lane == 0) a.stats[blockIdx.x] = n_direct * W + n_node * kNodes;
+}
+
+
+// --------------------------------------------------------------- tile-far pass
+// The lines of a tile's tile-far ranges (see k_worklist), far from the whole tile (4 spans),
+// are evaluated at the tile's Chebyshev nodes (far_line, far_accumulate). A work item is a tile
+// and a chunk of its tile-far lines; it writes its kNodes node sums (per lane in FP32 over 16
+// lines, then FP64; over the workgroup in a fixed order), and k_combine_far adds their
+// interpolation to the tile.
 __global__ __launch_bounds__(kThreads) void k_far(FarArgs a) {
   __shared__ double sRed[kWavesPerWG][kNodes];
   __shared__ int sItem, sTile, sPair;
@@ -1090,65 +1165,26 @@ __global__ __launch_bounds__(kThreads) void k_far(FarArgs a) {
     const int64_t tile0 = (int64_t)(g - pd.tile_base) * a.W;
     const double nu0 = grid_nu(pd.nu_start, pd.dnu, tile0);
     const double nu1 = grid_nu(pd.nu_start, pd.dnu, tile0 + a.W - 1);
-    const float dnu_f = (float)pd.dnu, inv_dnu = (float)(1.0 / pd.dnu), pfac = (float)pd.pfac;
+    const float inv_dnu = (float)(1.0 / pd.dnu);
     const float* __restrict__ S_T = a.S_T + (int64_t)pd.tidx * a.N;
     const float* __restrict__ gT = a.gT + (int64_t)pd.tidx * a.N;
 
-    double acc64[kNodes];
     float acc[kNodes];
 #pragma unroll
-    for (int k = 0; k < kNodes; ++k) {
-      acc64[k] = 0.0;
-      acc[k] = 0.0f;
-    }
+    for (int k = 0; k < kNodes; ++k) acc[k] = 0.0f;
+    if (lane < kNodes) sRed[wv][lane] = 0.0;
     int n = 0;
     for (int b = v_lo; b < v_hi; b += kThreads) {
       const int v = b + tid;
-      // an idle lane evaluates A = 0 at D = 1 (adds zero)
-      float h = 0.0f, e = 1.0f, gq = 1.0f, A = 0.0f, kc = 0.0f;
-      float4 ka = make_float4(0.f, 0.f, 0.f, 0.f), kb = ka;
-      int K = 1;
-      if (v < v_hi) {
-        const int64_t li = v < nl ? (int64_t)tf.x + v : (int64_t)tf.z + (v - nl);
-        const double nu = a.nu[li];
-        const float S = S_T[li];
-        const float alpha = (float)(nu * pd.beta);
-        const float gam = gT[li] * pfac;
-        const float a2 = alpha * alpha, g2 = gam * gam;
-        const float sc = a2 > g2 ? a2 : g2;
-        if (S > 0.0f && sc > 0.0f) {
-          const float rs = __frsqrt_rn(sc);
-          const float isc = rs * rs;
-          A = S * (gam * isc) * 0.318309886183790672f;  // S gamma / (pi s)
-          gq = g2 * isc;
-          wing_coeffs(a2 * isc, gq, A, ka, kb, kc);
-          h = dnu_f * rs;                                // one grid step in units of sqrt(s)
-          e = -((float)(nu - nu0) * inv_dnu) * h;        // minus the line's position, same units
-          const float dmin = (float)(nu < nu0 ? nu0 - nu : nu - nu1);  // to the nearest tile point
-          const float r2 = dmin * dmin + g2;
-#pragma unroll
-          for (int z = 0; z < kKmax - 1; ++z) K += (a.zK[z] * a.zK[z] * a2 > r2) ? 1 : 0;
-        }
-      }
-      const int Kw = 1 + (__ballot(K >= 2) != 0ull ? 1 : 0) + (__ballot(K >= 3) != 0ull ? 1 : 0) +
-                     (__ballot(K >= 4) != 0ull ? 1 : 0);
-      if (Kw == 1) far_nodes<1>(a, h, e, gq, A, ka, kb, kc, acc);
-      else if (Kw == 2) far_nodes<2>(a, h, e, gq, A, ka, kb, kc, acc);
-      else if (Kw == 3) far_nodes<3>(a, h, e, gq, A, ka, kb, kc, acc);
-      else far_nodes<4>(a, h, e, gq, A, ka, kb, kc, acc);
-      if (++n == 16) {
-#pragma unroll
-        for (int k = 0; k < kNodes; ++k) {
-          acc64[k] += (double)acc[k];
-          acc[k] = 0.0f;
-        }
+      const bool valid = v < v_hi;
+      const int64_t li = v < nl ? (int64_t)tf.x + v : (int64_t)tf.z + (v - nl);
+      const FarLine f = far_line(valid, valid ? a.nu[li] : 0.0, valid ? S_T[li] : 0.0f, valid ? gT[li] : 0.0f,
+                                 pd, nu0, nu1, inv_dnu, a.zK);
+      far_accumulate(a.tile_x, f, acc);
+      if (++n == 16 || b + kThreads >= v_hi) {
+        far_flush(acc, lane, sRed[wv]);
         n = 0;
       }
-    }
-#pragma unroll
-    for (int k = 0; k < kNodes; ++k) {
-      const double t = wave_sum64(acc64[k] + (double)acc[k]);
-      if (lane == 0) sRed[wv][k] = t;
     }
     __syncthreads();
     if (tid < kNodes) {
@@ -1691,41 +1727,23 @@ __global__ __launch_bounds__(1024) void k_reduce2(const double* __restrict__ in,
   if (threadIdx.x == 0) { out[2 * blockIdx.x] = s0[0]; out[2 * blockIdx.x + 1] = s1[0]; }
 }
 
-// Fixed-order (chunk 0, 1, ...) FP64 sum of the partial tiles of multi-chunk tiles;
-// one workgroup per tile.
-template <int P>
+// k = (ADD ? k : 0) + fixed-order (item 0, 1, ...) sum of the partial spans of multi-item
+// spans (wing pass: k =; line-core pass: k +=).
+template <int P, bool ADD>
 __global__ __launch_bounds__(kThreads) void k_combine(VoigtArgs a) {
-  constexpr int W = kWavesPerWG * kWave * P;
+  constexpr int W = kWave * P;
   const int g = blockIdx.x;
   const int nc = a.tile_nc[g];
   if (nc <= 1) return;
   const PairDesc pd = a.pairs[find_pair(a.pairs, a.n_pairs, g)];
-  const int64_t tile0 = (int64_t)(g - pd.tile_base) * W;
+  const int64_t span0 = (int64_t)(g - pd.tile_base) * W;
   const int base = a.item_base[g];
   for (int local = threadIdx.x; local < W; local += kThreads) {
-    if (tile0 + local >= pd.n) continue;
+    if (span0 + local >= pd.n) continue;
     double acc = 0.0;
     for (int c = 0; c < nc && base + c < a.items_cap; ++c) acc += (double)a.partial[(int64_t)(base + c) * W + local];
-    a.k[pd.out_off + tile0 + local] = (float)acc;
-  }
-}
-
-// k += fixed-order (chunk 0, 1, ...) sum of the core pass's partial tiles of split tiles.
-template <int P>
-__global__ __launch_bounds__(kThreads) void k_combine_core(VoigtArgs a) {
-  constexpr int W = kWave * P;  // core tiles are one wave wide
-  const int g = blockIdx.x;
-  const int nc = a.tile_nc[g];
-  if (nc <= 1) return;
-  const PairDesc pd = a.pairs[find_pair(a.pairs, a.n_pairs, g)];
-  const int64_t tile0 = (int64_t)(g - pd.tile_base) * W;
-  const int base = a.item_base[g];
-  for (int local = threadIdx.x; local < W; local += kThreads) {
-    if (tile0 + local >= pd.n) continue;
-    double acc = 0.0;
-    for (int c = 0; c < nc && base + c < a.items_cap; ++c) acc += (double)a.partial[(int64_t)(base + c) * W + local];
-    float* dst = a.k + pd.out_off + tile0 + local;
-    *dst = *dst + (float)acc;
+    float* dst = a.k + pd.out_off + span0 + local;
+    *dst = ADD ? *dst + (float)acc : (float)acc;
   }
 }
 
@@ -1830,11 +1848,9 @@ static hipError_t by_slots(int slots, A... args) {
 }
 
 template <int P>
-struct VoigtL {
-  static hipError_t run(const VoigtArgs& a, int lb, int grid, hipStream_t st) {
-    if (lb == 256) hipLaunchKernelGGL((k_voigt<P, 256>), dim3(grid), dim3(kThreads), 0, st, a);
-    else if (lb == 128) hipLaunchKernelGGL((k_voigt<P, 128>), dim3(grid), dim3(kThreads), 0, st, a);
-    else return hipErrorInvalidValue;
+struct WingL {
+  static hipError_t run(const VoigtArgs& a, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_wing<P>, dim3(grid), dim3(kWave), 0, st, a);
     return hipGetLastError();
   }
 };
@@ -1847,42 +1863,40 @@ struct CoreL {
 };
 template <int P>
 struct CombineL {
-  static hipError_t run(const VoigtArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_combine<P>, dim3((unsigned)a.n_tiles_total), dim3(kThreads), 0, st, a);
+  static hipError_t run(const VoigtArgs& a, bool add, hipStream_t st) {
+    if (add) hipLaunchKernelGGL((k_combine<P, true>), dim3((unsigned)a.n_tiles_total), dim3(kThreads), 0, st, a);
+    else hipLaunchKernelGGL((k_combine<P, false>), dim3((unsigned)a.n_tiles_total), dim3(kThreads), 0, st, a);
     return hipGetLastError();
   }
 };
 template <int P>
-struct CombineCoreL {
-  static hipError_t run(const VoigtArgs& a, hipStream_t st) {
-    hipLaunchKernelGGL(k_combine_core<P>, dim3((unsigned)a.n_tiles_total), dim3(kThreads), 0, st, a);
-    return hipGetLastError();
-  }
-};
-template <int P>
-struct VoigtOcc {
-  static hipError_t run(int lb, int* nb) {
-    if (lb == 256) return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_voigt<P, 256>, kThreads, 0);
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_voigt<P, 128>, kThreads, 0);
-  }
+struct WingOcc {
+  static hipError_t run(int* nb) { return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_wing<P>, kWave, 0); }
 };
 template <int P>
 struct CoreOcc {
   static hipError_t run(int* nb) { return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_core<P>, kWave, 0); }
 };
 
-hipError_t launch_voigt(const VoigtArgs& a, int slots, int lb, int grid, hipStream_t st) {
-  return by_slots<VoigtL>(slots, a, lb, grid, st);
+hipError_t launch_span_segments(const uint32_t* keys, int64_t N, KeyMap km, double numin, double numax,
+                                const PairDesc* spairs, const PairDesc* tpairs, int n_pairs, int n_spans,
+                                int span_w, double cut, double far_z, const int4* tile_far, int chunk,
+                                SpanSeg* segs, int32_t* nc, hipStream_t st) {
+  hipLaunchKernelGGL(k_span_segments, dim3(blocks_for(n_spans, kThreads)), dim3(kThreads), 0, st, keys, N, km,
+                     numin, numax, spairs, tpairs, n_pairs, n_spans, span_w, cut, far_z, tile_far, chunk, segs, nc);
+  return hipGetLastError();
+}
+
+hipError_t launch_wing(const VoigtArgs& a, int slots, int grid, hipStream_t st) {
+  return by_slots<WingL>(slots, a, grid, st);
 }
 
 hipError_t launch_core(const VoigtArgs& a, int slots, int grid, hipStream_t st) {
   return by_slots<CoreL>(slots, a, grid, st);
 }
 
-hipError_t launch_combine(const VoigtArgs& a, int slots, hipStream_t st) { return by_slots<CombineL>(slots, a, st); }
-
-hipError_t launch_combine_core(const VoigtArgs& a, int slots, hipStream_t st) {
-  return by_slots<CombineCoreL>(slots, a, st);
+hipError_t launch_combine(const VoigtArgs& a, int slots, bool add, hipStream_t st) {
+  return by_slots<CombineL>(slots, a, add, st);
 }
 
 hipError_t launch_cut_bounds(const double* nu, const int32_t* perm, int64_t N, double nu_start, double dnu,
@@ -1928,9 +1942,9 @@ int core_max_blocks_per_cu(int slots) {
   return nb > 0 ? nb : 1;
 }
 
-int voigt_max_blocks_per_cu(int slots, int lb) {
+int wing_max_blocks_per_cu(int slots) {
   int nb = 0;
-  (void)by_slots<VoigtOcc>(slots, lb, &nb);
+  (void)by_slots<WingOcc>(slots, &nb);
   return nb > 0 ? nb : 1;
 }
 
