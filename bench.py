@@ -25,14 +25,14 @@ METRIC = "lines/s + Voigt evals/s at 0.01 cm^-1; %FP32 VALU peak; batched vs pla
 PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (256 CU x 2.4 GHz x 256 flop/clk)
 FLOPS_PER_EVAL = 8           # FP32 work per wing evaluation made (at a grid point or a Chebyshev node):
                              # offset FMA, D^2+gamma^2 FMA, reciprocal, amplitude multiply, accumulate
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_voigt_c2_5e8_cut25_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "wing_pass_c2_5e8_cut25_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2101_02005_amd", "csrc", "hk_kernels.hip")
 
 
-def k_voigt_traffic(lines, cut, dnu, tile_width):
-    """HBM bytes per k_voigt launch from the committed FETCH_SIZE / WRITE_SIZE counter runs,
-    scaled by the same counters on a plain copy; None when absent, taken on another workload,
-    or taken on a different kernel source."""
+def wing_traffic(lines, cut, dnu, tile_width):
+    """HBM bytes of one wing pass (k_wing + k_far + k_combine_far) from the committed FETCH_SIZE /
+    WRITE_SIZE counter runs, scaled by the same counters on a plain copy; None when absent, taken
+    on another workload or span width, or taken on a different kernel source."""
     import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -322,7 +322,7 @@ def main():
         "voigt_evals_per_s": n_evals / ((voigt_ms + core_ms) * 1e-3),
         "evals": n_evals, "core_evals": core_evals,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": k_voigt_traffic(N, w.cut, w.dnu, tm.tile_width),
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": wing_traffic(N, w.cut, w.dnu, tm.tile_width),
                      "kernel": "wing pass: k_wing<%d> + k_far + k_combine_far" % (tm.tile_width // 64),
                      "flops_per_eval": FLOPS_PER_EVAL,
                      "evals_per_launch": made, "avg_launch_ms": voigt_ms,

@@ -79,8 +79,10 @@ struct DevInfo {
   int core_per_cu[4] = {};    // core kernel (one-wave workgroups) occupancy per slots
   double* cheb_w[4] = {};     // device: Lagrange weights of the span nodes, per slots 1/2/4/8
   float cheb_x[4][hk::kNodes] = {};  // node positions relative to the span's first point
-  double* tile_w[4] = {};     // device: the same for the wing tile (4 spans), per slots
+  double* tile_w[4] = {};     // device: the same for the tile-far tile (4 spans), per slots
   float tile_x[4][hk::kNodes] = {};
+  double* mid_w[4] = {};      // device: the span's middle-distance nodes (kMidNodes), per slots
+  float mid_x[4][hk::kMidNodes] = {};
   int far_per_cu = 1;         // tile-far kernel occupancy
 };
 
@@ -117,17 +119,21 @@ void weideman_coeffs(int N, double* a_out, double* L_out) {
   *L_out = L;
 }
 
-// Chebyshev points of the first kind on a span of S grid points [0, S-1] and, for every grid
-// point of the span, the Lagrange weights of the nodes (barycentric form). weights[k * S + j].
-void span_nodes(int S, float* x_out, std::vector<double>& weights) {
-  const int m = hk::kNodes;
-  const double h = 0.5 * (S - 1);
+// m Chebyshev points of the first kind on a span of S grid points [0, S-1], at the FP32
+// positions the kernels evaluate (node_pos), and for every grid point of the span the Lagrange
+// weights of those nodes (barycentric form with the weights of the actual positions):
+// weights[k * S + j].
+void span_nodes(int S, int m, float* x_out, std::vector<double>& weights) {
   std::vector<double> x(m), bw(m);
   for (int k = 0; k < m; ++k) {
-    const double th = (2.0 * k + 1.0) * M_PI / (2.0 * m);
-    x[k] = h + h * std::cos(th);
-    bw[k] = ((k & 1) ? -1.0 : 1.0) * std::sin(th);
-    x_out[k] = (float)x[k];
+    x_out[k] = hk::node_pos(S, m, k);
+    x[k] = (double)x_out[k];
+  }
+  for (int k = 0; k < m; ++k) {
+    double p = 1.0;
+    for (int i = 0; i < m; ++i)
+      if (i != k) p *= (x[k] - x[i]) / (0.25 * S);  // scaled differences keep the product in range
+    bw[k] = 1.0 / p;
   }
   weights.assign((size_t)m * S, 0.0);
   for (int j = 0; j < S; ++j) {
@@ -143,6 +149,15 @@ void span_nodes(int S, float* x_out, std::vector<double>& weights) {
   }
 }
 
+// The compiled Chebyshev tables against cos.
+bool cheb_tables_ok() {
+  for (int k = 0; k < 16; ++k)
+    if (std::fabs(hk::cheb_cos16(k) - std::cos((2 * k + 1) * M_PI / 32.0)) > 1e-15) return false;
+  for (int k = 0; k < 32; ++k)
+    if (std::fabs(hk::cheb_cos32(k) - std::cos((2 * k + 1) * M_PI / 64.0)) > 1e-15) return false;
+  return true;
+}
+
 hk_status device_init(int* dev_out, DevInfo* info) {
   int dev = -1;
   HK_HIP(hipGetDevice(&dev));
@@ -153,6 +168,7 @@ hk_status device_init(int* dev_out, DevInfo* info) {
     HK_HIP(hipGetDeviceProperties(&prop, dev));
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
       return fail(HK_EUNSUPPORTED, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+    if (!cheb_tables_ok()) return fail(HK_EDEVICE, "Chebyshev node table does not match cos");
     double a[hk::kWeidN], L;
     weideman_coeffs(hk::kWeidN, a, &L);
     HK_HIP(hk::upload_weideman(a, L));
@@ -163,12 +179,15 @@ hk_status device_init(int* dev_out, DevInfo* info) {
       di.core_per_cu[si] = hk::core_max_blocks_per_cu(1 << si);
       const int S = hk::kWave << si;
       std::vector<double> wts;
-      span_nodes(S, di.cheb_x[si], wts);
+      span_nodes(S, hk::kNodes, di.cheb_x[si], wts);
       HK_HIP(hipMalloc(&di.cheb_w[si], sizeof(double) * wts.size()));  // held for the process lifetime
       HK_HIP(hipMemcpy(di.cheb_w[si], wts.data(), sizeof(double) * wts.size(), hipMemcpyHostToDevice));
-      span_nodes(hk::kWavesPerWG * S, di.tile_x[si], wts);
+      span_nodes(hk::kWavesPerWG * S, hk::kNodes, di.tile_x[si], wts);
       HK_HIP(hipMalloc(&di.tile_w[si], sizeof(double) * wts.size()));  // held for the process lifetime
       HK_HIP(hipMemcpy(di.tile_w[si], wts.data(), sizeof(double) * wts.size(), hipMemcpyHostToDevice));
+      span_nodes(S, hk::kMidNodes, di.mid_x[si], wts);
+      HK_HIP(hipMalloc(&di.mid_w[si], sizeof(double) * wts.size()));  // held for the process lifetime
+      HK_HIP(hipMemcpy(di.mid_w[si], wts.data(), sizeof(double) * wts.size(), hipMemcpyHostToDevice));
     }
     di.far_per_cu = hk::far_max_blocks_per_cu();
     it = g_dev.emplace(dev, di).first;
@@ -517,7 +536,7 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   va.chunk = pl.chunk;
   va.items_cap = (int32_t)std::min<int64_t>(pl.items_bound_w, INT32_MAX);
   va.cheb_w = di.cheb_w[si];
-  for (int q = 0; q < hk::kNodes; ++q) va.cheb_x[q] = di.cheb_x[si][q];
+  va.mid_w = di.mid_w[si];
   HK_HIP(hk::launch_wing(va, pl.slots, pl.grid_w, st));
   tm.mark();
   HK_HIP(hk::launch_combine(va, pl.slots, false, st));

@@ -16,9 +16,77 @@ constexpr int kRadixBits = 8;
 constexpr int kSortItems = 16;   // keys per thread per sort block
 constexpr int kSortBlock = kThreads * kSortItems;
 constexpr int kFillPairs = 48;   // pair descriptors per fill launch (kernel-argument space)
-constexpr int kNodes = 16;       // Chebyshev nodes per wave span for lines far from the span
-constexpr float kFarSpans = 1.5f;  // far: centre at least 1.5 spans (3 half-spans) from the span centre
+constexpr int kNodes = 16;       // Chebyshev nodes of a span or tile for lines far from it
+constexpr double kFarSpans = 1.5;  // far: centre at least 1.5 spans (3 half-spans) from the span centre
+constexpr int kMidNodes = 32;    // Chebyshev nodes of a span for lines at middle distance
+constexpr double kMidSpans = 0.75; // middle: centre 0.75-1.5 spans (1.5-3 half-spans) from the span centre
 constexpr double kTileFar = 1.5;   // tile-far: centre at least 1.5 tile widths from the tile centre
+
+// cos((2k + 1) pi / (2m)), k < m: Chebyshev points of the first kind on [-1, 1] for m = 16 and 32
+// (the host checks the table against cos at initialisation).
+__host__ __device__ constexpr double cheb_cos16(int k) {
+  switch (k) {
+    case 0: return 0.99518472667219693;
+    case 1: return 0.95694033573220882;
+    case 2: return 0.88192126434835505;
+    case 3: return 0.77301045336273699;
+    case 4: return 0.63439328416364549;
+    case 5: return 0.47139673682599781;
+    case 6: return 0.29028467725446233;
+    case 7: return 0.09801714032956077;
+    case 8: return -0.098017140329560645;
+    case 9: return -0.29028467725446216;
+    case 10: return -0.4713967368259977;
+    case 11: return -0.63439328416364538;
+    case 12: return -0.77301045336273699;
+    case 13: return -0.88192126434835494;
+    case 14: return -0.95694033573220882;
+    case 15: return -0.99518472667219682;
+    default: return 0.0;
+  }
+}
+__host__ __device__ constexpr double cheb_cos32(int k) {
+  switch (k) {
+    case 0: return 0.99879545620517241;
+    case 1: return 0.98917650996478101;
+    case 2: return 0.97003125319454397;
+    case 3: return 0.94154406518302081;
+    case 4: return 0.90398929312344334;
+    case 5: return 0.85772861000027212;
+    case 6: return 0.80320753148064494;
+    case 7: return 0.74095112535495911;
+    case 8: return 0.67155895484701833;
+    case 9: return 0.59569930449243347;
+    case 10: return 0.51410274419322166;
+    case 11: return 0.4275550934302822;
+    case 12: return 0.33688985339222005;
+    case 13: return 0.24298017990326398;
+    case 14: return 0.14673047445536175;
+    case 15: return 0.049067674327418126;
+    case 16: return -0.049067674327418008;
+    case 17: return -0.14673047445536164;
+    case 18: return -0.24298017990326387;
+    case 19: return -0.33688985339221994;
+    case 20: return -0.42755509343028186;
+    case 21: return -0.51410274419322166;
+    case 22: return -0.59569930449243336;
+    case 23: return -0.67155895484701844;
+    case 24: return -0.74095112535495888;
+    case 25: return -0.80320753148064483;
+    case 26: return -0.85772861000027201;
+    case 27: return -0.90398929312344334;
+    case 28: return -0.9415440651830207;
+    case 29: return -0.97003125319454397;
+    case 30: return -0.98917650996478101;
+    case 31: return -0.99879545620517241;
+    default: return 0.0;
+  }
+}
+// Node k of m (16 or 32) on a span of S grid points [0, S - 1], in FP32: the device evaluates the
+// lines there, and the host's interpolation weights are exact for these positions.
+__host__ __device__ constexpr float node_pos(int S, int m, int k) {
+  return (float)(0.5 * (S - 1) * (1.0 + (m == 16 ? cheb_cos16(k) : cheb_cos32(k))));
+}
 
 // Wavenumber -> bin key: clamp(floor((v - numin) * scale), 0, kmax), evaluated in FP64.
 struct KeyMap {
@@ -42,11 +110,12 @@ struct PairDesc {
 
 // The lines of one span (64 P grid points, one wave of the wing pass) as segments of the
 // sorted list, in list order; the tile-far ranges of its tile are left out.
-constexpr int kMaxSeg = 9;
+constexpr int kMaxSeg = 13;  // elementary intervals between 14 range ends
 struct SpanSeg {
   int32_t lo[kMaxSeg];   // first line of segment q
   int32_t len[kMaxSeg];  // its line count
-  int32_t far_mask;      // bit q: segment q is far from the span (evaluated at the span's nodes)
+  int32_t far_mask;      // bit q: segment q is far from the span (evaluated at its kNodes nodes)
+  int32_t mid_mask;      // bit q: segment q is at middle distance (evaluated at its kMidNodes nodes)
   int32_t n;             // segment count
 };
 
@@ -76,7 +145,7 @@ struct VoigtArgs {
   int32_t chunk;           // lines per work item
   int32_t items_cap;       // rows of `partial` (work items beyond it are never written)
   const double* cheb_w;    // [kNodes][64 P] Lagrange weights of the span's Chebyshev nodes
-  float cheb_x[kNodes];    // node positions relative to the span's first point
+  const double* mid_w;     // [kMidNodes][64 P] the same for the middle-distance nodes
 };
 
 // Arguments of the tile-far pass (lines evaluated at the tile's Chebyshev nodes) and its combine.

@@ -416,7 +416,8 @@ __global__ void k_worklist(const uint32_t* __restrict__ keys, int64_t N, KeyMap 
 // segments -- lines that keep the whole span inside their cut (half a grid step to spare), lie
 // at least kFarSpans spans from the span centre and farther from the span than the reach of the
 // order-5 zone (far_z alpha_max), so that they have no core point and an order below 5 there,
-// all from the bounds alone -- and direct segments (every other line), in list order.
+// all from the bounds alone -- middle segments (the same with kMidSpans in place of kFarSpans,
+// closer than the far ones), and direct segments (every other line), in list order.
 __global__ void k_span_segments(const uint32_t* __restrict__ keys, int64_t N, KeyMap km, double numin,
                                 double numax, const PairDesc* __restrict__ spairs,
                                 const PairDesc* __restrict__ tpairs, int n_pairs, int n_spans, int span_w,
@@ -433,6 +434,7 @@ __global__ void k_span_segments(const uint32_t* __restrict__ keys, int64_t N, Ke
   SpanSeg sg;
   sg.n = 0;
   sg.far_mask = 0;
+  sg.mid_mask = 0;
   int64_t lo = 0, hi = N;
   if (!isinf(cut)) {
     const double va = __dsub_rn(nA, cut), vb = __dadd_rn(nB, cut);
@@ -453,36 +455,45 @@ __global__ void k_span_segments(const uint32_t* __restrict__ keys, int64_t N, Ke
     const int4 tf = tile_far[tpairs[p].tile_base + (int)(t / kWavesPerWG)];
     ta1 = tf.x; tb1 = tf.y; ta2 = tf.z; tb2 = tf.w;
   }
-  // far ranges of the span (full spans only)
-  int64_t fa1 = lo, fb1 = lo, fa2 = hi, fb2 = hi;
+  // far and middle ranges of the span (full spans only); the middle ones contain the far ones
+  int64_t fa1 = lo, fb1 = lo, fa2 = hi, fb2 = hi, ma1 = lo, mb1 = lo, ma2 = hi, mb2 = hi;
   if (j0 + span_w <= pd.n && hi > lo) {
     const double c = 0.5 * (nA + nB), half = 0.5 * (nB - nA);
     const double wlo = isinf(cut) ? numin : fmax(numin, nA - cut);
     const double whi = isinf(cut) ? numax : fmin(numax, nB + cut);
     const double amax = pd.beta * fmax(fabs(wlo), fabs(whi));
-    const double d = fmax((double)kFarSpans * span_w * pd.dnu, half + far_z * amax * 1.001 + 2.0 * pd.dnu);
+    const double reach = half + far_z * amax * 1.001 + 2.0 * pd.dnu;
+    const double d = fmax(kFarSpans * span_w * pd.dnu, reach);
+    const double dm = fmax(kMidSpans * span_w * pd.dnu, reach);
     const double m = 0.5 * pd.dnu;
-    key_range(keys, lo, hi, isinf(cut) ? -INFINITY : nB - cut + m, c - d, km, fa1, fb1);
-    key_range(keys, lo, hi, c + d, isinf(cut) ? INFINITY : nA + cut - m, km, fa2, fb2);
+    const double v0 = isinf(cut) ? -INFINITY : nB - cut + m, v1 = isinf(cut) ? INFINITY : nA + cut - m;
+    key_range(keys, lo, hi, v0, c - d, km, fa1, fb1);
+    key_range(keys, lo, hi, c + d, v1, km, fa2, fb2);
+    key_range(keys, lo, hi, v0, c - dm, km, ma1, mb1);
+    key_range(keys, lo, hi, c + dm, v1, km, ma2, mb2);
   }
   // elementary intervals between all range ends, in order; tile-far ones are left out
-  int64_t bp[10] = {lo, hi, fa1, fb1, fa2, fb2, ta1, tb1, ta2, tb2};
-  for (int i = 0; i < 10; ++i) bp[i] = bp[i] < lo ? lo : (bp[i] > hi ? hi : bp[i]);
-  for (int i = 1; i < 10; ++i)
+  int64_t bp[14] = {lo, hi, fa1, fb1, fa2, fb2, ma1, mb1, ma2, mb2, ta1, tb1, ta2, tb2};
+  for (int i = 0; i < 14; ++i) bp[i] = bp[i] < lo ? lo : (bp[i] > hi ? hi : bp[i]);
+  for (int i = 1; i < 14; ++i)
     for (int j = i; j > 0 && bp[j - 1] > bp[j]; --j) { const int64_t x = bp[j]; bp[j] = bp[j - 1]; bp[j - 1] = x; }
   int64_t total = 0;
-  for (int i = 0; i + 1 < 10; ++i) {
+  for (int i = 0; i + 1 < 14; ++i) {
     const int64_t x = bp[i], y = bp[i + 1];
     if (x >= y) continue;
     if ((x >= ta1 && y <= tb1) || (x >= ta2 && y <= tb2)) continue;
-    const int far = ((x >= fa1 && y <= fb1) || (x >= fa2 && y <= fb2)) ? 1 : 0;
+    // 1: far, 2: middle, 0: direct
+    const int kind = ((x >= fa1 && y <= fb1) || (x >= fa2 && y <= fb2)) ? 1
+                     : ((x >= ma1 && y <= mb1) || (x >= ma2 && y <= mb2)) ? 2 : 0;
     const int q = sg.n - 1;
-    if (q >= 0 && (int64_t)sg.lo[q] + sg.len[q] == x && ((sg.far_mask >> q) & 1) == far) {
+    const int kq = q < 0 ? -1 : (((sg.far_mask >> q) & 1) ? 1 : (((sg.mid_mask >> q) & 1) ? 2 : 0));
+    if (q >= 0 && (int64_t)sg.lo[q] + sg.len[q] == x && kq == kind) {
       sg.len[q] += (int32_t)(y - x);
     } else if (sg.n < kMaxSeg) {
       sg.lo[sg.n] = (int32_t)x;
       sg.len[sg.n] = (int32_t)(y - x);
-      sg.far_mask |= far << sg.n;
+      sg.far_mask |= (kind == 1 ? 1 : 0) << sg.n;
+      sg.mid_mask |= (kind == 2 ? 1 : 0) << sg.n;
       ++sg.n;
     }
     total += y - x;
@@ -585,7 +596,7 @@ __global__ __launch_bounds__(kThreads) void k_gridrec(const double* __restrict__
 //       as an inclusive span-local range (empty: x > y)
 //   list: the staged lines that reach the span, grouped by how they are evaluated (see
 //         direct_group), in staging order within a group
-//   node: the span's node sums of the item's far lines
+//   node, node_mid: the span's node sums of the item's far and middle-distance lines
 struct WaveLDS {
   float4 F0[kWave];
   float4 F1[kWave];
@@ -597,6 +608,7 @@ struct WaveLDS {
   int2 CZ[kWave];
   uint8_t list[kWave];
   double node[kNodes];
+  double node_mid[kMidNodes];
 };
 
 // Evaluation group of a staged line: 0 does not reach the span; 1-4 all points inside the cut,
@@ -897,11 +909,22 @@ __device__ __forceinline__ FarLine far_line(bool valid, double nu, float S, floa
   return f;
 }
 
-template <int K>
-__device__ __forceinline__ void far_nodes(const float (&xn)[kNodes], const FarLine& f, float (&acc)[kNodes]) {
+// Node positions: compile-time ones of a span (literal operands), or kernel arguments.
+template <int S, int M>
+struct SpanNodes {
+  __device__ constexpr float operator()(int k) const { return node_pos(S, M, k); }
+};
+struct ArgNodes {
+  const float* x;
+  __device__ float operator()(int k) const { return x[k]; }
+};
+
+// Adds f at nodes G0..G0+kNodes-1 of xs to acc[G0..]
+template <int K, int G0, int NN, class NS>
+__device__ __forceinline__ void far_nodes(const NS& xs, const FarLine& f, float (&acc)[NN]) {
 #pragma unroll
-  for (int k = 0; k < kNodes; ++k) {
-    const float D = __builtin_fmaf(xn[k], f.h, f.e);
+  for (int k = G0; k < G0 + kNodes; ++k) {
+    const float D = __builtin_fmaf(xs(k), f.h, f.e);
     const float R = __builtin_fmaf(D, D, f.gq);
     const float q = __builtin_amdgcn_rcpf(R);
     float t;
@@ -928,13 +951,19 @@ __device__ __forceinline__ void far_nodes(const float (&xn)[kNodes], const FarLi
 }
 
 // Adds each lane's line at the nodes to its node sums, with the wave's largest order.
-__device__ __forceinline__ void far_accumulate(const float (&xn)[kNodes], const FarLine& f, float (&acc)[kNodes]) {
+template <int G0, int NN, class NS>
+__device__ __forceinline__ void far_group(int Kw, const NS& xs, const FarLine& f, float (&acc)[NN]) {
+  if (Kw == 1) far_nodes<1, G0>(xs, f, acc);
+  else if (Kw == 2) far_nodes<2, G0>(xs, f, acc);
+  else if (Kw == 3) far_nodes<3, G0>(xs, f, acc);
+  else far_nodes<4, G0>(xs, f, acc);
+}
+
+template <class NS>
+__device__ __forceinline__ void far_accumulate(const NS& xs, const FarLine& f, float (&acc)[kNodes]) {
   const int Kw = 1 + (__ballot(f.K >= 2) != 0ull ? 1 : 0) + (__ballot(f.K >= 3) != 0ull ? 1 : 0) +
                  (__ballot(f.K >= 4) != 0ull ? 1 : 0);
-  if (Kw == 1) far_nodes<1>(xn, f, acc);
-  else if (Kw == 2) far_nodes<2>(xn, f, acc);
-  else if (Kw == 3) far_nodes<3>(xn, f, acc);
-  else far_nodes<4>(xn, f, acc);
+  far_group<0>(Kw, xs, f, acc);
 }
 
 // Adds the wave's node sums (a butterfly over the lanes in FP64, the same on every lane) to
@@ -951,6 +980,81 @@ __device__ __forceinline__ void far_flush(float (&acc)[kNodes], int lane, double
   if (lane < kNodes) node[lane] += mine;
 }
 
+__device__ __forceinline__ double half_sum32(double v) {
+#pragma unroll
+  for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// The same for the middle-distance segments: lane half h holds node j (h = 0) or 31 - j (h = 1)
+// in acc[j]; the sums are over the 32 lanes of each half.
+__device__ __forceinline__ void mid_flush(float (&acc)[kNodes], int lane, double* node) {
+  double mine = 0.0;
+  const int j = lane & 31;
+#pragma unroll
+  for (int k = 0; k < kNodes; ++k) {
+    const double t = half_sum32((double)acc[k]);
+    mine = j == k ? t : mine;
+    acc[k] = 0.0f;
+  }
+  if (j < kNodes) node[lane < 32 ? j : kMidNodes - 1 - j] += mine;
+}
+
+// One far segment of a span of S points: lines [i0, i1), one per lane, at its kNodes nodes;
+// the node sums go to node[] (see far_flush).
+template <int S>
+__device__ __forceinline__ void far_segment(const VoigtArgs& a, const PairDesc& pd, const float* __restrict__ S_T,
+                                            const float* __restrict__ gT, int i0, int i1, int lane, double nu_a,
+                                            double nu_b, double* node) {
+  const float inv_dnu = (float)(1.0 / pd.dnu);
+  float acc[kNodes];
+#pragma unroll
+  for (int k = 0; k < kNodes; ++k) acc[k] = 0.0f;
+  int n = 0;
+  for (int b = i0; b < i1; b += kWave) {
+    const int li = b + lane;
+    const bool valid = li < i1;
+    const FarLine f = far_line(valid, valid ? a.nu[li] : 0.0, valid ? S_T[li] : 0.0f, valid ? gT[li] : 0.0f, pd,
+                               nu_a, nu_b, inv_dnu, a.zK);
+    far_accumulate(SpanNodes<S, kNodes>(), f, acc);
+    if (++n == 16 || b + kWave >= i1) {
+      far_flush(acc, lane, node);
+      n = 0;
+    }
+  }
+}
+
+// One middle-distance segment: lines [i0, i1), each on two lanes (lane and lane + 32), at the
+// span's kMidNodes nodes. The nodes are symmetric (x_(31-j) = S - 1 - x_j), so the upper half
+// evaluates node 31 - j as node j with the step negated and the offset moved by S - 1 steps,
+// and each lane keeps kNodes sums (see mid_flush).
+template <int S>
+__device__ __forceinline__ void mid_segment(const VoigtArgs& a, const PairDesc& pd, const float* __restrict__ S_T,
+                                            const float* __restrict__ gT, int i0, int i1, int lane, double nu_a,
+                                            double nu_b, double* node) {
+  const float inv_dnu = (float)(1.0 / pd.dnu);
+  const bool upper = lane >= 32;
+  float acc[kNodes];
+#pragma unroll
+  for (int k = 0; k < kNodes; ++k) acc[k] = 0.0f;
+  int n = 0;
+  for (int b = i0; b < i1; b += 32) {
+    const int li = b + (lane & 31);
+    const bool valid = li < i1;
+    FarLine f = far_line(valid, valid ? a.nu[li] : 0.0, valid ? S_T[li] : 0.0f, valid ? gT[li] : 0.0f, pd, nu_a,
+                         nu_b, inv_dnu, a.zK);
+    if (upper) {
+      f.e = __builtin_fmaf((float)(S - 1), f.h, f.e);
+      f.h = -f.h;
+    }
+    far_accumulate(SpanNodes<S, kMidNodes>(), f, acc);
+    if (++n == 16 || b + 32 >= i1) {
+      mid_flush(acc, lane, node);
+      n = 0;
+    }
+  }
+}
+
 // ------------------------------------------------------------------- wing pass
 // One wave per span of 64 P grid points (lane + 64 p, p < P). A work item is a span and a
 // chunk of its line segments (k_span_segments), taken in list order:
@@ -959,9 +1063,10 @@ __device__ __forceinline__ void far_flush(float (&acc)[kNodes], int lane, double
 //    series order it needs there (lanes outside its cut range and its core points add
 //    nothing; the core points are the line-core pass's), in staging order, into per-lane
 //    FP32 sums with a compensated flush every 16 lines;
-//  * a far segment is evaluated at the span's Chebyshev nodes, one line per lane (per lane
-//    in FP32 over 16 lines, then FP64; over the wave by a butterfly, the same on every lane),
-//    and the node sums are interpolated to the span's points in FP64 at the end of the item.
+//  * a far (middle) segment is evaluated at the span's kNodes (kMidNodes) Chebyshev nodes,
+//    one line per lane (per lane in FP32 over 16 lines, then FP64; over the wave by a
+//    butterfly, the same on every lane), and the node sums are interpolated to the span's
+//    points in FP64 at the end of the item.
 // A span with one item writes k; otherwise each item writes its partial span and k_combine
 // sums them in item order. No workgroup barrier: waves run independently.
 template <int P>
@@ -972,7 +1077,7 @@ __global__ __launch_bounds__(kWave) void k_wing(VoigtArgs a) {
   const int total = a.item_base[a.n_tiles_total];
   const float jl0 = (float)lane;  // this lane's first span point
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  long long n_direct = 0, n_node = 0;
+  long long n_direct = 0, n_node = 0, n_mid = 0;
 
   for (;;) {
     int mine = 0;
@@ -996,7 +1101,7 @@ __global__ __launch_bounds__(kWave) void k_wing(VoigtArgs a) {
     const float* __restrict__ gT = a.gT + (int64_t)pd.tidx * a.N;
     const int4* __restrict__ grec = a.grec + (int64_t)pd.gidx * a.N;
     const SpanSeg* __restrict__ sg = a.segs + g;
-    const int nseg = sg->n, fmask = sg->far_mask;
+    const int nseg = sg->n, fmask = sg->far_mask, mmask = sg->mid_mask;
 
     float s[P], cc[P], part[P];
 #pragma unroll
@@ -1006,7 +1111,8 @@ __global__ __launch_bounds__(kWave) void k_wing(VoigtArgs a) {
       part[p] = 0.0f;
     }
     if (lane < kNodes) L.node[lane] = 0.0;
-    bool any_far = false;
+    if (lane < kMidNodes) L.node_mid[lane] = 0.0;
+    bool any_far = false, any_mid = false;
     int cum = 0, v_hi = v_lo;
     for (int q = 0; q < nseg; ++q) {
       const int len = sg->len[q];
@@ -1015,27 +1121,18 @@ __global__ __launch_bounds__(kWave) void k_wing(VoigtArgs a) {
       if (x0 < x1) {
         const int i0 = sg->lo[q] + (x0 - cum), i1 = i0 + (x1 - x0);
         v_hi = x1;
-        if ((fmask >> q) & 1) {
-          // ---- far segment: node sums, one line per lane
-          any_far = true;
+        if (((fmask | mmask) >> q) & 1) {
+          // ---- far or middle segment: node sums, one line per lane
           n_node += i1 - i0;
           const double nu_a = grid_nu(pd.nu_start, pd.dnu, span0);
           const double nu_b = grid_nu(pd.nu_start, pd.dnu, span0 + W - 1);
-          const float inv_dnu = (float)(1.0 / pd.dnu);
-          float acc[kNodes];
-#pragma unroll
-          for (int k = 0; k < kNodes; ++k) acc[k] = 0.0f;
-          int n = 0;
-          for (int b = i0; b < i1; b += kWave) {
-            const int li = b + lane;
-            const bool valid = li < i1;
-            const FarLine f = far_line(valid, valid ? a.nu[li] : 0.0, valid ? S_T[li] : 0.0f,
-                                       valid ? gT[li] : 0.0f, pd, nu_a, nu_b, inv_dnu, a.zK);
-            far_accumulate(a.cheb_x, f, acc);
-            if (++n == 16 || b + kWave >= i1) {
-              far_flush(acc, lane, L.node);
-              n = 0;
-            }
+          if ((fmask >> q) & 1) {
+            any_far = true;
+            far_segment<W>(a, pd, S_T, gT, i0, i1, lane, nu_a, nu_b, L.node);
+          } else {
+            any_mid = true;
+            n_mid += i1 - i0;
+            mid_segment<W>(a, pd, S_T, gT, i0, i1, lane, nu_a, nu_b, L.node_mid);
           }
         } else {
           // ---- direct segment: 64 lines per stage
@@ -1086,20 +1183,31 @@ __global__ __launch_bounds__(kWave) void k_wing(VoigtArgs a) {
       cum += len;
     }
     (void)v_hi;
-    // ---- far lines: interpolation of the node sums to the span's points, in FP64
-    if (any_far) {
+    // ---- far and middle lines: interpolation of the node sums to the span's points, in FP64
+    if (any_far || any_mid) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       double v[P];
 #pragma unroll
       for (int p = 0; p < P; ++p) v[p] = 0.0;
+      if (any_far) {
 #pragma unroll 1
-      for (int k = 0; k < kNodes; ++k) {
-        const double ns = L.node[k];
-        const double* __restrict__ wk = a.cheb_w + k * W + lane;
+        for (int k = 0; k < kNodes; ++k) {
+          const double ns = L.node[k];
+          const double* __restrict__ wk = a.cheb_w + k * W + lane;
 #pragma unroll
-        for (int p = 0; p < P; ++p) v[p] = fma(ns, wk[p * kWave], v[p]);
+          for (int p = 0; p < P; ++p) v[p] = fma(ns, wk[p * kWave], v[p]);
+        }
+      }
+      if (any_mid) {
+#pragma unroll 1
+        for (int k = 0; k < kMidNodes; ++k) {
+          const double ns = L.node_mid[k];
+          const double* __restrict__ wk = a.mid_w + k * W + lane;
+#pragma unroll
+          for (int p = 0; p < P; ++p) v[p] = fma(ns, wk[p * kWave], v[p]);
+        }
       }
 #pragma unroll
       for (int p = 0; p < P; ++p) part[p] += (float)v[p];
@@ -1120,7 +1228,8 @@ __global__ __launch_bounds__(kWave) void k_wing(VoigtArgs a) {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  if (a.stats && lane == 0) a.stats[blockIdx.x] = n_direct * W + n_node * kNodes;
+  if (a.stats && lane == 0)
+    a.stats[blockIdx.x] = n_direct * W + (n_node - n_mid) * kNodes + n_mid * kMidNodes;
 }
 
 
@@ -1180,7 +1289,7 @@ __global__ __launch_bounds__(kThreads) void k_far(FarArgs a) {
       const int64_t li = v < nl ? (int64_t)tf.x + v : (int64_t)tf.z + (v - nl);
       const FarLine f = far_line(valid, valid ? a.nu[li] : 0.0, valid ? S_T[li] : 0.0f, valid ? gT[li] : 0.0f,
                                  pd, nu0, nu1, inv_dnu, a.zK);
-      far_accumulate(a.tile_x, f, acc);
+      far_accumulate(ArgNodes{a.tile_x}, f, acc);
       if (++n == 16 || b + kThreads >= v_hi) {
         far_flush(acc, lane, sRed[wv]);
         n = 0;
