@@ -83,6 +83,8 @@ struct DevInfo {
   float tile_x[4][hk::kNodes] = {};
   double* mid_w[4] = {};      // device: the span's middle-distance nodes (kMidNodes), per slots
   float mid_x[4][hk::kMidNodes] = {};
+  float* mask_w[4] = {};      // device: the span's nodes for lines with a cut bound on it (FP32)
+  float mask_x[4][hk::kMaskNodes] = {};
   int far_per_cu = 1;         // tile-far kernel occupancy
 };
 
@@ -151,6 +153,8 @@ void span_nodes(int S, int m, float* x_out, std::vector<double>& weights) {
 
 // The compiled Chebyshev tables against cos.
 bool cheb_tables_ok() {
+  for (int k = 0; k < 6; ++k)
+    if (std::fabs(hk::cheb_cos6(k) - std::cos((2 * k + 1) * M_PI / 12.0)) > 1e-15) return false;
   for (int k = 0; k < 16; ++k)
     if (std::fabs(hk::cheb_cos16(k) - std::cos((2 * k + 1) * M_PI / 32.0)) > 1e-15) return false;
   for (int k = 0; k < 32; ++k)
@@ -188,6 +192,10 @@ hk_status device_init(int* dev_out, DevInfo* info) {
       span_nodes(S, hk::kMidNodes, di.mid_x[si], wts);
       HK_HIP(hipMalloc(&di.mid_w[si], sizeof(double) * wts.size()));  // held for the process lifetime
       HK_HIP(hipMemcpy(di.mid_w[si], wts.data(), sizeof(double) * wts.size(), hipMemcpyHostToDevice));
+      span_nodes(S, hk::kMaskNodes, di.mask_x[si], wts);
+      std::vector<float> wf(wts.begin(), wts.end());
+      HK_HIP(hipMalloc(&di.mask_w[si], sizeof(float) * wf.size()));  // held for the process lifetime
+      HK_HIP(hipMemcpy(di.mask_w[si], wf.data(), sizeof(float) * wf.size(), hipMemcpyHostToDevice));
     }
     di.far_per_cu = hk::far_max_blocks_per_cu();
     it = g_dev.emplace(dev, di).first;
@@ -475,7 +483,8 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
                               grec + (size_t)q * L->N, st));
   tm.mark();
   // work lists: tile windows and tile-far ranges, span segments, span core windows
-  const double far_z = kZK[hk::kKmax - 2], core_z = kZK[hk::kKmax - 1];
+  // lines evaluated at nodes must keep the interval outside their core (|z| >= the last threshold)
+  const double far_z = kZK[hk::kKmax - 1], core_z = kZK[hk::kKmax - 1];
   hk::PairDesc* dpairs = reinterpret_cast<hk::PairDesc*>(ws + pl.off_pairs);
   hk::PairDesc* dpairs_c = reinterpret_cast<hk::PairDesc*>(ws + pl.off_pairs_c);
   int* cnt = reinterpret_cast<int*>(ws + pl.off_cnt);  // dispensers: wing [0], core [8], tile-far [16]
@@ -537,6 +546,7 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   va.items_cap = (int32_t)std::min<int64_t>(pl.items_bound_w, INT32_MAX);
   va.cheb_w = di.cheb_w[si];
   va.mid_w = di.mid_w[si];
+  va.mask_w = di.mask_w[si];
   HK_HIP(hk::launch_wing(va, pl.slots, pl.grid_w, st));
   tm.mark();
   HK_HIP(hk::launch_combine(va, pl.slots, false, st));

@@ -20,10 +20,24 @@ constexpr int kNodes = 16;       // Chebyshev nodes of a span or tile for lines 
 constexpr double kFarSpans = 1.5;  // far: centre at least 1.5 spans (3 half-spans) from the span centre
 constexpr int kMidNodes = 32;    // Chebyshev nodes of a span for lines at middle distance
 constexpr double kMidSpans = 0.75; // middle: centre 0.75-1.5 spans (1.5-3 half-spans) from the span centre
+constexpr int kMaskNodes = 6;    // Chebyshev nodes of a span for lines whose cut bound falls on it
+constexpr double kMaskSpans = 6.0; // such lines are evaluated at nodes when at least 6 spans away
+constexpr int kMaskMaxSpan = 128;  // ... and only on spans of at most 128 points (P <= 2)
 constexpr double kTileFar = 1.5;   // tile-far: centre at least 1.5 tile widths from the tile centre
 
-// cos((2k + 1) pi / (2m)), k < m: Chebyshev points of the first kind on [-1, 1] for m = 16 and 32
-// (the host checks the table against cos at initialisation).
+// cos((2k + 1) pi / (2m)), k < m: Chebyshev points of the first kind on [-1, 1] for m = 6, 16 and
+// 32 (the host checks the tables against cos at initialisation).
+__host__ __device__ constexpr double cheb_cos6(int k) {
+  switch (k) {
+    case 0: return 0.96592582628906831;
+    case 1: return 0.70710678118654757;
+    case 2: return 0.25881904510252074;
+    case 3: return -0.25881904510252063;
+    case 4: return -0.70710678118654746;
+    case 5: return -0.9659258262890682;
+    default: return 0.0;
+  }
+}
 __host__ __device__ constexpr double cheb_cos16(int k) {
   switch (k) {
     case 0: return 0.99518472667219693;
@@ -82,10 +96,10 @@ __host__ __device__ constexpr double cheb_cos32(int k) {
     default: return 0.0;
   }
 }
-// Node k of m (16 or 32) on a span of S grid points [0, S - 1], in FP32: the device evaluates the
-// lines there, and the host's interpolation weights are exact for these positions.
+// Node k of m (6, 16 or 32) on a span of S grid points [0, S - 1], in FP32: the device evaluates
+// the lines there, and the host's interpolation weights are exact for these positions.
 __host__ __device__ constexpr float node_pos(int S, int m, int k) {
-  return (float)(0.5 * (S - 1) * (1.0 + (m == 16 ? cheb_cos16(k) : cheb_cos32(k))));
+  return (float)(0.5 * (S - 1) * (1.0 + (m == 6 ? cheb_cos6(k) : m == 16 ? cheb_cos16(k) : cheb_cos32(k))));
 }
 
 // Wavenumber -> bin key: clamp(floor((v - numin) * scale), 0, kmax), evaluated in FP64.
@@ -110,13 +124,19 @@ struct PairDesc {
 
 // The lines of one span (64 P grid points, one wave of the wing pass) as segments of the
 // sorted list, in list order; the tile-far ranges of its tile are left out.
-constexpr int kMaxSeg = 13;  // elementary intervals between 14 range ends
+constexpr int kMaxSeg = 17;  // elementary intervals between 18 range ends
+enum SegKind : uint8_t {
+  kSegDirect = 0,     // evaluated at every point of the span
+  kSegFar = 1,        // far: at the span's kNodes nodes
+  kSegMid = 2,        // middle distance: at the span's kMidNodes nodes
+  kSegMaskLeft = 3,   // far, cut bound on the span, reaching it from the left: kMaskNodes nodes
+  kSegMaskRight = 4,  // the same from the right
+};
 struct SpanSeg {
   int32_t lo[kMaxSeg];   // first line of segment q
   int32_t len[kMaxSeg];  // its line count
-  int32_t far_mask;      // bit q: segment q is far from the span (evaluated at its kNodes nodes)
-  int32_t mid_mask;      // bit q: segment q is at middle distance (evaluated at its kMidNodes nodes)
-  int32_t n;             // segment count
+  uint8_t kind[kMaxSeg]; // its SegKind
+  uint8_t n;             // segment count
 };
 
 // Arguments of the persistent Voigt kernels (wing pass over spans, line-core pass).
@@ -146,6 +166,7 @@ struct VoigtArgs {
   int32_t items_cap;       // rows of `partial` (work items beyond it are never written)
   const double* cheb_w;    // [kNodes][64 P] Lagrange weights of the span's Chebyshev nodes
   const double* mid_w;     // [kMidNodes][64 P] the same for the middle-distance nodes
+  const float* mask_w;     // [kMaskNodes][64 P] the same for the nodes of lines with a cut bound on it
 };
 
 // Arguments of the tile-far pass (lines evaluated at the tile's Chebyshev nodes) and its combine.

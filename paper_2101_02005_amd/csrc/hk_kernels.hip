@@ -344,8 +344,8 @@ __device__ __forceinline__ void key_range(const uint32_t* __restrict__ keys, int
 // far != null (wing pass): also the tile-far ranges of full tiles, the lines that (1) keep the
 // whole tile inside their cut (with half a grid step to spare), (2) lie at least kTileFar tile
 // widths from the tile centre, and (3) lie farther from the tile than far_z alpha_max, the
-// largest reach of the order-5 zone |z| < far_z (zone half-widths are at most far_z alpha),
-// so that they have no core point and a series order below 5 on the tile. These three facts
+// largest reach of the core |z| < far_z (zone half-widths are at most far_z alpha), so that
+// they have no core point on the tile. These three facts
 // follow from the bounds alone, so the tile-far pass needs no per-line test and the wing
 // pass skips the ranges; every other line of [lo, hi) stays in the wing pass.
 __global__ void k_worklist(const uint32_t* __restrict__ keys, int64_t N, KeyMap km, double numin, double numax,
@@ -415,9 +415,11 @@ __global__ void k_worklist(const uint32_t* __restrict__ keys, int64_t N, KeyMap 
 // minus the tile-far ranges of its tile (evaluated by the tile-far pass), split into far
 // segments -- lines that keep the whole span inside their cut (half a grid step to spare), lie
 // at least kFarSpans spans from the span centre and farther from the span than the reach of the
-// order-5 zone (far_z alpha_max), so that they have no core point and an order below 5 there,
-// all from the bounds alone -- middle segments (the same with kMidSpans in place of kFarSpans,
-// closer than the far ones), and direct segments (every other line), in list order.
+// core (far_z alpha_max), so that they have no core point there, all from the bounds alone --
+// middle segments (the same with kMidSpans in place of kFarSpans, closer than the far ones),
+// masked segments (lines whose cut bound falls on the span, at least kMaskSpans spans from its
+// centre and beyond the core's reach: on the left, lines that reach a prefix of the span's
+// points; on the right, a suffix), and direct segments (every other line), in list order.
 __global__ void k_span_segments(const uint32_t* __restrict__ keys, int64_t N, KeyMap km, double numin,
                                 double numax, const PairDesc* __restrict__ spairs,
                                 const PairDesc* __restrict__ tpairs, int n_pairs, int n_spans, int span_w,
@@ -433,8 +435,6 @@ __global__ void k_span_segments(const uint32_t* __restrict__ keys, int64_t N, Ke
   const double nA = grid_nu(pd.nu_start, pd.dnu, j0), nB = grid_nu(pd.nu_start, pd.dnu, j1);
   SpanSeg sg;
   sg.n = 0;
-  sg.far_mask = 0;
-  sg.mid_mask = 0;
   int64_t lo = 0, hi = N;
   if (!isinf(cut)) {
     const double va = __dsub_rn(nA, cut), vb = __dadd_rn(nB, cut);
@@ -455,8 +455,10 @@ __global__ void k_span_segments(const uint32_t* __restrict__ keys, int64_t N, Ke
     const int4 tf = tile_far[tpairs[p].tile_base + (int)(t / kWavesPerWG)];
     ta1 = tf.x; tb1 = tf.y; ta2 = tf.z; tb2 = tf.w;
   }
-  // far and middle ranges of the span (full spans only); the middle ones contain the far ones
+  // far, middle and masked ranges of the span (full spans only); the middle ones contain the
+  // far ones; the masked ones lie beyond the far ones' cut-side bounds
   int64_t fa1 = lo, fb1 = lo, fa2 = hi, fb2 = hi, ma1 = lo, mb1 = lo, ma2 = hi, mb2 = hi;
+  int64_t la = lo, lb = lo, ra = hi, rb = hi;
   if (j0 + span_w <= pd.n && hi > lo) {
     const double c = 0.5 * (nA + nB), half = 0.5 * (nB - nA);
     const double wlo = isinf(cut) ? numin : fmax(numin, nA - cut);
@@ -465,35 +467,43 @@ __global__ void k_span_segments(const uint32_t* __restrict__ keys, int64_t N, Ke
     const double reach = half + far_z * amax * 1.001 + 2.0 * pd.dnu;
     const double d = fmax(kFarSpans * span_w * pd.dnu, reach);
     const double dm = fmax(kMidSpans * span_w * pd.dnu, reach);
+    const double dk = fmax(kMaskSpans * span_w * pd.dnu, reach);
     const double m = 0.5 * pd.dnu;
     const double v0 = isinf(cut) ? -INFINITY : nB - cut + m, v1 = isinf(cut) ? INFINITY : nA + cut - m;
     key_range(keys, lo, hi, v0, c - d, km, fa1, fb1);
     key_range(keys, lo, hi, c + d, v1, km, fa2, fb2);
     key_range(keys, lo, hi, v0, c - dm, km, ma1, mb1);
     key_range(keys, lo, hi, c + dm, v1, km, ma2, mb2);
+    if (!isinf(cut) && cut > 2.0 * (nB - nA) + 2.0 * pd.dnu && span_w <= kMaskMaxSpan) {
+      // below v0 a line's cut range ends on the span (or before it) and starts far left of it;
+      // above v1 it starts on the span (or after it) and ends far right of it
+      key_range(keys, lo, hi, -INFINITY, fmin(v0 - 2.0 * m, c - dk), km, la, lb);
+      key_range(keys, lo, hi, fmax(v1 + 2.0 * m, c + dk), INFINITY, km, ra, rb);
+    }
   }
   // elementary intervals between all range ends, in order; tile-far ones are left out
-  int64_t bp[14] = {lo, hi, fa1, fb1, fa2, fb2, ma1, mb1, ma2, mb2, ta1, tb1, ta2, tb2};
-  for (int i = 0; i < 14; ++i) bp[i] = bp[i] < lo ? lo : (bp[i] > hi ? hi : bp[i]);
-  for (int i = 1; i < 14; ++i)
+  constexpr int NB = 18;
+  int64_t bp[NB] = {lo, hi, fa1, fb1, fa2, fb2, ma1, mb1, ma2, mb2, ta1, tb1, ta2, tb2, la, lb, ra, rb};
+  for (int i = 0; i < NB; ++i) bp[i] = bp[i] < lo ? lo : (bp[i] > hi ? hi : bp[i]);
+  for (int i = 1; i < NB; ++i)
     for (int j = i; j > 0 && bp[j - 1] > bp[j]; --j) { const int64_t x = bp[j]; bp[j] = bp[j - 1]; bp[j - 1] = x; }
   int64_t total = 0;
-  for (int i = 0; i + 1 < 14; ++i) {
+  for (int i = 0; i + 1 < NB; ++i) {
     const int64_t x = bp[i], y = bp[i + 1];
     if (x >= y) continue;
     if ((x >= ta1 && y <= tb1) || (x >= ta2 && y <= tb2)) continue;
-    // 1: far, 2: middle, 0: direct
-    const int kind = ((x >= fa1 && y <= fb1) || (x >= fa2 && y <= fb2)) ? 1
-                     : ((x >= ma1 && y <= mb1) || (x >= ma2 && y <= mb2)) ? 2 : 0;
-    const int q = sg.n - 1;
-    const int kq = q < 0 ? -1 : (((sg.far_mask >> q) & 1) ? 1 : (((sg.mid_mask >> q) & 1) ? 2 : 0));
-    if (q >= 0 && (int64_t)sg.lo[q] + sg.len[q] == x && kq == kind) {
+    const uint8_t kind = ((x >= fa1 && y <= fb1) || (x >= fa2 && y <= fb2))   ? kSegFar
+                         : ((x >= ma1 && y <= mb1) || (x >= ma2 && y <= mb2)) ? kSegMid
+                         : (x >= la && y <= lb)                               ? kSegMaskLeft
+                         : (x >= ra && y <= rb)                               ? kSegMaskRight
+                                                                              : kSegDirect;
+    const int q = (int)sg.n - 1;
+    if (q >= 0 && (int64_t)sg.lo[q] + sg.len[q] == x && sg.kind[q] == kind) {
       sg.len[q] += (int32_t)(y - x);
     } else if (sg.n < kMaxSeg) {
       sg.lo[sg.n] = (int32_t)x;
       sg.len[sg.n] = (int32_t)(y - x);
-      sg.far_mask |= (kind == 1 ? 1 : 0) << sg.n;
-      sg.mid_mask |= (kind == 2 ? 1 : 0) << sg.n;
+      sg.kind[sg.n] = kind;
       ++sg.n;
     }
     total += y - x;
@@ -870,13 +880,16 @@ __device__ __forceinline__ double wave_sum64(double v) {
 // ------------------------------------------------------- lines far from a span or a tile
 // A line whose centre lies far outside an interval of grid points (a span or a tile; see
 // k_span_segments and k_worklist for the bounds that make it so) is smooth on it: it is
-// evaluated at the interval's kNodes Chebyshev nodes only, one line per lane, with the
-// far-wing series of the order its nearest point of the interval needs (the largest over the
-// wave's lines; the bounds keep it below 5). The node sums are later interpolated to the
-// interval's points with the nodes' Lagrange weights.
+// evaluated at the interval's Chebyshev nodes only, one line per lane, with the far-wing
+// series of the order its nearest point of the interval needs (the largest over the wave's
+// lines; the bounds keep every point of the interval outside the line's core, where order 5
+// holds). The node sums are later interpolated to the interval's points with the nodes'
+// Lagrange weights.
 struct FarLine {
   float h, e, gq, A, kc;  // node offset D = x h + e (x: node position in grid steps), gamma^2/s
   float4 ka, kb;          // Ah times the series coefficients (see wing_coeffs)
+  float4 k5;              // c4-c7 of order 5 (c1-c3 as order 4)
+  float k5c;              // c8 of order 5
   int K;
 };
 
@@ -888,6 +901,8 @@ __device__ __forceinline__ FarLine far_line(bool valid, double nu, float S, floa
   f.h = 0.0f; f.e = 1.0f; f.gq = 1.0f; f.A = 0.0f; f.kc = 0.0f;
   f.ka = make_float4(0.f, 0.f, 0.f, 0.f);
   f.kb = f.ka;
+  f.k5 = f.ka;
+  f.k5c = 0.0f;
   f.K = 1;
   if (!valid) return f;
   const float alpha = (float)(nu * pd.beta);
@@ -900,6 +915,14 @@ __device__ __forceinline__ FarLine far_line(bool valid, double nu, float S, floa
   f.A = S * (gam * isc) * 0.318309886183790672f;  // S gamma / (pi s)
   f.gq = g2 * isc;
   wing_coeffs(a2 * isc, f.gq, f.A, f.ka, f.kb, f.kc);
+  {
+    const float av = a2 * isc, gv = f.gq;
+    const float a3 = av * av * av, a4 = a3 * av, g2v = gv * gv, g3v = g2v * gv;
+    f.k5 = make_float4(f.A * (12.0f * av * av * g2v - 105.0f * a3 * gv + 59.0625f * a4),
+                       f.A * (210.0f * a3 * g2v - 787.5f * a4 * gv), f.A * (-120.0f * a3 * g3v + 2835.0f * a4 * g2v),
+                       f.A * (-3780.0f * a4 * g3v));
+    f.k5c = f.A * (1680.0f * a4 * g2v * g2v);
+  }
   f.h = (float)pd.dnu * rs;                       // one grid step in units of sqrt(s)
   f.e = -((float)(nu - nu_a) * inv_dnu) * f.h;    // minus the line's position, same units
   const float dmin = (float)(nu < nu_a ? nu_a - nu : nu - nu_b);  // to the nearest point
@@ -919,11 +942,11 @@ struct ArgNodes {
   __device__ float operator()(int k) const { return x[k]; }
 };
 
-// Adds f at nodes G0..G0+kNodes-1 of xs to acc[G0..]
-template <int K, int G0, int NN, class NS>
+// Adds f at nodes G0..G0+CNT-1 of xs to acc[G0..]
+template <int K, int G0, int NN, class NS, int CNT = kNodes>
 __device__ __forceinline__ void far_nodes(const NS& xs, const FarLine& f, float (&acc)[NN]) {
 #pragma unroll
-  for (int k = G0; k < G0 + kNodes; ++k) {
+  for (int k = G0; k < G0 + CNT; ++k) {
     const float D = __builtin_fmaf(xs(k), f.h, f.e);
     const float R = __builtin_fmaf(D, D, f.gq);
     const float q = __builtin_amdgcn_rcpf(R);
@@ -938,9 +961,18 @@ __device__ __forceinline__ void far_nodes(const NS& xs, const FarLine& f, float 
       t = __builtin_fmaf(t, q, f.ka.z);
       t = __builtin_fmaf(t, q, f.ka.x);
       t = __builtin_fmaf(t, q, f.A);
-    } else {
+    } else if (K == 4) {
       t = __builtin_fmaf(f.kc, q, f.kb.w);
       t = __builtin_fmaf(t, q, f.kb.z);
+      t = __builtin_fmaf(t, q, f.kb.y);
+      t = __builtin_fmaf(t, q, f.ka.z);
+      t = __builtin_fmaf(t, q, f.ka.x);
+      t = __builtin_fmaf(t, q, f.A);
+    } else {  // K == 5: c8 .. c1
+      t = __builtin_fmaf(f.k5c, q, f.k5.w);
+      t = __builtin_fmaf(t, q, f.k5.z);
+      t = __builtin_fmaf(t, q, f.k5.y);
+      t = __builtin_fmaf(t, q, f.k5.x);
       t = __builtin_fmaf(t, q, f.kb.y);
       t = __builtin_fmaf(t, q, f.ka.z);
       t = __builtin_fmaf(t, q, f.ka.x);
@@ -956,13 +988,14 @@ __device__ __forceinline__ void far_group(int Kw, const NS& xs, const FarLine& f
   if (Kw == 1) far_nodes<1, G0>(xs, f, acc);
   else if (Kw == 2) far_nodes<2, G0>(xs, f, acc);
   else if (Kw == 3) far_nodes<3, G0>(xs, f, acc);
-  else far_nodes<4, G0>(xs, f, acc);
+  else if (Kw == 4) far_nodes<4, G0>(xs, f, acc);
+  else far_nodes<5, G0>(xs, f, acc);
 }
 
 template <class NS>
 __device__ __forceinline__ void far_accumulate(const NS& xs, const FarLine& f, float (&acc)[kNodes]) {
   const int Kw = 1 + (__ballot(f.K >= 2) != 0ull ? 1 : 0) + (__ballot(f.K >= 3) != 0ull ? 1 : 0) +
-                 (__ballot(f.K >= 4) != 0ull ? 1 : 0);
+                 (__ballot(f.K >= 4) != 0ull ? 1 : 0) + (__ballot(f.K >= 5) != 0ull ? 1 : 0);
   far_group<0>(Kw, xs, f, acc);
 }
 
@@ -978,6 +1011,12 @@ __device__ __forceinline__ void far_flush(float (&acc)[kNodes], int lane, double
     acc[k] = 0.0f;
   }
   if (lane < kNodes) node[lane] += mine;
+}
+
+__device__ __forceinline__ float wave_sum64f(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
 }
 
 __device__ __forceinline__ double half_sum32(double v) {
@@ -1055,6 +1094,92 @@ __device__ __forceinline__ void mid_segment(const VoigtArgs& a, const PairDesc& 
   }
 }
 
+// One masked segment of a span of W = 64 P points: far lines whose cut bound falls on the span,
+// one per lane, at the span's kMaskNodes nodes. A line adds its interpolant to the points
+// 0..b (LEFT: b = its last point inside the cut) or b..W-1 (b = its first), so the node values
+// are summed per bound b (over the lanes of each bound present in the batch, by a butterfly;
+// bound b's sums are held by lane b mod 64 in slot b / 64), and at the end each point j takes
+// the sums of the bounds b >= j (LEFT) or b <= j (a scan over the points) and interpolates them.
+template <int P, bool LEFT>
+__device__ __forceinline__ void masked_segment(const VoigtArgs& a, const PairDesc& pd, const float* __restrict__ S_T,
+                                               const float* __restrict__ gT, const int4* __restrict__ grec, int i0,
+                                               int i1, int lane, int64_t span0, double nu_a, double nu_b,
+                                               float (&part)[P]) {
+  constexpr int W = kWave * P;
+  const float inv_dnu = (float)(1.0 / pd.dnu);
+  float B[kMaskNodes][P];
+#pragma unroll
+  for (int k = 0; k < kMaskNodes; ++k)
+#pragma unroll
+    for (int p = 0; p < P; ++p) B[k][p] = 0.0f;
+  for (int b0 = i0; b0 < i1; b0 += kWave) {
+    const int li = b0 + lane;
+    const bool valid = li < i1;
+    const FarLine f = far_line(valid, valid ? a.nu[li] : 0.0, valid ? S_T[li] : 0.0f, valid ? gT[li] : 0.0f, pd,
+                               nu_a, nu_b, inv_dnu, a.zK);
+    // LEFT: the line reaches points 0..bnd; otherwise bnd..W-1 (live: at least one point)
+    int bnd = 0;
+    bool live = false;
+    if (valid) {
+      const int4 gr = grec[li];
+      if (gr.z <= gr.w) {
+        const int64_t e = LEFT ? (int64_t)gr.w - span0 : (int64_t)gr.z - span0;
+        live = LEFT ? e >= 0 : e <= W - 1;
+        bnd = (int)(LEFT ? (e > W - 1 ? W - 1 : e) : (e < 0 ? 0 : e));
+      }
+    }
+    float v[kMaskNodes];
+#pragma unroll
+    for (int k = 0; k < kMaskNodes; ++k) v[k] = 0.0f;
+    const int Kw = 1 + (__ballot(f.K >= 2) != 0ull ? 1 : 0) + (__ballot(f.K >= 3) != 0ull ? 1 : 0) +
+                   (__ballot(f.K >= 4) != 0ull ? 1 : 0) + (__ballot(f.K >= 5) != 0ull ? 1 : 0);
+    const SpanNodes<W, kMaskNodes> xs;
+    if (Kw == 1) far_nodes<1, 0, kMaskNodes, SpanNodes<W, kMaskNodes>, kMaskNodes>(xs, f, v);
+    else if (Kw == 2) far_nodes<2, 0, kMaskNodes, SpanNodes<W, kMaskNodes>, kMaskNodes>(xs, f, v);
+    else if (Kw == 3) far_nodes<3, 0, kMaskNodes, SpanNodes<W, kMaskNodes>, kMaskNodes>(xs, f, v);
+    else if (Kw == 4) far_nodes<4, 0, kMaskNodes, SpanNodes<W, kMaskNodes>, kMaskNodes>(xs, f, v);
+    else far_nodes<5, 0, kMaskNodes, SpanNodes<W, kMaskNodes>, kMaskNodes>(xs, f, v);
+    // the bounds present, in lane order of their first line
+    uint64_t rem = __ballot(live);
+    while (rem) {
+      const int bs = __builtin_amdgcn_readlane(bnd, (int)__builtin_ctzll(rem));
+      const bool in = live && bnd == bs;
+      rem &= ~__ballot(in);
+#pragma unroll
+      for (int k = 0; k < kMaskNodes; ++k) {
+        const float t = wave_sum64f(in ? v[k] : 0.0f);
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+          if (p * kWave + lane == bs) B[k][p] += t;
+      }
+    }
+  }
+  // scan over the points (LEFT: sums of the bounds >= j; otherwise <= j), then interpolation
+  float out[P];
+#pragma unroll
+  for (int p = 0; p < P; ++p) out[p] = 0.0f;
+#pragma unroll
+  for (int k = 0; k < kMaskNodes; ++k) {
+    float carry = 0.0f;
+#pragma unroll
+    for (int pp = 0; pp < P; ++pp) {
+      const int p = LEFT ? P - 1 - pp : pp;
+      float x = B[k][p];
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const float t = LEFT ? __shfl_down(x, off, 64) : __shfl_up(x, off, 64);
+        if (LEFT ? lane + off < kWave : lane >= off) x += t;
+      }
+      const float tot = __shfl(x, LEFT ? 0 : kWave - 1, 64);
+      x += carry;
+      carry += tot;
+      out[p] = __builtin_fmaf(x, a.mask_w[k * W + p * kWave + lane], out[p]);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < P; ++p) part[p] += out[p];
+}
+
 // ------------------------------------------------------------------- wing pass
 // One wave per span of 64 P grid points (lane + 64 p, p < P). A work item is a span and a
 // chunk of its line segments (k_span_segments), taken in list order:
@@ -1077,7 +1202,7 @@ __global__ __launch_bounds__(kWave) void k_wing(VoigtArgs a) {
   const int total = a.item_base[a.n_tiles_total];
   const float jl0 = (float)lane;  // this lane's first span point
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  long long n_direct = 0, n_node = 0, n_mid = 0;
+  long long n_direct = 0, n_node = 0, n_mid = 0, n_mask = 0;
 
   for (;;) {
     int mine = 0;
@@ -1101,7 +1226,7 @@ __global__ __launch_bounds__(kWave) void k_wing(VoigtArgs a) {
     const float* __restrict__ gT = a.gT + (int64_t)pd.tidx * a.N;
     const int4* __restrict__ grec = a.grec + (int64_t)pd.gidx * a.N;
     const SpanSeg* __restrict__ sg = a.segs + g;
-    const int nseg = sg->n, fmask = sg->far_mask, mmask = sg->mid_mask;
+    const int nseg = sg->n;
 
     float s[P], cc[P], part[P];
 #pragma unroll
@@ -1121,12 +1246,21 @@ __global__ __launch_bounds__(kWave) void k_wing(VoigtArgs a) {
       if (x0 < x1) {
         const int i0 = sg->lo[q] + (x0 - cum), i1 = i0 + (x1 - x0);
         v_hi = x1;
-        if (((fmask | mmask) >> q) & 1) {
+        const int kind = sg->kind[q];
+        if (W <= kMaskMaxSpan && (kind == kSegMaskLeft || kind == kSegMaskRight)) {
+          // ---- masked segment: bound-bucketed node sums, one line per lane
+          n_mask += i1 - i0;
+          const double nu_a = grid_nu(pd.nu_start, pd.dnu, span0);
+          const double nu_b = grid_nu(pd.nu_start, pd.dnu, span0 + W - 1);
+          if (kind == kSegMaskLeft) masked_segment<P, true>(a, pd, S_T, gT, grec, i0, i1, lane, span0, nu_a, nu_b, part);
+          else masked_segment<P, false>(a, pd, S_T, gT, grec, i0, i1, lane, span0, nu_a, nu_b, part);
+          kahan_flush<P>(part, s, cc);
+        } else if (kind == kSegFar || kind == kSegMid) {
           // ---- far or middle segment: node sums, one line per lane
           n_node += i1 - i0;
           const double nu_a = grid_nu(pd.nu_start, pd.dnu, span0);
           const double nu_b = grid_nu(pd.nu_start, pd.dnu, span0 + W - 1);
-          if ((fmask >> q) & 1) {
+          if (kind == kSegFar) {
             any_far = true;
             far_segment<W>(a, pd, S_T, gT, i0, i1, lane, nu_a, nu_b, L.node);
           } else {
@@ -1229,7 +1363,7 @@ __global__ __launch_bounds__(kWave) void k_wing(VoigtArgs a) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   if (a.stats && lane == 0)
-    a.stats[blockIdx.x] = n_direct * W + (n_node - n_mid) * kNodes + n_mid * kMidNodes;
+    a.stats[blockIdx.x] = n_direct * W + (n_node - n_mid) * kNodes + n_mid * kMidNodes + n_mask * kMaskNodes;
 }
 
 
