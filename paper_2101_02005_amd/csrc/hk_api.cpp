@@ -81,6 +81,8 @@ struct DevInfo {
   float cheb_x[4][hk::kNodes] = {};  // node positions relative to the span's first point
   double* tile_w[4] = {};     // device: the same for the tile-far tile (4 spans), per slots
   float tile_x[4][hk::kNodes] = {};
+  double* far8_w[4] = {};     // device: the span's very-far nodes (kFar8Nodes), per slots
+  float far8_x[4][hk::kFar8Nodes] = {};
   double* mid_w[4] = {};      // device: the span's middle-distance nodes (kMidNodes), per slots
   float mid_x[4][hk::kMidNodes] = {};
   float* mask_w[4] = {};      // device: the span's nodes for lines with a cut bound on it (FP32)
@@ -153,12 +155,9 @@ void span_nodes(int S, int m, float* x_out, std::vector<double>& weights) {
 
 // The compiled Chebyshev tables against cos.
 bool cheb_tables_ok() {
-  for (int k = 0; k < 6; ++k)
-    if (std::fabs(hk::cheb_cos6(k) - std::cos((2 * k + 1) * M_PI / 12.0)) > 1e-15) return false;
-  for (int k = 0; k < 16; ++k)
-    if (std::fabs(hk::cheb_cos16(k) - std::cos((2 * k + 1) * M_PI / 32.0)) > 1e-15) return false;
-  for (int k = 0; k < 32; ++k)
-    if (std::fabs(hk::cheb_cos32(k) - std::cos((2 * k + 1) * M_PI / 64.0)) > 1e-15) return false;
+  for (int m : {6, 8, 16, 32})
+    for (int k = 0; k < m; ++k)
+      if (std::fabs(hk::cheb_cos(m, k) - std::cos((2 * k + 1) * M_PI / (2.0 * m))) > 1e-15) return false;
   return true;
 }
 
@@ -189,6 +188,9 @@ hk_status device_init(int* dev_out, DevInfo* info) {
       span_nodes(hk::kWavesPerWG * S, hk::kNodes, di.tile_x[si], wts);
       HK_HIP(hipMalloc(&di.tile_w[si], sizeof(double) * wts.size()));  // held for the process lifetime
       HK_HIP(hipMemcpy(di.tile_w[si], wts.data(), sizeof(double) * wts.size(), hipMemcpyHostToDevice));
+      span_nodes(S, hk::kFar8Nodes, di.far8_x[si], wts);
+      HK_HIP(hipMalloc(&di.far8_w[si], sizeof(double) * wts.size()));  // held for the process lifetime
+      HK_HIP(hipMemcpy(di.far8_w[si], wts.data(), sizeof(double) * wts.size(), hipMemcpyHostToDevice));
       span_nodes(S, hk::kMidNodes, di.mid_x[si], wts);
       HK_HIP(hipMalloc(&di.mid_w[si], sizeof(double) * wts.size()));  // held for the process lifetime
       HK_HIP(hipMemcpy(di.mid_w[si], wts.data(), sizeof(double) * wts.size(), hipMemcpyHostToDevice));
@@ -546,6 +548,7 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   va.items_cap = (int32_t)std::min<int64_t>(pl.items_bound_w, INT32_MAX);
   va.cheb_w = di.cheb_w[si];
   va.mid_w = di.mid_w[si];
+  va.far8_w = di.far8_w[si];
   va.mask_w = di.mask_w[si];
   HK_HIP(hk::launch_wing(va, pl.slots, pl.grid_w, st));
   tm.mark();

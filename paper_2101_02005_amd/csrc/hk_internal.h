@@ -18,6 +18,8 @@ constexpr int kSortBlock = kThreads * kSortItems;
 constexpr int kFillPairs = 48;   // pair descriptors per fill launch (kernel-argument space)
 constexpr int kNodes = 16;       // Chebyshev nodes of a span or tile for lines far from it
 constexpr double kFarSpans = 1.5;  // far: centre at least 1.5 spans (3 half-spans) from the span centre
+constexpr int kFar8Nodes = 8;    // Chebyshev nodes of a span for lines very far from it
+constexpr double kFar8Spans = 3.0; // very far: centre at least 3 spans (6 half-spans) from the span centre
 constexpr int kMidNodes = 32;    // Chebyshev nodes of a span for lines at middle distance
 constexpr double kMidSpans = 0.75; // middle: centre 0.75-1.5 spans (1.5-3 half-spans) from the span centre
 constexpr int kMaskNodes = 6;    // Chebyshev nodes of a span for lines whose cut bound falls on it
@@ -25,8 +27,21 @@ constexpr double kMaskSpans = 6.0; // such lines are evaluated at nodes when at 
 constexpr int kMaskMaxSpan = 128;  // ... and only on spans of at most 128 points (P <= 2)
 constexpr double kTileFar = 1.5;   // tile-far: centre at least 1.5 tile widths from the tile centre
 
-// cos((2k + 1) pi / (2m)), k < m: Chebyshev points of the first kind on [-1, 1] for m = 6, 16 and
-// 32 (the host checks the tables against cos at initialisation).
+// cos((2k + 1) pi / (2m)), k < m: Chebyshev points of the first kind on [-1, 1] for m = 6, 8, 16
+// and 32 (the host checks the tables against cos at initialisation).
+__host__ __device__ constexpr double cheb_cos8(int k) {
+  switch (k) {
+    case 0: return 0.98078528040323043;
+    case 1: return 0.83146961230254524;
+    case 2: return 0.55557023301960229;
+    case 3: return 0.19509032201612833;
+    case 4: return -0.19509032201612819;
+    case 5: return -0.55557023301960196;
+    case 6: return -0.83146961230254535;
+    case 7: return -0.98078528040323043;
+    default: return 0.0;
+  }
+}
 __host__ __device__ constexpr double cheb_cos6(int k) {
   switch (k) {
     case 0: return 0.96592582628906831;
@@ -96,10 +111,13 @@ __host__ __device__ constexpr double cheb_cos32(int k) {
     default: return 0.0;
   }
 }
-// Node k of m (6, 16 or 32) on a span of S grid points [0, S - 1], in FP32: the device evaluates
-// the lines there, and the host's interpolation weights are exact for these positions.
+// Node k of m (6, 8, 16 or 32) on a span of S grid points [0, S - 1], in FP32: the device
+// evaluates the lines there, and the host's interpolation weights are exact for these positions.
+__host__ __device__ constexpr double cheb_cos(int m, int k) {
+  return m == 6 ? cheb_cos6(k) : m == 8 ? cheb_cos8(k) : m == 16 ? cheb_cos16(k) : cheb_cos32(k);
+}
 __host__ __device__ constexpr float node_pos(int S, int m, int k) {
-  return (float)(0.5 * (S - 1) * (1.0 + (m == 6 ? cheb_cos6(k) : m == 16 ? cheb_cos16(k) : cheb_cos32(k))));
+  return (float)(0.5 * (S - 1) * (1.0 + cheb_cos(m, k)));
 }
 
 // Wavenumber -> bin key: clamp(floor((v - numin) * scale), 0, kmax), evaluated in FP64.
@@ -124,13 +142,14 @@ struct PairDesc {
 
 // The lines of one span (64 P grid points, one wave of the wing pass) as segments of the
 // sorted list, in list order; the tile-far ranges of its tile are left out.
-constexpr int kMaxSeg = 17;  // elementary intervals between 18 range ends
+constexpr int kMaxSeg = 21;  // elementary intervals between 22 range ends
 enum SegKind : uint8_t {
   kSegDirect = 0,     // evaluated at every point of the span
   kSegFar = 1,        // far: at the span's kNodes nodes
   kSegMid = 2,        // middle distance: at the span's kMidNodes nodes
   kSegMaskLeft = 3,   // far, cut bound on the span, reaching it from the left: kMaskNodes nodes
   kSegMaskRight = 4,  // the same from the right
+  kSegFar8 = 5,       // very far: at the span's kFar8Nodes nodes
 };
 struct SpanSeg {
   int32_t lo[kMaxSeg];   // first line of segment q
@@ -165,6 +184,7 @@ struct VoigtArgs {
   int32_t chunk;           // lines per work item
   int32_t items_cap;       // rows of `partial` (work items beyond it are never written)
   const double* cheb_w;    // [kNodes][64 P] Lagrange weights of the span's Chebyshev nodes
+  const double* far8_w;    // [kFar8Nodes][64 P] the same for the very-far nodes
   const double* mid_w;     // [kMidNodes][64 P] the same for the middle-distance nodes
   const float* mask_w;     // [kMaskNodes][64 P] the same for the nodes of lines with a cut bound on it
 };

@@ -458,7 +458,7 @@ __global__ void k_span_segments(const uint32_t* __restrict__ keys, int64_t N, Ke
   // far, middle and masked ranges of the span (full spans only); the middle ones contain the
   // far ones; the masked ones lie beyond the far ones' cut-side bounds
   int64_t fa1 = lo, fb1 = lo, fa2 = hi, fb2 = hi, ma1 = lo, mb1 = lo, ma2 = hi, mb2 = hi;
-  int64_t la = lo, lb = lo, ra = hi, rb = hi;
+  int64_t la = lo, lb = lo, ra = hi, rb = hi, ea1 = lo, eb1 = lo, ea2 = hi, eb2 = hi;
   if (j0 + span_w <= pd.n && hi > lo) {
     const double c = 0.5 * (nA + nB), half = 0.5 * (nB - nA);
     const double wlo = isinf(cut) ? numin : fmax(numin, nA - cut);
@@ -467,6 +467,7 @@ __global__ void k_span_segments(const uint32_t* __restrict__ keys, int64_t N, Ke
     const double reach = half + far_z * amax * 1.001 + 2.0 * pd.dnu;
     const double d = fmax(kFarSpans * span_w * pd.dnu, reach);
     const double dm = fmax(kMidSpans * span_w * pd.dnu, reach);
+    const double d8 = fmax(kFar8Spans * span_w * pd.dnu, reach);
     const double dk = fmax(kMaskSpans * span_w * pd.dnu, reach);
     const double m = 0.5 * pd.dnu;
     const double v0 = isinf(cut) ? -INFINITY : nB - cut + m, v1 = isinf(cut) ? INFINITY : nA + cut - m;
@@ -474,6 +475,8 @@ __global__ void k_span_segments(const uint32_t* __restrict__ keys, int64_t N, Ke
     key_range(keys, lo, hi, c + d, v1, km, fa2, fb2);
     key_range(keys, lo, hi, v0, c - dm, km, ma1, mb1);
     key_range(keys, lo, hi, c + dm, v1, km, ma2, mb2);
+    key_range(keys, lo, hi, v0, c - d8, km, ea1, eb1);
+    key_range(keys, lo, hi, c + d8, v1, km, ea2, eb2);
     if (!isinf(cut) && cut > 2.0 * (nB - nA) + 2.0 * pd.dnu && span_w <= kMaskMaxSpan) {
       // below v0 a line's cut range ends on the span (or before it) and starts far left of it;
       // above v1 it starts on the span (or after it) and ends far right of it
@@ -482,8 +485,9 @@ __global__ void k_span_segments(const uint32_t* __restrict__ keys, int64_t N, Ke
     }
   }
   // elementary intervals between all range ends, in order; tile-far ones are left out
-  constexpr int NB = 18;
-  int64_t bp[NB] = {lo, hi, fa1, fb1, fa2, fb2, ma1, mb1, ma2, mb2, ta1, tb1, ta2, tb2, la, lb, ra, rb};
+  constexpr int NB = 22;
+  int64_t bp[NB] = {lo, hi, fa1, fb1, fa2, fb2, ma1, mb1, ma2, mb2, ta1, tb1, ta2, tb2, la, lb, ra, rb,
+                    ea1, eb1, ea2, eb2};
   for (int i = 0; i < NB; ++i) bp[i] = bp[i] < lo ? lo : (bp[i] > hi ? hi : bp[i]);
   for (int i = 1; i < NB; ++i)
     for (int j = i; j > 0 && bp[j - 1] > bp[j]; --j) { const int64_t x = bp[j]; bp[j] = bp[j - 1]; bp[j - 1] = x; }
@@ -492,7 +496,8 @@ __global__ void k_span_segments(const uint32_t* __restrict__ keys, int64_t N, Ke
     const int64_t x = bp[i], y = bp[i + 1];
     if (x >= y) continue;
     if ((x >= ta1 && y <= tb1) || (x >= ta2 && y <= tb2)) continue;
-    const uint8_t kind = ((x >= fa1 && y <= fb1) || (x >= fa2 && y <= fb2))   ? kSegFar
+    const uint8_t kind = ((x >= ea1 && y <= eb1) || (x >= ea2 && y <= eb2))   ? kSegFar8
+                         : ((x >= fa1 && y <= fb1) || (x >= fa2 && y <= fb2)) ? kSegFar
                          : ((x >= ma1 && y <= mb1) || (x >= ma2 && y <= mb2)) ? kSegMid
                          : (x >= la && y <= lb)                               ? kSegMaskLeft
                          : (x >= ra && y <= rb)                               ? kSegMaskRight
@@ -618,6 +623,7 @@ struct WaveLDS {
   int2 CZ[kWave];
   uint8_t list[kWave];
   double node[kNodes];
+  double node8[kFar8Nodes];
   double node_mid[kMidNodes];
 };
 
@@ -886,23 +892,46 @@ __device__ __forceinline__ double wave_sum64(double v) {
 // holds). The node sums are later interpolated to the interval's points with the nodes'
 // Lagrange weights.
 struct FarLine {
-  float h, e, gq, A, kc;  // node offset D = x h + e (x: node position in grid steps), gamma^2/s
-  float4 ka, kb;          // Ah times the series coefficients (see wing_coeffs)
-  float4 k5;              // c4-c7 of order 5 (c1-c3 as order 4)
-  float k5c;              // c8 of order 5
-  int K;
+  float h, e;   // node offset D = x h + e (x: node position in grid steps), in units of sqrt(s)
+  float gq, a;  // gamma^2/s, alpha^2/s
+  float A;      // S gamma / (pi s)
+  int K;        // series order the line needs on the interval
 };
+
+// The far-wing series coefficients c_1 .. c_(2K-2) of order K (see wing_coeffs), times A, formed
+// for the wave's order only.
+template <int K>
+__device__ __forceinline__ void far_coeffs(const FarLine& f, float (&c)[2 * kKmax - 2]) {
+  const float a = f.a, g = f.gq, A = f.A;
+  const float a2 = a * a, a3 = a2 * a, a4 = a2 * a2, g2 = g * g, g3 = g2 * g;
+  if (K >= 2) c[0] = A * (1.5f * a);
+  if (K == 2) c[1] = A * (-2.0f * a * g);
+  if (K >= 3) c[1] = A * (-2.0f * a * g + 3.75f * a2);
+  if (K == 3) {
+    c[2] = A * (-15.0f * a2 * g);
+    c[3] = A * (12.0f * a2 * g2);
+  }
+  if (K >= 4) c[2] = A * (-15.0f * a2 * g + 13.125f * a3);
+  if (K == 4) {
+    c[3] = A * (12.0f * a2 * g2 - 105.0f * a3 * g);
+    c[4] = A * (210.0f * a3 * g2);
+    c[5] = A * (-120.0f * a3 * g3);
+  }
+  if (K == 5) {
+    c[3] = A * (12.0f * a2 * g2 - 105.0f * a3 * g + 59.0625f * a4);
+    c[4] = A * (210.0f * a3 * g2 - 787.5f * a4 * g);
+    c[5] = A * (-120.0f * a3 * g3 + 2835.0f * a4 * g2);
+    c[6] = A * (-3780.0f * a4 * g3);
+    c[7] = A * (1680.0f * a4 * g2 * g2);
+  }
+}
 
 // The constants of one line for the interval of grid points [nu_a, nu_b] (an idle lane, or a
 // line with S = 0, evaluates A = 0 at D = 1 and adds zero).
 __device__ __forceinline__ FarLine far_line(bool valid, double nu, float S, float gTv, const PairDesc& pd,
                                             double nu_a, double nu_b, float inv_dnu, const float* zK) {
   FarLine f;
-  f.h = 0.0f; f.e = 1.0f; f.gq = 1.0f; f.A = 0.0f; f.kc = 0.0f;
-  f.ka = make_float4(0.f, 0.f, 0.f, 0.f);
-  f.kb = f.ka;
-  f.k5 = f.ka;
-  f.k5c = 0.0f;
+  f.h = 0.0f; f.e = 1.0f; f.gq = 1.0f; f.a = 0.0f; f.A = 0.0f;
   f.K = 1;
   if (!valid) return f;
   const float alpha = (float)(nu * pd.beta);
@@ -914,15 +943,7 @@ __device__ __forceinline__ FarLine far_line(bool valid, double nu, float S, floa
   const float isc = rs * rs;
   f.A = S * (gam * isc) * 0.318309886183790672f;  // S gamma / (pi s)
   f.gq = g2 * isc;
-  wing_coeffs(a2 * isc, f.gq, f.A, f.ka, f.kb, f.kc);
-  {
-    const float av = a2 * isc, gv = f.gq;
-    const float a3 = av * av * av, a4 = a3 * av, g2v = gv * gv, g3v = g2v * gv;
-    f.k5 = make_float4(f.A * (12.0f * av * av * g2v - 105.0f * a3 * gv + 59.0625f * a4),
-                       f.A * (210.0f * a3 * g2v - 787.5f * a4 * gv), f.A * (-120.0f * a3 * g3v + 2835.0f * a4 * g2v),
-                       f.A * (-3780.0f * a4 * g3v));
-    f.k5c = f.A * (1680.0f * a4 * g2v * g2v);
-  }
+  f.a = a2 * isc;
   f.h = (float)pd.dnu * rs;                       // one grid step in units of sqrt(s)
   f.e = -((float)(nu - nu_a) * inv_dnu) * f.h;    // minus the line's position, same units
   const float dmin = (float)(nu < nu_a ? nu_a - nu : nu - nu_b);  // to the nearest point
@@ -942,75 +963,54 @@ struct ArgNodes {
   __device__ float operator()(int k) const { return x[k]; }
 };
 
-// Adds f at nodes G0..G0+CNT-1 of xs to acc[G0..]
+// Adds f at nodes G0..G0+CNT-1 of xs to acc[G0..], with the series of order K
 template <int K, int G0, int NN, class NS, int CNT = kNodes>
 __device__ __forceinline__ void far_nodes(const NS& xs, const FarLine& f, float (&acc)[NN]) {
+  float c[2 * kKmax - 2];
+  far_coeffs<K>(f, c);
 #pragma unroll
   for (int k = G0; k < G0 + CNT; ++k) {
     const float D = __builtin_fmaf(xs(k), f.h, f.e);
     const float R = __builtin_fmaf(D, D, f.gq);
     const float q = __builtin_amdgcn_rcpf(R);
-    float t;
-    if (K == 1) {
-      t = f.A;
-    } else if (K == 2) {
-      t = __builtin_fmaf(f.ka.y, q, f.ka.x);
-      t = __builtin_fmaf(t, q, f.A);
-    } else if (K == 3) {
-      t = __builtin_fmaf(f.kb.x, q, f.ka.w);
-      t = __builtin_fmaf(t, q, f.ka.z);
-      t = __builtin_fmaf(t, q, f.ka.x);
-      t = __builtin_fmaf(t, q, f.A);
-    } else if (K == 4) {
-      t = __builtin_fmaf(f.kc, q, f.kb.w);
-      t = __builtin_fmaf(t, q, f.kb.z);
-      t = __builtin_fmaf(t, q, f.kb.y);
-      t = __builtin_fmaf(t, q, f.ka.z);
-      t = __builtin_fmaf(t, q, f.ka.x);
-      t = __builtin_fmaf(t, q, f.A);
-    } else {  // K == 5: c8 .. c1
-      t = __builtin_fmaf(f.k5c, q, f.k5.w);
-      t = __builtin_fmaf(t, q, f.k5.z);
-      t = __builtin_fmaf(t, q, f.k5.y);
-      t = __builtin_fmaf(t, q, f.k5.x);
-      t = __builtin_fmaf(t, q, f.kb.y);
-      t = __builtin_fmaf(t, q, f.ka.z);
-      t = __builtin_fmaf(t, q, f.ka.x);
-      t = __builtin_fmaf(t, q, f.A);
-    }
+    float t = K == 1 ? f.A : c[2 * K - 3];
+#pragma unroll
+    for (int m = 2 * K - 4; m >= 0; --m) t = __builtin_fmaf(t, q, c[m]);
+    if (K > 1) t = __builtin_fmaf(t, q, f.A);
     acc[k] = __builtin_fmaf(t, q, acc[k]);
   }
 }
 
-// Adds each lane's line at the nodes to its node sums, with the wave's largest order.
-template <int G0, int NN, class NS>
-__device__ __forceinline__ void far_group(int Kw, const NS& xs, const FarLine& f, float (&acc)[NN]) {
-  if (Kw == 1) far_nodes<1, G0>(xs, f, acc);
-  else if (Kw == 2) far_nodes<2, G0>(xs, f, acc);
-  else if (Kw == 3) far_nodes<3, G0>(xs, f, acc);
-  else if (Kw == 4) far_nodes<4, G0>(xs, f, acc);
-  else far_nodes<5, G0>(xs, f, acc);
+// The wave's order: the largest its lines need.
+__device__ __forceinline__ int wave_order(const FarLine& f) {
+  return 1 + (__ballot(f.K >= 2) != 0ull ? 1 : 0) + (__ballot(f.K >= 3) != 0ull ? 1 : 0) +
+         (__ballot(f.K >= 4) != 0ull ? 1 : 0) + (__ballot(f.K >= 5) != 0ull ? 1 : 0);
 }
 
-template <class NS>
-__device__ __forceinline__ void far_accumulate(const NS& xs, const FarLine& f, float (&acc)[kNodes]) {
-  const int Kw = 1 + (__ballot(f.K >= 2) != 0ull ? 1 : 0) + (__ballot(f.K >= 3) != 0ull ? 1 : 0) +
-                 (__ballot(f.K >= 4) != 0ull ? 1 : 0) + (__ballot(f.K >= 5) != 0ull ? 1 : 0);
-  far_group<0>(Kw, xs, f, acc);
+// Adds each lane's line at the NN nodes to its node sums (acc), with the wave's order.
+template <int NN, class NS>
+__device__ __forceinline__ void far_accumulate(const NS& xs, const FarLine& f, float (&acc)[NN]) {
+  const int Kw = wave_order(f);
+  if (Kw == 1) far_nodes<1, 0, NN, NS, NN>(xs, f, acc);
+  else if (Kw == 2) far_nodes<2, 0, NN, NS, NN>(xs, f, acc);
+  else if (Kw == 3) far_nodes<3, 0, NN, NS, NN>(xs, f, acc);
+  else if (Kw == 4) far_nodes<4, 0, NN, NS, NN>(xs, f, acc);
+  else far_nodes<5, 0, NN, NS, NN>(xs, f, acc);
 }
 
 // Adds the wave's node sums (a butterfly over the lanes in FP64, the same on every lane) to
 // node[k] (lane k) and clears the lanes' FP32 sums; every 16 lines per lane at most, so that
 // the FP32 sums stay short.
-__device__ __forceinline__ void far_flush(float (&acc)[kNodes], int lane, double* node) {
+template <int NN>
+__device__ __forceinline__ void far_flush(float (&acc)[NN], int lane, double* node) {
   double mine = 0.0;
 #pragma unroll
-  for (int k = 0; k < kNodes; ++k) {
+  for (int k = 0; k < NN; ++k) {
     const double t = wave_sum64((double)acc[k]);
     mine = lane == k ? t : mine;
     acc[k] = 0.0f;
   }
-  if (lane < kNodes) node[lane] += mine;
+  if (lane < NN) node[lane] += mine;
 }
 
 __device__ __forceinline__ float wave_sum64f(float v) {
@@ -1039,25 +1039,25 @@ __device__ __forceinline__ void mid_flush(float (&acc)[kNodes], int lane, double
   if (j < kNodes) node[lane < 32 ? j : kMidNodes - 1 - j] += mine;
 }
 
-// One far segment of a span of S points: lines [i0, i1), one per lane, at its kNodes nodes;
-// the node sums go to node[] (see far_flush).
-template <int S>
+// One far segment of a span of S points: lines [i0, i1), one per lane, at its NN nodes; the
+// node sums go to node[] (see far_flush).
+template <int S, int NN>
 __device__ __forceinline__ void far_segment(const VoigtArgs& a, const PairDesc& pd, const float* __restrict__ S_T,
                                             const float* __restrict__ gT, int i0, int i1, int lane, double nu_a,
                                             double nu_b, double* node) {
   const float inv_dnu = (float)(1.0 / pd.dnu);
-  float acc[kNodes];
+  float acc[NN];
 #pragma unroll
-  for (int k = 0; k < kNodes; ++k) acc[k] = 0.0f;
+  for (int k = 0; k < NN; ++k) acc[k] = 0.0f;
   int n = 0;
   for (int b = i0; b < i1; b += kWave) {
     const int li = b + lane;
     const bool valid = li < i1;
     const FarLine f = far_line(valid, valid ? a.nu[li] : 0.0, valid ? S_T[li] : 0.0f, valid ? gT[li] : 0.0f, pd,
                                nu_a, nu_b, inv_dnu, a.zK);
-    far_accumulate(SpanNodes<S, kNodes>(), f, acc);
+    far_accumulate<NN>(SpanNodes<S, NN>(), f, acc);
     if (++n == 16 || b + kWave >= i1) {
-      far_flush(acc, lane, node);
+      far_flush<NN>(acc, lane, node);
       n = 0;
     }
   }
@@ -1086,7 +1086,7 @@ __device__ __forceinline__ void mid_segment(const VoigtArgs& a, const PairDesc& 
       f.e = __builtin_fmaf((float)(S - 1), f.h, f.e);
       f.h = -f.h;
     }
-    far_accumulate(SpanNodes<S, kMidNodes>(), f, acc);
+    far_accumulate<kNodes>(SpanNodes<S, kMidNodes>(), f, acc);
     if (++n == 16 || b + 32 >= i1) {
       mid_flush(acc, lane, node);
       n = 0;
@@ -1131,8 +1131,7 @@ __device__ __forceinline__ void masked_segment(const VoigtArgs& a, const PairDes
     float v[kMaskNodes];
 #pragma unroll
     for (int k = 0; k < kMaskNodes; ++k) v[k] = 0.0f;
-    const int Kw = 1 + (__ballot(f.K >= 2) != 0ull ? 1 : 0) + (__ballot(f.K >= 3) != 0ull ? 1 : 0) +
-                   (__ballot(f.K >= 4) != 0ull ? 1 : 0) + (__ballot(f.K >= 5) != 0ull ? 1 : 0);
+    const int Kw = wave_order(f);
     const SpanNodes<W, kMaskNodes> xs;
     if (Kw == 1) far_nodes<1, 0, kMaskNodes, SpanNodes<W, kMaskNodes>, kMaskNodes>(xs, f, v);
     else if (Kw == 2) far_nodes<2, 0, kMaskNodes, SpanNodes<W, kMaskNodes>, kMaskNodes>(xs, f, v);
@@ -1188,10 +1187,12 @@ __device__ __forceinline__ void masked_segment(const VoigtArgs& a, const PairDes
 //    series order it needs there (lanes outside its cut range and its core points add
 //    nothing; the core points are the line-core pass's), in staging order, into per-lane
 //    FP32 sums with a compensated flush every 16 lines;
-//  * a far (middle) segment is evaluated at the span's kNodes (kMidNodes) Chebyshev nodes,
-//    one line per lane (per lane in FP32 over 16 lines, then FP64; over the wave by a
-//    butterfly, the same on every lane), and the node sums are interpolated to the span's
-//    points in FP64 at the end of the item.
+//  * a far, very far or middle segment is evaluated at the span's kNodes, kFar8Nodes or
+//    kMidNodes Chebyshev nodes, one line per lane (two for middle lines; per lane in FP32 over
+//    16 lines, then FP64; over the wave by a butterfly, the same on every lane), and the node
+//    sums are interpolated to the span's points in FP64 at the end of the item;
+//  * a masked segment is evaluated at kMaskNodes nodes and added to the prefix or suffix of
+//    the span's points inside each line's cut (masked_segment).
 // A span with one item writes k; otherwise each item writes its partial span and k_combine
 // sums them in item order. No workgroup barrier: waves run independently.
 template <int P>
@@ -1202,7 +1203,7 @@ __global__ __launch_bounds__(kWave) void k_wing(VoigtArgs a) {
   const int total = a.item_base[a.n_tiles_total];
   const float jl0 = (float)lane;  // this lane's first span point
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  long long n_direct = 0, n_node = 0, n_mid = 0, n_mask = 0;
+  long long n_direct = 0, n_node = 0, n_mid = 0, n_mask = 0, n_far8 = 0;
 
   for (;;) {
     int mine = 0;
@@ -1236,8 +1237,9 @@ __global__ __launch_bounds__(kWave) void k_wing(VoigtArgs a) {
       part[p] = 0.0f;
     }
     if (lane < kNodes) L.node[lane] = 0.0;
+    if (lane < kFar8Nodes) L.node8[lane] = 0.0;
     if (lane < kMidNodes) L.node_mid[lane] = 0.0;
-    bool any_far = false, any_mid = false;
+    bool any_far = false, any_far8 = false, any_mid = false;
     int cum = 0, v_hi = v_lo;
     for (int q = 0; q < nseg; ++q) {
       const int len = sg->len[q];
@@ -1255,14 +1257,18 @@ __global__ __launch_bounds__(kWave) void k_wing(VoigtArgs a) {
           if (kind == kSegMaskLeft) masked_segment<P, true>(a, pd, S_T, gT, grec, i0, i1, lane, span0, nu_a, nu_b, part);
           else masked_segment<P, false>(a, pd, S_T, gT, grec, i0, i1, lane, span0, nu_a, nu_b, part);
           kahan_flush<P>(part, s, cc);
-        } else if (kind == kSegFar || kind == kSegMid) {
+        } else if (kind == kSegFar || kind == kSegFar8 || kind == kSegMid) {
           // ---- far or middle segment: node sums, one line per lane
           n_node += i1 - i0;
           const double nu_a = grid_nu(pd.nu_start, pd.dnu, span0);
           const double nu_b = grid_nu(pd.nu_start, pd.dnu, span0 + W - 1);
           if (kind == kSegFar) {
             any_far = true;
-            far_segment<W>(a, pd, S_T, gT, i0, i1, lane, nu_a, nu_b, L.node);
+            far_segment<W, kNodes>(a, pd, S_T, gT, i0, i1, lane, nu_a, nu_b, L.node);
+          } else if (kind == kSegFar8) {
+            any_far8 = true;
+            n_far8 += i1 - i0;
+            far_segment<W, kFar8Nodes>(a, pd, S_T, gT, i0, i1, lane, nu_a, nu_b, L.node8);
           } else {
             any_mid = true;
             n_mid += i1 - i0;
@@ -1318,7 +1324,7 @@ __global__ __launch_bounds__(kWave) void k_wing(VoigtArgs a) {
     }
     (void)v_hi;
     // ---- far and middle lines: interpolation of the node sums to the span's points, in FP64
-    if (any_far || any_mid) {
+    if (any_far || any_far8 || any_mid) {
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1330,6 +1336,15 @@ __global__ __launch_bounds__(kWave) void k_wing(VoigtArgs a) {
         for (int k = 0; k < kNodes; ++k) {
           const double ns = L.node[k];
           const double* __restrict__ wk = a.cheb_w + k * W + lane;
+#pragma unroll
+          for (int p = 0; p < P; ++p) v[p] = fma(ns, wk[p * kWave], v[p]);
+        }
+      }
+      if (any_far8) {
+#pragma unroll 1
+        for (int k = 0; k < kFar8Nodes; ++k) {
+          const double ns = L.node8[k];
+          const double* __restrict__ wk = a.far8_w + k * W + lane;
 #pragma unroll
           for (int p = 0; p < P; ++p) v[p] = fma(ns, wk[p * kWave], v[p]);
         }
@@ -1363,7 +1378,8 @@ __global__ __launch_bounds__(kWave) void k_wing(VoigtArgs a) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   if (a.stats && lane == 0)
-    a.stats[blockIdx.x] = n_direct * W + (n_node - n_mid) * kNodes + n_mid * kMidNodes + n_mask * kMaskNodes;
+    a.stats[blockIdx.x] = n_direct * W + (n_node - n_mid - n_far8) * kNodes + n_far8 * kFar8Nodes +
+                          n_mid * kMidNodes + n_mask * kMaskNodes;
 }
 
 
@@ -1423,9 +1439,9 @@ __global__ __launch_bounds__(kThreads) void k_far(FarArgs a) {
       const int64_t li = v < nl ? (int64_t)tf.x + v : (int64_t)tf.z + (v - nl);
       const FarLine f = far_line(valid, valid ? a.nu[li] : 0.0, valid ? S_T[li] : 0.0f, valid ? gT[li] : 0.0f,
                                  pd, nu0, nu1, inv_dnu, a.zK);
-      far_accumulate(ArgNodes{a.tile_x}, f, acc);
+      far_accumulate<kNodes>(ArgNodes{a.tile_x}, f, acc);
       if (++n == 16 || b + kThreads >= v_hi) {
-        far_flush(acc, lane, sRed[wv]);
+        far_flush<kNodes>(acc, lane, sRed[wv]);
         n = 0;
       }
     }
