@@ -113,8 +113,9 @@ typedef struct hk_timings {
  *       n_exp finite. Checked on the device; a violation returns HK_EINVAL.
  *   n_lines : 1 <= n_lines < 2^31.
  *   sp      : host pointer, validated (all fields finite, mass, T_ref, P_ref, q_a > 0).
- *   stream  : work is ordered on this stream; the call blocks the host once to read the
- *             validation result and the wavenumber range.
+ *   stream  : work is ordered on this stream; the call blocks the host twice: after the
+ *             first pass (nu checked, its range read back for the bin key) and at the end
+ *             (the other fields' check, made while the records are copied for the sort).
  *   out     : host pointer receiving the handle (set only on HK_OK).
  * Memory: about 56 bytes per line are held by the handle (+ 24 temporary).
  */

@@ -762,7 +762,7 @@ hk_status hk_prepare_lines(const double* nu, const double* S_ref, const double* 
     (void)hipFree(hm);
     return fail(st, "%s: %s", what, e == hipSuccess ? "" : hipGetErrorString(e));
   };
-  hipError_t e = hk::launch_validate(nu, S_ref, E_low, gamma_ref, n_exp, N, mm, flags, stream);
+  hipError_t e = hk::launch_validate(nu, N, mm, flags, stream);
   if (e != hipSuccess) return cleanup_fail(HK_EDEVICE, "validate", e);
   unsigned long long hmm[2] = {0, 0};
   int hflag = 0;
@@ -773,7 +773,7 @@ hk_status hk_prepare_lines(const double* nu, const double* S_ref, const double* 
   if (hflag) {
     (void)hipFree(tmp);
     (void)hipFree(hm);
-    return fail(HK_EINVAL, "line data invalid: need nu > 0, S_ref >= 0, gamma_ref >= 0, all finite");
+    return fail(HK_EINVAL, "line data invalid: need nu > 0 and finite");
   }
   double vmin, vmax;
   memcpy(&vmin, &hmm[0], 8);
@@ -785,16 +785,21 @@ hk_status hk_prepare_lines(const double* nu, const double* S_ref, const double* 
   L->km.scale = vmax > vmin ? (double)L->km.kmax / (vmax - vmin) : 0.0;
   L->km.pad = 0;
   // keys -> stable LSD radix sort (3 passes of 8 bits; ping-pong ends in the handle arrays)
-  e = hk::launch_keys(nu, S_ref, E_low, gamma_ref, n_exp, N, L->km, kA, vA, rec, stream);
+  e = hk::launch_keys(nu, S_ref, E_low, gamma_ref, n_exp, N, L->km, kA, vA, rec, flags, stream);
   if (e == hipSuccess) e = hk::launch_radix_pass(kA, vA, L->keys, L->perm, N, 0, hist, dtot, stream);
   if (e == hipSuccess) e = hk::launch_radix_pass(L->keys, L->perm, kA, vA, N, 8, hist, dtot, stream);
   if (e == hipSuccess) e = hk::launch_radix_pass(kA, vA, L->keys, L->perm, N, 16, hist, dtot, stream);
   if (e == hipSuccess)
     e = hk::launch_gather(L->perm, N, rec, L->nu, L->Sref, L->E, L->gref, L->nexp, stream);
   tm.mark();
+  if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flags + 1, 4, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return cleanup_fail(HK_EDEVICE, "binning", e);
   (void)hipFree(tmp);
+  if (hflag) {
+    (void)hipFree(hm);
+    return fail(HK_EINVAL, "line data invalid: need S_ref >= 0, gamma_ref >= 0, E, n finite");
+  }
   g_tim.bin_ms = tm.ms(0);
   *out = L.release();
   return HK_OK;

@@ -249,11 +249,11 @@ struct AdjArgs {
 };
 
 // Launch wrappers (hk_kernels.hip); each returns the launch status.
-hipError_t launch_validate(const double* nu, const double* S, const double* E, const double* g,
-                           const double* n, int64_t N, unsigned long long* mm, int* flags,
-                           hipStream_t st);
+// flags[0]: a nu <= 0 or non-finite (k_validate); flags[1]: another field invalid (k_keys)
+hipError_t launch_validate(const double* nu, int64_t N, unsigned long long* mm, int* flags, hipStream_t st);
 hipError_t launch_keys(const double* nu, const double* S, const double* E, const double* g, const double* n,
-                       int64_t N, KeyMap km, uint32_t* keys, int32_t* vals, double* rec, hipStream_t st);
+                       int64_t N, KeyMap km, uint32_t* keys, int32_t* vals, double* rec, int* flags,
+                       hipStream_t st);
 hipError_t launch_radix_pass(const uint32_t* kin, const int32_t* vin, uint32_t* kout, int32_t* vout,
                              int64_t N, int shift, uint32_t* hist, uint32_t* dig_tot, hipStream_t st);
 hipError_t launch_gather(const int32_t* perm, int64_t N, const double* rec, double* onu, double* oS, double* oE,

@@ -60,11 +60,12 @@ __global__ void k_validate_init(unsigned long long* mm, int* flags) {
   mm[0] = ~0ull;
   mm[1] = 0ull;
   flags[0] = 0;
+  flags[1] = 0;
 }
 
-__global__ __launch_bounds__(kThreads) void k_validate(const double* __restrict__ nu,
-    const double* __restrict__ S, const double* __restrict__ E, const double* __restrict__ g,
-    const double* __restrict__ n, int64_t N, unsigned long long* mm, int* flags) {
+// nu > 0 and finite, and its range (the other fields are checked by k_keys, which reads them).
+__global__ __launch_bounds__(kThreads) void k_validate(const double* __restrict__ nu, int64_t N,
+                                                       unsigned long long* mm, int* flags) {
   __shared__ unsigned long long smin[kThreads], smax[kThreads];
   __shared__ int sbad;
   if (threadIdx.x == 0) sbad = 0;
@@ -73,9 +74,7 @@ __global__ __launch_bounds__(kThreads) void k_validate(const double* __restrict_
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (int64_t)gridDim.x * blockDim.x) {
     const double v = nu[i];
-    const bool ok = (v > 0.0) && isfinite(v) && (S[i] >= 0.0) && isfinite(S[i]) && isfinite(E[i]) &&
-                    (g[i] >= 0.0) && isfinite(g[i]) && isfinite(n[i]);
-    if (!ok) { bad = 1; continue; }
+    if (!((v > 0.0) && isfinite(v))) { bad = 1; continue; }
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);  // v > 0: order-preserving
     lmin = b < lmin ? b : lmin;
     lmax = b > lmax ? b : lmax;
@@ -99,21 +98,29 @@ __global__ __launch_bounds__(kThreads) void k_validate(const double* __restrict_
 }
 
 // Bin keys, identity values, and a record-per-line copy of the five fields (so that the
-// gather after the sort reads one record, not five scattered words, per line).
-__global__ void k_keys(const double* __restrict__ nu, const double* __restrict__ S, const double* __restrict__ E,
-                       const double* __restrict__ g, const double* __restrict__ n, int64_t N, KeyMap km,
-                       uint32_t* __restrict__ keys, int32_t* __restrict__ vals, double* __restrict__ rec) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  const double v = nu[i];
-  keys[i] = bin_key(v, km);
-  vals[i] = (int32_t)i;
-  double* r = rec + 5 * i;
-  r[0] = v;
-  r[1] = S[i];
-  r[2] = E[i];
-  r[3] = g[i];
-  r[4] = n[i];
+// gather after the sort reads one record, not five scattered words, per line); also checks
+// S_ref >= 0, gamma_ref >= 0 and finite E, S_ref, gamma_ref, n (flags[1] = 1 if not).
+__global__ __launch_bounds__(kThreads) void k_keys(const double* __restrict__ nu, const double* __restrict__ S,
+                                                   const double* __restrict__ E, const double* __restrict__ g,
+                                                   const double* __restrict__ n, int64_t N, KeyMap km,
+                                                   uint32_t* __restrict__ keys, int32_t* __restrict__ vals,
+                                                   double* __restrict__ rec, int* flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool bad = false;
+  if (i < N) {
+    const double v = nu[i];
+    const double Si = S[i], Ei = E[i], gi = g[i], ni = n[i];
+    bad = !((Si >= 0.0) && isfinite(Si) && isfinite(Ei) && (gi >= 0.0) && isfinite(gi) && isfinite(ni));
+    keys[i] = bin_key(v, km);
+    vals[i] = (int32_t)i;
+    double* r = rec + 5 * i;
+    r[0] = v;
+    r[1] = Si;
+    r[2] = Ei;
+    r[3] = gi;
+    r[4] = ni;
+  }
+  if (__ballot(bad) != 0ull && (threadIdx.x & (kWave - 1)) == 0) atomicOr(flags + 1, 1);
 }
 
 // Per-block digit histogram: hist[d * G + b].
@@ -2020,19 +2027,19 @@ __global__ void k_cut_bounds(const double* __restrict__ nu, const int32_t* __res
 // ----------------------------------------------------------------- launch wrappers
 static inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-hipError_t launch_validate(const double* nu, const double* S, const double* E, const double* g,
-                           const double* n, int64_t N, unsigned long long* mm, int* flags, hipStream_t st) {
+hipError_t launch_validate(const double* nu, int64_t N, unsigned long long* mm, int* flags, hipStream_t st) {
   hipLaunchKernelGGL(k_validate_init, dim3(1), dim3(1), 0, st, mm, flags);
   int64_t blocks = blocks_for(N, kThreads);
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_validate, dim3((unsigned)blocks), dim3(kThreads), 0, st, nu, S, E, g, n, N, mm, flags);
+  hipLaunchKernelGGL(k_validate, dim3((unsigned)blocks), dim3(kThreads), 0, st, nu, N, mm, flags);
   return hipGetLastError();
 }
 
 hipError_t launch_keys(const double* nu, const double* S, const double* E, const double* g, const double* n,
-                       int64_t N, KeyMap km, uint32_t* keys, int32_t* vals, double* rec, hipStream_t st) {
+                       int64_t N, KeyMap km, uint32_t* keys, int32_t* vals, double* rec, int* flags,
+                       hipStream_t st) {
   hipLaunchKernelGGL(k_keys, dim3(blocks_for(N, kThreads)), dim3(kThreads), 0, st, nu, S, E, g, n, N, km, keys,
-                     vals, rec);
+                     vals, rec, flags);
   return hipGetLastError();
 }
 

@@ -131,12 +131,20 @@ def test_deterministic_bitwise():
     lines.release()
 
 
-def test_invalid_line_data_rejected():
+@pytest.mark.parametrize("field,bad", [("nu", -2.0), ("nu", np.inf), ("S_ref", -1e-20), ("S_ref", np.nan),
+                                       ("E", np.inf), ("gamma_ref", -0.01), ("gamma_ref", np.nan), ("n", np.nan)])
+def test_invalid_line_data_rejected(field, bad):
+    """Each field's check (nu in the first pass, the others while the records are copied)."""
     import paper_2101_02005_amd as hk
-    L = _lines([1.0, -2.0, 3.0])
+    L = _lines([1.0, 2.0, 3.0, 4.0] * 100)
+    L[field] = L[field].copy()
+    L[field][257] = bad
     with pytest.raises(hk.HkError) as e:
         prepare(L, SP)
     assert e.value.status == hk.HK_EINVAL
+    # a valid list still prepares afterwards
+    lines = prepare(_lines([1.0, 2.0, 3.0]), SP)
+    lines.release()
 
 
 TUNINGS = [1, 2, 4, 8]  # slots P: span width 64 P, tile-far tile width 256 P
