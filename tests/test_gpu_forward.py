@@ -168,6 +168,36 @@ def test_every_tuning_matches_oracle(slots, monkeypatch):
         lines.release()
 
 
+_CLASS_CASES = [(1000.0, 1.0), (3000.0, 10.0)]
+_class_oracle = {}
+
+
+@pytest.mark.parametrize("T,P", _CLASS_CASES)
+@pytest.mark.parametrize("slots", TUNINGS)
+def test_every_evaluation_class_vs_oracle(slots, T, P, monkeypatch):
+    """Dense lines around a 2048-point grid with a 12 cm^-1 cut: every span sees direct lines,
+    middle (32-node), far (16-node), very far (8-node) and, for 64- and 128-point spans, masked
+    (6-node, cut bound on the span) lines, and tiles see tile-far lines; all points against the
+    FP64 oracle."""
+    monkeypatch.setenv("HK_SLOTS", str(slots))
+    rng = np.random.default_rng(77)
+    N = 40000
+    L = {"nu": np.sort(rng.uniform(985.0, 1045.0, N))[rng.permutation(N)],
+         "S_ref": 10.0 ** rng.uniform(-22.0, -19.0, N), "E": rng.uniform(0.0, 3000.0, N),
+         "gamma_ref": rng.uniform(0.01, 0.1, N), "n": rng.uniform(0.4, 0.8, N)}
+    nu0, dnu, n, cut = 1000.0, 0.01, 2048, 12.0
+    key = (T, P)
+    if key not in _class_oracle:
+        _class_oracle[key] = oracle_k(L, SP, T, P, nu0, dnu, cut, np.arange(n))
+    ko = _class_oracle[key]
+    lines = prepare(L, SP)
+    k = gpu_k(lines, T, P, nu0, dnu, n, cut)
+    lines.release()
+    e = rel_err(k, ko)
+    print("span %d points, T=%g P=%g: max |dk| / max k = %.3e" % (64 * slots, T, P, e))
+    assert e <= TOL_K
+
+
 def test_autotuner_picks_a_candidate_and_keeps_parity(monkeypatch):
     import paper_2101_02005_amd as hk
     monkeypatch.delenv("HK_SLOTS", raising=False)
