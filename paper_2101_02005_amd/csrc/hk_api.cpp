@@ -81,6 +81,8 @@ struct DevInfo {
   float cheb_x[4][hk::kNodes] = {};  // node positions relative to the span's first point
   double* tile_w[4] = {};     // device: the same for the tile-far tile (4 spans), per slots
   float tile_x[4][hk::kNodes] = {};
+  double* tile_w8[4] = {};    // device: the tile's very-far nodes (kFar8Nodes), per slots
+  float tile_x8[4][hk::kFar8Nodes] = {};
   double* far8_w[4] = {};     // device: the span's very-far nodes (kFar8Nodes), per slots
   float far8_x[4][hk::kFar8Nodes] = {};
   double* mid_w[4] = {};      // device: the span's middle-distance nodes (kMidNodes), per slots
@@ -188,6 +190,9 @@ hk_status device_init(int* dev_out, DevInfo* info) {
       span_nodes(hk::kWavesPerWG * S, hk::kNodes, di.tile_x[si], wts);
       HK_HIP(hipMalloc(&di.tile_w[si], sizeof(double) * wts.size()));  // held for the process lifetime
       HK_HIP(hipMemcpy(di.tile_w[si], wts.data(), sizeof(double) * wts.size(), hipMemcpyHostToDevice));
+      span_nodes(hk::kWavesPerWG * S, hk::kFar8Nodes, di.tile_x8[si], wts);
+      HK_HIP(hipMalloc(&di.tile_w8[si], sizeof(double) * wts.size()));  // held for the process lifetime
+      HK_HIP(hipMemcpy(di.tile_w8[si], wts.data(), sizeof(double) * wts.size(), hipMemcpyHostToDevice));
       span_nodes(S, hk::kFar8Nodes, di.far8_x[si], wts);
       HK_HIP(hipMalloc(&di.far8_w[si], sizeof(double) * wts.size()));  // held for the process lifetime
       HK_HIP(hipMemcpy(di.far8_w[si], wts.data(), sizeof(double) * wts.size(), hipMemcpyHostToDevice));
@@ -384,14 +389,14 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   pl->off_pairs = take(sizeof(hk::PairDesc) * n_pairs);
   pl->off_pairs_c = take(sizeof(hk::PairDesc) * n_pairs);
   pl->off_cnt = take(sizeof(int) * 64);
-  pl->off_stats = take(sizeof(long long) * ((size_t)pl->grid_w + pl->grid_c + pl->grid_f));
+  pl->off_stats = take(sizeof(long long) * ((size_t)pl->grid_w + pl->grid_c + 2 * (size_t)pl->grid_f));
   pl->off_lo = take(sizeof(int32_t) * tiles);
   pl->off_hi = take(sizeof(int32_t) * tiles);
   pl->off_nc = take(sizeof(int32_t) * tiles);
-  pl->off_far = take(sizeof(int4) * tiles);
-  pl->off_nf = take(sizeof(int32_t) * tiles);
-  pl->off_ibf = take(sizeof(int32_t) * (tiles + 1));
-  pl->off_partf = take(sizeof(double) * hk::kNodes * (size_t)pl->items_bound_f);
+  pl->off_far = take(sizeof(int4) * 2 * tiles);
+  pl->off_nf = take(sizeof(int32_t) * 2 * tiles);
+  pl->off_ibf = take(sizeof(int32_t) * 2 * (tiles + 1));
+  pl->off_partf = take(sizeof(double) * (hk::kNodes + hk::kFar8Nodes) * (size_t)pl->items_bound_f);
   pl->off_segs = take(sizeof(hk::SpanSeg) * tiles_c);
   pl->off_nc_w = take(sizeof(int32_t) * tiles_c);
   pl->off_ib_w = take(sizeof(int32_t) * (tiles_c + 1));
@@ -508,6 +513,7 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   HK_HIP(hk::launch_worklist(L->keys, L->N, L->km, L->numin, L->numax, dpairs, pl.n_pairs, pl.n_tiles_total,
                              pl.W, cut, 0.0, pl.chunk, lo, hi, nc, tfar, nf, pl.chunk_f, far_z, st));
   HK_HIP(hk::launch_item_scan(nf, pl.n_tiles_total, ibf, cnt + 16, st));
+  HK_HIP(hk::launch_item_scan(nf + pl.n_tiles_total, pl.n_tiles_total, ibf + pl.n_tiles_total + 1, cnt + 24, st));
   HK_HIP(hk::launch_span_segments(L->keys, L->N, L->km, L->numin, L->numax, dpairs_c, dpairs, pl.n_pairs,
                                   pl.n_tiles_c, pl.W_c, cut, far_z, tfar, pl.chunk, segs, nc_w, st));
   HK_HIP(hk::launch_item_scan(nc_w, pl.n_tiles_c, ib_w, cnt, st));
@@ -562,21 +568,27 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   fa.gT = gT;
   fa.pairs = dpairs;
   fa.tile_far = tfar;
-  fa.item_base = ibf;
-  fa.node_part = reinterpret_cast<double*>(ws + pl.off_partf);
-  fa.counter = cnt + 16;
+  fa.item_base[0] = ibf;
+  fa.item_base[1] = ibf + pl.n_tiles_total + 1;
+  fa.node_part[0] = reinterpret_cast<double*>(ws + pl.off_partf);
+  fa.node_part[1] = fa.node_part[0] + (size_t)hk::kNodes * pl.items_bound_f;
+  fa.counter[0] = cnt + 16;
+  fa.counter[1] = cnt + 24;
   fa.stats = tm.on ? stats_f : nullptr;
-  fa.tile_w = di.tile_w[si];
+  fa.tile_w[0] = di.tile_w[si];
+  fa.tile_w[1] = di.tile_w8[si];
   fa.k = k;
   fa.N = L->N;
   for (int i = 0; i < hk::kKmax; ++i) fa.zK[i] = (float)kZK[i];
   fa.n_pairs = pl.n_pairs;
   fa.n_tiles_total = pl.n_tiles_total;
   fa.chunk = pl.chunk_f;
-  fa.items_cap = (int32_t)std::min<int64_t>(pl.items_bound_f, INT32_MAX);
+  fa.items_cap[0] = fa.items_cap[1] = (int32_t)std::min<int64_t>(pl.items_bound_f, INT32_MAX);
   fa.W = pl.W;
   for (int q = 0; q < hk::kNodes; ++q) fa.tile_x[q] = di.tile_x[si][q];
-  HK_HIP(hk::launch_far(fa, pl.grid_f, st));
+  for (int q = 0; q < hk::kFar8Nodes; ++q) fa.tile_x8[q] = di.tile_x8[si][q];
+  HK_HIP(hk::launch_far(fa, 0, pl.grid_f, st));
+  HK_HIP(hk::launch_far(fa, 1, pl.grid_f, st));
   HK_HIP(hk::launch_combine_far(fa, st));
   tm.mark();
   // line-core pass over its own (narrower) work list, after the wing sums are final
@@ -604,7 +616,7 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   g_tim.core_evals = -1;
   g_tim.wing_evals = -1;
   if (tm.on) {
-    std::vector<long long> h((size_t)pl.grid_w + pl.grid_c + pl.grid_f);
+    std::vector<long long> h((size_t)pl.grid_w + pl.grid_c + 2 * (size_t)pl.grid_f);
     HK_HIP(hipMemcpy(h.data(), stats, sizeof(long long) * h.size(), hipMemcpyDeviceToHost));
     long long tw = 0, tc = 0;
     for (size_t i = 0; i < h.size(); ++i)

@@ -190,26 +190,29 @@ struct VoigtArgs {
 };
 
 // Arguments of the tile-far pass (lines evaluated at the tile's Chebyshev nodes) and its combine.
+// Tile-far lines come in two classes: c = 0 (1.5-3 tile widths from the tile centre) at the
+// tile's kNodes nodes, c = 1 (at least 3) at its kFar8Nodes nodes.
 struct FarArgs {
   const double* nu;        // sorted, N
   const float* S_T;        // [n_temps][N]
   const float* gT;         // [n_temps][N]
   const PairDesc* pairs;
-  const int4* tile_far;    // per global tile: [x, y) and [z, w), the tile-far line ranges
-  const int32_t* item_base;// per global tile: first far item; [n_tiles_total] = total far items
-  double* node_part;       // [item][kNodes]: node sums of one work item
-  int* counter;            // work-item dispenser (scheduling only)
-  long long* stats;        // nullable: per-block count of node evaluations
-  const double* tile_w;    // [kNodes][tile width] Lagrange weights of the tile's nodes
+  const int4* tile_far;    // [tile][c]: the class-c line ranges [x, y) and [z, w)
+  const int32_t* item_base[2];  // per class, per global tile: first item; [n_tiles_total] = total
+  double* node_part[2];    // per class: [item][node count] node sums of one work item
+  int* counter[2];         // per class: work-item dispenser (scheduling only)
+  long long* stats;        // nullable: [class][block] count of node evaluations
+  const double* tile_w[2]; // per class: [node count][tile width] Lagrange weights of the tile's nodes
   float* k;
   int64_t N;
   float zK[kKmax];
   int32_t n_pairs;
   int32_t n_tiles_total;
   int32_t chunk;           // tile-far lines per work item
-  int32_t items_cap;       // rows of node_part
+  int32_t items_cap[2];    // rows of node_part
   int32_t W;               // tile width in grid points
-  float tile_x[kNodes];    // node positions relative to the tile's first point
+  float tile_x[kNodes];    // class-0 node positions relative to the tile's first point
+  float tile_x8[kFar8Nodes];  // class-1 node positions
 };
 
 struct PrepArgs {
@@ -265,7 +268,7 @@ hipError_t launch_worklist(const uint32_t* keys, int64_t N, KeyMap km, double nu
                            const PairDesc* pairs,
                            int n_pairs, int n_tiles_total, int tile_w, double cut, double core_z, int chunk,
                            int32_t* lo, int32_t* hi, int32_t* nc, int4* far, int32_t* nf, int far_chunk,
-                           double far_z, hipStream_t st);
+                           double far_z, hipStream_t st);  // far: [tile][2]; nf: [2][tiles]
 hipError_t launch_item_scan(const int32_t* nc, int n_tiles_total, int32_t* item_base, int* counter,
                             hipStream_t st);
 hipError_t launch_gridrec(const double* nu, int64_t N, double nu_start, double dnu, int64_t n, double cut,
@@ -281,7 +284,7 @@ hipError_t launch_combine(const VoigtArgs& a, int slots, bool add, hipStream_t s
 hipError_t launch_cut_bounds(const double* nu, const int32_t* perm, int64_t N, double nu_start,
                              double dnu, int64_t n, double cut, int32_t* jlo, int32_t* jhi,
                              hipStream_t st);
-hipError_t launch_far(const FarArgs& a, int grid, hipStream_t st);
+hipError_t launch_far(const FarArgs& a, int cls, int grid, hipStream_t st);
 hipError_t launch_combine_far(const FarArgs& a, hipStream_t st);
 int far_max_blocks_per_cu();
 hipError_t launch_adjoint(const AdjArgs& a, int grid, hipStream_t st);

@@ -378,7 +378,10 @@ __global__ void k_worklist(const uint32_t* __restrict__ keys, int64_t N, KeyMap 
     const double vb = __dadd_rn(grid_nu(pd.nu_start, pd.dnu, j1), hw);
     if (vb < numin || va > numax) {
       lo_out[g] = 0; hi_out[g] = 0; nc_out[g] = 1;
-      if (far_out) { far_out[g] = make_int4(0, 0, 0, 0); nf_out[g] = 0; }
+      if (far_out) {
+        far_out[2 * g] = far_out[2 * g + 1] = make_int4(0, 0, 0, 0);
+        nf_out[g] = nf_out[n_tiles_total + g] = 0;
+      }
       return;
     }
     uint32_t ka = bin_key(va, km), kb = bin_key(vb, km);
@@ -391,20 +394,32 @@ __global__ void k_worklist(const uint32_t* __restrict__ keys, int64_t N, KeyMap 
     while (a < b) { int64_t m = (a + b) >> 1; if (keys[m] <= kb) a = m + 1; else b = m; }
     hi = a;
   }
-  int64_t a1 = lo, b1 = lo, a2 = hi, b2 = hi;
+  int64_t a1 = lo, b1 = lo, a2 = hi, b2 = hi, x1 = lo, x2 = hi;
   if (far_out && j0 + tile_w <= pd.n && hi > lo) {
     const double nA = grid_nu(pd.nu_start, pd.dnu, j0), nB = grid_nu(pd.nu_start, pd.dnu, j0 + tile_w - 1);
     const double nc = 0.5 * (nA + nB), half = 0.5 * (nB - nA);
     const double wlo = isinf(cut) ? numin : fmax(numin, nA - cut);
     const double whi = isinf(cut) ? numax : fmin(numax, nB + cut);
     const double amax = pd.beta * fmax(fabs(wlo), fabs(whi));
-    const double dfar = fmax(kTileFar * tile_w * pd.dnu, half + far_z * amax * 1.001 + 2.0 * pd.dnu);
+    const double reach = half + far_z * amax * 1.001 + 2.0 * pd.dnu;
+    const double dfar = fmax(kTileFar * tile_w * pd.dnu, reach);
+    const double d8 = fmax(kFar8Spans * tile_w * pd.dnu, reach);
     const double m = 0.5 * pd.dnu;
-    key_range(keys, lo, hi, isinf(cut) ? -INFINITY : nB - cut + m, nc - dfar, km, a1, b1);
-    key_range(keys, lo, hi, nc + dfar, isinf(cut) ? INFINITY : nA + cut - m, km, a2, b2);
+    const double v0 = isinf(cut) ? -INFINITY : nB - cut + m, v1 = isinf(cut) ? INFINITY : nA + cut - m;
+    key_range(keys, lo, hi, v0, nc - dfar, km, a1, b1);
+    key_range(keys, lo, hi, nc + dfar, v1, km, a2, b2);
     if (a1 == b1) a1 = b1 = lo;
     if (a2 == b2) a2 = b2 = hi;
     if (b1 > a2) { a1 = b1 = lo; a2 = b2 = hi; }  // cannot happen (disjoint key ranges); kept safe
+    // the class-1 parts: the same outer bounds, so the same first (last) line when not empty
+    int64_t e1 = lo, f1 = lo, e2 = hi, f2 = hi;
+    key_range(keys, lo, hi, v0, nc - d8, km, e1, f1);
+    key_range(keys, lo, hi, nc + d8, v1, km, e2, f2);
+    x1 = (e1 < f1 && e1 == a1 && f1 <= b1) ? f1 : a1;
+    x2 = (e2 < f2 && f2 == b2 && e2 >= a2) ? e2 : b2;
+  } else {
+    x1 = a1;
+    x2 = b2;
   }
   const int64_t cnt = (a1 - lo) + (a2 - b1) + (hi - b2);
   int64_t nc = (cnt + chunk - 1) / chunk;
@@ -412,9 +427,12 @@ __global__ void k_worklist(const uint32_t* __restrict__ keys, int64_t N, KeyMap 
   hi_out[g] = (int32_t)hi;
   nc_out[g] = (int32_t)(nc > 0 ? nc : 1);
   if (far_out) {
-    far_out[g] = make_int4((int)a1, (int)b1, (int)a2, (int)b2);
-    const int64_t nfl = (b1 - a1) + (b2 - a2);
-    nf_out[g] = (int32_t)((nfl + far_chunk - 1) / far_chunk);
+    // class 0: [x1, b1) and [a2, x2); class 1: [a1, x1) and [x2, b2)
+    far_out[2 * g] = make_int4((int)x1, (int)b1, (int)a2, (int)x2);
+    far_out[2 * g + 1] = make_int4((int)a1, (int)x1, (int)x2, (int)b2);
+    const int64_t n0 = (b1 - x1) + (x2 - a2), n1 = (x1 - a1) + (b2 - x2);
+    nf_out[g] = (int32_t)((n0 + far_chunk - 1) / far_chunk);
+    nf_out[n_tiles_total + g] = (int32_t)((n1 + far_chunk - 1) / far_chunk);
   }
 }
 
@@ -459,8 +477,9 @@ __global__ void k_span_segments(const uint32_t* __restrict__ keys, int64_t N, Ke
   // tile-far ranges of the span's tile
   int64_t ta1 = lo, tb1 = lo, ta2 = hi, tb2 = hi;
   if (tile_far) {
-    const int4 tf = tile_far[tpairs[p].tile_base + (int)(t / kWavesPerWG)];
-    ta1 = tf.x; tb1 = tf.y; ta2 = tf.z; tb2 = tf.w;
+    const int tg = tpairs[p].tile_base + (int)(t / kWavesPerWG);
+    const int4 c0 = tile_far[2 * tg], c1 = tile_far[2 * tg + 1];
+    ta1 = c1.x; tb1 = c0.y; ta2 = c0.z; tb2 = c1.w;  // the union of the two classes' ranges
   }
   // far, middle and masked ranges of the span (full spans only); the middle ones contain the
   // far ones; the masked ones lie beyond the far ones' cut-side bounds
@@ -1396,22 +1415,25 @@ __global__ __launch_bounds__(kWave) void k_wing(VoigtArgs a) {
 // and a chunk of its tile-far lines; it writes its kNodes node sums (per lane in FP32 over 16
 // lines, then FP64; over the workgroup in a fixed order), and k_combine_far adds their
 // interpolation to the tile.
+template <int C>
 __global__ __launch_bounds__(kThreads) void k_far(FarArgs a) {
-  __shared__ double sRed[kWavesPerWG][kNodes];
+  constexpr int NN = C == 0 ? kNodes : kFar8Nodes;
+  __shared__ double sRed[kWavesPerWG][NN];
   __shared__ int sItem, sTile, sPair;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int total = a.item_base[a.n_tiles_total];
+  const int32_t* __restrict__ item_base = a.item_base[C];
+  const int total = item_base[a.n_tiles_total];
   long long n_lines = 0;
   for (;;) {
     if (tid == 0) {
-      const int it = atomicAdd(a.counter, 1);
+      const int it = atomicAdd(a.counter[C], 1);
       sItem = it;
       if (it < total) {
         int lo = 0, hi = a.n_tiles_total - 1;  // last tile with item_base <= it
         while (lo < hi) {
           const int m = (lo + hi + 1) >> 1;
-          if (a.item_base[m] <= it) lo = m; else hi = m - 1;
+          if (item_base[m] <= it) lo = m; else hi = m - 1;
         }
         sTile = lo;
         sPair = find_pair(a.pairs, a.n_pairs, lo);
@@ -1422,8 +1444,8 @@ __global__ __launch_bounds__(kThreads) void k_far(FarArgs a) {
     if (it >= total) break;
     const int g = __builtin_amdgcn_readfirstlane(sTile);
     const PairDesc pd = wave_uniform(a.pairs[__builtin_amdgcn_readfirstlane(sPair)]);
-    const int ibase = __builtin_amdgcn_readfirstlane(a.item_base[g]);
-    const int4 tf = wave_uniform(a.tile_far[g]);
+    const int ibase = __builtin_amdgcn_readfirstlane(item_base[g]);
+    const int4 tf = wave_uniform(a.tile_far[2 * g + C]);
     const int nl = tf.y - tf.x, nv = nl + (tf.w - tf.z);
     const int v_lo = (it - ibase) * a.chunk;
     const int v_hi = v_lo + a.chunk < nv ? v_lo + a.chunk : nv;
@@ -1435,10 +1457,10 @@ __global__ __launch_bounds__(kThreads) void k_far(FarArgs a) {
     const float* __restrict__ S_T = a.S_T + (int64_t)pd.tidx * a.N;
     const float* __restrict__ gT = a.gT + (int64_t)pd.tidx * a.N;
 
-    float acc[kNodes];
+    float acc[NN];
 #pragma unroll
-    for (int k = 0; k < kNodes; ++k) acc[k] = 0.0f;
-    if (lane < kNodes) sRed[wv][lane] = 0.0;
+    for (int k = 0; k < NN; ++k) acc[k] = 0.0f;
+    if (lane < NN) sRed[wv][lane] = 0.0;
     int n = 0;
     for (int b = v_lo; b < v_hi; b += kThreads) {
       const int v = b + tid;
@@ -1446,34 +1468,41 @@ __global__ __launch_bounds__(kThreads) void k_far(FarArgs a) {
       const int64_t li = v < nl ? (int64_t)tf.x + v : (int64_t)tf.z + (v - nl);
       const FarLine f = far_line(valid, valid ? a.nu[li] : 0.0, valid ? S_T[li] : 0.0f, valid ? gT[li] : 0.0f,
                                  pd, nu0, nu1, inv_dnu, a.zK);
-      far_accumulate<kNodes>(ArgNodes{a.tile_x}, f, acc);
+      far_accumulate<NN>(ArgNodes{C == 0 ? a.tile_x : a.tile_x8}, f, acc);
       if (++n == 16 || b + kThreads >= v_hi) {
-        far_flush<kNodes>(acc, lane, sRed[wv]);
+        far_flush<NN>(acc, lane, sRed[wv]);
         n = 0;
       }
     }
     __syncthreads();
-    if (tid < kNodes) {
+    if (tid < NN) {
       double t = 0.0;
 #pragma unroll
       for (int w = 0; w < kWavesPerWG; ++w) t += sRed[w][tid];
-      if (it < a.items_cap) a.node_part[(int64_t)it * kNodes + tid] = t;
+      if (it < a.items_cap[C]) a.node_part[C][(int64_t)it * NN + tid] = t;
     }
     __syncthreads();
   }
-  if (a.stats && tid == 0) a.stats[blockIdx.x] = n_lines * kNodes;
+  if (a.stats && tid == 0) a.stats[C * gridDim.x + blockIdx.x] = n_lines * NN;
 }
 
-// k += interpolation onto the tile of the fixed-order (item 0, 1, ...) sum of its node sums.
+// k += interpolation onto the tile of the fixed-order (class 0 then 1; item 0, 1, ...) sums of
+// its node sums.
 __global__ __launch_bounds__(kThreads) void k_combine_far(FarArgs a) {
-  __shared__ double ns[kNodes];
+  __shared__ double ns[kNodes + kFar8Nodes];
   const int g = blockIdx.x;
-  const int base = a.item_base[g], nf = a.item_base[g + 1] - base;
-  if (nf <= 0) return;
+  const int b0 = a.item_base[0][g], n0 = a.item_base[0][g + 1] - b0;
+  const int b1 = a.item_base[1][g], n1 = a.item_base[1][g + 1] - b1;
+  if (n0 <= 0 && n1 <= 0) return;
   const PairDesc pd = a.pairs[find_pair(a.pairs, a.n_pairs, g)];
   if (threadIdx.x < kNodes) {
     double t = 0.0;
-    for (int c = 0; c < nf && base + c < a.items_cap; ++c) t += a.node_part[(int64_t)(base + c) * kNodes + threadIdx.x];
+    for (int c = 0; c < n0 && b0 + c < a.items_cap[0]; ++c) t += a.node_part[0][(int64_t)(b0 + c) * kNodes + threadIdx.x];
+    ns[threadIdx.x] = t;
+  } else if (threadIdx.x < kNodes + kFar8Nodes) {
+    const int k = threadIdx.x - kNodes;
+    double t = 0.0;
+    for (int c = 0; c < n1 && b1 + c < a.items_cap[1]; ++c) t += a.node_part[1][(int64_t)(b1 + c) * kFar8Nodes + k];
     ns[threadIdx.x] = t;
   }
   __syncthreads();
@@ -1482,7 +1511,9 @@ __global__ __launch_bounds__(kThreads) void k_combine_far(FarArgs a) {
     if (tile0 + local >= pd.n) continue;
     double v = 0.0;
 #pragma unroll
-    for (int k = 0; k < kNodes; ++k) v = fma(ns[k], a.tile_w[k * a.W + local], v);
+    for (int k = 0; k < kNodes; ++k) v = fma(ns[k], a.tile_w[0][k * a.W + local], v);
+#pragma unroll
+    for (int k = 0; k < kFar8Nodes; ++k) v = fma(ns[kNodes + k], a.tile_w[1][k * a.W + local], v);
     float* dst = a.k + pd.out_off + tile0 + local;
     *dst = (float)((double)*dst + v);
   }
@@ -2172,8 +2203,9 @@ hipError_t launch_cut_bounds(const double* nu, const int32_t* perm, int64_t N, d
   return hipGetLastError();
 }
 
-hipError_t launch_far(const FarArgs& a, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_far, dim3(grid), dim3(kThreads), 0, st, a);
+hipError_t launch_far(const FarArgs& a, int cls, int grid, hipStream_t st) {
+  if (cls == 0) hipLaunchKernelGGL(k_far<0>, dim3(grid), dim3(kThreads), 0, st, a);
+  else hipLaunchKernelGGL(k_far<1>, dim3(grid), dim3(kThreads), 0, st, a);
   return hipGetLastError();
 }
 
@@ -2185,7 +2217,7 @@ hipError_t launch_combine_far(const FarArgs& a, hipStream_t st) {
 
 int far_max_blocks_per_cu() {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_far, kThreads, 0) != hipSuccess) return 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_far<0>, kThreads, 0) != hipSuccess) return 1;
   return n > 0 ? n : 1;
 }
 
