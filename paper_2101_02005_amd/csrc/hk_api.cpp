@@ -232,7 +232,8 @@ struct Plan {
   int slots = 4;
   int W = 1024;    // tile width of the tile-far pass (4 spans)
   int W_c = 256;   // span width of the wing and line-core passes (one wave, 64 slots)
-  int chunk = 0;   // lines per work item of the wing and line-core passes
+  int chunk = 0;   // lines per work item of the wing pass
+  int chunk_c = 0; // lines per work item of the line-core pass
   int n_pairs = 0, n_temps = 0;
   int n_tiles_total = 0;  // tiles
   int n_tiles_c = 0;      // spans
@@ -318,6 +319,10 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   // windows of the core pass)
   int64_t tiles = 0, tiles_c = 0;
   double visits = 0.0, visits_w = 0.0, visits_c = 0.0;
+  // the wing pass visits a line on the spans within the tile-far bound (1.5 tile widths of the
+  // tile centre) and on the two spans of its cut bounds only: at most this many spans per line
+  const int64_t wing_span_visits = 2 * (int64_t)(hk::kTileFar * hk::kWavesPerWG + hk::kWavesPerWG) + 4;
+  double visits_wing = 0.0;
   pl->W_c = hk::kWave * pl->slots;
   pl->pairs.assign(n_pairs, hk::PairDesc{});
   pl->pairs_c.assign(n_pairs, hk::PairDesc{});
@@ -348,14 +353,18 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
     dc.tile_base = (int32_t)tiles_c;
     dc.n_tiles = (int32_t)nt_c;
     tiles_c += nt_c;
-    visits_w += (double)N * (double)visits_per_line(L, grids[p], cut, pl->W_c, nt_c);
+    const int64_t vw = visits_per_line(L, grids[p], cut, pl->W_c, nt_c);
+    visits_w += (double)N * (double)vw;
+    visits_wing += (double)N * (double)std::min<int64_t>(vw, wing_span_visits);
     visits_c += (double)N * (double)visits_per_line(L, grids[p], T ? hc : cut, pl->W_c, nt_c);
   }
   pl->n_tiles_total = (int)tiles;
   pl->n_tiles_c = (int)tiles_c;
-  // work-item size: enough items to balance the persistent grid of the wing pass
+  // work-item sizes: enough items to balance the persistent grids (measured on the large list:
+  // the wing pass gains down to about 64 items per wave slot, the core pass loses below about 1)
   const int wgs_w = di.cus * di.wing_per_cu[slot_index(pl->slots)];
-  double c = std::ceil(visits_w / (16.0 * (wgs_w > 0 ? wgs_w : 4096)));
+  const int wgs_c = di.cus * di.core_per_cu[slot_index(pl->slots)];
+  double c = std::ceil(visits_wing / (64.0 * (wgs_w > 0 ? wgs_w : 4096)));
   const int env_chunk = env_int("HK_CHUNK", 0);
   if (env_chunk > 0) c = env_chunk;
   if (c < 256) c = 256;
@@ -364,7 +373,11 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   const double items_w = (double)tiles_c + std::ceil(visits_w / pl->chunk);
   if (items_w >= 2.0e9) return fail(HK_ENOMEM, "work list too large (%.3g items)", items_w);
   pl->items_bound_w = (int64_t)items_w;
-  const double items_c = (double)tiles_c + std::ceil(visits_c / pl->chunk);
+  double cc = std::ceil(visits_c / (double)(wgs_c > 0 ? wgs_c : 4096));
+  if (cc < 4096) cc = 4096;
+  if (cc > (1 << 22)) cc = 1 << 22;
+  pl->chunk_c = (int)(std::ceil(cc / hk::kWave) * hk::kWave);
+  const double items_c = (double)tiles_c + std::ceil(visits_c / pl->chunk_c);
   if (items_c >= 2.0e9) return fail(HK_ENOMEM, "core work list too large (%.3g items)", items_c);
   pl->items_bound_c = (int64_t)items_c;
   // tile-far items: large chunks (a line costs kNodes evaluations), still enough to balance
@@ -378,7 +391,6 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   pl->items_bound_f = (int64_t)items_f;
   pl->grid_w = (int)std::max<int64_t>(1, std::min<int64_t>(pl->items_bound_w, (int64_t)(wgs_w > 0 ? wgs_w : 4096)));
   pl->grid_f = (int)std::max<int64_t>(1, std::min<int64_t>(pl->items_bound_f, (int64_t)(wgs_f > 0 ? wgs_f : 1024)));
-  const int wgs_c = di.cus * di.core_per_cu[slot_index(pl->slots)];
   pl->grid_c = (int)std::max<int64_t>(1, std::min<int64_t>(pl->items_bound_c, (int64_t)(wgs_c > 0 ? wgs_c : 4096)));
   // workspace layout (256-byte aligned sections)
   size_t off = 0;
@@ -518,7 +530,7 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
                                   pl.n_tiles_c, pl.W_c, cut, far_z, tfar, pl.chunk, segs, nc_w, st));
   HK_HIP(hk::launch_item_scan(nc_w, pl.n_tiles_c, ib_w, cnt, st));
   HK_HIP(hk::launch_worklist(L->keys, L->N, L->km, L->numin, L->numax, dpairs_c, pl.n_pairs, pl.n_tiles_c,
-                             pl.W_c, cut, core_z, pl.chunk, lo_c, hi_c, nc_c, nullptr, nullptr, 1, 0.0, st));
+                             pl.W_c, cut, core_z, pl.chunk_c, lo_c, hi_c, nc_c, nullptr, nullptr, 1, 0.0, st));
   HK_HIP(hk::launch_item_scan(nc_c, pl.n_tiles_c, ib_c, cnt + 8, st));
   tm.mark();
   int dev = 0;
@@ -593,6 +605,7 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   tm.mark();
   // line-core pass over its own (narrower) work list, after the wing sums are final
   hk::VoigtArgs vc = va;
+  vc.chunk = pl.chunk_c;
   vc.segs = nullptr;
   vc.tile_lo = lo_c;
   vc.tile_hi = hi_c;
@@ -950,6 +963,7 @@ hk_status hk_opacity_batched(const hk_lines* lines, int32_t n_pairs, const doubl
   put(&n_pairs, sizeof n_pairs);
   put(&pl.slots, sizeof pl.slots);
   put(&pl.chunk, sizeof pl.chunk);
+  put(&pl.chunk_c, sizeof pl.chunk_c);
   put(T, sizeof(double) * n_pairs);
   put(P_atm, sizeof(double) * n_pairs);
   put(grids, sizeof(hk_grid) * n_pairs);
