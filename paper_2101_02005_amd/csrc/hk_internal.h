@@ -10,7 +10,7 @@ constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kThreads = 256;    // threads per workgroup of the tile-far and sort kernels
 constexpr int kWavesPerWG = kThreads / kWave;  // spans per tile of the tile-far pass
 constexpr int kKmax = 5;         // highest order of the far-wing series
-constexpr int kWeidN = 20;       // terms of the FP64 core rational approximation
+constexpr int kWeidN = 18;       // terms of the FP64 core rational approximation
 constexpr int kKeyBits = 24;     // linear wavenumber-bin key width
 constexpr int kRadixBits = 8;
 constexpr int kSortItems = 16;   // keys per thread per sort block
