@@ -422,12 +422,13 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   return HK_OK;
 }
 
-// Backward workspace: grid records, per-line (dL/dT, dL/dlnP) terms, reduction partials.
+// Backward workspace: grid records, per-line (dL/dT, dL/dlnP) terms, reduction partials,
+// per-line FP64 records and the node weights of dL/dk per span of the grid.
 constexpr int kBwdPartials = 256;
 struct BwdLayout {
-  size_t off_gr = 0, off_contrib = 0, off_part = 0, off_lrec = 0, total = 0;
+  size_t off_gr = 0, off_contrib = 0, off_part = 0, off_lrec = 0, off_pref = 0, total = 0;
 };
-BwdLayout backward_layout(int64_t N) {
+BwdLayout backward_layout(int64_t N, int64_t n_grid) {
   BwdLayout b;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
@@ -435,6 +436,8 @@ BwdLayout backward_layout(int64_t N) {
   b.off_contrib = take(2 * sizeof(double) * (size_t)N);
   b.off_part = take(2 * sizeof(double) * kBwdPartials);
   b.off_lrec = take(6 * sizeof(double) * (size_t)N);
+  const size_t spans = (size_t)((n_grid + hk::kAdjSpan - 1) / hk::kAdjSpan);
+  b.off_pref = take(sizeof(double) * hk::kNodes * hk::kAdjSpan * spans);
   b.total = off;
   return b;
 }
@@ -874,7 +877,7 @@ hk_status hk_workspace_size(const hk_lines* lines, int mode, int32_t n_pairs, in
   s = device_init(&dev, &di);
   if (s != HK_OK) return s;
   if (mode == 2) {
-    *bytes = backward_layout(lines->N).total;
+    *bytes = backward_layout(lines->N, grids[0].n).total;
     return HK_OK;
   }
   // enough for every tuning the autotuner may pick
@@ -1028,7 +1031,7 @@ hk_status hk_opacity_backward(const hk_lines* lines, const hk_line_override* ovr
   DevInfo di;
   s = device_init(&dev, &di);
   if (s != HK_OK) return s;
-  const BwdLayout bl = backward_layout(lines->N);
+  const BwdLayout bl = backward_layout(lines->N, grid.n);
   if (ws_bytes < bl.total) return fail(HK_EINVAL, "workspace too small: %zu < %zu bytes", ws_bytes, bl.total);
   Timer tm(stream);
   tm.mark();
@@ -1054,10 +1057,17 @@ hk_status hk_opacity_backward(const hk_lines* lines, const hk_line_override* ovr
   a.dn = dL_dn;
   a.contrib = contrib;
   a.lrec = reinterpret_cast<double*>(w + bl.off_lrec);
+  double* gpref = reinterpret_cast<double*>(w + bl.off_pref);
+  a.gpref = gpref;
   const int64_t want = (lines->N + hk::kWavesPerWG - 1) / hk::kWavesPerWG;
   const int64_t cap = (int64_t)di.cus * 8;
   const int blocks = (int)std::max<int64_t>(1, std::min(want, cap));
-  if (lines->N > 0) HK_HIP(hk::launch_adjoint(a, blocks, stream));
+  if (lines->N > 0) {
+    // node weights of the adjoint's far spans: Lagrange weights of the 16 nodes of a 256-point span
+    static_assert(hk::kWavesPerWG * hk::kWave == hk::kAdjSpan, "adjoint span = tile of one slot");
+    HK_HIP(hk::launch_adj_nodes(dL_dk, grid.n, di.tile_w[0], gpref, stream));
+    HK_HIP(hk::launch_adjoint(a, blocks, stream));
+  }
   HK_HIP(hk::launch_reduce2(contrib, lines->N, part, kBwdPartials, dL_dT_lnP, stream));
   tm.mark();
   tm.finish();

@@ -249,7 +249,10 @@ struct AdjArgs {
   float* dn;               // caller order, nullable
   double* contrib;         // [N][2], sorted order: per-line dL/dT and dL/dlnP terms
   double* lrec;            // [N][6], sorted order: per-line FP64 quantities (k_adj_lines)
+  const double* gpref;     // [span][kNodes][kAdjSpan]: per span of kAdjSpan points, the prefix sums
+                           // over its points j of dL/dk_j times node k's Lagrange weight at j
 };
+constexpr int kAdjSpan = 256;  // points per span of the adjoint (one step of a wave)
 
 // Launch wrappers (hk_kernels.hip); each returns the launch status.
 // flags[0]: a nu <= 0 or non-finite (k_validate); flags[1]: another field invalid (k_keys)
@@ -287,6 +290,8 @@ hipError_t launch_cut_bounds(const double* nu, const int32_t* perm, int64_t N, d
 hipError_t launch_far(const FarArgs& a, int cls, int grid, hipStream_t st);
 hipError_t launch_combine_far(const FarArgs& a, hipStream_t st);
 int far_max_blocks_per_cu();
+// gpref of AdjArgs from dL/dk (g, n points) and the node weights w [kNodes][kAdjSpan]
+hipError_t launch_adj_nodes(const float* g, int64_t n, const double* w, double* gpref, hipStream_t st);
 hipError_t launch_adjoint(const AdjArgs& a, int grid, hipStream_t st);
 hipError_t launch_reduce2(const double* contrib, int64_t N, double* partial, int n_partial, double* out,
                           hipStream_t st);

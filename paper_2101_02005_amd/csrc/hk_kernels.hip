@@ -1819,6 +1819,33 @@ __device__ __forceinline__ void adj_step(const AdjPoly& P, int jc, int lane, int
 }
 
 
+// Node weights of dL/dk for the adjoint's far spans: for span s (points s kAdjSpan + jj) and
+// node k, the prefix sums over jj of g_j L_k(jj) (L_k: the Lagrange weight of node k of the span
+// at its point jj), in FP64 by a fixed-order scan. A line that covers points a..b of a span far
+// from its centre then takes sum_j g_j f(j) = sum_k f(x_k) (P_k(b) - P_k(a - 1)) up to the
+// interpolation error of f on the span.
+__global__ __launch_bounds__(kAdjSpan) void k_adj_nodes(const float* __restrict__ g, int64_t n,
+                                                        const double* __restrict__ w, double* __restrict__ gpref) {
+  __shared__ double sc[kAdjSpan];
+  const int s = blockIdx.x, jj = threadIdx.x;
+  const int64_t j = (int64_t)s * kAdjSpan + jj;
+  const double gv = j < n ? (double)g[j] : 0.0;
+  for (int k = 0; k < kNodes; ++k) {
+    double v = gv * w[k * kAdjSpan + jj];
+    sc[jj] = v;
+    __syncthreads();
+    for (int off = 1; off < kAdjSpan; off <<= 1) {
+      const double t = jj >= off ? sc[jj - off] : 0.0;
+      __syncthreads();
+      v += t;
+      sc[jj] = v;
+      __syncthreads();
+    }
+    gpref[((int64_t)s * kNodes + k) * kAdjSpan + jj] = v;
+    __syncthreads();
+  }
+}
+
 // One wave per line (static assignment), lanes over its grid points inside the cut.
 // Per-line FP64 quantities of the adjoint, one thread per line (sorted order), kept apart from
 // the point loop so that the transcendental functions do not hold registers there:
@@ -1849,23 +1876,46 @@ __global__ __launch_bounds__(kThreads) void k_adj_lines(AdjArgs a) {
   r[5] = nexp * gam / T;
 }
 
+// Far spans of the adjoint: kAdjSpan-point spans at least this many span widths from the line
+// centre (span centre to line centre) and clear of its core zone take the node weights of dL/dk.
+constexpr double kAdjFarSpans = 1.5;
+constexpr int kAdjSpansPerPass = kWave / kNodes;  // far spans per wave pass (one lane per node)
+
+// One far-span pass: lanes 16 q + k evaluate the profile polynomials of the set P at node k of
+// span s (lane-dependent), weighted by that span's node weight G of dL/dk over the line's points.
+template <int DV, int DA, int DG>
+__device__ __forceinline__ void adj_far(const AdjPoly& P, float G, float xoff, float xk, float dnh, float dh, float gh,
+                                        float& bV, float& bA, float& bG) {
+  const float D = __builtin_fmaf(xoff, dnh, __builtin_fmaf(xk, dnh, dh));
+  const float q = __builtin_amdgcn_rcpf(__builtin_fmaf(D, D, gh * gh));
+  const float gq = G * q;
+  bV = __builtin_fmaf(gq, adj_horner1<DV>(P.v, q), bV);
+  bA = __builtin_fmaf(gq, adj_horner1<DA>(P.da, q), bA);
+  bG = __builtin_fmaf(gq, adj_horner1<DG>(P.dg, q), bG);
+}
+
 __global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
   __shared__ AdjPoly sP[kWavesPerWG][3];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t nw = (int64_t)gridDim.x * kWavesPerWG;
   const PrepArgs& pa = a.pa;
+  // node position of this lane in its far span (node k = lane mod kNodes)
+  const int kn = lane & (kNodes - 1);
+  float xk = 0.0f;
+#pragma unroll
+  for (int k = 0; k < kNodes; ++k) xk = kn == k ? node_pos(kAdjSpan, kNodes, k) : xk;
   for (int64_t i = (int64_t)blockIdx.x * kWavesPerWG + wv; i < pa.N; i += nw) {
     const double* lr = a.lrec + 6 * i;
     const double gam = lr[1];
     const double nu0 = pa.nu[i];
     const double alpha = nu0 * pa.beta;
     const int4 gr = a.grec[i];
-    const int jref = gr.y, jlo = gr.z, jhi = gr.w;
+    const int jref = gr.y, jlo0 = gr.z, jhi0 = gr.w;
     double SVw = 0.0, SGw = 0.0, SAw = 0.0, SVc = 0.0, SGc = 0.0, SAc = 0.0;
     const double a2d = alpha * alpha, g2d = gam * gam;
     const double scd = a2d > g2d ? a2d : g2d;
-    if (jlo <= jhi && scd > 0.0) {
+    if (jlo0 <= jhi0 && scd > 0.0) {
       const float rs = (float)(1.0 / sqrt(scd));
       const float dh = __int_as_float(gr.x) * rs, dnh = (float)a.dnu * rs, gh = (float)gam * rs;
       // coefficient sets of this line: 3 terms (chunks of series order <= 2) and 6 terms
@@ -1903,6 +1953,58 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
       const double ia = 1.0 / alpha, y = gam / alpha;
       const double zc2 = (double)a.zK[kKmax - 1] * (double)a.zK[kKmax - 1];
       float bV = 0.f, bG = 0.f, bA = 0.f;
+      // spans sa..sb of the line's points: far on the left up to sL, far on the right from sR,
+      // direct in between (the direct spans are the ones near the centre and its core zone)
+      const int sa = jlo0 / kAdjSpan, sb = jhi0 / kAdjSpan;
+      const double reach = kAdjFarSpans * kAdjSpan, half = 0.5 * (kAdjSpan - 1);
+      int sL, sR;
+      {
+        const double l1 = floor((cpos - reach - half) / kAdjSpan);
+        const double l2 = floor(((double)zlo[kKmax - 1] - kAdjSpan) / kAdjSpan);
+        const double r1 = ceil((cpos + reach - half) / kAdjSpan);
+        const double r2 = floor((double)zhi[kKmax - 1] / kAdjSpan) + 1.0;
+        const double l = fmin(fmin(l1, l2), (double)sb), r = fmax(fmax(r1, r2), (double)sa);
+        sL = __builtin_amdgcn_readfirstlane(l < sa - 1.0 ? sa - 1 : (int)l);
+        sR = __builtin_amdgcn_readfirstlane(r > sb + 1.0 ? sb + 1 : (int)r);
+      }
+      const int nL = sL - sa + 1, nF = nL + (sb - sR + 1);
+      for (int fb = 0; fb < nF; fb += kAdjSpansPerPass) {
+        asm volatile("" ::: "memory");
+        const int f = fb + (lane >> 4);
+        const int fs = f < nF ? f : nF - 1;
+        const int s = fs < nL ? sa + fs : sR + (fs - nL);
+        const int s0 = s * kAdjSpan;
+        const int pa0 = (jlo0 > s0 ? jlo0 : s0) - s0, pb = (jhi0 < s0 + kAdjSpan - 1 ? jhi0 : s0 + kAdjSpan - 1) - s0;
+        const double* pr = a.gpref + ((int64_t)s * kNodes + kn) * kAdjSpan;
+        double Gd = pr[pb];
+        if (pa0 > 0) Gd -= pr[pa0 - 1];
+        const float G = f < nF ? (float)Gd : 0.0f;
+        // series terms for this group: as for a direct step over the group's spans
+        const int fl = fb + kAdjSpansPerPass - 1 < nF ? fb + kAdjSpansPerPass - 1 : nF - 1;
+        const int e0 = (fb < nL ? sa + fb : sR + (fb - nL)) * kAdjSpan;
+        const int e1 = (fl < nL ? sa + fl : sR + (fl - nL)) * kAdjSpan + kAdjSpan - 1;
+        int KD = 2;
+#pragma unroll
+        for (int z = 0; z < kKmax - 1; ++z) {
+          // a group may straddle the centre (left and right spans): test each side's range
+          const bool hitL = fb < nL && (sa + (fl < nL ? fl : nL - 1)) * kAdjSpan + kAdjSpan - 1 >= zlo[z] && e0 <= zhi[z];
+          const bool hitR = fl >= nL && e1 >= zlo[z] && (sR + (fb > nL ? fb - nL : 0)) * kAdjSpan <= zhi[z];
+          KD += (hitL || hitR) ? 1 : 0;
+        }
+        const float xoff = (float)(s0 - jref);
+        if (KD == 2) {
+          adj_far<3, 3, 4>(sP[wv][0], G, xoff, xk, dnh, dh, gh, bV, bA, bG);
+        } else if (KD == 3) {
+          adj_far<5, 5, 6>(sP[wv][1], G, xoff, xk, dnh, dh, gh, bV, bA, bG);
+        } else {
+          adj_far<kAdjDeg - 2, kAdjDeg - 2, kAdjDeg - 1>(sP[wv][2], G, xoff, xk, dnh, dh, gh, bV, bA, bG);
+        }
+        SVw += (double)bV; SGw += (double)bG; SAw += (double)bA;
+        bV = bG = bA = 0.f;
+      }
+      // direct points: the line's points in spans sL + 1 .. sR - 1
+      const int jlo = jlo0 > (sL + 1) * kAdjSpan ? jlo0 : (sL + 1) * kAdjSpan;
+      const int jhi = jhi0 < sR * kAdjSpan - 1 ? jhi0 : sR * kAdjSpan - 1;
       // steps of kAdjP x 64 points (kAdjP per lane); the next step's dL/dk is loaded ahead
       constexpr int kAdjP = 4, kStep = kAdjP * kWave;
       float gcur[kAdjP];
@@ -2219,6 +2321,11 @@ int far_max_blocks_per_cu() {
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_far<0>, kThreads, 0) != hipSuccess) return 1;
   return n > 0 ? n : 1;
+}
+
+hipError_t launch_adj_nodes(const float* g, int64_t n, const double* w, double* gpref, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_nodes, dim3(blocks_for(n, kAdjSpan)), dim3(kAdjSpan), 0, st, g, n, w, gpref);
+  return hipGetLastError();
 }
 
 hipError_t launch_adjoint(const AdjArgs& a, int grid, hipStream_t st) {
