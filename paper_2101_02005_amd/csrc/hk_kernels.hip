@@ -587,6 +587,25 @@ __device__ __forceinline__ double rcp64(double d) {
 // Re w(x + iy) by Weideman's rational series: w = 2 p(Z)/(L - iz)^2 + 1/(sqrt(pi)(L - iz)),
 // Z = (L + iz)/(L - iz), p(Z) = sum_n a_n Z^(n-1). The coefficients live in constant memory
 // and are read with scalar loads into SGPRs (the loop is fully unrolled).
+// p(Z) = sum_m a_m Z^m for the real coefficients a_m at the complex point Z, by the second-order
+// recurrence of division by the real quadratic Z^2 - r Z + s (r = 2 Re Z, s = |Z|^2) of which Z is
+// a root (Knuth, TAOCP vol. 2, Sec. 4.6.4): b_m = a_m + r b_(m+1) - s b_(m+2), p = a_0 - s b_2 +
+// Z b_1; two real FMAs per coefficient instead of four for complex Horner.
+static_assert(kWeidN >= 3, "the recurrence needs three coefficients");
+__device__ __forceinline__ void weideman_poly(double Zr, double Zi, double& pr, double& pi) {
+  const double r = 2.0 * Zr, s = fma(Zr, Zr, Zi * Zi);
+  double b2 = c_weid[kWeidN - 1];
+  double b1 = fma(r, b2, c_weid[kWeidN - 2]);
+#pragma unroll
+  for (int m = kWeidN - 3; m >= 1; --m) {
+    const double t = fma(r, b1, fma(-s, b2, c_weid[m]));
+    b2 = b1;
+    b1 = t;
+  }
+  pr = fma(Zr, b1, fma(-s, b2, c_weid[0]));
+  pi = Zi * b1;
+}
+
 __device__ __forceinline__ double weideman_re(double x, double y) {
   const double L = c_weidL;
   const double dr = L + y, di = -x;  // L - iz
@@ -594,13 +613,8 @@ __device__ __forceinline__ double weideman_re(double x, double y) {
   const double inv = rcp64(dr * dr + di * di);
   const double Zr = (nr * dr + ni * di) * inv;
   const double Zi = (ni * dr - nr * di) * inv;
-  double pr = c_weid[kWeidN - 1], pi = 0.0;
-#pragma unroll
-  for (int m = kWeidN - 2; m >= 0; --m) {
-    const double t = fma(pr, Zr, fma(-pi, Zi, c_weid[m]));
-    pi = fma(pr, Zi, pi * Zr);
-    pr = t;
-  }
+  double pr, pi;
+  weideman_poly(Zr, Zi, pr, pi);
   const double ur = dr * inv, ui = -di * inv;               // 1/(L - iz)
   const double vr = ur * ur - ui * ui, vi = 2.0 * ur * ui;  // 1/(L - iz)^2
   return 2.0 * (pr * vr - pi * vi) + 0.56418958354775628695 * ur;
@@ -1726,13 +1740,8 @@ __device__ __forceinline__ void weideman_w(double x, double y, double& K, double
   const double inv = rcp64(dr * dr + di * di);
   const double Zr = (nr * dr + ni * di) * inv;
   const double Zi = (ni * dr - nr * di) * inv;
-  double pr = c_weid[kWeidN - 1], pi = 0.0;
-#pragma unroll
-  for (int m = kWeidN - 2; m >= 0; --m) {
-    const double t = fma(pr, Zr, fma(-pi, Zi, c_weid[m]));
-    pi = fma(pr, Zi, pi * Zr);
-    pr = t;
-  }
+  double pr, pi;
+  weideman_poly(Zr, Zi, pr, pi);
   const double ur = dr * inv, ui = -di * inv;
   const double vr = ur * ur - ui * ui, vi = 2.0 * ur * ui;
   K = 2.0 * (pr * vr - pi * vi) + 0.56418958354775628695 * ur;
