@@ -609,15 +609,16 @@ __device__ __forceinline__ void weideman_poly(double Zr, double Zi, double& pr, 
 __device__ __forceinline__ double weideman_re(double x, double y) {
   const double L = c_weidL;
   const double dr = L + y, di = -x;  // L - iz
-  const double nr = L - y, ni = x;   // L + iz
-  const double inv = rcp64(dr * dr + di * di);
-  const double Zr = (nr * dr + ni * di) * inv;
-  const double Zi = (ni * dr - nr * di) * inv;
+  const double inv = rcp64(fma(dr, dr, di * di));
+  const double ur = dr * inv, ui = -di * inv;  // u = 1/(L - iz)
+  // Z = (L + iz)/(L - iz) = 2 L u - 1
+  const double Zr = fma(2.0 * L, ur, -1.0), Zi = 2.0 * L * ui;
   double pr, pi;
   weideman_poly(Zr, Zi, pr, pi);
-  const double ur = dr * inv, ui = -di * inv;               // 1/(L - iz)
-  const double vr = ur * ur - ui * ui, vi = 2.0 * ur * ui;  // 1/(L - iz)^2
-  return 2.0 * (pr * vr - pi * vi) + 0.56418958354775628695 * ur;
+  // Re(2 p u^2 + u/sqrt(pi)) = Re(u t), t = 2 p u + 1/sqrt(pi)
+  const double tr = 2.0 * fma(pr, ur, -pi * ui) + 0.56418958354775628695;
+  const double ti = 2.0 * fma(pr, ui, pi * ur);
+  return fma(ur, tr, -ui * ti);
 }
 
 // Per-line, per-grid record: the parts of a line's evaluation that depend on the grid but
@@ -1548,6 +1549,12 @@ __global__ __launch_bounds__(kThreads) void k_combine_far(FarArgs a) {
 template <int P>
 struct CoreLDS {
   float acc[kWave * P];
+  // the staged batch, one entry per line (lane): 1/alpha, offset of the reference point, y,
+  // tile-local point of the line's pair g minus g, tile-local reference point, amplitude
+  double ia[kWave], d64[kWave], y[kWave];
+  int off[kWave], jr[kWave];
+  float amp[kWave];
+  int mark[kWave];  // queue position -> line whose first pair of the current fill lands there
 };
 
 template <int P>
@@ -1676,35 +1683,49 @@ __global__ __launch_bounds__(kWave) void k_core(VoigtArgs a) {
         }
       }
       const int jrl = (int)((int64_t)jref - tile0);
-      // append each line's pairs in staging order
-      uint64_t m = __ballot(czl <= czh);
-      while (m) {
-        const int l = (int)__builtin_ctzll(m);
-        m &= m - 1ull;
-        int j0 = __builtin_amdgcn_readlane(czl, l);
-        const int j1 = __builtin_amdgcn_readlane(czh, l);
-        const int jr = __builtin_amdgcn_readlane(jrl, l);
-        const float amp = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lamp), l));
-        const double ia = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(lia), l),
-                                           __builtin_amdgcn_readlane(__double2loint(lia), l));
-        const double d64 = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(ld64), l),
-                                            __builtin_amdgcn_readlane(__double2loint(ld64), l));
-        const double yv = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(ly), l),
-                                           __builtin_amdgcn_readlane(__double2loint(ly), l));
-        while (j0 <= j1) {
-          const int take = (j1 - j0 + 1) < (kWave - qn) ? (j1 - j0 + 1) : (kWave - qn);
-          segs |= 1ull << qn;
-          if (lane >= qn && lane < qn + take) {
-            const int j = j0 + (lane - qn);
-            qj = j;
-            qx = ((double)(j - jr) * pd.dnu + d64) * ia;
-            qy = yv;
-            qa = amp;
-          }
-          qn += take;
-          j0 += take;
-          if (qn == kWave) run_round();
+      // the batch's pairs in staging order: line l (lane l) holds pairs excl .. incl - 1
+      const int nl = czl <= czh ? czh - czl + 1 : 0;
+      int incl = nl;
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) {
+        const int t = __shfl_up(incl, d, kWave);
+        if (lane >= d) incl += t;
+      }
+      const int T = __builtin_amdgcn_readlane(incl, kWave - 1);
+      if (T == 0) continue;
+      const int excl = incl - nl;
+      L.off[lane] = czl - excl;
+      L.jr[lane] = jrl;
+      L.amp[lane] = lamp;
+      L.ia[lane] = lia;
+      L.d64[lane] = ld64;
+      L.y[lane] = ly;
+      // fills: pairs g0 .. g0 + take - 1 go to queue positions qn .. qn + take - 1
+      for (int g0 = 0; g0 < T;) {
+        const int take = (T - g0) < (kWave - qn) ? (T - g0) : (kWave - qn);
+        // each line with pairs in the fill marks the position of its first one (a segment start;
+        // position qn always gets one). LDS operations of a wave stay in order; the accesses are
+        // volatile so that the compiler keeps every one of them (a lane reads marks that other
+        // lanes wrote, which it cannot see)
+        volatile __attribute__((address_space(3))) int* mark = (volatile __attribute__((address_space(3))) int*)L.mark;
+        mark[lane] = -1;
+        const int first = excl > g0 ? excl : g0;
+        if (nl > 0 && first < g0 + take && incl > g0) mark[first - g0 + qn] = lane;
+        const uint64_t starts = __ballot(mark[lane] >= 0);
+        segs |= starts;
+        if (lane >= qn && lane < qn + take) {
+          // this position's line: the one of the last start at or below it
+          const int sp = 63 - __builtin_clzll(starts & ((2ull << lane) - 1ull));
+          const int li = mark[sp];
+          const int j = g0 + (lane - qn) + L.off[li];
+          qj = j;
+          qx = ((double)(j - L.jr[li]) * pd.dnu + L.d64[li]) * L.ia[li];
+          qy = L.y[li];
+          qa = L.amp[li];
         }
+        qn += take;
+        g0 += take;
+        if (qn == kWave) run_round();
       }
     }
     if (qn > 0) run_round();
@@ -1736,13 +1757,11 @@ __global__ __launch_bounds__(kWave) void k_core(VoigtArgs a) {
 __device__ __forceinline__ void weideman_w(double x, double y, double& K, double& L) {
   const double Lw = c_weidL;
   const double dr = Lw + y, di = -x;
-  const double nr = Lw - y, ni = x;
-  const double inv = rcp64(dr * dr + di * di);
-  const double Zr = (nr * dr + ni * di) * inv;
-  const double Zi = (ni * dr - nr * di) * inv;
+  const double inv = rcp64(fma(dr, dr, di * di));
+  const double ur = dr * inv, ui = -di * inv;
+  const double Zr = fma(2.0 * Lw, ur, -1.0), Zi = 2.0 * Lw * ui;
   double pr, pi;
   weideman_poly(Zr, Zi, pr, pi);
-  const double ur = dr * inv, ui = -di * inv;
   const double vr = ur * ur - ui * ui, vi = 2.0 * ur * ui;
   K = 2.0 * (pr * vr - pi * vi) + 0.56418958354775628695 * ur;
   L = 2.0 * (pr * vi + pi * vr) + 0.56418958354775628695 * ui;
