@@ -71,14 +71,23 @@ __global__ __launch_bounds__(kThreads) void k_validate(const double* __restrict_
   if (threadIdx.x == 0) sbad = 0;
   unsigned long long lmin = ~0ull, lmax = 0ull;
   int bad = 0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    const double v = nu[i];
-    if (!((v > 0.0) && isfinite(v))) { bad = 1; continue; }
+  auto take = [&](double v) {
+    if (!((v > 0.0) && isfinite(v))) { bad = 1; return; }
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);  // v > 0: order-preserving
     lmin = b < lmin ? b : lmin;
     lmax = b > lmax ? b : lmax;
+  };
+  // grid-stride, four independent loads in flight per thread
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < N; i += 4 * stride) {
+    const double v0 = nu[i], v1 = nu[i + stride], v2 = nu[i + 2 * stride], v3 = nu[i + 3 * stride];
+    take(v0);
+    take(v1);
+    take(v2);
+    take(v3);
   }
+  for (; i < N; i += stride) take(nu[i]);
   smin[threadIdx.x] = lmin;
   smax[threadIdx.x] = lmax;
   __syncthreads();
