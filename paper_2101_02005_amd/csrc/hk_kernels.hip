@@ -139,9 +139,16 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint32_t* __restr
   cnt[threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortBlock;
+  uint32_t rkey[kSortItems];
+#pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
-    if (i < N) atomicAdd(&cnt[(kin[i] >> shift) & 255u], 1u);  // integer: order-independent
+    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
+    rkey[r] = i < N ? kin[i] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = base + (int64_t)r * kThreads + threadIdx.x;
+    if (i < N) atomicAdd(&cnt[(rkey[r] >> shift) & 255u], 1u);  // integer: order-independent
   }
   __syncthreads();
   hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = cnt[threadIdx.x];
@@ -221,11 +228,21 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint32_t* __re
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int64_t b0 = (int64_t)blockIdx.x * kSortBlock;
+  // every round's key and value are loaded up front (one memory latency, not one per round)
+  uint32_t rkey[kSortItems];
+  int32_t rval[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int64_t i = b0 + (int64_t)r * kThreads + tid;
+    rkey[r] = i < N ? kin[i] : 0u;
+    rval[r] = i < N ? vin[i] : 0;
+  }
+#pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const int64_t i = b0 + (int64_t)r * kThreads + tid;
     const bool valid = i < N;
-    const uint32_t key = valid ? kin[i] : 0u;
-    const int32_t val = valid ? vin[i] : 0;
+    const uint32_t key = rkey[r];
+    const int32_t val = rval[r];
     const uint32_t d = (key >> shift) & 255u;
     uint64_t peers = __ballot(valid);
     for (int bit = 0; bit < 8; ++bit) {
