@@ -124,8 +124,18 @@ hk_status hk_prepare_lines(const double* nu, const double* S_ref, const double* 
                            const hk_species* sp, hipStream_t stream, hk_lines** out);
 
 /* Release a handle; blocks until work issued through it on its preparation stream completes.
- * NULL is accepted. */
+ * NULL is accepted. The handle's device block goes to the library's block cache (see
+ * hk_empty_cache), not back to the driver. */
 hk_status hk_release_lines(hk_lines* lines);
+
+/* The library keeps the device blocks of released handles and of hk_prepare_lines' temporaries
+ * for reuse by later hk_prepare_lines calls of about the same size on the same device (at most
+ * 8 blocks and 128 GiB; the oldest go back first). Memory that another process freed can be
+ * cleared by the driver when it is allocated again, which would otherwise be paid on every
+ * prepare. A hipMalloc that fails empties the device's cache and is tried again. This call
+ * returns every cached block to the driver (all devices); HK_NO_CACHE=1 in the environment
+ * turns the cache off. Not to be called while another thread prepares or releases lines. */
+hk_status hk_empty_cache(void);
 
 /* Number of lines held by a handle (host). */
 int64_t hk_lines_count(const hk_lines* lines);

@@ -4,6 +4,6 @@ The computation lives in libhk.so (hand-written HIP, C ABI in include/hk.h); thi
 its Python binding. ``HkOpacityFn`` wraps the forward and backward calls for autograd."""
 from ._lib import (HK_EDEVICE, HK_EINVAL, HK_ENOMEM, HK_EUNSUPPORTED, HK_OK, Grid, HkError,  # noqa: F401
                    LineOverride, Lines, Species, grid, hk_debug_cut_bounds, hk_debug_line_params,
-                   hk_debug_sorted, hk_get_timings, hk_opacity, hk_opacity_backward, hk_opacity_batched,
+                   hk_debug_sorted, hk_empty_cache, hk_get_timings, hk_opacity, hk_opacity_backward, hk_opacity_batched,
                    hk_prepare_lines, hk_release_lines, hk_workspace_size, load, species)
 from .autograd import HkOpacityFn, opacity  # noqa: F401,E402

@@ -55,6 +55,7 @@ def load():
     sig = {
         "hk_prepare_lines": ([_vp, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(Species), _vp, ctypes.POINTER(_vp)], st),
         "hk_release_lines": ([_vp], st),
+        "hk_empty_cache": ([], st),
         "hk_lines_count": ([_vp], _i64),
         "hk_workspace_size": ([_vp, ctypes.c_int, _i32, _i32, ctypes.POINTER(Grid), _dbl, ctypes.POINTER(_sz)], st),
         "hk_opacity": ([_vp, ctypes.POINTER(LineOverride), _dbl, _dbl, Grid, _dbl, _vp, _vp, _sz, _vp], st),
@@ -141,6 +142,11 @@ def hk_prepare_lines(nu, S_ref, E_low, gamma_ref, n_exp, sp, stream=None):
 
 def hk_release_lines(lines):
     lines.release()
+
+
+def hk_empty_cache():
+    """Return the library's cached device blocks (released handles, binning temporaries)."""
+    _check(load().hk_empty_cache())
 
 
 def hk_workspace_size(lines, mode, grids, cutoff, n_temps=None):

@@ -27,6 +27,7 @@ struct hk_lines {
   uint32_t* keys;                       // sorted bin keys
   int32_t* perm;                        // sorted position -> caller index
   void* mem;
+  size_t mem_bytes;                     // size of the block mem (from the block cache)
 };
 
 namespace {
@@ -213,6 +214,110 @@ hk_status device_init(int* dev_out, DevInfo* info) {
 }
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Block cache for the library's own large device allocations (a line handle's arrays and the
+// binning temporaries). A released block is kept, per device, for a later request of about its
+// size instead of going back to the driver: memory another process freed can be cleared by the
+// driver when it is handed out again, which cost about 0.5 s per 48 GB handle. At most
+// kPoolMaxBlocks blocks and kPoolMaxBytes are kept (oldest returned first); a failed hipMalloc
+// empties the device's cache and tries again; HK_NO_CACHE=1 turns the cache off and
+// hk_empty_cache() returns every cached block. Blocks are cached only after the work that used
+// them has completed.
+struct PoolBlock {
+  int dev;
+  void* p;
+  size_t bytes;
+};
+std::mutex g_pool_mu;
+std::vector<PoolBlock> g_pool;  // oldest first
+constexpr size_t kPoolMaxBlocks = 8;
+constexpr size_t kPoolMaxBytes = size_t(128) << 30;
+
+void pool_return(const std::vector<PoolBlock>& blocks) {
+  if (blocks.empty()) return;
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  for (const PoolBlock& b : blocks) {
+    if (b.dev != cur) (void)hipSetDevice(b.dev);
+    (void)hipFree(b.p);
+    if (b.dev != cur && cur >= 0) (void)hipSetDevice(cur);
+  }
+}
+
+// Every cached block of device dev (all devices for dev < 0) back to the driver.
+void pool_drain(int dev) {
+  std::vector<PoolBlock> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (size_t i = 0; i < g_pool.size();) {
+      if (dev < 0 || g_pool[i].dev == dev) {
+        drop.push_back(g_pool[i]);
+        g_pool.erase(g_pool.begin() + (std::ptrdiff_t)i);
+      } else {
+        ++i;
+      }
+    }
+  }
+  pool_return(drop);
+}
+
+// A block of at least `bytes` on the current device dev: the smallest cached one that is no
+// more than a quarter (plus 64 MiB) larger, else a new one. *got receives its size.
+hipError_t pool_alloc(int dev, size_t bytes, void** p, size_t* got) {
+  *p = nullptr;
+  *got = 0;
+  if (!env_flag("HK_NO_CACHE", false)) {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    int best = -1;
+    for (size_t i = 0; i < g_pool.size(); ++i) {
+      const PoolBlock& b = g_pool[i];
+      if (b.dev == dev && b.bytes >= bytes && b.bytes - bytes <= bytes / 4 + (size_t(64) << 20) &&
+          (best < 0 || b.bytes < g_pool[(size_t)best].bytes))
+        best = (int)i;
+    }
+    if (best >= 0) {
+      *p = g_pool[(size_t)best].p;
+      *got = g_pool[(size_t)best].bytes;
+      g_pool.erase(g_pool.begin() + best);
+      return hipSuccess;
+    }
+  }
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    pool_drain(dev);
+    e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return e;
+    }
+  }
+  *got = bytes;
+  return hipSuccess;
+}
+
+// Returns a block whose work has completed to the cache (or to the driver without the cache).
+void pool_free(int dev, void* p, size_t bytes) {
+  if (!p) return;
+  if (env_flag("HK_NO_CACHE", false)) {
+    pool_return({PoolBlock{dev, p, bytes}});
+    return;
+  }
+  std::vector<PoolBlock> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    g_pool.push_back(PoolBlock{dev, p, bytes});
+    size_t total = 0;
+    for (const PoolBlock& b : g_pool) total += b.bytes;
+    while (g_pool.size() > kPoolMaxBlocks || total > kPoolMaxBytes) {
+      drop.push_back(g_pool.front());
+      total -= g_pool.front().bytes;
+      g_pool.erase(g_pool.begin());
+    }
+  }
+  pool_return(drop);
+}
 
 bool species_ok(const hk_species* sp) {
   return sp && std::isfinite(sp->mass_amu) && sp->mass_amu > 0 && std::isfinite(sp->T_ref) && sp->T_ref > 0 &&
@@ -763,13 +868,15 @@ hk_status hk_prepare_lines(const double* nu, const double* S_ref, const double* 
   L->sp = *sp;
   char* hm = nullptr;
   char* tmp = nullptr;
-  if (hipMalloc(&hm, hbytes) != hipSuccess) { (void)hipGetLastError(); return fail(HK_ENOMEM, "hipMalloc of %zu bytes failed", hbytes); }
-  if (hipMalloc(&tmp, tbytes) != hipSuccess) {
-    (void)hipGetLastError();
-    (void)hipFree(hm);
+  size_t hgot = 0, tgot = 0;
+  if (pool_alloc(dev, hbytes, reinterpret_cast<void**>(&hm), &hgot) != hipSuccess)
+    return fail(HK_ENOMEM, "hipMalloc of %zu bytes failed", hbytes);
+  if (pool_alloc(dev, tbytes, reinterpret_cast<void**>(&tmp), &tgot) != hipSuccess) {
+    pool_free(dev, hm, hgot);
     return fail(HK_ENOMEM, "hipMalloc of %zu bytes failed", tbytes);
   }
   L->mem = hm;
+  L->mem_bytes = hgot;
   L->nu = reinterpret_cast<double*>(hm + o_nu);
   L->Sref = reinterpret_cast<double*>(hm + o_S);
   L->E = reinterpret_cast<double*>(hm + o_E);
@@ -785,9 +892,12 @@ hk_status hk_prepare_lines(const double* nu, const double* S_ref, const double* 
   int* flags = reinterpret_cast<int*>(tmp + t_f);
   double* rec = reinterpret_cast<double*>(tmp + t_r);
   auto cleanup_fail = [&](hk_status st, const char* what, hipError_t e) {
-    (void)hipStreamSynchronize(stream);
-    (void)hipFree(tmp);
-    (void)hipFree(hm);
+    if (hipStreamSynchronize(stream) == hipSuccess) {
+      pool_free(dev, tmp, tgot);
+      pool_free(dev, hm, hgot);
+    } else {
+      (void)hipGetLastError();  // the blocks' work did not complete: leak them rather than reuse them
+    }
     return fail(st, "%s: %s", what, e == hipSuccess ? "" : hipGetErrorString(e));
   };
   hipError_t e = hk::launch_validate(nu, N, mm, flags, stream);
@@ -799,8 +909,8 @@ hk_status hk_prepare_lines(const double* nu, const double* S_ref, const double* 
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return cleanup_fail(HK_EDEVICE, "validate readback", e);
   if (hflag) {
-    (void)hipFree(tmp);
-    (void)hipFree(hm);
+    pool_free(dev, tmp, tgot);
+    pool_free(dev, hm, hgot);
     return fail(HK_EINVAL, "line data invalid: need nu > 0 and finite");
   }
   double vmin, vmax;
@@ -823,9 +933,9 @@ hk_status hk_prepare_lines(const double* nu, const double* S_ref, const double* 
   if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flags + 1, 4, hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return cleanup_fail(HK_EDEVICE, "binning", e);
-  (void)hipFree(tmp);
+  pool_free(dev, tmp, tgot);
   if (hflag) {
-    (void)hipFree(hm);
+    pool_free(dev, hm, hgot);
     return fail(HK_EINVAL, "line data invalid: need S_ref >= 0, gamma_ref >= 0, E, n finite");
   }
   g_tim.bin_ms = tm.ms(0);
@@ -853,11 +963,20 @@ hk_status hk_release_lines(hk_lines* lines) {
   (void)hipGetDevice(&cur);
   if (cur != lines->device) (void)hipSetDevice(lines->device);
   hipError_t e = hipDeviceSynchronize();
-  hipError_t f = hipFree(lines->mem);
+  hipError_t f = hipSuccess;
+  if (e == hipSuccess)
+    pool_free(lines->device, lines->mem, lines->mem_bytes);  // its work has completed: reusable
+  else
+    f = hipFree(lines->mem);
   if (cur >= 0 && cur != lines->device) (void)hipSetDevice(cur);
   delete lines;
   if (e != hipSuccess) return fail(HK_EDEVICE, "hipDeviceSynchronize: %s", hipGetErrorString(e));
   if (f != hipSuccess) return fail(HK_EDEVICE, "hipFree: %s", hipGetErrorString(f));
+  return HK_OK;
+}
+
+hk_status hk_empty_cache(void) {
+  pool_drain(-1);
   return HK_OK;
 }
 

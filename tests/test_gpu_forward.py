@@ -212,3 +212,18 @@ def test_autotuner_picks_a_candidate_and_keeps_parity(monkeypatch):
     ko = oracle_k(L, w.species_tuple(), w.T[0], w.P[0], w.nu_start, w.dnu, w.cut, np.arange(w.n_grid))
     assert rel_err(k2, ko) <= TOL_K
     lines.release()
+
+
+def test_block_cache_reuse_and_empty():
+    """A handle prepared into a cached block (released by an earlier handle of the same size)
+    gives the same opacity, and so does one prepared after the cache is emptied."""
+    import paper_2101_02005_amd as hk
+    w, L = workload_lines("c1")
+    ks = []
+    for i in range(3):
+        if i == 2:
+            hk.hk_empty_cache()
+        lines = prepare(L, w.species_tuple())
+        ks.append(gpu_k(lines, w.T[0], w.P[0], w.nu_start, w.dnu, w.n_grid, w.cut))
+        lines.release()
+    assert np.array_equal(ks[0], ks[1]) and np.array_equal(ks[0], ks[2])
