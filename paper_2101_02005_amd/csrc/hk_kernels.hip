@@ -792,6 +792,15 @@ __device__ __forceinline__ uint32_t stage_span_line(WaveLDS& L, int lane, const 
   const float c = (float)jt - delta * inv_dnu;
   const int clo = (int)((int64_t)jlo - span0 < -1 ? -1 : (int64_t)jlo - span0);
   const int chi = (int)((int64_t)jhi - span0 > W ? W : (int64_t)jhi - span0);
+  // zone half-widths, once per line (the hardware square root: the bounds carry a relative slack
+  // of 1e-5 and only choose how many series terms the span's points get)
+  float hz[kKmax - 1];
+#pragma unroll
+  for (int z = 0; z < kKmax - 1; ++z) {
+    const float zz = zK[z] * af;
+    const float h2 = zz * zz - gf * gf;
+    hz[z] = h2 > 0.0f ? __builtin_amdgcn_sqrtf(h2) * 1.00001f + 1e-3f : -1.0f;
+  }
   uint32_t K = 1u;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
@@ -799,12 +808,7 @@ __device__ __forceinline__ uint32_t stage_span_line(WaveLDS& L, int lane, const 
     if (s1 < clo || s0 > chi) continue;
     uint32_t path = 1u;
 #pragma unroll
-    for (int z = 0; z < kKmax - 1; ++z) {
-      const float zz = zK[z] * af;
-      const float h2 = zz * zz - gf * gf;
-      const float h = h2 > 0.0f ? sqrtf(h2) * 1.00001f + 1e-3f : -1.0f;
-      path += ((float)s0 < c + h && (float)s1 > c - h) ? 1u : 0u;
-    }
+    for (int z = 0; z < kKmax - 1; ++z) path += ((float)s0 < c + hz[z] && (float)s1 > c - hz[z]) ? 1u : 0u;
     K = path > K ? path : K;
   }
   // core points: strictly inside the last zone, and within the cut range
@@ -1065,19 +1069,63 @@ __device__ __forceinline__ void far_accumulate(const NS& xs, const FarLine& f, f
   else far_nodes<5, 0, NN, NS, NN>(xs, f, acc);
 }
 
-// Adds the wave's node sums (a butterfly over the lanes in FP64, the same on every lane) to
-// node[k] (lane k) and clears the lanes' FP32 sums; every 16 lines per lane at most, so that
-// the FP32 sums stay short.
+// Adds the wave's node sums to node[k] (in a fixed order) and clears the lanes' FP32 sums; every
+// 16 lines per lane at most, so that the FP32 sums stay short. A reduce-scatter by recursive
+// halving over the lane bits 5, 4, ...: in the step on bit b a lane keeps the half of its node
+// values selected by its bit b and adds its partner's (lane ^ 2^b) copy of that half; after
+// log2(NN) steps lane L holds the sum, over the lanes that differ from it in those bits, of node
+// L >> (6 - log2(NN)); butterflies over the remaining bits complete it over the wave.
+// The steps on bits 5, 4, 3 (sums of 8 lanes' values) are FP32, in place, without LDS: for the
+// pair (x = acc[i], y = acc[h + i]), gfx950's permlane32_swap exchanges the upper 32 lanes of x
+// with the lower 32 lanes of y, after which x + y is node i's pair sum in the lower half of the
+// wave and node h + i's in the upper half; permlane16_swap does the same for odd and even 16-lane
+// rows; bit 3 uses a rotation by 8 within the 16-lane rows (lane ^ 8). The rest is FP64: three
+// exchanges of doubles for 8 or 16 nodes (6 NN with one butterfly per node).
 template <int NN>
 __device__ __forceinline__ void far_flush(float (&acc)[NN], int lane, double* node) {
-  double mine = 0.0;
+  static_assert(NN >= 8 && NN <= kWave && (NN & (NN - 1)) == 0, "node count: a power of two, 8 to 64");
 #pragma unroll
-  for (int k = 0; k < NN; ++k) {
-    const double t = wave_sum64((double)acc[k]);
-    mine = lane == k ? t : mine;
-    acc[k] = 0.0f;
+  for (int i = 0; i < NN / 2; ++i) {  // lane bit 5
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc[i]), __float_as_uint(acc[NN / 2 + i]), false,
+                                                    false);
+    acc[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
   }
-  if (lane < NN) node[lane] += mine;
+#pragma unroll
+  for (int i = 0; i < NN / 4; ++i) {  // lane bit 4
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(acc[i]), __float_as_uint(acc[NN / 4 + i]), false,
+                                                    false);
+    acc[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  {
+    const bool up = (lane >> 3) & 1;  // lane bit 3: row rotation by 8 (DPP row_ror:8)
+#pragma unroll
+    for (int i = 0; i < NN / 8; ++i) {
+      const float send = up ? acc[i] : acc[NN / 8 + i];
+      const float keep = up ? acc[NN / 8 + i] : acc[i];
+      acc[i] = keep + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(send), 0x128, 0xf, 0xf, false));
+    }
+  }
+  constexpr int F = NN / 8;  // values per lane from here on, FP64
+  double v[F];
+#pragma unroll
+  for (int k = 0; k < F; ++k) v[k] = (double)acc[k];
+#pragma unroll
+  for (int k = 0; k < NN; ++k) acc[k] = 0.0f;
+  int bit = 2;
+#pragma unroll
+  for (int h = F / 2; h >= 1; h >>= 1, --bit) {
+    const bool up = (lane >> bit) & 1;
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      const double send = up ? v[i] : v[h + i];
+      const double keep = up ? v[h + i] : v[i];
+      v[i] = keep + __shfl_xor(send, 1 << bit, kWave);
+    }
+  }
+#pragma unroll
+  for (; bit >= 0; --bit) v[0] += __shfl_xor(v[0], 1 << bit, kWave);
+  constexpr int lo = 6 - __builtin_ctz(NN);  // lane bits below the node index
+  if ((lane & ((1 << lo) - 1)) == 0) node[lane >> lo] += v[0];
 }
 
 __device__ __forceinline__ float wave_sum64f(float v) {
@@ -1086,24 +1134,49 @@ __device__ __forceinline__ float wave_sum64f(float v) {
   return v;
 }
 
-__device__ __forceinline__ double half_sum32(double v) {
-#pragma unroll
-  for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 // The same for the middle-distance segments: lane half h holds node j (h = 0) or 31 - j (h = 1)
 // in acc[j]; the sums are over the 32 lanes of each half.
+// By the reduce-scatter of far_flush within each 32-lane half (bits 4, 3 in FP32, then FP64):
+// lane 2 j of the lower half ends with node j, of the upper half with node 31 - j.
 __device__ __forceinline__ void mid_flush(float (&acc)[kNodes], int lane, double* node) {
-  double mine = 0.0;
-  const int j = lane & 31;
+  static_assert(kNodes == 16 && kMidNodes == 32, "two 16-value halves");
 #pragma unroll
-  for (int k = 0; k < kNodes; ++k) {
-    const double t = half_sum32((double)acc[k]);
-    mine = j == k ? t : mine;
-    acc[k] = 0.0f;
+  for (int i = 0; i < 8; ++i) {  // lane bit 4: odd and even 16-lane rows of each half
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(acc[i]), __float_as_uint(acc[8 + i]), false, false);
+    acc[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
   }
-  if (j < kNodes) node[lane < 32 ? j : kMidNodes - 1 - j] += mine;
+  {
+    const bool up = (lane >> 3) & 1;  // lane bit 3: row rotation by 8
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float send = up ? acc[i] : acc[4 + i];
+      const float keep = up ? acc[4 + i] : acc[i];
+      acc[i] = keep + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(send), 0x128, 0xf, 0xf, false));
+    }
+  }
+  double v[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = (double)acc[k];
+#pragma unroll
+  for (int k = 0; k < kNodes; ++k) acc[k] = 0.0f;
+  {
+    const bool up = (lane >> 2) & 1;  // lane bit 2
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double send = up ? v[i] : v[2 + i];
+      const double keep = up ? v[2 + i] : v[i];
+      v[i] = keep + __shfl_xor(send, 4, kWave);
+    }
+  }
+  {
+    const bool up = (lane >> 1) & 1;  // lane bit 1
+    const double send = up ? v[0] : v[1];
+    const double keep = up ? v[1] : v[0];
+    v[0] = keep + __shfl_xor(send, 2, kWave);
+  }
+  v[0] += __shfl_xor(v[0], 1, kWave);  // lane bit 0
+  const int j = (lane >> 1) & 15;
+  if ((lane & 1) == 0) node[lane < 32 ? j : kMidNodes - 1 - j] += v[0];
 }
 
 // One far segment of a span of S points: lines [i0, i1), one per lane, at its NN nodes; the
