@@ -1336,7 +1336,7 @@ __device__ __forceinline__ void masked_segment(const VoigtArgs& a, const PairDes
 // A span with one item writes k; otherwise each item writes its partial span and k_combine
 // sums them in item order. No workgroup barrier: waves run independently.
 template <int P>
-__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P <= 4 ? 5 : 4))) void k_wing(VoigtArgs a) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P <= 4 ? 6 : 4))) void k_wing(VoigtArgs a) {
   constexpr int W = kWave * P;  // span width in grid points
   __shared__ WaveLDS L;
   const int lane = threadIdx.x;
