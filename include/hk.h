@@ -134,7 +134,8 @@ hk_status hk_release_lines(hk_lines* lines);
  * cleared by the driver when it is allocated again, which would otherwise be paid on every
  * prepare. A hipMalloc that fails empties the device's cache and is tried again. This call
  * returns every cached block to the driver (all devices); HK_NO_CACHE=1 in the environment
- * turns the cache off. Not to be called while another thread prepares or releases lines. */
+ * turns the cache off. The cache is shared by all threads and holds only blocks whose work has
+ * completed, so this call is safe at any time. Returns HK_OK. */
 hk_status hk_empty_cache(void);
 
 /* Number of lines held by a handle (host). */
