@@ -1672,7 +1672,7 @@ __device__ __forceinline__ void core_round(CoreLDS<P>& L, int lane, int qn, uint
 }
 
 template <int P>
-__global__ __launch_bounds__(kWave) void k_core(VoigtArgs a) {
+__global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 8 : (P == 1 ? 7 : (P == 4 ? 6 : 5))))) void k_core(VoigtArgs a) {
   constexpr int W = kWave * P;  // core tile width in grid points
   __shared__ CoreLDS<P> L;
   const int lane = threadIdx.x;
