@@ -6,7 +6,7 @@
  *
  *   k(nu_j) = sum over lines i with |nu_j - nu_i| <= cut of S_i(T) V(nu_j - nu_i; alpha_i, gamma_i)
  *
- *   S_i(T)  line strength at T: eq. (S) in the form of eq. (S1) (Sec. 2.2.3, Sec. 2.4.3
+ *   S_i(T)  line strength at T: eq. (S) in the form of eq. (S1) (Sec. 2.2.2, Sec. 2.4.3
  *           step 1); from the strength S_ref at T_ref it is
  *           S_ref Q(T_ref)/Q(T) exp(c2 E''(1/T_ref - 1/T)) (1 - e^{-c2 nu/T})/(1 - e^{-c2 nu/T_ref}),
  *           with Q(T) = q_a T^q_b and c2 = h c / k_B.
@@ -15,7 +15,7 @@
  *   gamma_i Lorentz half-width, ExoMol form of Sec. 2.2 without the natural term:
  *           gamma = gamma_ref (T_ref/T)^n (P/P_ref).
  *   V       unit-area Voigt profile Re w((d + i gamma)/alpha) / (sqrt(pi) alpha), w the
- *           Faddeeva function (Sec. 2.2.4, Sec. 2.4.2 parameters x and y).
+ *           Faddeeva function (Sec. 2.2.3, Sec. 2.4.2 parameters x and y).
  *   grid    nu_j = nu_start + j dnu, 0 <= j < n (uniform resolution, Sec. 2.4.2 eq. x).
  *   cut     fixed cutting length in cm^-1, inclusive (Sec. 2.4.3 step 4); +INFINITY: none.
  *
@@ -168,7 +168,7 @@ hk_status hk_opacity(const hk_lines* lines, const hk_line_override* ovr, double 
 
 /*
  * hk_opacity_batched -- k for many (T, P) pairs in one persistent launch (the paper's
- * several pressures per run, Sec. 2.4.5 and Table timing2, extended to temperatures).
+ * several pressures per run, Sec. 2.4.6 and Table timing2, extended to temperatures).
  *   n_pairs >= 1; T, P_atm : host float64[n_pairs]; grids : host hk_grid[n_pairs] (may
  *   differ per pair); out_offset : host int64[n_pairs], pair p writes
  *   k[out_offset[p] .. out_offset[p] + grids[p].n). Output ranges must not overlap.

@@ -1,6 +1,6 @@
 """The five workloads: synthetic line lists shaped like the paper's (input recipe).
 
-The paper's timings (Sec. 4, Tables timing0-timing2) use the ExoMol BT2 water list, which
+The paper's timings (Sec. 3.5, Tables timing0-timing2) use the ExoMol BT2 water list, which
 is not available here; the large list below is a synthetic stand-in with the same
 wavenumber range and a density rising toward the infrared. All fields are drawn by
 ``linegen_core.h``; S_ref follows the "scale reading": the drawn log10 value s is the

@@ -7,7 +7,7 @@ The arithmetic lives in ``oracle.c`` (plain C, IEEE double, OpenMP over output p
 this module only builds that file with gcc and marshals numpy arrays through ctypes.
 Definitions followed (see the header of oracle.c for the full list):
 
-* S(T): Sec. 2.2.3 eq. (S) in the form of eq. (S1) with S' (Sec. 2.4.3, step 1).
+* S(T): Sec. 2.2.2 eq. (S) in the form of eq. (S1) with S' (Sec. 2.4.3, step 1).
 * alpha: inverse of eq. (alphaD); gamma: the ExoMol Lorentz width of Sec. 2.2 without
   the natural-broadening term.
 * V = Re w(x+iy)/(sqrt(pi) alpha), x, y as in Sec. 2.4.2.

@@ -9,7 +9,7 @@
  * What it computes (plain definitions, slow and direct, all in IEEE double,
  * compiled with -ffp-contract=off):
  *
- *   line strength   S_i(T)  : Sec. 2.2.3 "Line intensity", eq. (S) rewritten as
+ *   line strength   S_i(T)  : Sec. 2.2.2 "Line intensity", eq. (S) rewritten as
  *                             eq. (S1) with the temperature-independent S'
  *                             (Sec. 2.4.3, step 1). S' is recovered from the
  *                             input strength at the reference temperature.
@@ -186,8 +186,11 @@ static double or_strength(const or_species* sp, double T, double nu0, double Sre
     const double Sprime = Sref * or_Q(sp, sp->T_ref) * exp(bexp_ref) / stim_ref;
     return Sprime / or_Q(sp, T) * exp(-c2 * E / T) * stim;
   }
-  /* exp(c2 E''/T_ref) would overflow: the same product with the exponents combined */
-  return Sref * (or_Q(sp, sp->T_ref) / or_Q(sp, T)) * exp(c2 * E * (1.0 / sp->T_ref - 1.0 / T)) *
+  /* exp(c2 E''/T_ref) would overflow: the same product with the exponents combined, and with
+   * S_ref inside the exponential, since exp(c2 E'' (1/T_ref - 1/T)) alone can still overflow
+   * while S(T) itself is representable */
+  if (!(Sref > 0.0)) return 0.0;
+  return exp(log(Sref) + c2 * E * (1.0 / sp->T_ref - 1.0 / T)) * (or_Q(sp, sp->T_ref) / or_Q(sp, T)) *
          (stim / stim_ref);
 }
 

@@ -1,7 +1,7 @@
 """Pins of the oracle's FP64 Faddeeva function w(z) = exp(-z^2) erfc(-iz) against
 independent references: scipy's wofz (a different implementation), mpmath at 30 digits,
 and closed forms on the axes and at infinity. The paper itself checks its Voigt code
-against scipy.special.wofz over the a-u plane (Sec. 2.2.4, figure of fractional errors)."""
+against scipy.special.wofz over the a-u plane (Sec. 2.2.3, figure of fractional errors)."""
 import mpmath
 import numpy as np
 import pytest

@@ -1,4 +1,4 @@
-"""Pins of the oracle's per-line quantities: strength S(T) (Sec. 2.2.3 eqs. S, S1), Doppler
+"""Pins of the oracle's per-line quantities: strength S(T) (Sec. 2.2.2 eqs. S, S1), Doppler
 width (eqs. gammaD/alphaD) and ExoMol Lorentz width (Sec. 2.2)."""
 import mpmath
 import numpy as np
@@ -79,3 +79,33 @@ def test_lorentz_width_scalings():
     _, _, g1 = oracle.line_params(L, sp, 500.0, 1.0)
     _, _, g2 = oracle.line_params(L, sp, 1500.0, 1.0)
     assert np.max(np.abs(g1 / g2 - 3.0 ** L["n"])) < 1e-13
+
+
+def test_strength_high_lower_state_energy_branch():
+    """Lines with c2 E''/T_ref >= 700 (E'' above about 1.44e5 cm^-1 at 296 K) take the oracle's
+    combined-exponent form, since exp(c2 E''/T_ref) alone would overflow. Pinned against eq. (S)
+    per molecule evaluated in mpmath from synthetic A, g' (the input S_ref being that expression
+    at T_ref, rounded to double), across the switch between the two forms."""
+    mpmath.mp.dps = 50
+    c2 = mpmath.mpf(H) * mpmath.mpf(C) / mpmath.mpf(KB)
+    sp = oracle.species(18.0, 296.0, 1.0, 0.05, 1.5)
+    Q = lambda T: mpmath.mpf(0.05) * mpmath.mpf(T) ** mpmath.mpf(1.5)
+
+    def S_eq(Agp, nu, E, T):
+        T = mpmath.mpf(T)
+        return (Agp / (8 * mpmath.pi * C * nu ** 2 * Q(T)) * mpmath.exp(-c2 * E / T)
+                * (1 - mpmath.exp(-c2 * nu / T)))
+
+    E_switch = 700.0 * 296.0 / float(c2)
+    energies = [E_switch * (1 - 1e-9), E_switch * (1 + 1e-9), 1.5e5, 1.8e5, 2.0e5]
+    for E in energies:
+        for nu in (0.5, 2000.0, 25000.0):
+            # A g' chosen so that S_ref stays a normal double however small exp(-c2 E''/T_ref) is
+            Agp = mpmath.mpf(10) ** (int(float(c2) * E / 296.0 / mpmath.log(10)) - 270) * nu ** 2
+            sref = S_eq(Agp, mpmath.mpf(nu), mpmath.mpf(E), 296.0)
+            assert 1e-300 < float(sref) < 1e300
+            L = {"nu": [nu], "S_ref": [float(sref)], "E": [E], "gamma_ref": [0.05], "n": [0.5]}
+            for T in (500.0, 3000.0, 10000.0):
+                S, _, _ = oracle.line_params(L, sp, T, 1.0)
+                ref = S_eq(Agp, mpmath.mpf(nu), mpmath.mpf(E), T) * (mpmath.mpf(float(sref)) / sref)
+                assert abs(S[0] / float(ref) - 1) < 2e-13, (E, nu, T, S[0], float(ref))

@@ -78,3 +78,35 @@ def test_literal_and_scale_readings_small_config():
         L = linegen.generate(w.recipe(s_reading=reading), w.seed, w.N)
         k = oracle.opacity(L, sp, w.T[0], w.P[0], w.nu_start, w.dnu, w.cut, pts)
         assert np.all(np.isfinite(k)) and k.max() > 0
+
+
+def test_line_functional_sums_to_weighted_opacity():
+    """sum_i L_i = sum_j g_j k_j: the per-line functional (a loop over each line's cut range)
+    against the per-point sum (a loop over each point's lines), on tiny lists and three cuts."""
+    rng = np.random.default_rng(12)
+    sp = oracle.species(18.0, 296.0, 1.0, 0.05, 1.5)
+    for T, P, cut in [(700.0, 0.5, 1.5), (2000.0, 10.0, 0.2), (300.0, 1e-4, np.inf)]:
+        L = _tiny(rng, 25, 50.0, 60.0)
+        n = 1500
+        g = rng.standard_normal(n)
+        Li = oracle.line_functional(L, sp, T, P, 49.0, 0.008, n, cut, g)
+        k = oracle.opacity(L, sp, T, P, 49.0, 0.008, cut, np.arange(n))
+        ref = float(np.dot(g, k))
+        assert abs(Li.sum() - ref) <= 1e-13 * float(np.dot(np.abs(g), k)), (T, P, cut, Li.sum(), ref)
+
+
+def test_line_functional_per_line_brute_force():
+    """L_i = sum over the line's cut range of g_j S_i V_ij with scipy's wofz, line by line."""
+    rng = np.random.default_rng(13)
+    sp = oracle.species(18.0, 296.0, 1.0, 0.05, 1.5)
+    L = _tiny(rng, 12, 20.0, 22.0)
+    T, P, cut, nu0, dnu, n = 900.0, 2.0, 0.6, 19.5, 0.004, 800
+    g = rng.standard_normal(n)
+    Li = oracle.line_functional(L, sp, T, P, nu0, dnu, n, cut, g)
+    S, a, gam = oracle.line_params(L, sp, T, P)
+    nuj = nu0 + np.arange(n) * dnu
+    for i in range(12):
+        d = nuj - L["nu"][i]
+        V = sc.wofz((d + 1j * gam[i]) / a[i]).real / (np.sqrt(np.pi) * a[i])
+        ref = float(np.sum(np.where(np.abs(d) <= cut, g * S[i] * V, 0.0)))
+        assert abs(Li[i] - ref) <= 1e-12 * float(np.sum(np.abs(g) * S[i] * V)), (i, Li[i], ref)
