@@ -64,7 +64,15 @@ def _load():
         lib.or_count_evals.restype = ctypes.c_int64
         lib.or_jranges.argtypes = [i64, _D, dbl, dbl, i64, dbl, _I64, _I64]
         lib.or_num_threads.restype = ctypes.c_int
-        lib.or_voigt_derivs_arr.argtypes = [i64, _D, _D, _D, _D, _D]
+        lib.or_voigt_derivs_arr.argtypes = [i64, _D, _D, _D, _D, _D, _D]
+        ci = ctypes.c_int
+        lib.or_opacity_ex.argtypes = [i64, _D, _D, _D, _D, _D, sp, dbl, dbl, dbl, dbl, dbl, ci, ci, ci, i64,
+                                      _I64, _D]
+        lib.or_opacity_ex.restype = ctypes.c_int
+        lib.or_gradient_ex.argtypes = [i64, _D, _D, _D, _D, _D, sp, dbl, dbl, dbl, dbl, i64, dbl, ci, ci, _D,
+                                       i64, _I64, _D, _D, _D, _D, _D, _D, _D, _D]
+        lib.or_gradient_ex.restype = ctypes.c_int
+        lib.or_cut_lengths.argtypes = [i64, _D, _D, _D, sp, dbl, dbl, ci, dbl, _D]
         lib.or_set_gauss_hermite.argtypes = [ctypes.c_int, _D, _D]
         lib.or_set_gauss_hermite.restype = ctypes.c_int
         t, w = np.polynomial.hermite.hermgauss(GH_NODES)
@@ -113,14 +121,14 @@ def voigt(delta, alpha, gamma):
     return out
 
 
-def voigt_derivs(delta, alpha, gamma):
-    """(dV/dgamma, dV/dalpha) of the unit-area Voigt profile (closed form near the centre,
-    Gauss-Hermite quadrature of the convolution integral for |z| >= 10)."""
+def voigt_derivs(delta, alpha, gamma, with_delta=False):
+    """(dV/dgamma, dV/dalpha[, dV/ddelta]) of the unit-area Voigt profile (closed form near the
+    centre, Gauss-Hermite quadrature of the convolution integral for |z| >= 10)."""
     d, a, g = np.broadcast_arrays(_d(delta), _d(alpha), _d(gamma))
     d, a, g = _d(d).ravel(), _d(a).ravel(), _d(g).ravel()
-    dg, da = np.empty_like(d), np.empty_like(d)
-    _load().or_voigt_derivs_arr(d.size, _p(d), _p(a), _p(g), _p(dg), _p(da))
-    return dg, da
+    dg, da, dd = np.empty_like(d), np.empty_like(d), np.empty_like(d)
+    _load().or_voigt_derivs_arr(d.size, _p(d), _p(a), _p(g), _p(dg), _p(da), _p(dd))
+    return (dg, da, dd) if with_delta else (dg, da)
 
 
 def line_params(lines, sp, T, P):
@@ -185,3 +193,47 @@ def jranges(nu, nu_start, dnu, n_grid, cut):
     j0, j1 = np.empty(nu.size, np.int64), np.empty(nu.size, np.int64)
     _load().or_jranges(nu.size, _p(nu), nu_start, dnu, n_grid, cut, _pi(j0), _pi(j1))
     return j0, j1
+
+
+# Options of the extended forward (profiles of Sec. 2.1, plinth of Sec. 2.1.1, cut modes of
+# Sec. 2.4.3 step 4): the same codes as the library's options.
+PROFILE_VOIGT, PROFILE_LORENTZ, PROFILE_DOPPLER, PROFILE_BINNED_GAUSS = 0, 1, 2, 3
+CUT_FIXED, CUT_DOPPLER, CUT_LORENTZ = 0, 1, 2
+
+
+def opacity_ex(lines, sp, T, P, nu_start, dnu, cut, pts, cut_mode=CUT_FIXED, profile=PROFILE_VOIGT, plinth=False):
+    """FP64 k at the grid indices ``pts`` with a line profile, a cut mode (cut is then a multiple of
+    the Doppler or Lorentz half-width) and optional plinth removal."""
+    nu, S, E, g, n = (_d(lines[k]) for k in ("nu", "S_ref", "E", "gamma_ref", "n"))
+    pts = np.ascontiguousarray(pts, dtype=np.int64)
+    out = np.empty(pts.size)
+    rc = _load().or_opacity_ex(nu.size, _p(nu), _p(S), _p(E), _p(g), _p(n), ctypes.byref(sp), T, P,
+                               nu_start, dnu, cut, int(cut_mode), int(profile), int(bool(plinth)), pts.size,
+                               _pi(pts), _p(out))
+    if rc != 0:
+        raise ValueError("or_opacity_ex: invalid arguments (%d)" % rc)
+    return out
+
+
+def gradient_ex(lines, sp, T, P, nu_start, dnu, n_grid, cut, g, cut_mode=CUT_FIXED, plinth=False, sel=None):
+    """As gradient(), for the Voigt profile with a cut mode and optional plinth removal."""
+    nu, S, E, gr, n = (_d(lines[k]) for k in ("nu", "S_ref", "E", "gamma_ref", "n"))
+    gg = _d(g)
+    assert gg.size == n_grid
+    sel = np.arange(nu.size, dtype=np.int64) if sel is None else np.ascontiguousarray(sel, dtype=np.int64)
+    names = ("GS", "Gg", "Ga", "dS_ref", "dgamma_ref", "dn", "dT_part", "dlnP_part")
+    out = {k: np.empty(sel.size) for k in names}
+    rc = _load().or_gradient_ex(nu.size, _p(nu), _p(S), _p(E), _p(gr), _p(n), ctypes.byref(sp), T, P,
+                                nu_start, dnu, n_grid, cut, int(cut_mode), int(bool(plinth)), _p(gg), sel.size,
+                                _pi(sel), *[_p(out[k]) for k in names])
+    if rc != 0:
+        raise ValueError("or_gradient_ex: invalid arguments (%d)" % rc)
+    return out
+
+
+def cut_lengths(lines, sp, T, P, cut_mode, cut):
+    """Per-line cutting length at (T, P) in cm^-1."""
+    nu, g, n = (_d(lines[k]) for k in ("nu", "gamma_ref", "n"))
+    out = np.empty(nu.size)
+    _load().or_cut_lengths(nu.size, _p(nu), _p(g), _p(n), ctypes.byref(sp), T, P, int(cut_mode), cut, _p(out))
+    return out

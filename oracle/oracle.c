@@ -26,6 +26,12 @@
  *   opacity         k_j     : sum over lines with |nu_j - nu_i| <= cut of
  *                             S_i V(nu_j - nu_i) (Sec. 2.4.3 step 4, fixed
  *                             cutting length), grid nu_j = nu_start + j dnu.
+ *   options (or_opacity_ex) : the four line profiles of Sec. 2.1 (Voigt, Lorentz,
+ *                             Doppler, binned Gaussian integrated cross section),
+ *                             plinth removal (Sec. 2.1.1: the line's own value at its
+ *                             cutting length subtracted inside the cut), and the cut
+ *                             as a fixed length or a multiple of the Doppler or the
+ *                             Lorentz half-width (Sec. 2.4.3 step 4, Sec. 2.4.5).
  *   gradient                : analytic adjoint of k (no counterpart in the paper):
  *                             profile derivatives from w'(z) = -2 z w(z) + 2i/sqrt(pi)
  *                             for |z| < 10, and by Gauss-Hermite quadrature of the
@@ -253,7 +259,8 @@ int or_set_gauss_hermite(int n, const double* t, const double* w) {
  * quadrature (the integrand is analytic in |t| < |z|, so the rule converges geometrically):
  *   dV/dgamma = pi^-1/2 sum_k w_k (x_k^2 - gamma^2) / (pi (x_k^2 + gamma^2)^2),
  *   dV/dalpha = pi^-1/2 sum_k w_k t_k 2 gamma x_k / (pi (x_k^2 + gamma^2)^2),  x_k = delta - alpha t_k. */
-static void or_voigt_derivs(double delta, double alpha, double gamma, double* dVdg, double* dVda) {
+static void or_voigt_derivs3(double delta, double alpha, double gamma, double* dVdg, double* dVda,
+                             double* dVdd) {
   const double x = delta / alpha, y = gamma / alpha;
   if (x * x + y * y < OR_DERIV_ZQUAD * OR_DERIV_ZQUAD || or_gh_n == 0) {
     double K, L;
@@ -263,24 +270,37 @@ static void or_voigt_derivs(double delta, double alpha, double gamma, double* dV
     const double den = OR_SQRT_PI * alpha * alpha;
     *dVdg = Ky / den;
     *dVda = -(K + x * Kx + y * Ky) / den;
+    *dVdd = Kx / den;
     return;
   }
-  double sg = 0.0, sa = 0.0;
+  /* d/d(delta) of the Lorentzian under the integral: -2 gamma x_k / (pi (x_k^2 + gamma^2)^2) */
+  double sg = 0.0, sa = 0.0, sd = 0.0;
   for (int k = 0; k < or_gh_n; ++k) {
     const double xk = delta - alpha * or_gh_t[k];
     const double d = xk * xk + gamma * gamma;
     const double inv = 1.0 / (OR_PI * d * d);
     sg += or_gh_w[k] * (xk * xk - gamma * gamma) * inv;
     sa += or_gh_w[k] * or_gh_t[k] * 2.0 * gamma * xk * inv;
+    sd -= or_gh_w[k] * 2.0 * gamma * xk * inv;
   }
   *dVdg = sg / OR_SQRT_PI;
   *dVda = sa / OR_SQRT_PI;
+  *dVdd = sd / OR_SQRT_PI;
+}
+
+static void or_voigt_derivs(double delta, double alpha, double gamma, double* dVdg, double* dVda) {
+  double dd;
+  or_voigt_derivs3(delta, alpha, gamma, dVdg, dVda, &dd);
 }
 
 void or_voigt_derivs_arr(int64_t n, const double* delta, const double* alpha, const double* gamma,
-                         double* dVdg, double* dVda) {
+                         double* dVdg, double* dVda, double* dVdd) {
   #pragma omp parallel for schedule(static)
-  for (int64_t i = 0; i < n; ++i) or_voigt_derivs(delta[i], alpha[i], gamma[i], &dVdg[i], &dVda[i]);
+  for (int64_t i = 0; i < n; ++i) {
+    double dd;
+    or_voigt_derivs3(delta[i], alpha[i], gamma[i], &dVdg[i], &dVda[i], &dd);
+    if (dVdd) dVdd[i] = dd;
+  }
 }
 
 /* grid point: nu_j = nu_start + j*dnu, a product then a sum */
@@ -455,4 +475,163 @@ void or_jranges(int64_t N, const double* nu, double nu_start, double dnu, int64_
                 int64_t* j0, int64_t* j1) {
   #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < N; ++i) or_jrange(nu[i], nu_start, dnu, n_grid, cut, j0 + i, j1 + i);
+}
+
+/* ===================================================================== options */
+/* The four line profiles HELIOS-K offers (Sec. 2.1), per unit strength, at offset d from the
+ * line centre:
+ *   0 Voigt            Re w((d + i gamma)/alpha) / (sqrt(pi) alpha)
+ *   1 Lorentz          gamma / (pi (d^2 + gamma^2))            (gamma = 0: zero)
+ *   2 Doppler          exp(-(d/alpha)^2) / (sqrt(pi) alpha)
+ *   3 binned Gaussian  the Doppler profile averaged over the grid bin [d - dnu/2, d + dnu/2]
+ *                      (the integrated cross section per bin, divided by the bin width):
+ *                      (erf((d + dnu/2)/alpha) - erf((d - dnu/2)/alpha)) / (2 dnu), the
+ *                      difference of erfc taken where both arguments have the same sign */
+enum { OR_VOIGT = 0, OR_LORENTZ = 1, OR_DOPPLER = 2, OR_BINNED_GAUSS = 3 };
+/* The cutting length of a line (Sec. 2.4.3 step 4): a fixed length, or the given multiple of its
+ * Doppler half-width Gamma_D = sqrt(ln 2) alpha (eq. gammaD) or of its Lorentz half-width gamma. */
+enum { OR_CUT_FIXED = 0, OR_CUT_DOPPLER = 1, OR_CUT_LORENTZ = 2 };
+
+static double or_profile(int prof, double d, double alpha, double gamma, double dnu) {
+  if (prof == OR_LORENTZ) return gamma > 0.0 ? gamma / (OR_PI * (d * d + gamma * gamma)) : 0.0;
+  if (prof == OR_DOPPLER) {
+    const double x = d / alpha;
+    return exp(-x * x) / (OR_SQRT_PI * alpha);
+  }
+  if (prof == OR_BINNED_GAUSS) {
+    const double a = (d - 0.5 * dnu) / alpha, b = (d + 0.5 * dnu) / alpha;
+    double diff;
+    if (a >= 0.0) diff = erfc(a) - erfc(b);
+    else if (b <= 0.0) diff = erfc(-b) - erfc(-a);
+    else diff = erf(b) - erf(a);
+    return diff / (2.0 * dnu);
+  }
+  return or_voigt(d, alpha, gamma);
+}
+
+static double or_cut_length(int mode, double cut, double alpha, double gamma) {
+  if (isinf(cut)) return cut;
+  if (mode == OR_CUT_DOPPLER) return cut * sqrt(log(2.0)) * alpha;
+  if (mode == OR_CUT_LORENTZ) return cut * gamma;
+  return cut;
+}
+
+/* per-line cut lengths at (T, P) */
+void or_cut_lengths(int64_t N, const double* nu, const double* gref, const double* nexp,
+                    const or_species* sp, double T, double P, int cut_mode, double cut, double* out) {
+  #pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < N; ++i)
+    out[i] = or_cut_length(cut_mode, cut, or_alpha(sp, T, nu[i]), or_gamma(sp, T, P, gref[i], nexp[i]));
+}
+
+/* k at the grid indices pts with a profile, a cut mode and optional plinth removal: per point, the
+ * compensated sum over the lines with |nu_j - nu_i| <= cut_i of S_i (f(nu_j - nu_i) - [plinth]
+ * f(cut_i)), f the profile (the plinth is zero without a cut). Returns 0, or -1 on bad input. */
+int or_opacity_ex(int64_t N, const double* nu, const double* Sref, const double* E, const double* gref,
+                  const double* nexp, const or_species* sp, double T, double P, double nu_start,
+                  double dnu, double cut, int cut_mode, int profile, int plinth, int64_t n_pts,
+                  const int64_t* pts, double* k_out) {
+  if (N < 0 || n_pts < 0 || !(T > 0.0) || !(P >= 0.0) || !(dnu > 0.0) || !(cut > 0.0)) return -1;
+  if (cut_mode < 0 || cut_mode > 2 || profile < 0 || profile > 3) return -1;
+  const size_t NN = (size_t)(N > 0 ? N : 1);
+  double* S = (double*)malloc(sizeof(double) * NN);
+  double* al = (double*)malloc(sizeof(double) * NN);
+  double* ga = (double*)malloc(sizeof(double) * NN);
+  double* cl = (double*)malloc(sizeof(double) * NN);
+  double* pl = (double*)malloc(sizeof(double) * NN);
+  or_key* key = (or_key*)malloc(sizeof(or_key) * NN);
+  if (!S || !al || !ga || !cl || !pl || !key) {
+    free(S); free(al); free(ga); free(cl); free(pl); free(key);
+    return -2;
+  }
+  or_line_params(N, nu, Sref, E, gref, nexp, sp, T, P, S, al, ga);
+  double cmax = 0.0;
+  for (int64_t i = 0; i < N; ++i) {
+    cl[i] = or_cut_length(cut_mode, cut, al[i], ga[i]);
+    pl[i] = (plinth && !isinf(cl[i])) ? or_profile(profile, cl[i], al[i], ga[i], dnu) : 0.0;
+    if (cl[i] > cmax) cmax = cl[i];
+    key[i].nu = nu[i];
+    key[i].i = i;
+  }
+  qsort(key, (size_t)N, sizeof(or_key), or_key_cmp);
+  #pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < n_pts; ++q) {
+    const double nuj = or_grid(nu_start, dnu, pts[q]);
+    int64_t a = 0, b = N;
+    if (!isinf(cmax)) {
+      const double pad = cmax * 1e-9 + fabs(nuj) * 1e-12;
+      a = or_lower(key, N, nuj - cmax - pad);
+      b = or_lower(key, N, nuj + cmax + pad);
+      while (b < N && key[b].nu <= nuj + cmax + pad) ++b;
+    }
+    or_sum acc = {0.0, 0.0};
+    for (int64_t p = a; p < b; ++p) {
+      const int64_t i = key[p].i;
+      const double d = nuj - nu[i];
+      if (!(fabs(d) <= cl[i])) continue;
+      or_sum_add(&acc, S[i] * (or_profile(profile, d, al[i], ga[i], dnu) - pl[i]));
+    }
+    k_out[q] = or_sum_get(&acc);
+  }
+  free(S); free(al); free(ga); free(cl); free(pl); free(key);
+  return 0;
+}
+
+/* The adjoint of L = sum_j g_j k_j for the Voigt profile with a cut mode and optional plinth
+ * removal, per selected line (outputs as or_gradient). The cut indicator is not differentiated;
+ * the plinth S_i V(c_i) is, including the cut length c_i's own dependence on alpha (Doppler mode,
+ * c = m sqrt(ln 2) alpha) or gamma (Lorentz mode, c = m gamma):
+ *   GS -= G_box V(c),  Gg -= S G_box (dV/dgamma + [Lorentz] m dV/dd),
+ *   Ga -= S G_box (dV/dalpha + [Doppler] m sqrt(ln 2) dV/dd),  G_box = sum of g over the cut range. */
+int or_gradient_ex(int64_t N, const double* nu, const double* Sref, const double* E, const double* gref,
+                   const double* nexp, const or_species* sp, double T, double P, double nu_start,
+                   double dnu, int64_t n_grid, double cut, int cut_mode, int plinth, const double* g,
+                   int64_t n_sel, const int64_t* sel, double* GS, double* Gg, double* Ga, double* dSref,
+                   double* dgref, double* dn, double* dT_part, double* dlnP_part) {
+  if (N < 0 || n_sel < 0 || n_grid < 0 || !(T > 0.0) || !(P >= 0.0) || !(dnu > 0.0) || !(cut > 0.0))
+    return -1;
+  if (cut_mode < 0 || cut_mode > 2) return -1;
+  const double c2 = or_c2();
+  #pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t q = 0; q < n_sel; ++q) {
+    const int64_t i = sel[q];
+    const double S = or_strength(sp, T, nu[i], Sref[i], E[i]);
+    const double al = or_alpha(sp, T, nu[i]);
+    const double ga = or_gamma(sp, T, P, gref[i], nexp[i]);
+    const double ci = or_cut_length(cut_mode, cut, al, ga);
+    int64_t j0, j1;
+    or_jrange(nu[i], nu_start, dnu, n_grid, ci, &j0, &j1);
+    or_sum sV = {0, 0}, sY = {0, 0}, sA = {0, 0}, sB = {0, 0};
+    for (int64_t j = j0; j <= j1; ++j) {
+      const double d = or_grid(nu_start, dnu, j) - nu[i];
+      double dVdg, dVda;
+      or_voigt_derivs(d, al, ga, &dVdg, &dVda);
+      or_sum_add(&sV, g[j] * or_voigt(d, al, ga));
+      or_sum_add(&sY, g[j] * dVdg);
+      or_sum_add(&sA, g[j] * dVda);
+      or_sum_add(&sB, g[j]);
+    }
+    double gs = or_sum_get(&sV), yy = or_sum_get(&sY), aa = or_sum_get(&sA);
+    if (plinth && !isinf(ci) && j1 >= j0) {
+      const double Gbox = or_sum_get(&sB);
+      double pg, pa, pd;
+      or_voigt_derivs3(ci, al, ga, &pg, &pa, &pd);
+      if (cut_mode == OR_CUT_LORENTZ) pg += cut * pd;                   /* dc/dgamma = m */
+      if (cut_mode == OR_CUT_DOPPLER) pa += cut * sqrt(log(2.0)) * pd;  /* dc/dalpha = m sqrt(ln 2) */
+      gs -= Gbox * or_voigt(ci, al, ga);
+      yy -= Gbox * pg;
+      aa -= Gbox * pa;
+    }
+    const double gg = S * yy, gal = S * aa;
+    if (GS) GS[q] = gs;
+    if (Gg) Gg[q] = gg;
+    if (Ga) Ga[q] = gal;
+    const double dlnS_dT = -sp->q_b / T + c2 * E[i] / (T * T) - (c2 * nu[i] / (T * T)) / expm1(c2 * nu[i] / T);
+    if (dSref) dSref[q] = (Sref[i] != 0.0 ? S / Sref[i] : 0.0) * gs;
+    if (dgref) dgref[q] = (gref[i] != 0.0 ? ga / gref[i] : 0.0) * gg;
+    if (dn) dn[q] = ga * log(sp->T_ref / T) * gg;
+    if (dT_part) dT_part[q] = gs * S * dlnS_dT + gal * al / (2.0 * T) - gg * nexp[i] * ga / T;
+    if (dlnP_part) dlnP_part[q] = ga * gg;
+  }
+  return 0;
 }
