@@ -73,6 +73,9 @@ def _load():
                                        i64, _I64, _D, _D, _D, _D, _D, _D, _D, _D]
         lib.or_gradient_ex.restype = ctypes.c_int
         lib.or_cut_lengths.argtypes = [i64, _D, _D, _D, sp, dbl, dbl, ci, dbl, _D]
+        lib.or_opacity_hitran.argtypes = [i64, _D, _D, _D, _D, _D, _D, _D, sp, dbl, dbl, dbl, dbl, dbl, dbl, ci,
+                                          ci, ci, i64, _I64, _D]
+        lib.or_opacity_hitran.restype = ctypes.c_int
         lib.or_set_gauss_hermite.argtypes = [ctypes.c_int, _D, _D]
         lib.or_set_gauss_hermite.restype = ctypes.c_int
         t, w = np.polynomial.hermite.hermgauss(GH_NODES)
@@ -236,4 +239,19 @@ def cut_lengths(lines, sp, T, P, cut_mode, cut):
     nu, g, n = (_d(lines[k]) for k in ("nu", "gamma_ref", "n"))
     out = np.empty(nu.size)
     _load().or_cut_lengths(nu.size, _p(nu), _p(g), _p(n), ctypes.byref(sp), T, P, int(cut_mode), cut, _p(out))
+    return out
+
+
+def opacity_hitran(lines, sp, T, P, P_self, nu_start, dnu, cut, pts, cut_mode=CUT_FIXED, profile=PROFILE_VOIGT,
+                   plinth=False):
+    """FP64 k at the grid indices ``pts`` for a HITRAN-style list: ``lines`` holds nu, S_ref, E,
+    gamma_air, gamma_self, n and delta (the pressure shift, cm^-1/atm); the Lorentz half-width is
+    eq. (gammaL) without the natural term and the centre is shifted to nu + delta P / P_ref."""
+    f = [_d(lines[k]) for k in ("nu", "S_ref", "E", "gamma_air", "gamma_self", "n", "delta")]
+    pts = np.ascontiguousarray(pts, dtype=np.int64)
+    out = np.empty(pts.size)
+    rc = _load().or_opacity_hitran(f[0].size, *[_p(a) for a in f], ctypes.byref(sp), T, P, P_self, nu_start, dnu,
+                                   cut, int(cut_mode), int(profile), int(bool(plinth)), pts.size, _pi(pts), _p(out))
+    if rc != 0:
+        raise ValueError("or_opacity_hitran: invalid arguments (%d)" % rc)
     return out

@@ -635,3 +635,68 @@ int or_gradient_ex(int64_t N, const double* nu, const double* Sref, const double
   }
   return 0;
 }
+
+/* ======================================================= HITRAN widths and shift */
+/* The HITRAN form of the Lorentz half-width, eq. (gammaL) without the natural A/(4 pi c) term,
+ *   gamma = (T/T_ref)^(-n) [gamma_air (P - P_self) + gamma_self P_self] / P_ref,
+ * and the pressure-shifted line centre nu* = nu + delta_air P / P_ref, delta_air being the
+ * pressure-dependent line shift of Table binary2 (cm^-1 atm^-1). The shift moves only the centre
+ * of the profile: the strength and the Doppler width are those of the transition wavenumber nu.
+ * k at the grid indices pts: per point, the compensated sum over the lines with
+ * |nu_j - nu*_i| <= cut_i of S_i (f(nu_j - nu*_i) - [plinth] f(cut_i)), with the profile, cut mode
+ * and plinth options of or_opacity_ex. Returns 0, or -1 on bad input. */
+int or_opacity_hitran(int64_t N, const double* nu, const double* Sref, const double* E, const double* gair,
+                      const double* gself, const double* nexp, const double* delta, const or_species* sp,
+                      double T, double P, double Pself, double nu_start, double dnu, double cut, int cut_mode,
+                      int profile, int plinth, int64_t n_pts, const int64_t* pts, double* k_out) {
+  if (N < 0 || n_pts < 0 || !(T > 0.0) || !(P >= 0.0) || !(Pself >= 0.0) || Pself > P || !(dnu > 0.0) ||
+      !(cut > 0.0))
+    return -1;
+  if (cut_mode < 0 || cut_mode > 2 || profile < 0 || profile > 3) return -1;
+  const size_t NN = (size_t)(N > 0 ? N : 1);
+  double* S = (double*)malloc(sizeof(double) * NN);
+  double* al = (double*)malloc(sizeof(double) * NN);
+  double* ga = (double*)malloc(sizeof(double) * NN);
+  double* cl = (double*)malloc(sizeof(double) * NN);
+  double* pl = (double*)malloc(sizeof(double) * NN);
+  double* cen = (double*)malloc(sizeof(double) * NN);
+  or_key* key = (or_key*)malloc(sizeof(or_key) * NN);
+  if (!S || !al || !ga || !cl || !pl || !cen || !key) {
+    free(S); free(al); free(ga); free(cl); free(pl); free(cen); free(key);
+    return -2;
+  }
+  double cmax = 0.0;
+  for (int64_t i = 0; i < N; ++i) {
+    S[i] = or_strength(sp, T, nu[i], Sref[i], E[i]);
+    al[i] = or_alpha(sp, T, nu[i]);
+    ga[i] = pow(T / sp->T_ref, -nexp[i]) * (gair[i] * (P - Pself) + gself[i] * Pself) / sp->P_ref_atm;
+    cen[i] = nu[i] + delta[i] * P / sp->P_ref_atm;
+    cl[i] = or_cut_length(cut_mode, cut, al[i], ga[i]);
+    pl[i] = (plinth && !isinf(cl[i])) ? or_profile(profile, cl[i], al[i], ga[i], dnu) : 0.0;
+    if (cl[i] > cmax) cmax = cl[i];
+    key[i].nu = cen[i];
+    key[i].i = i;
+  }
+  qsort(key, (size_t)N, sizeof(or_key), or_key_cmp);
+  #pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t q = 0; q < n_pts; ++q) {
+    const double nuj = or_grid(nu_start, dnu, pts[q]);
+    int64_t a = 0, b = N;
+    if (!isinf(cmax)) {
+      const double pad = cmax * 1e-9 + fabs(nuj) * 1e-12;
+      a = or_lower(key, N, nuj - cmax - pad);
+      b = or_lower(key, N, nuj + cmax + pad);
+      while (b < N && key[b].nu <= nuj + cmax + pad) ++b;
+    }
+    or_sum acc = {0.0, 0.0};
+    for (int64_t p = a; p < b; ++p) {
+      const int64_t i = key[p].i;
+      const double d = nuj - cen[i];
+      if (!(fabs(d) <= cl[i])) continue;
+      or_sum_add(&acc, S[i] * (or_profile(profile, d, al[i], ga[i], dnu) - pl[i]));
+    }
+    k_out[q] = or_sum_get(&acc);
+  }
+  free(S); free(al); free(ga); free(cl); free(pl); free(cen); free(key);
+  return 0;
+}
