@@ -101,7 +101,44 @@ typedef struct hk_timings {
   int64_t wing_evals;      /* profile evaluations the wing and tile-far passes made: every
                               point of a wave for a line evaluated directly, 16 per line
                               evaluated at the Chebyshev nodes of a wave span or a tile */
+  int64_t class_evals[8];  /* the same per evaluation class: [0] lines evaluated at every point
+                              of a span (wing pass, or the direct pass of the options path),
+                              [1] far lines at a span's 16 nodes, [2] very far lines at its 8
+                              nodes, [3] middle-distance lines at its 32 nodes, [4] lines with a
+                              cut bound on the span at its 6 nodes, [5] and [6] tile-far lines at
+                              a tile's 16 and 8 nodes, [7] core evaluations (FP64) */
+  int32_t status;          /* status word of the last timed call (0: every work item stored) */
 } hk_timings;
+
+/* Options of hk_opacity_ex / hk_opacity_batched_ex (NULL: all zero).
+ *   profile  : the line profile (Sec. 2.1): HK_PROFILE_VOIGT (default); HK_PROFILE_LORENTZ,
+ *              gamma/(pi (d^2 + gamma^2)); HK_PROFILE_DOPPLER, exp(-(d/alpha)^2)/(sqrt(pi) alpha);
+ *              HK_PROFILE_BINNED_GAUSS, the Doppler profile averaged over each grid bin (the
+ *              integrated cross section of the bin over its width; Sec. 2.1 and the comparison
+ *              with ExoCross in Sec. 3.2): (erf((d + dnu/2)/alpha) - erf((d - dnu/2)/alpha))/(2 dnu).
+ *   cut_mode : HK_CUT_FIXED, cutoff is the cutting length in cm^-1 (default); HK_CUT_DOPPLER,
+ *              each line's cutting length is cutoff x its Doppler half-width sqrt(ln 2) alpha;
+ *              HK_CUT_LORENTZ, cutoff x its Lorentz half-width gamma (Sec. 2.4.3 step 4).
+ *              Per-line lengths are decided in FP64 as alpha = (nu/c) sqrt(2 k_B T/m),
+ *              gamma = gamma_ref (T_ref/T)^n P/P_ref. The first HK_CUT_LORENTZ call on a handle
+ *              reads back the list's largest gamma_ref and range of n (one host synchronization),
+ *              and such calls reject an override of gamma_ref or n (HK_EUNSUPPORTED).
+ *   plinth   : 1 subtracts each line's own profile value at its cutting length from every point
+ *              inside its cut (plinth removal, Sec. 2.1.1); needs a finite cut.
+ *   direct   : 1 makes the default path (Voigt, fixed cut, no plinth) evaluate every (line,
+ *              point) pair inside the cut: lines far from a span or a tile are then not evaluated
+ *              at its Chebyshev nodes and interpolated. For measurement of the per-pair rate.
+ * Any option other than the default Voigt with a fixed cut and no plinth runs a direct pass that
+ * evaluates every (line, point) pair inside each line's own cut in FP32 with compensated sums
+ * (the Voigt core points, |z| < 6.75, keep the FP64 core pass). */
+enum { HK_PROFILE_VOIGT = 0, HK_PROFILE_LORENTZ = 1, HK_PROFILE_DOPPLER = 2, HK_PROFILE_BINNED_GAUSS = 3 };
+enum { HK_CUT_FIXED = 0, HK_CUT_DOPPLER = 1, HK_CUT_LORENTZ = 2 };
+typedef struct hk_options {
+  int32_t profile;
+  int32_t cut_mode;
+  int32_t plinth;
+  int32_t direct;
+} hk_options;
 
 /*
  * hk_prepare_lines -- bin a line list by wavenumber (the paper sorts the line quantities
@@ -123,8 +160,10 @@ hk_status hk_prepare_lines(const double* nu, const double* S_ref, const double* 
                            const double* gamma_ref, const double* n_exp, int64_t n_lines,
                            const hk_species* sp, hipStream_t stream, hk_lines** out);
 
-/* Release a handle; blocks until work issued through it on its preparation stream completes.
- * NULL is accepted. The handle's device block goes to the library's block cache (see
+/* Release a handle; blocks until the work issued through it has completed (the last call on each
+ * stream it was used on; the whole device only when a use could not be tracked: a call on a
+ * capturing stream, on more than 8 streams, or an allocation-free call on a new stream). Other
+ * work on the device is not waited for. NULL is accepted. The handle's device block goes to the library's block cache (see
  * hk_empty_cache), not back to the driver. */
 hk_status hk_release_lines(hk_lines* lines);
 
@@ -182,6 +221,80 @@ hk_status hk_opacity_batched(const hk_lines* lines, int32_t n_pairs, const doubl
                              double cutoff, float* k, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * hk_opacity_ex, hk_opacity_batched_ex -- hk_opacity and hk_opacity_batched with options (see
+ * hk_options; NULL: the defaults). With a width-multiple cut mode, cutoff is the multiple.
+ * The workspace must hold hk_workspace_size_ex bytes for the same arguments.
+ */
+hk_status hk_opacity_ex(const hk_lines* lines, const hk_line_override* ovr, double T, double P_atm,
+                        hk_grid grid, double cutoff, const hk_options* options, float* k, void* ws,
+                        size_t ws_bytes, hipStream_t stream);
+hk_status hk_opacity_batched_ex(const hk_lines* lines, int32_t n_pairs, const double* T,
+                                const double* P_atm, const hk_grid* grids, const int64_t* out_offset,
+                                double cutoff, const hk_options* options, float* k, void* ws,
+                                size_t ws_bytes, hipStream_t stream);
+/* Workspace bytes of hk_opacity_ex (mode 0, n_pairs 1) or hk_opacity_batched_ex (mode 1): T and
+ * P_atm are host arrays of n_pairs (needed for width-multiple cut modes, which size the work
+ * lists by the largest cutting length; may be NULL otherwise); stream orders the one-time read
+ * of the list's width statistics (HK_CUT_LORENTZ). */
+hk_status hk_workspace_size_ex(const hk_lines* lines, int mode, int32_t n_pairs, const double* T,
+                               const double* P_atm, const hk_grid* grids, double cutoff,
+                               const hk_options* options, hipStream_t stream, size_t* bytes);
+
+/*
+ * HITRAN-style lists: air and self broadening and the pressure shift of line centres.
+ *
+ * hk_prepare_lines_hitran -- as hk_prepare_lines, with the Lorentz half-width of eq. (gammaL)
+ * (Sec. 2.2, without the natural term A/(4 pi c)) in place of the ExoMol form,
+ *   gamma = (T_ref/T)^n [gamma_air (P - P_self) + gamma_self P_self] / P_ref,
+ * and line centres moved by the pressure shift of Table binary2, nu* = nu + delta_air P/P_ref.
+ * The strength and the Doppler width keep the transition wavenumber nu.
+ *   gamma_air, gamma_self : device float64[n_lines], >= 0 and finite (cm^-1 atm^-1)
+ *   delta_air             : device float64[n_lines], finite (cm^-1 atm^-1)
+ * Other arguments, checks and memory as hk_prepare_lines (plus 16 bytes per line); the call
+ * blocks the host once more (the check of the two extra fields).
+ *
+ * hk_opacity_hitran -- k on one grid at (T, P) with self partial pressure 0 <= P_self <= P. The
+ * shift can change the order of the centres along nu (the paper sorts after applying it, Sec.
+ * 2.4.3 step 3), so each call bins the list again by nu* in its workspace, then evaluates every
+ * (line, point) pair inside each line's cut (the direct pass of the options path; the Voigt core
+ * points by the FP64 core pass). options as hk_opacity_ex (direct must be 0); the workspace must
+ * hold hk_workspace_size_hitran bytes (about 68 bytes per line more than hk_opacity_ex).
+ */
+hk_status hk_prepare_lines_hitran(const double* nu, const double* S_ref, const double* E_low,
+                                  const double* gamma_air, const double* gamma_self, const double* n_exp,
+                                  const double* delta_air, int64_t n_lines, const hk_species* sp,
+                                  hipStream_t stream, hk_lines** out);
+hk_status hk_workspace_size_hitran(const hk_lines* lines, double T, double P_atm, double P_self,
+                                   hk_grid grid, double cutoff, const hk_options* options, hipStream_t stream,
+                                   size_t* bytes);
+hk_status hk_opacity_hitran(const hk_lines* lines, double T, double P_atm, double P_self, hk_grid grid,
+                            double cutoff, const hk_options* options, float* k, void* ws, size_t ws_bytes,
+                            hipStream_t stream);
+
+/*
+ * hk_opacity_stream -- k of a line list held in HOST memory, larger than the device can hold
+ * at once, processed in chunks of chunk_lines lines (the paper streams blocks of the list from
+ * host memory to the GPU, overlapping the transfers with the computation, Sec. 2.4.1 and
+ * Sec. 2.4.6 with Fig. stream). While one chunk is binned and evaluated on `stream`, the next
+ * is copied on a copy stream of the library. Each chunk is evaluated on the band of the grid
+ * within its largest cutting length of its lines (for a list sorted along nu, as the paper's
+ * preprocessed files are, a band is a small part of the grid), and the chunk results are added
+ * to k in chunk order, so the result is deterministic for a given chunk_lines and equals the
+ * one-call result up to FP32 rounding of those additions.
+ *   nu, S_ref, E_low, gamma_ref, n_exp : HOST float64[n_lines] (pinned memory lets the copies
+ *       overlap the computation); checked per chunk as in hk_prepare_lines.
+ *   chunk_lines : >= 1; device memory used is about (56 + 80) bytes per chunk line plus the
+ *       workspace of one chunk's hk_opacity_ex and 4 bytes per grid point, from the library's
+ *       block cache (this entry point allocates; it is not for graph capture).
+ *   options : as hk_opacity_ex. k : device float32[grid.n], written entirely.
+ * The call returns when k is complete (it synchronizes `stream`).
+ */
+hk_status hk_opacity_stream(const double* nu, const double* S_ref, const double* E_low,
+                            const double* gamma_ref, const double* n_exp, int64_t n_lines,
+                            const hk_species* sp, double T, double P_atm, hk_grid grid, double cutoff,
+                            const hk_options* options, int64_t chunk_lines, float* k, hipStream_t stream);
+
+/*
  * hk_opacity_backward -- adjoint of L = sum_j dL_dk[j] k_j at one (T, P) (not in the paper;
  * derived from eqs. S1, alphaD and the ExoMol width). Strengths and widths are recomputed.
  *   dL_dk     : device float32[grid.n] upstream gradient.
@@ -200,6 +313,14 @@ hk_status hk_opacity_backward(const hk_lines* lines, const hk_line_override* ovr
  * j_lo, j_hi: device int32[n_lines]. */
 hk_status hk_debug_cut_bounds(const hk_lines* lines, hk_grid grid, double cutoff, int32_t* j_lo,
                               int32_t* j_hi, hipStream_t stream);
+
+/* Per-line grid records of a call with options, for tests: the inclusive grid range [j_lo, j_hi]
+ * of each line's own cutting length and its plinth S(T) f(cut) (0 without plinth removal), in
+ * caller order (device int32/float32 arrays of n_lines, any may be NULL). ws: device scratch of
+ * at least 28 n_lines + 768 bytes, 256-byte aligned. */
+hk_status hk_debug_grid_records(const hk_lines* lines, double T, double P_atm, hk_grid grid, double cutoff,
+                                const hk_options* options, void* ws, size_t ws_bytes, int32_t* j_lo,
+                                int32_t* j_hi, float* plinth, hipStream_t stream);
 
 /* Sorted view for tests: copies the handle's bin keys (uint32) and permutation (int32:
  * sorted position -> caller index) to device buffers of n_lines elements. */

@@ -11,6 +11,7 @@ constexpr int kThreads = 256;    // threads per workgroup of the tile-far and so
 constexpr int kWavesPerWG = kThreads / kWave;  // spans per tile of the tile-far pass
 constexpr int kKmax = 5;         // highest order of the far-wing series
 constexpr int kWeidN = 18;       // terms of the FP64 core rational approximation
+constexpr int kWeidN40 = 40;     // terms of the FP64 approximation of the plinth values (one per line)
 constexpr int kKeyBits = 24;     // linear wavenumber-bin key width
 constexpr int kRadixBits = 8;
 constexpr int kSortItems = 16;   // keys per thread per sort block
@@ -187,6 +188,9 @@ struct VoigtArgs {
   const double* far8_w;    // [kFar8Nodes][64 P] the same for the very-far nodes
   const double* mid_w;     // [kMidNodes][64 P] the same for the middle-distance nodes
   const float* mask_w;     // [kMaskNodes][64 P] the same for the nodes of lines with a cut bound on it
+  int* status;             // nullable: bit 0 set when a work item fell beyond the partial rows
+  const double* nu_pos;    // nullable: line centres when they differ from nu (a shifted list's
+                           // view; nu then holds the transition wavenumbers the widths are taken at)
 };
 
 // Arguments of the tile-far pass (lines evaluated at the tile's Chebyshev nodes) and its combine.
@@ -213,6 +217,7 @@ struct FarArgs {
   int32_t W;               // tile width in grid points
   float tile_x[kNodes];    // class-0 node positions relative to the tile's first point
   float tile_x8[kFar8Nodes];  // class-1 node positions
+  int* status;             // nullable: bit 0 set when a work item fell beyond the node-sum rows
 };
 
 struct PrepArgs {
@@ -254,6 +259,39 @@ struct AdjArgs {
 };
 constexpr int kAdjSpan = 256;  // points per span of the adjoint (one step of a wave)
 
+// Line profiles and cutting-length modes of the options path.
+enum { kProfVoigt = 0, kProfLorentz = 1, kProfDoppler = 2, kProfBinned = 3 };
+enum { kCutFixed = 0, kCutDoppler = 1, kCutLorentz = 2 };
+
+// Arguments of the per-line grid records with per-line cutting lengths and plinth values.
+struct GridRecArgs {
+  PrepArgs pa;             // sorted line data, overrides, pfac
+  const float* S_T;        // strength at T (plinth values)
+  double nu_start, dnu;
+  int64_t n;
+  double cut;              // fixed length, or the multiple of the line's width (+inf: no cut)
+  double cut_dop;          // cut sqrt(ln 2): multiple of alpha for the Doppler half-width mode
+  double c_light;          // alpha = (nu / c_light) alpha_fac
+  double alpha_fac;        // sqrt(2 k_B T / m)
+  double t_ratio;          // T_ref / T
+  int32_t cut_mode, profile, plinth;
+  int4* grec;              // out: per line (offset bits, reference index, cut lo, cut hi)
+  float* plin;             // out, nullable: per line S(T) f(cut)
+  const double* nu_pos;    // nullable: line centres when they differ from pa.nu (shifted list)
+};
+
+// Arguments of the shifted view of a HITRAN-style list at one pressure (k_shift_gather).
+struct ShiftArgs {
+  const int32_t* src;      // view position -> handle position (sorted by shifted centre)
+  const double *nu, *Sref, *E, *gair, *gself, *nexp, *delta;  // handle (sorted by nu) arrays
+  const int32_t* perm;     // handle position -> caller index
+  int64_t N;
+  double pshift;           // P / P_ref: centre = nu + delta pshift
+  double P, Pself;         // atm
+  double *o_nu, *o_pos, *o_S, *o_E, *o_g, *o_n;
+  int32_t* o_perm;
+};
+
 // Launch wrappers (hk_kernels.hip); each returns the launch status.
 // flags[0]: a nu <= 0 or non-finite (k_validate); flags[1]: another field invalid (k_keys)
 hipError_t launch_validate(const double* nu, int64_t N, unsigned long long* mm, int* flags, hipStream_t st);
@@ -266,12 +304,13 @@ hipError_t launch_gather(const int32_t* perm, int64_t N, const double* rec, doub
                          double* og, double* on, hipStream_t st);
 hipError_t launch_prep(const PrepArgs& a, float* S_T, float* gT, double* S64, double* a64, double* g64,
                        hipStream_t st);
-hipError_t launch_fill_pairs(const PairDesc* host_pairs, int count, PairDesc* dst, hipStream_t st);
+hipError_t launch_fill_pairs(const PairDesc* host_pairs, int count, PairDesc* dst, int* status, hipStream_t st);
 hipError_t launch_worklist(const uint32_t* keys, int64_t N, KeyMap km, double numin, double numax,
                            const PairDesc* pairs,
                            int n_pairs, int n_tiles_total, int tile_w, double cut, double core_z, int chunk,
                            int32_t* lo, int32_t* hi, int32_t* nc, int4* far, int32_t* nf, int far_chunk,
-                           double far_z, hipStream_t st);  // far: [tile][2]; nf: [2][tiles]
+                           double far_z, int direct_only, double core_pad,
+                           hipStream_t st);  // far: [tile][2]; nf: [2][tiles]
 hipError_t launch_item_scan(const int32_t* nc, int n_tiles_total, int32_t* item_base, int* counter,
                             hipStream_t st);
 hipError_t launch_gridrec(const double* nu, int64_t N, double nu_start, double dnu, int64_t n, double cut,
@@ -279,7 +318,7 @@ hipError_t launch_gridrec(const double* nu, int64_t N, double nu_start, double d
 hipError_t launch_span_segments(const uint32_t* keys, int64_t N, KeyMap km, double numin, double numax,
                                 const PairDesc* spairs, const PairDesc* tpairs, int n_pairs, int n_spans,
                                 int span_w, double cut, double far_z, const int4* tile_far, int chunk,
-                                SpanSeg* segs, int32_t* nc, hipStream_t st);
+                                SpanSeg* segs, int32_t* nc, int direct_only, hipStream_t st);
 hipError_t launch_wing(const VoigtArgs& a, int slots, int grid, hipStream_t st);
 hipError_t launch_core(const VoigtArgs& a, int slots, int grid, hipStream_t st);
 // k = (add ? k : 0) + fixed-order sum of the partial spans of multi-item spans
@@ -298,5 +337,34 @@ hipError_t launch_reduce2(const double* contrib, int64_t N, double* partial, int
 int wing_max_blocks_per_cu(int slots);
 int core_max_blocks_per_cu(int slots);
 hipError_t upload_weideman(const double* coef, double L);
+hipError_t upload_weideman40(const double* coef, double L);
+hipError_t launch_gridrec_ex(const GridRecArgs& a, hipStream_t st);
+// HITRAN-style lists: field check and max |delta|, max gamma_self (ordered words); gather of the two
+// extra fields into the handle's order; keys of the shifted centres; the shifted view
+hipError_t launch_hitran_check(const double* gself, const double* delta, int64_t N, int* flags,
+                               unsigned long long* out, hipStream_t st);
+hipError_t launch_gather2(const int32_t* perm, int64_t N, const double* a, const double* b, double* oa, double* ob,
+                          hipStream_t st);
+hipError_t launch_shift_keys(const double* nu, const double* delta, int64_t N, double pshift, KeyMap km,
+                             uint32_t* keys, int32_t* vals, hipStream_t st);
+hipError_t launch_shift_gather(const ShiftArgs& a, hipStream_t st);
+// k[0..n) = 0; k[0..n) += t[0..n)
+hipError_t launch_fill0(float* k, int64_t n, hipStream_t st);
+hipError_t launch_accumulate(float* k, const float* t, int64_t n, hipStream_t st);
+// k_direct over the span work list of a (tile_lo/tile_hi/tile_nc/item_base), profile prof
+hipError_t launch_direct(const VoigtArgs& a, const float* plin, int prof, int slots, int grid, hipStream_t st);
+int direct_max_blocks_per_cu(int slots);
+// out[0..2] = ordered words of max gamma_ref, min n, max n (see ordered_to_double)
+hipError_t launch_line_stats(const double* gref, const double* nexp, int64_t N, unsigned long long* out,
+                             hipStream_t st);
+hipError_t launch_scatter_grec(const int4* grec, const float* plin, const int32_t* perm, int64_t N, int32_t* jlo,
+                               int32_t* jhi, float* plin_out, hipStream_t st);
+// inverse of the kernels' order-preserving map of doubles to unsigned words
+inline double ordered_to_double(unsigned long long w) {
+  const unsigned long long b = (w >> 63) ? (w & 0x7FFFFFFFFFFFFFFFull) : ~w;
+  double v;
+  __builtin_memcpy(&v, &b, sizeof v);
+  return v;
+}
 
 }  // namespace hk

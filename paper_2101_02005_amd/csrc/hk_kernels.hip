@@ -23,6 +23,7 @@
 namespace hk {
 
 __constant__ double c_weid[kWeidN];  // Weideman (1994) coefficients a_1..a_N (host-computed)
+__constant__ float c_weid32[kWeidN]; // the same rounded to FP32 (the high-order steps of the core pass)
 __constant__ double c_weidL;         // its scale L = sqrt(N / sqrt 2)
 
 // grid point nu_j = nu_start + j dnu: a rounded product, then a rounded sum (no FMA)
@@ -310,7 +311,10 @@ __global__ __launch_bounds__(kThreads) void k_prep(PrepArgs a, float* __restrict
   }
   const double v = a.nu[i];
   const double stim = expm1(-a.c2_over_T * v) / expm1(-a.c2_over_Tref * v);
-  const double S = Sref * a.q_ratio * exp(a.c2E_coef * a.E[i]) * stim;
+  // a Boltzmann factor ratio beyond the FP64 range is taken with S_ref inside the exponential
+  const double arg = a.c2E_coef * a.E[i];
+  const double S = arg < 700.0 ? Sref * a.q_ratio * exp(arg) * stim
+                               : (Sref > 0.0 ? exp(log(Sref) + arg) * a.q_ratio * stim : 0.0);
   const double g = gref * exp(nexp * a.log_tr);
   if (S_T) S_T[i] = (float)S;
   if (gT) gT[i] = (float)g;
@@ -324,8 +328,11 @@ struct PairPack {
   int count;
 };
 
-__global__ void k_fill_pairs(PairPack pk, PairDesc* dst) {
+// Copies the pair descriptors; also clears the call's status word when given (a kernel, not a
+// memset, so that the call can be recorded into a graph).
+__global__ void k_fill_pairs(PairPack pk, PairDesc* dst, int* status) {
   if ((int)threadIdx.x < pk.count) dst[threadIdx.x] = pk.p[threadIdx.x];
+  if (status && threadIdx.x == 0) *status = 0;
 }
 
 // Force a value that is uniform across the wave into scalar registers (its load may have
@@ -385,7 +392,8 @@ __global__ void k_worklist(const uint32_t* __restrict__ keys, int64_t N, KeyMap 
                            const PairDesc* __restrict__ pairs, int n_pairs, int n_tiles_total,
                            int tile_w, double cut, double core_z, int chunk, int32_t* __restrict__ lo_out,
                            int32_t* __restrict__ hi_out, int32_t* __restrict__ nc_out, int4* __restrict__ far_out,
-                           int32_t* __restrict__ nf_out, int far_chunk, double far_z) {
+                           int32_t* __restrict__ nf_out, int far_chunk, double far_z, int direct_only,
+                           double core_pad) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n_tiles_total) return;
   const PairDesc pd = pairs[find_pair(pairs, n_pairs, g)];
@@ -396,7 +404,9 @@ __global__ void k_worklist(const uint32_t* __restrict__ keys, int64_t N, KeyMap 
   double hw = cut;
   if (core_z > 0.0) {
     const double vmax = fabs(grid_nu(pd.nu_start, pd.dnu, j1)) + (isinf(cut) ? numax : cut);
-    const double hc = core_z * pd.beta * (vmax > numax ? numax : vmax) * 1.0001 + 0.01 * pd.dnu + 1e-300;
+    // core_pad: the largest alpha increase of a list whose centres are shifted from the
+    // wavenumbers their widths are taken at, times core_z
+    const double hc = core_z * pd.beta * (vmax > numax ? numax : vmax) * 1.0001 + 0.01 * pd.dnu + core_pad + 1e-300;
     hw = hc < cut ? hc : cut;
   }
   if (!isinf(hw)) {
@@ -421,7 +431,7 @@ __global__ void k_worklist(const uint32_t* __restrict__ keys, int64_t N, KeyMap 
     hi = a;
   }
   int64_t a1 = lo, b1 = lo, a2 = hi, b2 = hi, x1 = lo, x2 = hi;
-  if (far_out && j0 + tile_w <= pd.n && hi > lo) {
+  if (far_out && !direct_only && j0 + tile_w <= pd.n && hi > lo) {
     const double nA = grid_nu(pd.nu_start, pd.dnu, j0), nB = grid_nu(pd.nu_start, pd.dnu, j0 + tile_w - 1);
     const double nc = 0.5 * (nA + nB), half = 0.5 * (nB - nA);
     const double wlo = isinf(cut) ? numin : fmax(numin, nA - cut);
@@ -475,7 +485,7 @@ __global__ void k_span_segments(const uint32_t* __restrict__ keys, int64_t N, Ke
                                 double numax, const PairDesc* __restrict__ spairs,
                                 const PairDesc* __restrict__ tpairs, int n_pairs, int n_spans, int span_w,
                                 double cut, double far_z, const int4* __restrict__ tile_far, int chunk,
-                                SpanSeg* __restrict__ segs, int32_t* __restrict__ nc_out) {
+                                SpanSeg* __restrict__ segs, int32_t* __restrict__ nc_out, int direct_only) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n_spans) return;
   const int p = find_pair(spairs, n_pairs, g);
@@ -511,7 +521,7 @@ __global__ void k_span_segments(const uint32_t* __restrict__ keys, int64_t N, Ke
   // far ones; the masked ones lie beyond the far ones' cut-side bounds
   int64_t fa1 = lo, fb1 = lo, fa2 = hi, fb2 = hi, ma1 = lo, mb1 = lo, ma2 = hi, mb2 = hi;
   int64_t la = lo, lb = lo, ra = hi, rb = hi, ea1 = lo, eb1 = lo, ea2 = hi, eb2 = hi;
-  if (j0 + span_w <= pd.n && hi > lo) {
+  if (!direct_only && j0 + span_w <= pd.n && hi > lo) {
     const double c = 0.5 * (nA + nB), half = 0.5 * (nB - nA);
     const double wlo = isinf(cut) ? numin : fmax(numin, nA - cut);
     const double whi = isinf(cut) ? numax : fmin(numax, nB + cut);
@@ -632,6 +642,36 @@ __device__ __forceinline__ void weideman_poly(double Zr, double Zi, double& pr, 
   pi = Zi * b1;
 }
 
+// The same polynomial with the recurrence's high-order steps (m >= kWeidSplit) in FP32: the
+// coefficients of those steps are at most 0.02 (the first ones reach 1.9), so their FP32 rounding
+// stays far below the approximation's own error (checked over |z| < 6.75 against scipy's wofz:
+// largest error 7.40e-9 of the profile's peak with the split at 6, against 7.37e-9 all in FP64);
+// the low-order steps, which carry the large coefficients, stay FP64. Ten of the fifteen steps
+// run at the FP32 rate.
+constexpr int kWeidSplit = 6;
+static_assert(kWeidSplit >= 2 && kWeidSplit <= kWeidN - 3, "split inside the recurrence");
+__device__ __forceinline__ void weideman_poly_mixed(double Zr, double Zi, double& pr, double& pi) {
+  const double r = 2.0 * Zr, s = fma(Zr, Zr, Zi * Zi);
+  const float rf = (float)r, sf = (float)s;
+  float f2 = c_weid32[kWeidN - 1];
+  float f1 = __builtin_fmaf(rf, f2, c_weid32[kWeidN - 2]);
+#pragma unroll
+  for (int m = kWeidN - 3; m >= kWeidSplit; --m) {
+    const float t = __builtin_fmaf(rf, f1, __builtin_fmaf(-sf, f2, c_weid32[m]));
+    f2 = f1;
+    f1 = t;
+  }
+  double b2 = (double)f2, b1 = (double)f1;
+#pragma unroll
+  for (int m = kWeidSplit - 1; m >= 1; --m) {
+    const double t = fma(r, b1, fma(-s, b2, c_weid[m]));
+    b2 = b1;
+    b1 = t;
+  }
+  pr = fma(Zr, b1, fma(-s, b2, c_weid[0]));
+  pi = Zi * b1;
+}
+
 __device__ __forceinline__ double weideman_re(double x, double y) {
   const double L = c_weidL;
   const double dr = L + y, di = -x;  // L - iz
@@ -640,7 +680,7 @@ __device__ __forceinline__ double weideman_re(double x, double y) {
   // Z = (L + iz)/(L - iz) = 2 L u - 1
   const double Zr = fma(2.0 * L, ur, -1.0), Zi = 2.0 * L * ui;
   double pr, pi;
-  weideman_poly(Zr, Zi, pr, pi);
+  weideman_poly_mixed(Zr, Zi, pr, pi);
   // Re(2 p u^2 + u/sqrt(pi)) = Re(u t), t = 2 p u + 1/sqrt(pi)
   const double tr = 2.0 * fma(pr, ur, -pi * ui) + 0.56418958354775628695;
   const double ti = 2.0 * fma(pr, ui, pi * ur);
@@ -1513,13 +1553,23 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P <= 4 ? 
         a.partial[((int64_t)it) * W + local] = v;
       }
     }
+    // an item beyond the partial rows (the host bound is a proof, so never expected): flagged,
+    // and the combine writes NaN over its span
+    if (nc != 1 && it >= a.items_cap && a.status && lane == 0) atomicOr(a.status, 1);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  if (a.stats && lane == 0)
-    a.stats[blockIdx.x] = n_direct * W + (n_node - n_mid - n_far8) * kNodes + n_far8 * kFar8Nodes +
-                          n_mid * kMidNodes + n_mask * kMaskNodes;
+  // evaluations made, per class: [0] direct (every point of the span), [1] far (kNodes nodes),
+  // [2] very far (kFar8Nodes), [3] middle (kMidNodes), [4] masked (kMaskNodes)
+  if (a.stats && lane == 0) {
+    const int nb = gridDim.x;
+    a.stats[blockIdx.x] = n_direct * W;
+    a.stats[nb + blockIdx.x] = (n_node - n_mid - n_far8) * kNodes;
+    a.stats[2 * nb + blockIdx.x] = n_far8 * kFar8Nodes;
+    a.stats[3 * nb + blockIdx.x] = n_mid * kMidNodes;
+    a.stats[4 * nb + blockIdx.x] = n_mask * kMaskNodes;
+  }
 }
 
 
@@ -1594,6 +1644,7 @@ __global__ __launch_bounds__(kThreads) void k_far(FarArgs a) {
 #pragma unroll
       for (int w = 0; w < kWavesPerWG; ++w) t += sRed[w][tid];
       if (it < a.items_cap[C]) a.node_part[C][(int64_t)it * NN + tid] = t;
+      else if (a.status && tid == 0) atomicOr(a.status, 1);
     }
     __syncthreads();
   }
@@ -1609,15 +1660,17 @@ __global__ __launch_bounds__(kThreads) void k_combine_far(FarArgs a) {
   const int b1 = a.item_base[1][g], n1 = a.item_base[1][g + 1] - b1;
   if (n0 <= 0 && n1 <= 0) return;
   const PairDesc pd = a.pairs[find_pair(a.pairs, a.n_pairs, g)];
+  // items beyond the node-sum rows were not stored (flagged by k_far): the tile gets NaN
+  const bool lost = b0 + n0 > a.items_cap[0] || b1 + n1 > a.items_cap[1];
   if (threadIdx.x < kNodes) {
     double t = 0.0;
     for (int c = 0; c < n0 && b0 + c < a.items_cap[0]; ++c) t += a.node_part[0][(int64_t)(b0 + c) * kNodes + threadIdx.x];
-    ns[threadIdx.x] = t;
+    ns[threadIdx.x] = lost ? NAN : t;
   } else if (threadIdx.x < kNodes + kFar8Nodes) {
     const int k = threadIdx.x - kNodes;
     double t = 0.0;
     for (int c = 0; c < n1 && b1 + c < a.items_cap[1]; ++c) t += a.node_part[1][(int64_t)(b1 + c) * kFar8Nodes + k];
-    ns[threadIdx.x] = t;
+    ns[threadIdx.x] = lost ? NAN : t;
   }
   __syncthreads();
   const int64_t tile0 = (int64_t)(g - pd.tile_base) * a.W;
@@ -1776,7 +1829,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
             czh = (int)(gh - tile0);
             lamp = S / (1.7724538509055160273f * alpha);
             lia = rcp64(nu0 * pd.beta);
-            ld64 = __dsub_rn(grid_nu(pd.nu_start, pd.dnu, (int64_t)jref), nu0);
+            ld64 = __dsub_rn(grid_nu(pd.nu_start, pd.dnu, (int64_t)jref),
+                             a.nu_pos ? a.nu_pos[b + lane] : nu0);
             ly = (double)gTv * pd.pfac * lia;
           }
         }
@@ -1846,9 +1900,457 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
     } else if (it < a.items_cap) {
 #pragma unroll
       for (int p = 0; p < P; ++p) a.partial[(int64_t)it * W + p * kWave + lane] = s[p] - cc[p];
+    } else if (a.status && lane == 0) {
+      atomicOr(a.status, 1);
     }
   }
   if (a.stats && lane == 0) a.stats[blockIdx.x] = ncore;
+}
+
+// --------------------------------------------------- line profiles, plinth and cut options
+// The four line profiles of Sec. 2.1, per unit strength at offset d from the line centre:
+//   Voigt           Re w((d + i gamma)/alpha) / (sqrt(pi) alpha)
+//   Lorentz         gamma / (pi (d^2 + gamma^2))                 (gamma = 0: no contribution)
+//   Doppler         exp(-(d/alpha)^2) / (sqrt(pi) alpha)
+//   binned Gaussian the Doppler profile averaged over the grid bin [d - dnu/2, d + dnu/2] (the
+//                   integrated cross section of the bin over its width):
+//                   (erf((d + dnu/2)/alpha) - erf((d - dnu/2)/alpha)) / (2 dnu)
+// Plinth removal (Sec. 2.1.1) subtracts a line's own profile value at its cutting length from
+// every point inside its cut. The cutting length (Sec. 2.4.3 step 4) is a fixed length, or a
+// multiple of the line's Doppler half-width sqrt(ln 2) alpha or of its Lorentz half-width gamma.
+
+__constant__ double c_weid40[kWeidN40];  // Weideman coefficients a_1..a_40 (host-computed)
+__constant__ double c_weid40L;
+
+// Re w(x + iy), y >= 0, for the plinth values (one evaluation per line, in FP64): Weideman's
+// approximation with 40 terms for |z| < 8 (about 1e-15 of w(0)), the Laplace continued fraction
+// w = (i/sqrt(pi)) / (z - (1/2)/(z - (2/2)/(z - (3/2)/(z - ...)))) with 20 levels beyond (about
+// 1e-14 relative there).
+__device__ double re_w_accurate(double x, double y) {
+  if (x * x + y * y < 64.0) {
+    const double L = c_weid40L;
+    const double dr = L + y, di = -x;  // L - iz
+    const double inv = 1.0 / (dr * dr + di * di);
+    const double ur = dr * inv, ui = -di * inv;  // 1/(L - iz)
+    const double Zr = 2.0 * L * ur - 1.0, Zi = 2.0 * L * ui;
+    double pr = c_weid40[kWeidN40 - 1], pi = 0.0;  // complex Horner in Z
+    for (int m = kWeidN40 - 2; m >= 0; --m) {
+      const double t = pr * Zr - pi * Zi + c_weid40[m];
+      pi = pr * Zi + pi * Zr;
+      pr = t;
+    }
+    const double tr = 2.0 * (pr * ur - pi * ui) + 0.56418958354775628695;
+    const double ti = 2.0 * (pr * ui + pi * ur);
+    return ur * tr - ui * ti;
+  }
+  double tr = 0.0, ti = 0.0;  // innermost level first: t = (k/2)/(z - t)
+  for (int k = 20; k >= 1; --k) {
+    const double dr = x - tr, di = y - ti;
+    const double f = (0.5 * k) / (dr * dr + di * di);
+    tr = dr * f;
+    ti = -di * f;
+  }
+  const double dr = x - tr, di = y - ti;
+  return di * (0.56418958354775628695 / (dr * dr + di * di));  // Re i/(sqrt(pi)(z - t))
+}
+
+// A profile's value per unit strength at offset d >= 0, in FP64 (the plinth of a line).
+__device__ double profile_value64(int prof, double d, double alpha, double gamma, double dnu) {
+  if (prof == kProfLorentz) return gamma > 0.0 ? gamma / (3.14159265358979323846 * (d * d + gamma * gamma)) : 0.0;
+  if (prof == kProfDoppler) {
+    const double x = d / alpha;
+    return exp(-x * x) / (1.7724538509055160273 * alpha);
+  }
+  if (prof == kProfBinned) {
+    const double lo = (d - 0.5 * dnu) / alpha, hi = (d + 0.5 * dnu) / alpha;
+    const double diff = lo >= 0.0 ? erfc(lo) - erfc(hi) : (hi <= 0.0 ? erfc(-hi) - erfc(-lo) : erf(hi) - erf(lo));
+    return diff / (2.0 * dnu);
+  }
+  return re_w_accurate(d / alpha, gamma / alpha) / (1.7724538509055160273 * alpha);
+}
+
+// Grid record of each line (as k_gridrec) with the line's own cutting length, and its plinth
+// S(T) f(cut) (0 without plinth removal or without a cut). The length is decided in FP64 from
+// alpha = (nu/c) sqrt(2 k_B T/m) and gamma = gamma_ref (T_ref/T)^n P/P_ref.
+__global__ __launch_bounds__(kThreads) void k_gridrec_ex(GridRecArgs a) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.pa.N) return;
+  double gref, nexp;
+  if (a.pa.ovr_g || a.pa.ovr_n) {
+    const int32_t c = a.pa.perm[i];
+    gref = a.pa.ovr_g ? a.pa.ovr_g[c] : a.pa.gref[i];
+    nexp = a.pa.ovr_n ? a.pa.ovr_n[c] : a.pa.nexp[i];
+  } else {
+    gref = a.pa.gref[i];
+    nexp = a.pa.nexp[i];
+  }
+  const double nuw = a.pa.nu[i];                       // the transition wavenumber (widths)
+  const double nu0 = a.nu_pos ? a.nu_pos[i] : nuw;      // the line centre (position)
+  const double alpha = nuw / a.c_light * a.alpha_fac;
+  const double gam = gref * pow(a.t_ratio, nexp) * a.pa.pfac;
+  double cut = a.cut;
+  if (!isinf(cut)) {
+    if (a.cut_mode == kCutDoppler) cut = a.cut_dop * alpha;
+    else if (a.cut_mode == kCutLorentz) cut = a.cut * gam;
+  }
+  int64_t jlo, jhi;
+  cut_range(nu0, a.nu_start, a.dnu, a.n, cut, jlo, jhi);
+  double jr = rint((nu0 - a.nu_start) / a.dnu);
+  jr = jr < 0.0 ? 0.0 : (jr > (double)(a.n - 1) ? (double)(a.n - 1) : jr);
+  const int64_t jref = (int64_t)jr;
+  const double delta = __dsub_rn(grid_nu(a.nu_start, a.dnu, jref), nu0);
+  if (jlo > jhi) { jlo = 1; jhi = 0; }
+  a.grec[i] = make_int4(__float_as_int((float)delta), (int)jref, (int)jlo, (int)jhi);
+  if (a.plin) {
+    float p = 0.0f;
+    if (a.plinth && !isinf(cut) && jlo <= jhi)
+      p = (float)((double)a.S_T[i] * profile_value64(a.profile, cut, alpha, gam, a.dnu));
+    a.plin[i] = p;
+  }
+}
+
+// Direct evaluation of every (line, point) pair inside the lines' cuts, for every profile, with
+// optional plinth removal and per-line cutting lengths (the grid records of k_gridrec_ex). One
+// wave per work item: a span of 64 P grid points and a chunk of the lines whose centre lies
+// within the largest cutting length of it. The wave stages 64 lines at a time in LDS (one per
+// lane) and evaluates each staged line that reaches the span at all its points, into per-lane
+// FP32 sums with a compensated flush every 16 lines. The Voigt profile takes the far-wing series
+// of order kKmax at every point outside the line's core (|z| >= the last series threshold); its
+// core points are added by k_core, whose classification (core_rel) is the same. The plinth is
+// subtracted at every point inside the cut, core points included.
+struct DirectLDS {
+  float4 F0[kWave];  // offset / scale, reference index - span start, dnu / scale, r (see stage_direct)
+  float4 F1[kWave];  // amplitude (Voigt: the series' leading coefficient), plinth
+  float4 KA[kWave];  // Voigt: series coefficients c1..c4 times the amplitude
+  float4 KB[kWave];  // Voigt: c5..c8
+  int4 B[kWave];     // span-local inclusive cut range, core range (empty: x > y)
+  uint8_t list[kWave];
+};
+
+// Stage one line for the span starting at span0; false: it adds nothing there. The scale is
+// sqrt(max(alpha^2, gamma^2)) (Voigt), gamma (Lorentz) or alpha (Doppler, binned Gaussian);
+// r is gamma^2 / scale^2 (Voigt) or dnu / (2 alpha) (binned Gaussian).
+template <int P, int PROF>
+__device__ __forceinline__ bool stage_direct(DirectLDS& L, int lane, const int4 gr, double nu0, float S, float gTv,
+                                             float pl, const PairDesc& pd, float zc, int64_t span0) {
+  constexpr int W = kWave * P;
+  const int jref = gr.y, jlo = gr.z, jhi = gr.w;
+  if (!(S > 0.0f) || jlo > jhi || (int64_t)jhi < span0 || (int64_t)jlo > span0 + (W - 1)) return false;
+  const float alpha = (float)(nu0 * pd.beta);
+  const float gam = gTv * (float)pd.pfac;
+  const float delta = __int_as_float(gr.x);
+  const float dnf = (float)pd.dnu;
+  const int64_t rl = (int64_t)jlo - span0, rh = (int64_t)jhi - span0;
+  const int clo = (int)(rl < -1 ? -1 : rl), chi = (int)(rh > W ? W : rh);
+  int czl = 1, czh = 0;
+  float rs, amp, r = 0.0f;
+  if (PROF == kProfVoigt) {
+    const float a2 = alpha * alpha, g2 = gam * gam;
+    const float sc = a2 > g2 ? a2 : g2;
+    if (!(sc > 0.0f)) return false;
+    rs = __frsqrt_rn(sc);
+    const float isc = rs * rs;
+    amp = S * (gam * isc) * 0.318309886183790672f;  // S gamma / (pi s)
+    const float av = a2 * isc, gv = g2 * isc;
+    r = gv;
+    const float a3 = av * av * av, a4 = a3 * av, gv2 = gv * gv, gv3 = gv2 * gv;
+    L.KA[lane] = make_float4(amp * (1.5f * av), amp * (-2.0f * av * gv + 3.75f * av * av),
+                             amp * (-15.0f * av * av * gv + 13.125f * a3),
+                             amp * (12.0f * av * av * gv2 - 105.0f * a3 * gv + 59.0625f * a4));
+    L.KB[lane] = make_float4(amp * (210.0f * a3 * gv2 - 787.5f * a4 * gv), amp * (-120.0f * a3 * gv3 + 2835.0f * a4 * gv2),
+                             amp * (-3780.0f * a4 * gv3), amp * (1680.0f * a4 * gv2 * gv2));
+    int rlo, rhi;
+    if (core_rel(alpha, gam, delta, (float)(1.0 / pd.dnu), zc, rlo, rhi)) {
+      const int64_t gl = (int64_t)jref + rlo - span0, gh = (int64_t)jref + rhi - span0;
+      czl = (int)(gl < -1 ? -1 : (gl > W ? W : gl));
+      czh = (int)(gh < -1 ? -1 : (gh > W ? W : gh));
+    }
+  } else if (PROF == kProfLorentz) {
+    if (!(gam > 0.0f)) return false;
+    rs = 1.0f / gam;
+    amp = S * rs * 0.318309886183790672f;  // S / (pi gamma)
+  } else {
+    if (!(alpha > 0.0f)) return false;
+    rs = 1.0f / alpha;
+    if (PROF == kProfDoppler) {
+      amp = S * rs * 0.564189583547756287f;  // S / (sqrt(pi) alpha)
+    } else {
+      amp = S / (2.0f * dnf);
+      r = 0.5f * dnf * rs;
+    }
+  }
+  L.F0[lane] = make_float4(delta * rs, (float)((int64_t)jref - span0), dnf * rs, r);
+  L.F1[lane] = make_float4(amp, pl, 0.0f, 0.0f);
+  L.B[lane] = make_int4(clo, chi, czl, czh);
+  return true;
+}
+
+// erf(b) - erf(a) for a <= b in FP32, from erfc where both have one sign (no cancellation of
+// values near 1).
+__device__ __forceinline__ float erf_diff(float a, float b) {
+  if (a >= 0.0f) return erfcf(a) - erfcf(b);
+  if (b <= 0.0f) return erfcf(-b) - erfcf(-a);
+  return erff(b) - erff(a);
+}
+
+// One staged line (uniform index l) at all P points of this lane.
+template <int P, int PROF>
+__device__ __forceinline__ void direct_eval(const DirectLDS& L, int l, int lane, float (&part)[P]) {
+  const float4 f0 = L.F0[l];
+  const float4 f1 = L.F1[l];
+  const int4 bb = L.B[l];
+  float4 ka = make_float4(0.f, 0.f, 0.f, 0.f), kb = ka;
+  if (PROF == kProfVoigt) {
+    ka = L.KA[l];
+    kb = L.KB[l];
+  }
+  const float kf0 = (float)lane - f0.y;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int j = lane + kWave * p;
+    const float D = __builtin_fmaf(kf0 + (float)(kWave * p), f0.z, f0.x);
+    float v;
+    if (PROF == kProfVoigt) {
+      const float q = __builtin_amdgcn_rcpf(__builtin_fmaf(D, D, f0.w));
+      float t = __builtin_fmaf(kb.w, q, kb.z);
+      t = __builtin_fmaf(t, q, kb.y);
+      t = __builtin_fmaf(t, q, kb.x);
+      t = __builtin_fmaf(t, q, ka.w);
+      t = __builtin_fmaf(t, q, ka.z);
+      t = __builtin_fmaf(t, q, ka.y);
+      t = __builtin_fmaf(t, q, ka.x);
+      t = __builtin_fmaf(t, q, f1.x);
+      v = (j >= bb.z && j <= bb.w) ? 0.0f : t * q;  // core points: k_core
+    } else if (PROF == kProfLorentz) {
+      v = f1.x * __builtin_amdgcn_rcpf(__builtin_fmaf(D, D, 1.0f));
+    } else if (PROF == kProfDoppler) {
+      v = f1.x * __builtin_amdgcn_exp2f(-(D * D) * 1.44269504088896341f);
+    } else {
+      v = f1.x * erf_diff(D - f0.w, D + f0.w);
+    }
+    const bool in = j >= bb.x && j <= bb.y;
+    part[p] += in ? v - f1.y : 0.0f;
+  }
+}
+
+template <int P, int PROF>
+__global__ __launch_bounds__(kWave) void k_direct(VoigtArgs a, const float* __restrict__ plin_all) {
+  constexpr int W = kWave * P;
+  __shared__ DirectLDS L;
+  const int lane = threadIdx.x;
+  const int total = a.item_base[a.n_tiles_total];
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const float zc = a.zK[kKmax - 1];
+  long long n_lines = 0;
+  for (;;) {
+    int mine = 0;
+    if (lane == 0) mine = atomicAdd(a.counter, 1);
+    const int it = __builtin_amdgcn_readfirstlane(mine);
+    if (it >= total) break;
+    int lo = 0, hi = a.n_tiles_total - 1;  // last span with item_base <= it
+    while (lo < hi) {
+      const int m = (lo + hi + 1) >> 1;
+      if (a.item_base[m] <= it) lo = m; else hi = m - 1;
+    }
+    const int g = lo;
+    const PairDesc pd = wave_uniform(a.pairs[find_pair(a.pairs, a.n_pairs, g)]);
+    const int ibase = __builtin_amdgcn_readfirstlane(a.item_base[g]);
+    const int nc = __builtin_amdgcn_readfirstlane(a.tile_nc[g]);
+    const int64_t span0 = (int64_t)(g - pd.tile_base) * W;
+    const int64_t line_lo = (int64_t)__builtin_amdgcn_readfirstlane(a.tile_lo[g]) + (int64_t)(it - ibase) * a.chunk;
+    int64_t line_hi = line_lo + a.chunk;
+    const int64_t thi = __builtin_amdgcn_readfirstlane(a.tile_hi[g]);
+    if (line_hi > thi) line_hi = thi;
+    const float* __restrict__ S_T = a.S_T + (int64_t)pd.tidx * a.N;
+    const float* __restrict__ gT = a.gT + (int64_t)pd.tidx * a.N;
+    const int4* __restrict__ grec = a.grec + (int64_t)pd.gidx * a.N;
+    const float* __restrict__ plin = plin_all ? plin_all + (int64_t)pd.gidx * a.N : nullptr;
+
+    float s[P], cc[P], part[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) { s[p] = 0.0f; cc[p] = 0.0f; part[p] = 0.0f; }
+    for (int64_t b = line_lo; b < line_hi; b += kWave) {
+      const int64_t li = b + lane;
+      bool ok = false;
+      if (li < line_hi)
+        ok = stage_direct<P, PROF>(L, lane, grec[li], a.nu[li], S_T[li], gT[li], plin ? plin[li] : 0.0f, pd, zc,
+                                   span0);
+      const uint64_t m = __ballot(ok);
+      if (ok) L.list[__popcll(m & lt)] = (uint8_t)lane;
+      const int cnt = (int)__popcll(m);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int i = 0; i < cnt; ++i) {
+        direct_eval<P, PROF>(L, __builtin_amdgcn_readfirstlane((int)L.list[i]), lane, part);
+        if ((i & 15) == 15) kahan_flush<P>(part, s, cc);
+      }
+      kahan_flush<P>(part, s, cc);
+      n_lines += cnt;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+      const int local = p * kWave + lane;
+      const float v = s[p] - cc[p];
+      if (nc == 1) {
+        if (span0 + local < pd.n) a.k[pd.out_off + span0 + local] = v;
+      } else if (it < a.items_cap) {
+        a.partial[((int64_t)it) * W + local] = v;
+      }
+    }
+    if (nc != 1 && it >= a.items_cap && a.status && lane == 0) atomicOr(a.status, 1);
+  }
+  if (a.stats && lane == 0) a.stats[blockIdx.x] = n_lines * W;
+}
+
+// Order-preserving map of doubles to unsigned 64-bit integers (integer max/min = FP64 max/min).
+__device__ __forceinline__ unsigned long long double_to_ordered(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__global__ void k_line_stats_init(unsigned long long* out) {
+  out[0] = 0ull;     // max gamma_ref
+  out[1] = ~0ull;    // min n
+  out[2] = 0ull;     // max n
+}
+
+// The list's largest gamma_ref and smallest and largest n (integer atomics on ordered words:
+// the result does not depend on the order).
+__global__ __launch_bounds__(kThreads) void k_line_stats(const double* __restrict__ gref,
+                                                        const double* __restrict__ nexp, int64_t N,
+                                                        unsigned long long* out) {
+  unsigned long long gmax = 0ull, nmin = ~0ull, nmax = 0ull;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const unsigned long long g = double_to_ordered(gref[i]), n = double_to_ordered(nexp[i]);
+    gmax = g > gmax ? g : gmax;
+    nmin = n < nmin ? n : nmin;
+    nmax = n > nmax ? n : nmax;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long a = __shfl_xor(gmax, off, 64), b = __shfl_xor(nmin, off, 64),
+                             c = __shfl_xor(nmax, off, 64);
+    gmax = a > gmax ? a : gmax;
+    nmin = b < nmin ? b : nmin;
+    nmax = c > nmax ? c : nmax;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(out, gmax);
+    atomicMin(out + 1, nmin);
+    atomicMax(out + 2, nmax);
+  }
+}
+
+// Per-line cut bounds and plinth values of sorted-order grid records, in the caller's order.
+__global__ __launch_bounds__(kThreads) void k_scatter_grec(const int4* __restrict__ grec,
+                                                          const float* __restrict__ plin,
+                                                          const int32_t* __restrict__ perm, int64_t N,
+                                                          int32_t* __restrict__ jlo, int32_t* __restrict__ jhi,
+                                                          float* __restrict__ plin_out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int4 g = grec[i];
+  const int32_t c = perm[i];
+  if (jlo) jlo[c] = g.z;
+  if (jhi) jhi[c] = g.w;
+  if (plin_out) plin_out[c] = plin ? plin[i] : 0.0f;
+}
+
+// ------------------------------------------------------- HITRAN widths and line shift
+// A HITRAN-style list adds per line the self-broadening coefficient gamma_self and the pressure
+// shift delta_air (Table binary2). At pressure P with self partial pressure P_self the Lorentz
+// half-width is eq. (gammaL) without the natural term, (T_ref/T)^n (gamma_air (P - P_self) +
+// gamma_self P_self)/P_ref, and the centre moves to nu* = nu + delta_air P/P_ref, which can change
+// the order along nu (Sec. 2.4.3 step 3): such a call bins the list again by nu*.
+
+// gamma_self >= 0 and finite, delta finite (flags[0] = 1 if not); out[0] = ordered max |delta|,
+// out[1] = ordered max gamma_self.
+__global__ __launch_bounds__(kThreads) void k_hitran_check(const double* __restrict__ gself,
+                                                          const double* __restrict__ delta, int64_t N, int* flags,
+                                                          unsigned long long* out) {
+  unsigned long long dmax = double_to_ordered(0.0), gmax = double_to_ordered(0.0);
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    const double g = gself[i], d = delta[i];
+    bad |= !(g >= 0.0) || isinf(g) || !isfinite(d);
+    const unsigned long long dw = double_to_ordered(fabs(d)), gw = double_to_ordered(g);
+    if (isfinite(d)) dmax = dw > dmax ? dw : dmax;
+    if (g >= 0.0 && !isinf(g)) gmax = gw > gmax ? gw : gmax;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const unsigned long long a = __shfl_xor(dmax, off, 64), b = __shfl_xor(gmax, off, 64);
+    dmax = a > dmax ? a : dmax;
+    gmax = b > gmax ? b : gmax;
+  }
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flags, 1);
+  if ((threadIdx.x & 63) == 0) {
+    atomicMax(out, dmax);
+    atomicMax(out + 1, gmax);
+  }
+}
+
+__global__ void k_hitran_check_init(int* flags, unsigned long long* out) {
+  flags[0] = 0;
+  out[0] = double_to_ordered(0.0);
+  out[1] = double_to_ordered(0.0);
+}
+
+// The two extra fields in the handle's (sorted) order: out[s] = in[perm[s]].
+__global__ __launch_bounds__(kThreads) void k_gather2(const int32_t* __restrict__ perm, int64_t N,
+                                                     const double* __restrict__ a, const double* __restrict__ b,
+                                                     double* __restrict__ oa, double* __restrict__ ob) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= N) return;
+  const int32_t c = perm[s];
+  oa[s] = a[c];
+  ob[s] = b[c];
+}
+
+// Keys of the shifted centres (handle order), with identity values for the radix sort.
+__global__ __launch_bounds__(kThreads) void k_shift_keys(const double* __restrict__ nu,
+                                                        const double* __restrict__ delta, int64_t N, double pshift,
+                                                        KeyMap km, uint32_t* __restrict__ keys,
+                                                        int32_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  keys[i] = bin_key(nu[i] + delta[i] * pshift, km);
+  vals[i] = (int32_t)i;
+}
+
+// The view of the list at one pressure, sorted by shifted centre: for view position s, handle
+// line i = src[s]: the transition wavenumber (strength and widths), the centre, S_ref, E'', the
+// reference width that gives the HITRAN half-width through gamma_ref (T_ref/T)^n P/P_ref, n, and
+// the caller index.
+__global__ __launch_bounds__(kThreads) void k_shift_gather(ShiftArgs a) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= a.N) return;
+  const int32_t i = a.src[s];
+  const double v = a.nu[i];
+  a.o_nu[s] = v;
+  a.o_pos[s] = v + a.delta[i] * a.pshift;
+  a.o_S[s] = a.Sref[i];
+  a.o_E[s] = a.E[i];
+  a.o_g[s] = a.P > 0.0 ? (a.gair[i] * (a.P - a.Pself) + a.gself[i] * a.Pself) / a.P : 0.0;
+  a.o_n[s] = a.nexp[i];
+  a.o_perm[s] = a.perm[i];
+}
+
+// ------------------------------------------------------------ streamed line lists
+// k[i] = 0 (a kernel, so that it may be recorded into a graph) and k[i] += t[i] (a chunk's
+// contribution, added in chunk order).
+__global__ __launch_bounds__(kThreads) void k_fill0(float* __restrict__ k, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) k[i] = 0.0f;
+}
+__global__ __launch_bounds__(kThreads) void k_accumulate(float* __restrict__ k, const float* __restrict__ t,
+                                                        int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) k[i] += t[i];
 }
 
 // ------------------------------------------------------------------------ adjoint
@@ -2264,9 +2766,11 @@ __global__ __launch_bounds__(kThreads) void k_combine(VoigtArgs a) {
   const PairDesc pd = a.pairs[find_pair(a.pairs, a.n_pairs, g)];
   const int64_t span0 = (int64_t)(g - pd.tile_base) * W;
   const int base = a.item_base[g];
+  // items beyond the partial rows were not stored (flagged by their pass): the span gets NaN
+  const bool lost = base + nc > a.items_cap;
   for (int local = threadIdx.x; local < W; local += kThreads) {
     if (span0 + local >= pd.n) continue;
-    double acc = 0.0;
+    double acc = lost ? (double)NAN : 0.0;
     for (int c = 0; c < nc && base + c < a.items_cap; ++c) acc += (double)a.partial[(int64_t)(base + c) * W + local];
     float* dst = a.k + pd.out_off + span0 + local;
     *dst = ADD ? *dst + (float)acc : (float)acc;
@@ -2326,12 +2830,12 @@ hipError_t launch_prep(const PrepArgs& a, float* S_T, float* gT, double* S64, do
   return hipGetLastError();
 }
 
-hipError_t launch_fill_pairs(const PairDesc* host_pairs, int count, PairDesc* dst, hipStream_t st) {
+hipError_t launch_fill_pairs(const PairDesc* host_pairs, int count, PairDesc* dst, int* status, hipStream_t st) {
   for (int c0 = 0; c0 < count; c0 += kFillPairs) {
     PairPack pk;
     pk.count = count - c0 < kFillPairs ? count - c0 : kFillPairs;
     for (int i = 0; i < pk.count; ++i) pk.p[i] = host_pairs[c0 + i];
-    hipLaunchKernelGGL(k_fill_pairs, dim3(1), dim3(64), 0, st, pk, dst + c0);
+    hipLaunchKernelGGL(k_fill_pairs, dim3(1), dim3(64), 0, st, pk, dst + c0, c0 == 0 ? status : nullptr);
   }
   return hipGetLastError();
 }
@@ -2340,10 +2844,10 @@ hipError_t launch_worklist(const uint32_t* keys, int64_t N, KeyMap km, double nu
                            const PairDesc* pairs, int n_pairs,
                            int n_tiles_total, int tile_w, double cut, double core_z, int chunk, int32_t* lo,
                            int32_t* hi, int32_t* nc, int4* far, int32_t* nf, int far_chunk, double far_z,
-                           hipStream_t st) {
+                           int direct_only, double core_pad, hipStream_t st) {
   hipLaunchKernelGGL(k_worklist, dim3(blocks_for(n_tiles_total, kThreads)), dim3(kThreads), 0, st, keys, N, km,
                      numin, numax, pairs, n_pairs, n_tiles_total, tile_w, cut, core_z, chunk, lo, hi, nc, far, nf,
-                     far_chunk, far_z);
+                     far_chunk, far_z, direct_only, core_pad);
   return hipGetLastError();
 }
 
@@ -2407,9 +2911,10 @@ struct CoreOcc {
 hipError_t launch_span_segments(const uint32_t* keys, int64_t N, KeyMap km, double numin, double numax,
                                 const PairDesc* spairs, const PairDesc* tpairs, int n_pairs, int n_spans,
                                 int span_w, double cut, double far_z, const int4* tile_far, int chunk,
-                                SpanSeg* segs, int32_t* nc, hipStream_t st) {
+                                SpanSeg* segs, int32_t* nc, int direct_only, hipStream_t st) {
   hipLaunchKernelGGL(k_span_segments, dim3(blocks_for(n_spans, kThreads)), dim3(kThreads), 0, st, keys, N, km,
-                     numin, numax, spairs, tpairs, n_pairs, n_spans, span_w, cut, far_z, tile_far, chunk, segs, nc);
+                     numin, numax, spairs, tpairs, n_pairs, n_spans, span_w, cut, far_z, tile_far, chunk, segs, nc,
+                     direct_only);
   return hipGetLastError();
 }
 
@@ -2480,8 +2985,108 @@ int wing_max_blocks_per_cu(int slots) {
   return nb > 0 ? nb : 1;
 }
 
+template <int P>
+struct DirectL {
+  static hipError_t run(const VoigtArgs& a, const float* plin, int prof, int grid, hipStream_t st) {
+    switch (prof) {
+      case kProfVoigt: hipLaunchKernelGGL((k_direct<P, kProfVoigt>), dim3(grid), dim3(kWave), 0, st, a, plin); break;
+      case kProfLorentz: hipLaunchKernelGGL((k_direct<P, kProfLorentz>), dim3(grid), dim3(kWave), 0, st, a, plin); break;
+      case kProfDoppler: hipLaunchKernelGGL((k_direct<P, kProfDoppler>), dim3(grid), dim3(kWave), 0, st, a, plin); break;
+      case kProfBinned: hipLaunchKernelGGL((k_direct<P, kProfBinned>), dim3(grid), dim3(kWave), 0, st, a, plin); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
+};
+
+hipError_t launch_direct(const VoigtArgs& a, const float* plin, int prof, int slots, int grid, hipStream_t st) {
+  return by_slots<DirectL>(slots, a, plin, prof, grid, st);
+}
+
+template <int P>
+struct DirectOcc {
+  static hipError_t run(int* nb) {
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(nb, k_direct<P, kProfBinned>, kWave, 0);
+  }
+};
+int direct_max_blocks_per_cu(int slots) {
+  int nb = 0;
+  (void)by_slots<DirectOcc>(slots, &nb);
+  return nb > 0 ? nb : 1;
+}
+
+hipError_t launch_gridrec_ex(const GridRecArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_gridrec_ex, dim3(blocks_for(a.pa.N, kThreads)), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_line_stats(const double* gref, const double* nexp, int64_t N, unsigned long long* out,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_line_stats_init, dim3(1), dim3(1), 0, st, out);
+  int64_t blocks = blocks_for(N, kThreads);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_line_stats, dim3((unsigned)blocks), dim3(kThreads), 0, st, gref, nexp, N, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_grec(const int4* grec, const float* plin, const int32_t* perm, int64_t N, int32_t* jlo,
+                               int32_t* jhi, float* plin_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter_grec, dim3(blocks_for(N, kThreads)), dim3(kThreads), 0, st, grec, plin, perm, N, jlo,
+                     jhi, plin_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_hitran_check(const double* gself, const double* delta, int64_t N, int* flags,
+                               unsigned long long* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_hitran_check_init, dim3(1), dim3(1), 0, st, flags, out);
+  int64_t blocks = blocks_for(N, kThreads);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_hitran_check, dim3((unsigned)blocks), dim3(kThreads), 0, st, gself, delta, N, flags, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather2(const int32_t* perm, int64_t N, const double* a, const double* b, double* oa, double* ob,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_gather2, dim3(blocks_for(N, kThreads)), dim3(kThreads), 0, st, perm, N, a, b, oa, ob);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift_keys(const double* nu, const double* delta, int64_t N, double pshift, KeyMap km,
+                             uint32_t* keys, int32_t* vals, hipStream_t st) {
+  hipLaunchKernelGGL(k_shift_keys, dim3(blocks_for(N, kThreads)), dim3(kThreads), 0, st, nu, delta, N, pshift, km,
+                     keys, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift_gather(const ShiftArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_shift_gather, dim3(blocks_for(a.N, kThreads)), dim3(kThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill0(float* k, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill0, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, k, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_accumulate(float* k, const float* t, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_accumulate, dim3(blocks_for(n, kThreads)), dim3(kThreads), 0, st, k, t, n);
+  return hipGetLastError();
+}
+
+hipError_t upload_weideman40(const double* coef, double L) {
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_weid40), coef, sizeof(double) * kWeidN40);
+  if (e != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_weid40L), &L, sizeof(double));
+}
+
 hipError_t upload_weideman(const double* coef, double L) {
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_weid), coef, sizeof(double) * kWeidN);
+  if (e != hipSuccess) return e;
+  float c32[kWeidN];
+  for (int i = 0; i < kWeidN; ++i) c32[i] = (float)coef[i];
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_weid32), c32, sizeof(float) * kWeidN);
   if (e != hipSuccess) return e;
   return hipMemcpyToSymbol(HIP_SYMBOL(c_weidL), &L, sizeof(double));
 }

@@ -96,3 +96,48 @@ def test_batched_matches_plain_and_graph_replays():
         del os.environ["HK_GRAPH"]
     assert torch.equal(eager, ref)
     lines.release()
+
+
+def test_batched_300_pairs_windows_vs_oracle():
+    """The benched form: the full 1e7-line list, all 300 (T, P) pairs in one launch, checked on 12
+    pairs (the corners and pairs across the grid of T and P) x 8 windows each against the oracle."""
+    import paper_2101_02005_amd as hk
+    w = linegen.workload("c3")
+    lines = _prep_device(w)
+    T = [t for t in w.T for _ in w.P]
+    P = [p for _ in w.T for p in w.P]
+    n_pairs = len(T)
+    assert n_pairs == 300
+    grd = hk.grid(w.nu_start, w.dnu, w.n_grid)
+    k = hk.hk_opacity_batched(lines, T, P, [grd] * n_pairs, w.cut)
+    nT, nP = len(w.T), len(w.P)
+    pick = sorted(set([0, nP - 1, (nT - 1) * nP, n_pairs - 1] +
+                      [it * nP + ip for it, ip in ((2, 3), (5, 11), (8, 7), (10, 0), (12, 14), (15, 5), (17, 9),
+                                                   (19, 2))]))
+    assert len(pick) >= 12
+    rows = k.view(n_pairs, -1)[pick].cpu().numpy()
+    lines.release()
+    sp = oracle.species(*w.species_tuple())
+    width = 16
+    fixed = [0, 100_000, 250_000, 420_000, 610_000, 800_000, w.n_grid - width]  # shared window starts
+    sel_cache = {}
+
+    def lines_for(s0):
+        if s0 not in sel_cache:
+            lo = w.nu_start + s0 * w.dnu - w.cut - 0.5
+            hi = w.nu_start + (s0 + width) * w.dnu + w.cut + 0.5
+            sel_cache[s0] = linegen.select(w.recipe(), w.seed, w.N, max(lo, 0.0), hi, cap=1 << 24)[1]
+        return sel_cache[s0]
+
+    for r, p in enumerate(pick):
+        kp = rows[r].astype(np.float64)
+        starts = fixed + [min(max(int(np.argmax(kp)) - width // 2, 0), w.n_grid - width)]
+        worst = 0.0
+        for s0 in starts:
+            pts = np.arange(s0, s0 + width)
+            ko = oracle.opacity(lines_for(s0), sp, T[p], P[p], w.nu_start, w.dnu, w.cut, pts)
+            e = rel_err(kp[pts], ko)
+            worst = max(worst, e)
+            assert e <= TOL_K, (T[p], P[p], s0, e)
+        print("300-pair launch, pair %d (T=%.1f K, P=%.3g atm): worst of %d windows %.3e"
+              % (p, T[p], P[p], len(starts), worst))

@@ -27,19 +27,23 @@ def _windows(w, k, rng, n_rand, width):
     return sorted(set(int(min(max(s, 0), n - width)) for s in starts))
 
 
-@pytest.mark.parametrize("cut", [25.0, 100.0])
-def test_large_list_windows(cut):
+@pytest.mark.parametrize("cut,dnu,direct", [(25.0, 0.01, 0), (100.0, 0.01, 0), (25.0, 0.1, 0), (100.0, 0.1, 0),
+                                             (25.0, 0.1, 1)])
+def test_large_list_windows(cut, dnu, direct):
+    """The full 5e8-line list at both resolutions and both cutting lengths; direct = 1: every
+    (line, point) pair evaluated (no Chebyshev-node classes)."""
     import torch
 
     import paper_2101_02005_amd as hk
-    w = linegen.workload("c2", cut=cut)
+    w = linegen.workload("c2", cut=cut, dnu=dnu)
     dev = _device_lines(w)
     lines = hk.hk_prepare_lines(*dev, hk.species(*w.species_tuple()))
     del dev
-    k = hk.hk_opacity(lines, w.T[0], w.P[0], hk.grid(w.nu_start, w.dnu, w.n_grid), w.cut).cpu().numpy()
+    k = hk.hk_opacity(lines, w.T[0], w.P[0], hk.grid(w.nu_start, w.dnu, w.n_grid), w.cut,
+                      opts=hk.options(direct=1) if direct else None).cpu().numpy()
     lines.release()
     torch.cuda.empty_cache()
-    rng = np.random.default_rng(20)
+    rng = np.random.default_rng(20 + int(cut) + int(100 * dnu))
     width = 24
     sp = oracle.species(*w.species_tuple())
     worst = 0.0
@@ -51,10 +55,10 @@ def test_large_list_windows(cut):
         ko = oracle.opacity(L, sp, w.T[0], w.P[0], w.nu_start, w.dnu, w.cut, pts)
         e = rel_err(k[pts].astype(np.float64), ko)
         worst = max(worst, e)
-        print("c2 cut %g window @%d (%.2f cm^-1): %d lines, max rel err %.3e" % (cut, s0, w.nu_start + s0 * w.dnu,
-                                                                                  len(L["nu"]), e))
+        print("c2 cut %g dnu %g direct %d window @%d (%.2f cm^-1): %d lines, max rel err %.3e"
+              % (cut, dnu, direct, s0, w.nu_start + s0 * w.dnu, len(L["nu"]), e))
         assert e <= TOL_K
-    print("c2 cut %g: worst window %.3e" % (cut, worst))
+    print("c2 cut %g dnu %g direct %d: worst window %.3e" % (cut, dnu, direct, worst))
 
 
 def test_uncut_precision_per_decade():
