@@ -295,6 +295,22 @@ hk_status hk_opacity_stream(const double* nu, const double* S_ref, const double*
                             const hk_options* options, int64_t chunk_lines, float* k, hipStream_t stream);
 
 /*
+ * hk_opacity_noalloc -- hk_opacity without a workspace argument, for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops). The workspace is a
+ * fixed device array of the library (hk_noalloc_max_bytes() bytes, held on each device the
+ * library runs on until the process ends); the call performs no device or host allocation.
+ * A problem whose workspace (hk_workspace_size mode 0 for the tuning in use) exceeds it returns
+ * HK_ENOMEM before any launch. Every call on a device shares that device's array: calls that
+ * overlap in time on one device (different streams, or different threads) race and must be
+ * serialized by the caller. Arguments, results and determinism as hk_opacity. Its work is
+ * tracked by hk_release_lines only on streams the handle has already been used on with another
+ * entry point; otherwise release waits for the whole device.
+ */
+hk_status hk_opacity_noalloc(const hk_lines* lines, const hk_line_override* ovr, double T, double P_atm,
+                             hk_grid grid, double cutoff, float* k, hipStream_t stream);
+size_t hk_noalloc_max_bytes(void);
+
+/*
  * hk_opacity_backward -- adjoint of L = sum_j dL_dk[j] k_j at one (T, P) (not in the paper;
  * derived from eqs. S1, alphaD and the ExoMol width). Strengths and widths are recomputed.
  *   dL_dk     : device float32[grid.n] upstream gradient.

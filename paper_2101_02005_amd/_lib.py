@@ -85,6 +85,8 @@ def load():
                            _vp, _sz, _vp], st),
         "hk_opacity_batched_ex": ([_vp, _i32, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), ctypes.POINTER(Grid),
                                    ctypes.POINTER(_i64), _dbl, ctypes.POINTER(Options), _vp, _vp, _sz, _vp], st),
+        "hk_opacity_noalloc": ([_vp, ctypes.POINTER(LineOverride), _dbl, _dbl, Grid, _dbl, _vp, _vp], st),
+        "hk_noalloc_max_bytes": ([], _sz),
         "hk_prepare_lines_hitran": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i64, ctypes.POINTER(Species), _vp,
                                      ctypes.POINTER(_vp)], st),
         "hk_workspace_size_hitran": ([_vp, _dbl, _dbl, _dbl, Grid, _dbl, ctypes.POINTER(Options), _vp,
@@ -324,6 +326,18 @@ def hk_opacity(lines, T, P_atm, grd, cutoff, k=None, ws=None, ovr=None, stream=N
                                     _stream(stream)))
     _keep_for_stream(stream, k if new_k else None, ws if new_ws else None)
     return k
+
+
+def hk_opacity_noalloc(lines, T, P_atm, grd, cutoff, k, ovr=None, stream=None):
+    """hk_opacity with the library's fixed scratch array as workspace: nothing is allocated (k is
+    the caller's float32 tensor of grd.n)."""
+    _check(load().hk_opacity_noalloc(ctypes.c_void_p(lines.handle), _override(ovr), float(T), float(P_atm), grd,
+                                     float(cutoff), _ptr(k), _stream(stream)))
+    return k
+
+
+def hk_noalloc_max_bytes():
+    return int(load().hk_noalloc_max_bytes())
 
 
 def hk_debug_grid_records(lines, T, P_atm, grd, cutoff, opts=None, stream=None):

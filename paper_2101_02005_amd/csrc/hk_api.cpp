@@ -117,6 +117,7 @@ struct DevInfo {
   float mask_x[4][hk::kMaskNodes] = {};
   int far_per_cu = 1;         // tile-far kernel occupancy
   int direct_per_cu[4] = {};  // direct-evaluation kernel occupancy per slots
+  void* scratch = nullptr;    // device address of the allocation-free entry point's scratch array
   unsigned long long* stats_buf = nullptr;  // device: line statistics (3 words)
 };
 std::mutex g_stats_mu;
@@ -211,6 +212,9 @@ hk_status device_init(int* dev_out, DevInfo* info) {
     HK_HIP(hk::upload_weideman40(a40, L40));
     DevInfo di;
     di.cus = prop.multiProcessorCount;
+    // the scratch array's address on this device (the device is current here)
+    HK_HIP(hk::scratch_address(&di.scratch));
+    if (!di.scratch) return fail(HK_EDEVICE, "scratch array has no device address");
     for (int si = 0; si < 4; ++si) {
       di.wing_per_cu[si] = hk::wing_max_blocks_per_cu(1 << si);
       di.core_per_cu[si] = hk::core_max_blocks_per_cu(1 << si);
@@ -1135,6 +1139,10 @@ hk_status opacity_impl(const hk_lines* lines, const hk_line_override* ovr, doubl
   DevInfo di;
   s = device_init(&dev, &di);
   if (s != HK_OK) return s;
+  if (scratch) {
+    ws = di.scratch;
+    ws_bytes = hk::kScratchBytes;
+  }
   s = check_opts(const_cast<hk_lines*>(lines), ovr, o, stream);
   if (s != HK_OK) return s;
   const int64_t zero = 0;
@@ -1624,6 +1632,15 @@ hk_status hk_opacity_ex(const hk_lines* lines, const hk_line_override* ovr, doub
   if (s == HK_OK) note_use(const_cast<hk_lines*>(lines), stream, true);
   return s;
 }
+
+hk_status hk_opacity_noalloc(const hk_lines* lines, const hk_line_override* ovr, double T, double P_atm,
+                             hk_grid grid, double cutoff, float* k, hipStream_t stream) {
+  hk_status s = opacity_impl(lines, ovr, T, P_atm, grid, cutoff, nullptr, k, nullptr, 0, stream, true);
+  if (s == HK_OK) note_use(const_cast<hk_lines*>(lines), stream, false);
+  return s;
+}
+
+size_t hk_noalloc_max_bytes(void) { return hk::kScratchBytes; }
 
 hk_status hk_opacity_batched(const hk_lines* lines, int32_t n_pairs, const double* T, const double* P_atm,
                              const hk_grid* grids, const int64_t* out_offset, double cutoff, float* k, void* ws,

@@ -292,6 +292,9 @@ struct ShiftArgs {
   int32_t* o_perm;
 };
 
+// Bytes of the fixed scratch array of the allocation-free entry point.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+
 // Launch wrappers (hk_kernels.hip); each returns the launch status.
 // flags[0]: a nu <= 0 or non-finite (k_validate); flags[1]: another field invalid (k_keys)
 hipError_t launch_validate(const double* nu, int64_t N, unsigned long long* mm, int* flags, hipStream_t st);
@@ -354,6 +357,8 @@ hipError_t launch_accumulate(float* k, const float* t, int64_t n, hipStream_t st
 // k_direct over the span work list of a (tile_lo/tile_hi/tile_nc/item_base), profile prof
 hipError_t launch_direct(const VoigtArgs& a, const float* plin, int prof, int slots, int grid, hipStream_t st);
 int direct_max_blocks_per_cu(int slots);
+// device address of the allocation-free entry point's scratch array on the current device
+hipError_t scratch_address(void** p);
 // out[0..2] = ordered words of max gamma_ref, min n, max n (see ordered_to_double)
 hipError_t launch_line_stats(const double* gref, const double* nexp, int64_t N, unsigned long long* out,
                              hipStream_t st);

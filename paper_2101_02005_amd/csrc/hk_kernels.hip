@@ -2353,6 +2353,16 @@ __global__ __launch_bounds__(kThreads) void k_accumulate(float* __restrict__ k, 
   if (i < n) k[i] += t[i];
 }
 
+// Scratch of the allocation-free entry point: a fixed device array that stands in for the
+// caller's workspace. Host code never names it as an address: it takes the array's device
+// address once per device (scratch_address) and passes that.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_address(void** p) {
+  *p = nullptr;
+  return hipGetSymbolAddress(p, HIP_SYMBOL(scratch));
+}
+
 // ------------------------------------------------------------------------ adjoint
 // w(x + iy) = K + iL in FP64 by the same rational approximation (both parts).
 __device__ __forceinline__ void weideman_w(double x, double y, double& K, double& L) {
