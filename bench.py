@@ -103,13 +103,13 @@ def count_evals(hk, lines, grd, cut):
 
 
 def cpu_baseline(w, n_total_evals):
-    """The FP64 oracle on a bounded sample of the same workload: 1500 grid points at
-    5000-5015 cm^-1 with every line within the cut of them."""
+    """The FP64 oracle on a bounded sample of the same workload: 2000 grid points at
+    5000-5020 cm^-1 with every line within the cut of them."""
     import numpy as np
 
     import linegen
     import oracle
-    nu_a, npts = 5000.0, 1500
+    nu_a, npts = 5000.0, 2000
     j0 = int(round((nu_a - w.nu_start) / w.dnu))
     pts = np.arange(j0, j0 + npts)
     lo = w.nu_start + j0 * w.dnu - w.cut - 1.0
@@ -353,7 +353,7 @@ def bench_options(hk, n_lines, repeats=3):
     del dev
     grd = hk.grid(w.nu_start, w.dnu, w.n_grid)
     T, P = w.T[0], w.P[0]
-    cases = [("voigt", dict(profile=0), w.cut), ("voigt_plinth", dict(profile=0, plinth=1), w.cut),
+    cases = [("voigt_plinth", dict(profile=0, plinth=1), w.cut),
              ("lorentz", dict(profile=1), w.cut), ("doppler", dict(profile=2), w.cut),
              ("binned_gauss", dict(profile=3), w.cut), ("voigt_lorentz_cut_plinth", dict(cut_mode=2, plinth=1), 500.0),
              ("voigt_doppler_cut", dict(cut_mode=1), 1000.0)]
@@ -413,12 +413,13 @@ def bench_stream(hk, n_lines, chunk):
     grd = hk.grid(w.nu_start, w.dnu, w.n_grid)
     k = torch.empty(w.n_grid, dtype=torch.float32, device="cuda")
     with _env(HK_TIMING=None):
-        t0 = time.perf_counter()
-        ln = hk.hk_prepare_lines(*dev, sp)
-        hk.hk_opacity(ln, w.T[0], w.P[0], grd, w.cut, k=k)
-        torch.cuda.synchronize()
-        ln.release()
-        t_res = time.perf_counter() - t0
+        for _ in range(2):  # the first pass tunes the list size's key; the second is timed
+            t0 = time.perf_counter()
+            ln = hk.hk_prepare_lines(*dev, sp)
+            hk.hk_opacity(ln, w.T[0], w.P[0], grd, w.cut, k=k)
+            torch.cuda.synchronize()
+            ln.release()
+            t_res = time.perf_counter() - t0
         del dev
         torch.cuda.empty_cache()
         hk.hk_opacity_stream(*host, sp, w.T[0], w.P[0], grd, w.cut, int(chunk), k=k)  # warms the block cache
@@ -569,6 +570,7 @@ def main():
             "evals_made": made, "evals_made_per_s": made / (interp_ms * 1e-3),
             "wing_pairs_per_s": wing_pairs / (interp_ms * 1e-3),
             "speedup_vs_direct": direct["k_wing_ms"] / interp_ms,
+            "traffic": wing_traffic(N, w.cut, w.dnu, tm.tile_width),
             "frac_fp32_on_evals_made": FLOPS_PER_EVAL * made / (interp_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS,
             "class_evals": cls},
         "direct": direct,

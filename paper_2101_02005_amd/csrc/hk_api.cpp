@@ -486,6 +486,16 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
     for (int p = 0; p < n_pairs; ++p) cut = std::max(cut, max_cut_length(L, opts, cut_arg, T[p], P[p]));
     if (!(cut > 0.0)) cut = 1e-300;  // every line's cut is empty but its centre point (gamma = 0)
   }
+  if (!dflt && (opts.profile == hk::kProfDoppler || opts.profile == hk::kProfBinned) && T) {
+    // a Gaussian line reaches no further than 9 alpha (+ a bin) above e^-81 of its peak: the
+    // window need not (k_direct evaluates only those points)
+    double reach = 0.0;
+    for (int p = 0; p < n_pairs; ++p) {
+      const double a = std::sqrt(2.0 * kB * T[p] / (L->sp.mass_amu * kAMU)) / kC * std::fabs(L->numax);
+      reach = std::max(reach, (9.0 * a + 2.0 * grids[p].dnu) * (1.0 + 1e-6));
+    }
+    cut = std::min(cut, reach);
+  }
   pl->cut_w = cut;
   if (L->shift_max > 0.0 && T) {
     double bmax = 0.0;

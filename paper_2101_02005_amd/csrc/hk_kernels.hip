@@ -23,7 +23,6 @@
 namespace hk {
 
 __constant__ double c_weid[kWeidN];  // Weideman (1994) coefficients a_1..a_N (host-computed)
-__constant__ float c_weid32[kWeidN]; // the same rounded to FP32 (the high-order steps of the core pass)
 __constant__ double c_weidL;         // its scale L = sqrt(N / sqrt 2)
 
 // grid point nu_j = nu_start + j dnu: a rounded product, then a rounded sum (no FMA)
@@ -642,36 +641,6 @@ __device__ __forceinline__ void weideman_poly(double Zr, double Zi, double& pr, 
   pi = Zi * b1;
 }
 
-// The same polynomial with the recurrence's high-order steps (m >= kWeidSplit) in FP32: the
-// coefficients of those steps are at most 0.02 (the first ones reach 1.9), so their FP32 rounding
-// stays far below the approximation's own error (checked over |z| < 6.75 against scipy's wofz:
-// largest error 7.40e-9 of the profile's peak with the split at 6, against 7.37e-9 all in FP64);
-// the low-order steps, which carry the large coefficients, stay FP64. Ten of the fifteen steps
-// run at the FP32 rate.
-constexpr int kWeidSplit = 6;
-static_assert(kWeidSplit >= 2 && kWeidSplit <= kWeidN - 3, "split inside the recurrence");
-__device__ __forceinline__ void weideman_poly_mixed(double Zr, double Zi, double& pr, double& pi) {
-  const double r = 2.0 * Zr, s = fma(Zr, Zr, Zi * Zi);
-  const float rf = (float)r, sf = (float)s;
-  float f2 = c_weid32[kWeidN - 1];
-  float f1 = __builtin_fmaf(rf, f2, c_weid32[kWeidN - 2]);
-#pragma unroll
-  for (int m = kWeidN - 3; m >= kWeidSplit; --m) {
-    const float t = __builtin_fmaf(rf, f1, __builtin_fmaf(-sf, f2, c_weid32[m]));
-    f2 = f1;
-    f1 = t;
-  }
-  double b2 = (double)f2, b1 = (double)f1;
-#pragma unroll
-  for (int m = kWeidSplit - 1; m >= 1; --m) {
-    const double t = fma(r, b1, fma(-s, b2, c_weid[m]));
-    b2 = b1;
-    b1 = t;
-  }
-  pr = fma(Zr, b1, fma(-s, b2, c_weid[0]));
-  pi = Zi * b1;
-}
-
 __device__ __forceinline__ double weideman_re(double x, double y) {
   const double L = c_weidL;
   const double dr = L + y, di = -x;  // L - iz
@@ -680,7 +649,7 @@ __device__ __forceinline__ double weideman_re(double x, double y) {
   // Z = (L + iz)/(L - iz) = 2 L u - 1
   const double Zr = fma(2.0 * L, ur, -1.0), Zi = 2.0 * L * ui;
   double pr, pi;
-  weideman_poly_mixed(Zr, Zi, pr, pi);
+  weideman_poly(Zr, Zi, pr, pi);
   // Re(2 p u^2 + u/sqrt(pi)) = Re(u t), t = 2 p u + 1/sqrt(pi)
   const double tr = 2.0 * fma(pr, ur, -pi * ui) + 0.56418958354775628695;
   const double ti = 2.0 * fma(pr, ui, pi * ur);
@@ -2041,7 +2010,7 @@ __device__ __forceinline__ bool stage_direct(DirectLDS& L, int lane, const int4 
   const float delta = __int_as_float(gr.x);
   const float dnf = (float)pd.dnu;
   const int64_t rl = (int64_t)jlo - span0, rh = (int64_t)jhi - span0;
-  const int clo = (int)(rl < -1 ? -1 : rl), chi = (int)(rh > W ? W : rh);
+  int clo = (int)(rl < -1 ? -1 : rl), chi = (int)(rh > W ? W : rh);
   int czl = 1, czh = 0;
   float rs, amp, r = 0.0f;
   if (PROF == kProfVoigt) {
@@ -2072,6 +2041,17 @@ __device__ __forceinline__ bool stage_direct(DirectLDS& L, int lane, const int4 
   } else {
     if (!(alpha > 0.0f)) return false;
     rs = 1.0f / alpha;
+    // a Gaussian (or its bin average) is below e^-81 of its peak beyond 9 alpha (+ a bin):
+    // only those points are evaluated (the window of the work list is cut the same way)
+    const float inv = 1.0f / dnf;
+    const float cen = (float)((int64_t)jref - span0) - delta * inv;
+    const float R = (9.0f * alpha + dnf) * inv + 1.0f;
+    const float fl = fmaxf(fminf(floorf(cen - R), (float)(W + 1)), -2.0f);
+    const float fh = fmaxf(fminf(ceilf(cen + R), (float)(W + 1)), -2.0f);
+    const int gl = (int)fl, gh = (int)fh;
+    if (gl > clo) clo = gl;
+    if (gh < chi) chi = gh;
+    if (clo > chi || chi < 0 || clo > W - 1) return false;
     if (PROF == kProfDoppler) {
       amp = S * rs * 0.564189583547756287f;  // S / (sqrt(pi) alpha)
     } else {
@@ -3093,10 +3073,6 @@ hipError_t upload_weideman40(const double* coef, double L) {
 
 hipError_t upload_weideman(const double* coef, double L) {
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_weid), coef, sizeof(double) * kWeidN);
-  if (e != hipSuccess) return e;
-  float c32[kWeidN];
-  for (int i = 0; i < kWeidN; ++i) c32[i] = (float)coef[i];
-  e = hipMemcpyToSymbol(HIP_SYMBOL(c_weid32), c32, sizeof(float) * kWeidN);
   if (e != hipSuccess) return e;
   return hipMemcpyToSymbol(HIP_SYMBOL(c_weidL), &L, sizeof(double));
 }
