@@ -350,9 +350,11 @@ def bench_options(hk, n_lines, repeats=3):
     w = linegen.workload("c4", N=int(n_lines))
     dev = _device_list(w, w.N)
     lines = hk.hk_prepare_lines(*dev, hk.species(*w.species_tuple()))
+    nu = dev[0]
     del dev
     grd = hk.grid(w.nu_start, w.dnu, w.n_grid)
     T, P = w.T[0], w.P[0]
+    alpha = hk.hk_debug_line_params(lines, T, P)[1]
     cases = [("voigt_plinth", dict(profile=0, plinth=1), w.cut),
              ("lorentz", dict(profile=1), w.cut), ("doppler", dict(profile=2), w.cut),
              ("binned_gauss", dict(profile=3), w.cut), ("voigt_lorentz_cut_plinth", dict(cut_mode=2, plinth=1), 500.0),
@@ -378,20 +380,34 @@ def bench_options(hk, n_lines, repeats=3):
                 tc.append(tm.core_ms if tm.core_ms > 0 else 0.0)
         made = tm.class_evals[0]  # lines staged per span x span points (points outside a cut included)
         lo, hi, _ = hk.hk_debug_grid_records(lines, T, P, grd, cut, opts)
-        pairs = int((hi.to(torch.int64) - lo.to(torch.int64) + 1).clamp_(min=0).sum().item())
+        lo, hi = lo.to(torch.int64), hi.to(torch.int64)
+        pairs = int((hi - lo + 1).clamp_(min=0).sum().item())
+        prof = kw.get("profile", 0)
+        if prof in (2, 3):
+            # a Gaussian (or its bin average) is below e^-81 of its peak beyond 9 alpha + a bin
+            # from the centre: the pairs that carry a value are those within that reach
+            cen = (nu - w.nu_start) / w.dnu
+            reach = (9.0 * alpha + w.dnu) / w.dnu
+            glo = torch.maximum(lo, torch.ceil(cen - reach).to(torch.int64))
+            ghi = torch.minimum(hi, torch.floor(cen + reach).to(torch.int64))
+            work = int((ghi - glo + 1).clamp_(min=0).sum().item())
+            del glo, ghi, cen, reach
+        else:
+            work = pairs - tm.core_evals if prof == 0 else pairs
         del lo, hi
         t_d = _median(td)
-        ach = FLOPS_PER_EVAL * (pairs - tm.core_evals if kw.get("profile", 0) == 0 else pairs) / (t_d * 1e-3) / 1e12
+        ach = FLOPS_PER_EVAL * work / (t_d * 1e-3) / 1e12
         out[name] = {"cut": cut, "opacity_s": _median(tt), "k_direct_ms": t_d, "k_core_ms": _median(tc),
-                     "pairs": pairs, "core_pairs": tm.core_evals if kw.get("profile", 0) == 0 else 0,
-                     "pairs_per_s": pairs / _median(tt), "span_evals_made": made,
+                     "pairs": pairs, "core_pairs": tm.core_evals if prof == 0 else 0,
+                     "pairs_evaluated": work, "pairs_per_s": pairs / _median(tt), "span_evals_made": made,
                      "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                                   "frac": ach / PEAK_FP32_TFLOPS, "flops_per_pair": FLOPS_PER_EVAL,
-                                  "kernel": "k_direct (pairs outside the Voigt cores)"}}
+                                  "kernel": "k_direct (pairs_evaluated: outside the Voigt cores; Gaussians "
+                                            "within 9 alpha + a bin)"}}
         del ws
         print("bench: options %s done" % name, file=sys.stderr, flush=True)
     lines.release()
-    del k
+    del k, nu, alpha
     torch.cuda.empty_cache()
     return out
 

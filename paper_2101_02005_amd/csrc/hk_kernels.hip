@@ -1984,9 +1984,10 @@ __global__ __launch_bounds__(kThreads) void k_gridrec_ex(GridRecArgs a) {
 // within the largest cutting length of it. The wave stages 64 lines at a time in LDS (one per
 // lane) and evaluates each staged line that reaches the span at all its points, into per-lane
 // FP32 sums with a compensated flush every 16 lines. The Voigt profile takes the far-wing series
-// of order kKmax at every point outside the line's core (|z| >= the last series threshold); its
-// core points are added by k_core, whose classification (core_rel) is the same. The plinth is
-// subtracted at every point inside the cut, core points included.
+// of the order the line's points on the span need (the wing pass's zones) at every point outside
+// the line's core (|z| >= the last series threshold); its core points are added by k_core, whose
+// classification (core_rel) is the same. The plinth is subtracted at every point inside the cut,
+// core points included.
 struct DirectLDS {
   float4 F0[kWave];  // offset / scale, reference index - span start, dnu / scale, r (see stage_direct)
   float4 F1[kWave];  // amplitude (Voigt: the series' leading coefficient), plinth
@@ -1998,10 +1999,14 @@ struct DirectLDS {
 
 // Stage one line for the span starting at span0; false: it adds nothing there. The scale is
 // sqrt(max(alpha^2, gamma^2)) (Voigt), gamma (Lorentz) or alpha (Doppler, binned Gaussian);
-// r is gamma^2 / scale^2 (Voigt) or dnu / (2 alpha) (binned Gaussian).
+// r is gamma^2 / scale^2 (Voigt) or dnu / (2 alpha) (binned Gaussian). For the Voigt profile the
+// series order K is the one the line's points on the span need (as in the wing pass: one more
+// term per zone |z| < zK of the thresholds the points reach), and KA, KB hold that order's
+// coefficients c1..c(2K-2) (zero beyond).
 template <int P, int PROF>
 __device__ __forceinline__ bool stage_direct(DirectLDS& L, int lane, const int4 gr, double nu0, float S, float gTv,
-                                             float pl, const PairDesc& pd, float zc, int64_t span0) {
+                                             float pl, const PairDesc& pd, const float* zK, int64_t span0) {
+  const float zc = zK[kKmax - 1];
   constexpr int W = kWave * P;
   const int jref = gr.y, jlo = gr.z, jhi = gr.w;
   if (!(S > 0.0f) || jlo > jhi || (int64_t)jhi < span0 || (int64_t)jlo > span0 + (W - 1)) return false;
@@ -2012,7 +2017,7 @@ __device__ __forceinline__ bool stage_direct(DirectLDS& L, int lane, const int4 
   const int64_t rl = (int64_t)jlo - span0, rh = (int64_t)jhi - span0;
   int clo = (int)(rl < -1 ? -1 : rl), chi = (int)(rh > W ? W : rh);
   int czl = 1, czh = 0;
-  float rs, amp, r = 0.0f;
+  float rs, amp, r = 0.0f, order = 1.0f;
   if (PROF == kProfVoigt) {
     const float a2 = alpha * alpha, g2 = gam * gam;
     const float sc = a2 > g2 ? a2 : g2;
@@ -2022,12 +2027,40 @@ __device__ __forceinline__ bool stage_direct(DirectLDS& L, int lane, const int4 
     amp = S * (gam * isc) * 0.318309886183790672f;  // S gamma / (pi s)
     const float av = a2 * isc, gv = g2 * isc;
     r = gv;
+    // the order the line's points on the span need: zones |z| < zK[z] around the centre c
+    const float inv_dnu = (float)(1.0 / pd.dnu);
+    const float af = alpha * inv_dnu, gf = gam * inv_dnu;
+    const float c = (float)((int64_t)jref - span0) - delta * inv_dnu;
+    const float x0 = (float)(clo > 0 ? clo : 0), x1 = (float)(chi < W - 1 ? chi : W - 1);
+    int K = 1;
+#pragma unroll
+    for (int z = 0; z < kKmax - 1; ++z) {
+      const float zz = zK[z] * af;
+      const float h2 = zz * zz - gf * gf;
+      const float h = h2 > 0.0f ? __builtin_amdgcn_sqrtf(h2) * 1.00001f + 1e-3f : -1.0f;
+      K += (h > 0.0f && x0 < c + h && x1 > c - h) ? 1 : 0;
+    }
+    order = (float)K;
     const float a3 = av * av * av, a4 = a3 * av, gv2 = gv * gv, gv3 = gv2 * gv;
-    L.KA[lane] = make_float4(amp * (1.5f * av), amp * (-2.0f * av * gv + 3.75f * av * av),
-                             amp * (-15.0f * av * av * gv + 13.125f * a3),
-                             amp * (12.0f * av * av * gv2 - 105.0f * a3 * gv + 59.0625f * a4));
-    L.KB[lane] = make_float4(amp * (210.0f * a3 * gv2 - 787.5f * a4 * gv), amp * (-120.0f * a3 * gv3 + 2835.0f * a4 * gv2),
-                             amp * (-3780.0f * a4 * gv3), amp * (1680.0f * a4 * gv2 * gv2));
+    float4 ka = make_float4(0.f, 0.f, 0.f, 0.f), kb = ka;
+    if (K == 2) {
+      ka = make_float4(amp * (1.5f * av), amp * (-2.0f * av * gv), 0.f, 0.f);
+    } else if (K == 3) {
+      ka = make_float4(amp * (1.5f * av), amp * (-2.0f * av * gv + 3.75f * av * av), amp * (-15.0f * av * av * gv),
+                       amp * (12.0f * av * av * gv2));
+    } else if (K == 4) {
+      ka = make_float4(amp * (1.5f * av), amp * (-2.0f * av * gv + 3.75f * av * av),
+                       amp * (-15.0f * av * av * gv + 13.125f * a3), amp * (12.0f * av * av * gv2 - 105.0f * a3 * gv));
+      kb = make_float4(amp * (210.0f * a3 * gv2), amp * (-120.0f * a3 * gv3), 0.f, 0.f);
+    } else if (K == 5) {
+      ka = make_float4(amp * (1.5f * av), amp * (-2.0f * av * gv + 3.75f * av * av),
+                       amp * (-15.0f * av * av * gv + 13.125f * a3),
+                       amp * (12.0f * av * av * gv2 - 105.0f * a3 * gv + 59.0625f * a4));
+      kb = make_float4(amp * (210.0f * a3 * gv2 - 787.5f * a4 * gv), amp * (-120.0f * a3 * gv3 + 2835.0f * a4 * gv2),
+                       amp * (-3780.0f * a4 * gv3), amp * (1680.0f * a4 * gv2 * gv2));
+    }
+    L.KA[lane] = ka;
+    L.KB[lane] = kb;
     int rlo, rhi;
     if (core_rel(alpha, gam, delta, (float)(1.0 / pd.dnu), zc, rlo, rhi)) {
       const int64_t gl = (int64_t)jref + rlo - span0, gh = (int64_t)jref + rhi - span0;
@@ -2060,7 +2093,7 @@ __device__ __forceinline__ bool stage_direct(DirectLDS& L, int lane, const int4 
     }
   }
   L.F0[lane] = make_float4(delta * rs, (float)((int64_t)jref - span0), dnf * rs, r);
-  L.F1[lane] = make_float4(amp, pl, 0.0f, 0.0f);
+  L.F1[lane] = make_float4(amp, pl, order, 0.0f);
   L.B[lane] = make_int4(clo, chi, czl, czh);
   return true;
 }
@@ -2073,35 +2106,85 @@ __device__ __forceinline__ float erf_diff(float a, float b) {
   return erff(b) - erff(a);
 }
 
-// One staged line (uniform index l) at all P points of this lane.
-template <int P, int PROF>
-__device__ __forceinline__ void direct_eval(const DirectLDS& L, int l, int lane, float (&part)[P]) {
+// The Voigt far-wing series of order K in q (coefficients c1..c(2K-2) in ka, kb; c0 = amp).
+template <int K>
+__device__ __forceinline__ float voigt_series(float q, const float4& ka, const float4& kb, float amp) {
+  float t;
+  if (K == 1) {
+    t = amp;
+  } else if (K == 2) {
+    t = __builtin_fmaf(ka.y, q, ka.x);
+    t = __builtin_fmaf(t, q, amp);
+  } else if (K == 3) {
+    t = __builtin_fmaf(ka.w, q, ka.z);
+    t = __builtin_fmaf(t, q, ka.y);
+    t = __builtin_fmaf(t, q, ka.x);
+    t = __builtin_fmaf(t, q, amp);
+  } else if (K == 4) {
+    t = __builtin_fmaf(kb.y, q, kb.x);
+    t = __builtin_fmaf(t, q, ka.w);
+    t = __builtin_fmaf(t, q, ka.z);
+    t = __builtin_fmaf(t, q, ka.y);
+    t = __builtin_fmaf(t, q, ka.x);
+    t = __builtin_fmaf(t, q, amp);
+  } else {
+    t = __builtin_fmaf(kb.w, q, kb.z);
+    t = __builtin_fmaf(t, q, kb.y);
+    t = __builtin_fmaf(t, q, kb.x);
+    t = __builtin_fmaf(t, q, ka.w);
+    t = __builtin_fmaf(t, q, ka.z);
+    t = __builtin_fmaf(t, q, ka.y);
+    t = __builtin_fmaf(t, q, ka.x);
+    t = __builtin_fmaf(t, q, amp);
+  }
+  return t * q;
+}
+
+// One staged Voigt line of series order K at all P points of this lane.
+template <int P, int K>
+__device__ __forceinline__ void direct_voigt(const DirectLDS& L, int l, int lane, float (&part)[P]) {
   const float4 f0 = L.F0[l];
   const float4 f1 = L.F1[l];
   const int4 bb = L.B[l];
   float4 ka = make_float4(0.f, 0.f, 0.f, 0.f), kb = ka;
-  if (PROF == kProfVoigt) {
-    ka = L.KA[l];
-    kb = L.KB[l];
+  if (K >= 2) ka = L.KA[l];
+  if (K >= 4) kb = L.KB[l];
+  const float kf0 = (float)lane - f0.y;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const int j = lane + kWave * p;
+    const float D = __builtin_fmaf(kf0 + (float)(kWave * p), f0.z, f0.x);
+    const float q = __builtin_amdgcn_rcpf(__builtin_fmaf(D, D, f0.w));
+    const float v = voigt_series<K>(q, ka, kb, f1.x);
+    // core points (k_core's) take only the plinth; excluded points may have q infinite
+    const float t = (j >= bb.z && j <= bb.w) ? 0.0f : v;
+    const bool in = j >= bb.x && j <= bb.y;
+    part[p] += in ? t - f1.y : 0.0f;
   }
+}
+
+// One staged line (uniform index l) at all P points of this lane.
+template <int P, int PROF>
+__device__ __forceinline__ void direct_eval(const DirectLDS& L, int l, int lane, float (&part)[P]) {
+  if (PROF == kProfVoigt) {
+    const int K = __builtin_amdgcn_readfirstlane(__float_as_int(L.F1[l].z));  // the line's order (uniform)
+    if (K == __float_as_int(1.0f)) direct_voigt<P, 1>(L, l, lane, part);
+    else if (K == __float_as_int(2.0f)) direct_voigt<P, 2>(L, l, lane, part);
+    else if (K == __float_as_int(3.0f)) direct_voigt<P, 3>(L, l, lane, part);
+    else if (K == __float_as_int(4.0f)) direct_voigt<P, 4>(L, l, lane, part);
+    else direct_voigt<P, 5>(L, l, lane, part);
+    return;
+  }
+  const float4 f0 = L.F0[l];
+  const float4 f1 = L.F1[l];
+  const int4 bb = L.B[l];
   const float kf0 = (float)lane - f0.y;
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     const int j = lane + kWave * p;
     const float D = __builtin_fmaf(kf0 + (float)(kWave * p), f0.z, f0.x);
     float v;
-    if (PROF == kProfVoigt) {
-      const float q = __builtin_amdgcn_rcpf(__builtin_fmaf(D, D, f0.w));
-      float t = __builtin_fmaf(kb.w, q, kb.z);
-      t = __builtin_fmaf(t, q, kb.y);
-      t = __builtin_fmaf(t, q, kb.x);
-      t = __builtin_fmaf(t, q, ka.w);
-      t = __builtin_fmaf(t, q, ka.z);
-      t = __builtin_fmaf(t, q, ka.y);
-      t = __builtin_fmaf(t, q, ka.x);
-      t = __builtin_fmaf(t, q, f1.x);
-      v = (j >= bb.z && j <= bb.w) ? 0.0f : t * q;  // core points: k_core
-    } else if (PROF == kProfLorentz) {
+    if (PROF == kProfLorentz) {
       v = f1.x * __builtin_amdgcn_rcpf(__builtin_fmaf(D, D, 1.0f));
     } else if (PROF == kProfDoppler) {
       v = f1.x * __builtin_amdgcn_exp2f(-(D * D) * 1.44269504088896341f);
@@ -2120,7 +2203,6 @@ __global__ __launch_bounds__(kWave) void k_direct(VoigtArgs a, const float* __re
   const int lane = threadIdx.x;
   const int total = a.item_base[a.n_tiles_total];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const float zc = a.zK[kKmax - 1];
   long long n_lines = 0;
   for (;;) {
     int mine = 0;
@@ -2153,7 +2235,7 @@ __global__ __launch_bounds__(kWave) void k_direct(VoigtArgs a, const float* __re
       const int64_t li = b + lane;
       bool ok = false;
       if (li < line_hi)
-        ok = stage_direct<P, PROF>(L, lane, grec[li], a.nu[li], S_T[li], gT[li], plin ? plin[li] : 0.0f, pd, zc,
+        ok = stage_direct<P, PROF>(L, lane, grec[li], a.nu[li], S_T[li], gT[li], plin ? plin[li] : 0.0f, pd, a.zK,
                                    span0);
       const uint64_t m = __ballot(ok);
       if (ok) L.list[__popcll(m & lt)] = (uint8_t)lane;
