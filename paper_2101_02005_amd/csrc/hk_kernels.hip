@@ -1988,6 +1988,9 @@ __global__ __launch_bounds__(kThreads) void k_gridrec_ex(GridRecArgs a) {
 // the line's core (|z| >= the last series threshold); its core points are added by k_core, whose
 // classification (core_rel) is the same. The plinth is subtracted at every point inside the cut,
 // core points included.
+// Staged lines are grouped: 1-5 (Voigt: series order; Lorentz: 1) for lines whose cut covers
+// the whole span with no core point on it, evaluated without masks; kDirGeneral for the rest.
+constexpr int kDirGeneral = kKmax + 1;
 struct DirectLDS {
   float4 F0[kWave];  // offset / scale, reference index - span start, dnu / scale, r (see stage_direct)
   float4 F1[kWave];  // amplitude (Voigt: the series' leading coefficient), plinth
@@ -1997,19 +2000,19 @@ struct DirectLDS {
   uint8_t list[kWave];
 };
 
-// Stage one line for the span starting at span0; false: it adds nothing there. The scale is
+// Stage one line for the span starting at span0; its group, 0: it adds nothing there. The scale is
 // sqrt(max(alpha^2, gamma^2)) (Voigt), gamma (Lorentz) or alpha (Doppler, binned Gaussian);
 // r is gamma^2 / scale^2 (Voigt) or dnu / (2 alpha) (binned Gaussian). For the Voigt profile the
 // series order K is the one the line's points on the span need (as in the wing pass: one more
 // term per zone |z| < zK of the thresholds the points reach), and KA, KB hold that order's
 // coefficients c1..c(2K-2) (zero beyond).
 template <int P, int PROF>
-__device__ __forceinline__ bool stage_direct(DirectLDS& L, int lane, const int4 gr, double nu0, float S, float gTv,
-                                             float pl, const PairDesc& pd, const float* zK, int64_t span0) {
+__device__ __forceinline__ int stage_direct(DirectLDS& L, int lane, const int4 gr, double nu0, float S, float gTv,
+                                            float pl, const PairDesc& pd, const float* zK, int64_t span0) {
   const float zc = zK[kKmax - 1];
   constexpr int W = kWave * P;
   const int jref = gr.y, jlo = gr.z, jhi = gr.w;
-  if (!(S > 0.0f) || jlo > jhi || (int64_t)jhi < span0 || (int64_t)jlo > span0 + (W - 1)) return false;
+  if (!(S > 0.0f) || jlo > jhi || (int64_t)jhi < span0 || (int64_t)jlo > span0 + (W - 1)) return 0;
   const float alpha = (float)(nu0 * pd.beta);
   const float gam = gTv * (float)pd.pfac;
   const float delta = __int_as_float(gr.x);
@@ -2021,7 +2024,7 @@ __device__ __forceinline__ bool stage_direct(DirectLDS& L, int lane, const int4 
   if (PROF == kProfVoigt) {
     const float a2 = alpha * alpha, g2 = gam * gam;
     const float sc = a2 > g2 ? a2 : g2;
-    if (!(sc > 0.0f)) return false;
+    if (!(sc > 0.0f)) return 0;
     rs = __frsqrt_rn(sc);
     const float isc = rs * rs;
     amp = S * (gam * isc) * 0.318309886183790672f;  // S gamma / (pi s)
@@ -2068,11 +2071,11 @@ __device__ __forceinline__ bool stage_direct(DirectLDS& L, int lane, const int4 
       czh = (int)(gh < -1 ? -1 : (gh > W ? W : gh));
     }
   } else if (PROF == kProfLorentz) {
-    if (!(gam > 0.0f)) return false;
+    if (!(gam > 0.0f)) return 0;
     rs = 1.0f / gam;
     amp = S * rs * 0.318309886183790672f;  // S / (pi gamma)
   } else {
-    if (!(alpha > 0.0f)) return false;
+    if (!(alpha > 0.0f)) return 0;
     rs = 1.0f / alpha;
     // a Gaussian (or its bin average) is below e^-81 of its peak beyond 9 alpha (+ a bin):
     // only those points are evaluated (the window of the work list is cut the same way)
@@ -2084,7 +2087,7 @@ __device__ __forceinline__ bool stage_direct(DirectLDS& L, int lane, const int4 
     const int gl = (int)fl, gh = (int)fh;
     if (gl > clo) clo = gl;
     if (gh < chi) chi = gh;
-    if (clo > chi || chi < 0 || clo > W - 1) return false;
+    if (clo > chi || chi < 0 || clo > W - 1) return 0;
     if (PROF == kProfDoppler) {
       amp = S * rs * 0.564189583547756287f;  // S / (sqrt(pi) alpha)
     } else {
@@ -2095,7 +2098,13 @@ __device__ __forceinline__ bool stage_direct(DirectLDS& L, int lane, const int4 
   L.F0[lane] = make_float4(delta * rs, (float)((int64_t)jref - span0), dnf * rs, r);
   L.F1[lane] = make_float4(amp, pl, order, 0.0f);
   L.B[lane] = make_int4(clo, chi, czl, czh);
-  return true;
+  // a Voigt or Lorentz line whose cut covers the whole span and that has no core point on it
+  // takes the unmasked loop of its order (its plinth is added once per span, not per point)
+  const bool full = clo <= 0 && chi >= W - 1;
+  const bool core = czl <= czh && czh >= 0 && czl <= W - 1;
+  if (PROF == kProfVoigt && full && !core) return (int)order;
+  if (PROF == kProfLorentz && full) return 1;
+  return kDirGeneral;
 }
 
 // erf(b) - erf(a) for a <= b in FP32, from erfc where both have one sign (no cancellation of
@@ -2163,6 +2172,56 @@ __device__ __forceinline__ void direct_voigt(const DirectLDS& L, int l, int lane
   }
 }
 
+// One staged line of a full-span group at all P points of this lane: Voigt of series order K
+// (PROF = kProfVoigt), or Lorentz (K = 1). No point is masked: the plinth is not taken here.
+template <int P, int PROF, int K>
+__device__ __forceinline__ void direct_full(const DirectLDS& L, int l, int lane, float (&part)[P]) {
+  const float4 f0 = L.F0[l];
+  const float amp = L.F1[l].x;
+  float4 ka = make_float4(0.f, 0.f, 0.f, 0.f), kb = ka;
+  if (K >= 2) ka = L.KA[l];
+  if (K >= 4) kb = L.KB[l];
+  const float kf0 = (float)lane - f0.y;
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const float D = __builtin_fmaf(kf0 + (float)(kWave * p), f0.z, f0.x);
+    if (PROF == kProfVoigt) {
+      const float q = __builtin_amdgcn_rcpf(__builtin_fmaf(D, D, f0.w));
+      float t;
+      if (K == 1) {
+        t = amp;
+      } else if (K == 2) {
+        t = __builtin_fmaf(ka.y, q, ka.x);
+        t = __builtin_fmaf(t, q, amp);
+      } else if (K == 3) {
+        t = __builtin_fmaf(ka.w, q, ka.z);
+        t = __builtin_fmaf(t, q, ka.y);
+        t = __builtin_fmaf(t, q, ka.x);
+        t = __builtin_fmaf(t, q, amp);
+      } else if (K == 4) {
+        t = __builtin_fmaf(kb.y, q, kb.x);
+        t = __builtin_fmaf(t, q, ka.w);
+        t = __builtin_fmaf(t, q, ka.z);
+        t = __builtin_fmaf(t, q, ka.y);
+        t = __builtin_fmaf(t, q, ka.x);
+        t = __builtin_fmaf(t, q, amp);
+      } else {
+        t = __builtin_fmaf(kb.w, q, kb.z);
+        t = __builtin_fmaf(t, q, kb.y);
+        t = __builtin_fmaf(t, q, kb.x);
+        t = __builtin_fmaf(t, q, ka.w);
+        t = __builtin_fmaf(t, q, ka.z);
+        t = __builtin_fmaf(t, q, ka.y);
+        t = __builtin_fmaf(t, q, ka.x);
+        t = __builtin_fmaf(t, q, amp);
+      }
+      part[p] = __builtin_fmaf(t, q, part[p]);
+    } else {
+      part[p] = __builtin_fmaf(amp, __builtin_amdgcn_rcpf(__builtin_fmaf(D, D, 1.0f)), part[p]);
+    }
+  }
+}
+
 // One staged line (uniform index l) at all P points of this lane.
 template <int P, int PROF>
 __device__ __forceinline__ void direct_eval(const DirectLDS& L, int l, int lane, float (&part)[P]) {
@@ -2194,6 +2253,36 @@ __device__ __forceinline__ void direct_eval(const DirectLDS& L, int l, int lane,
     const bool in = j >= bb.x && j <= bb.y;
     part[p] += in ? v - f1.y : 0.0f;
   }
+}
+
+// The staged lines of one group (list entries [i0, i1)), a compensated flush after every 16
+// lines counted over the groups of the batch (since).
+template <int P, int PROF, int G>
+__device__ __forceinline__ void direct_one(const DirectLDS& L, int l, int lane, float (&part)[P], float (&s)[P],
+                                           float (&cc)[P], int& since) {
+  if (G == kDirGeneral) direct_eval<P, PROF>(L, l, lane, part);
+  else direct_full<P, PROF, G>(L, l, lane, part);
+  if (++since == 16) {
+    kahan_flush<P>(part, s, cc);
+    since = 0;
+  }
+}
+
+template <int P, int PROF, int G>
+__device__ __forceinline__ void direct_group_loop(const DirectLDS& L, int i0, int i1, int lane, float (&part)[P],
+                                                  float (&s)[P], float (&cc)[P], int& since) {
+  int i = i0;
+  for (; i < i1 && (i & 3); ++i)  // unaligned head
+    direct_one<P, PROF, G>(L, __builtin_amdgcn_readfirstlane((int)L.list[i]), lane, part, s, cc, since);
+  for (; i + 4 <= i1; i += 4) {  // four list entries per scalar read
+    const uint32_t w4 = (uint32_t)__builtin_amdgcn_readfirstlane((int)*reinterpret_cast<const uint32_t*>(&L.list[i]));
+    direct_one<P, PROF, G>(L, (int)(w4 & 255u), lane, part, s, cc, since);
+    direct_one<P, PROF, G>(L, (int)((w4 >> 8) & 255u), lane, part, s, cc, since);
+    direct_one<P, PROF, G>(L, (int)((w4 >> 16) & 255u), lane, part, s, cc, since);
+    direct_one<P, PROF, G>(L, (int)(w4 >> 24), lane, part, s, cc, since);
+  }
+  for (; i < i1; ++i)
+    direct_one<P, PROF, G>(L, __builtin_amdgcn_readfirstlane((int)L.list[i]), lane, part, s, cc, since);
 }
 
 template <int P, int PROF>
@@ -2231,27 +2320,56 @@ __global__ __launch_bounds__(kWave) void k_direct(VoigtArgs a, const float* __re
     float s[P], cc[P], part[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) { s[p] = 0.0f; cc[p] = 0.0f; part[p] = 0.0f; }
+    double pl_full = 0.0;  // this lane's share of the plinths of the full-span lines
     for (int64_t b = line_lo; b < line_hi; b += kWave) {
       const int64_t li = b + lane;
-      bool ok = false;
-      if (li < line_hi)
-        ok = stage_direct<P, PROF>(L, lane, grec[li], a.nu[li], S_T[li], gT[li], plin ? plin[li] : 0.0f, pd, a.zK,
-                                   span0);
-      const uint64_t m = __ballot(ok);
-      if (ok) L.list[__popcll(m & lt)] = (uint8_t)lane;
-      const int cnt = (int)__popcll(m);
+      int code = 0;
+      float pl = 0.0f;
+      if (li < line_hi) {
+        pl = plin ? plin[li] : 0.0f;
+        code = stage_direct<P, PROF>(L, lane, grec[li], a.nu[li], S_T[li], gT[li], pl, pd, a.zK, span0);
+      }
+      if (code > 0 && code < kDirGeneral) pl_full += (double)pl;
+      // the list, grouped: full-span groups 1..kKmax in order, then the general one
+      int start[kDirGeneral + 2];
+      int base = 0, pos = -1;
+#pragma unroll
+      for (int g = 1; g <= kDirGeneral; ++g) {
+        const uint64_t m = __ballot(code == g);
+        start[g] = base;
+        if (code == g) pos = base + (int)__popcll(m & lt);
+        base += (int)__popcll(m);
+      }
+      start[kDirGeneral + 1] = base;
+      if (pos >= 0) L.list[pos] = (uint8_t)lane;
+      const int cnt = base;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int i = 0; i < cnt; ++i) {
-        direct_eval<P, PROF>(L, __builtin_amdgcn_readfirstlane((int)L.list[i]), lane, part);
-        if ((i & 15) == 15) kahan_flush<P>(part, s, cc);
+      int since = 0;
+      if (PROF == kProfVoigt) {
+        direct_group_loop<P, PROF, 1>(L, start[1], start[2], lane, part, s, cc, since);
+        direct_group_loop<P, PROF, 2>(L, start[2], start[3], lane, part, s, cc, since);
+        direct_group_loop<P, PROF, 3>(L, start[3], start[4], lane, part, s, cc, since);
+        direct_group_loop<P, PROF, 4>(L, start[4], start[5], lane, part, s, cc, since);
+        direct_group_loop<P, PROF, 5>(L, start[5], start[6], lane, part, s, cc, since);
+      } else if (PROF == kProfLorentz) {
+        direct_group_loop<P, PROF, 1>(L, start[1], start[2], lane, part, s, cc, since);
       }
+      direct_group_loop<P, PROF, kDirGeneral>(L, start[kDirGeneral], start[kDirGeneral + 1], lane, part, s, cc,
+                                               since);
       kahan_flush<P>(part, s, cc);
       n_lines += cnt;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (plin) {
+      // the full-span lines' plinths: one subtraction at every point of the span
+      const float tot = (float)wave_sum64(pl_full);
+#pragma unroll
+      for (int p = 0; p < P; ++p) part[p] = -tot;
+      kahan_flush<P>(part, s, cc);
     }
 #pragma unroll
     for (int p = 0; p < P; ++p) {
