@@ -65,9 +65,17 @@ constexpr double kH = 6.62606957e-27;     // erg s
 constexpr double kAMU = 1.660538921e-24;  // g
 constexpr double kC2 = kH * kC / kB;      // cm K
 
-// |z| thresholds of the far-wing series orders 1..5 (relative truncation error < 2e-6);
-// below the last one the core approximation is used
+// |z| thresholds of the far-wing series orders 1..5: at and above zK[K-1] the series of order K
+// is within 1.4e-7 of the line's peak value Re w(iy) (and within 2e-6 relative); below the last
+// one the core approximation is used
 constexpr double kZK[hk::kKmax] = {870.0, 37.5, 13.8, 8.7, 6.75};
+// the same for orders 1..9 (orders 6-9 within 1.3e-7 of the peak); the default path's wing pass
+// takes lines next to their cores down to |z| = 4.4 with them, and its core pass the rest
+constexpr double kZW[hk::kKw] = {870.0, 37.5, 13.8, 8.7, 6.75, 5.65, 5.0, 4.65, 4.4};
+
+// |z| below which a pair is a core point: the default path's (the wing pass has orders up to
+// kKw), or that of the options path (k_direct has orders up to kKmax)
+double core_threshold(bool default_path) { return default_path ? kZW[hk::kKw - 1] : kZK[hk::kKmax - 1]; }
 
 thread_local std::string g_err;
 thread_local hk_timings g_tim = {-1, -1, -1, -1, -1, -1, 0, 0, 0, 0, -1, -1, -1, -1, {-1, -1, -1, -1, -1, -1, -1, -1}, 0};
@@ -500,7 +508,7 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
   if (L->shift_max > 0.0 && T) {
     double bmax = 0.0;
     for (int p = 0; p < n_pairs; ++p) bmax = std::max(bmax, std::sqrt(2.0 * kB * T[p] / (L->sp.mass_amu * kAMU)) / kC);
-    pl->core_pad = kZK[hk::kKmax - 1] * bmax * L->shift_max * 1.001;
+    pl->core_pad = core_threshold(dflt) * bmax * L->shift_max * 1.001;
   }
   pl->W = hk::kWavesPerWG * hk::kWave * pl->slots;
   pl->n_pairs = n_pairs;
@@ -562,7 +570,7 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
     const double gend = std::max(std::fabs(grids[p].nu_start),
                                  std::fabs(grids[p].nu_start + (double)grids[p].n * grids[p].dnu));
     const double vmax = std::min(L->numax, gend + (std::isinf(cut) ? L->numax : cut));
-    const double hc = std::min(cut, kZK[hk::kKmax - 1] * d.beta * vmax * 1.0001 + 0.01 * grids[p].dnu);
+    const double hc = std::min(cut, core_threshold(dflt) * d.beta * vmax * 1.0001 + 0.01 * grids[p].dnu);
     const int64_t nt_c = (grids[p].n + pl->W_c - 1) / pl->W_c;
     if (tiles_c + nt_c >= (int64_t(1) << 30)) return fail(HK_ENOMEM, "too many grid tiles");
     hk::PairDesc& dc = pl->pairs_c[p];
@@ -786,7 +794,7 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   tm.mark();
   // work lists: tile windows and tile-far ranges, span segments, span core windows
   // lines evaluated at nodes must keep the interval outside their core (|z| >= the last threshold)
-  const double far_z = kZK[hk::kKmax - 1], core_z = kZK[hk::kKmax - 1];
+  const double far_z = kZK[hk::kKmax - 1], core_z = core_threshold(dflt);
   const double cut_w = pl.cut_w;
   hk::PairDesc* dpairs = reinterpret_cast<hk::PairDesc*>(ws + pl.off_pairs);
   hk::PairDesc* dpairs_c = reinterpret_cast<hk::PairDesc*>(ws + pl.off_pairs_c);
@@ -858,6 +866,8 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   va.N = L->N;
   va.cut = cut_w;
   for (int i = 0; i < hk::kKmax; ++i) va.zK[i] = (float)kZK[i];
+  for (int i = 0; i < hk::kKw; ++i) va.zw[i] = (float)kZW[i];
+  va.zcore = (float)core_z;
   va.n_pairs = pl.n_pairs;
   va.n_tiles_total = pl.n_tiles_c;
   va.status = status;

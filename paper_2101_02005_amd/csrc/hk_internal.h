@@ -10,6 +10,7 @@ constexpr int kWave = 64;        // CDNA wavefront width
 constexpr int kThreads = 256;    // threads per workgroup of the tile-far and sort kernels
 constexpr int kWavesPerWG = kThreads / kWave;  // spans per tile of the tile-far pass
 constexpr int kKmax = 5;         // highest order of the far-wing series
+constexpr int kKw = 9;           // ... in the wing pass next to the line cores (the default path)
 constexpr int kWeidN = 18;       // terms of the FP64 core rational approximation
 constexpr int kWeidN40 = 40;     // terms of the FP64 approximation of the plinth values (one per line)
 constexpr int kKeyBits = 24;     // linear wavenumber-bin key width
@@ -180,6 +181,8 @@ struct VoigtArgs {
   int64_t N;
   double cut;              // > 0; +inf: no cut
   float zK[kKmax];         // |z| above which the series of order K (1..kKmax) is used
+  float zw[kKw];           // the same for orders 1..kKw (the wing pass's lines next to their cores)
+  float zcore;             // core points: |z| below it (k_core's; the wing pass and k_direct skip them)
   int32_t n_pairs;
   int32_t n_tiles_total;   // spans
   int32_t chunk;           // lines per work item

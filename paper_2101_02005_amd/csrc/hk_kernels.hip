@@ -682,9 +682,12 @@ __global__ __launch_bounds__(kThreads) void k_gridrec(const double* __restrict__
 //   F1 = (Ah, lo_rel, hi_rel, a): S gamma/(pi s), cut bounds relative to the reference
 //        index, alpha^2/s
 //   KA, KB, KC: Ah times the far-wing series coefficients of orders 2-4 (see wing_coeffs)
-//   K5, K5C: c4-c7 and c8 of order 5 (c1-c3 as order 4), for lines that need it
-//   CZ: the line's core points (|z| below the last series threshold) within its cut range,
+//   K5, K5C: c4-c7 and c8 of order 5 (c1-c3 as order 4), for lines that need order 5
+//   CZ: the line's core points (|z| below the core threshold zcore) within its cut range,
 //       as an inclusive span-local range (empty: x > y)
+//   A line that needs an order above 5 on the span (points next to its core) holds instead
+//   Ah times c1-c16 of order kKw: KA = c1-c4, KB = c5-c8, K5 = c9-c12, KC = c13, K5C = c14,
+//   F1.w = c15, CZ.y = c16 (bits), and its core range in CZ.x (low and high 16 bits).
 //   list: the staged lines that reach the span, grouped by how they are evaluated (see
 //         direct_group), in staging order within a group
 //   node, node_mid: the span's node sums of the item's far and middle-distance lines
@@ -704,14 +707,15 @@ struct WaveLDS {
 };
 
 // Evaluation group of a staged line: 0 does not reach the span; 1-4 all points inside the cut,
-// no core points, series order 1-4; 5-8 the same with some points outside the cut; 9 general
-// (order 5 or core points on the span).
-constexpr int kDirectGroups = 9;
+// no core points, series order 1-4; 5-8 the same with some points outside the cut; 9 order 5
+// (no core points); 10 order kKw (points next to the core, core points excluded).
+constexpr int kDirectGroups = 10;
 __device__ __forceinline__ int direct_group(uint32_t code) {
   if (code == 0u) return 0;
-  const int K = (int)(code & 7u);
-  if ((code & 16u) || K > 4) return 9;
-  return (code & 8u) ? 4 + K : K;
+  const int K = (int)(code & 15u);
+  if ((code & 32u) || K > kKmax) return 10;
+  if (K == kKmax) return 9;
+  return (code & 16u) ? 4 + K : K;
 }
 // Far-wing series of the Voigt profile in q = 1/(D^2 + gamma^2), from the asymptotic
 // expansion w(z) ~ (i/sqrt(pi)) sum_k (2k-1)!!/(2^k z^(2k+1)): with t = alpha^2 q and
@@ -728,6 +732,43 @@ __device__ __forceinline__ int direct_group(uint32_t code) {
 //   K=5: c1..c3 (as K=4), c4 = 12a^2g^2 - 105a^3g + 945a^4/16, c5 = 210a^3g^2 - 1575a^4g/2,
 //        c6 = -120a^3g^3 + 2835a^4g^2, c7 = -3780a^4g^3, c8 = 1680a^4g^4
 //   (a_4 = 105/16; P_4(u) = 9 - 120u + 432u^2 - 576u^3 + 256u^4)
+// Order 9 (terms k <= 8; P_(k+1) = (2 - 4u) P_k - P_(k-1), P_(-1) = -1), c1-c3 as order 4:
+//   c4  = 12a^2g^2 - 105a^3g + 945a^4/16
+//   c5  = 210a^3g^2 - 1575a^4g/2 + 10395a^5/32
+//   c6  = -120a^3g^3 + 2835a^4g^2 - 51975a^5g/8 + 135135a^6/64
+//   c7  = -3780a^4g^3 + 72765a^5g^2/2 - 945945a^6g/16 + 2027025a^7/128
+//   c8  = 1680a^4g^4 - 83160a^5g^3 + 945945a^6g^2/2 - 4729725a^7g/8 + 34459425a^8/256
+//   c9  = 83160a^5g^4 - 1621620a^6g^3 + 25540515a^7g^2/4 - 103378275a^8g/16
+//   c10 = -30240a^5g^5 + 2702700a^6g^4 - 30405375a^7g^3 + 723647925a^8g^2/8
+//   c11 = -2162160a^6g^5 + 74324250a^7g^4 - 1137161025a^8g^3/2
+//   c12 = 665280a^6g^6 - 97297200a^7g^5 + 1895268375a^8g^4
+//   c13 = 64864800a^7g^6 - 3583780200a^8g^5
+//   c14 = -17297280a^7g^7 + 3859455600a^8g^6
+//   c15 = -2205403200a^8g^7
+//   c16 = 518918400a^8g^8
+// For |z| >= 4.4 the order-9 series is within 1.3e-7 of the line's peak value (FP32 Horner).
+__device__ __forceinline__ void order9_coeffs(float a, float g, float Ah, float4& c1_4, float4& c5_8, float4& c9_12,
+                                              float& c13, float& c14, float& c15, float& c16) {
+  const float a2 = a * a, a3 = a2 * a, a4 = a2 * a2, a5 = a4 * a, a6 = a3 * a3, a7 = a6 * a, a8 = a4 * a4;
+  const float g2 = g * g, g3 = g2 * g, g4 = g2 * g2, g5 = g4 * g, g6 = g3 * g3, g7 = g6 * g, g8 = g4 * g4;
+  c1_4 = make_float4(Ah * (1.5f * a), Ah * (-2.0f * a * g + 3.75f * a2), Ah * (-15.0f * a2 * g + 13.125f * a3),
+                     Ah * (12.0f * a2 * g2 - 105.0f * a3 * g + 59.0625f * a4));
+  c5_8 = make_float4(Ah * (210.0f * a3 * g2 - 787.5f * a4 * g + 324.84375f * a5),
+                     Ah * (-120.0f * a3 * g3 + 2835.0f * a4 * g2 - 6496.875f * a5 * g + 2111.484375f * a6),
+                     Ah * (-3780.0f * a4 * g3 + 36382.5f * a5 * g2 - 59121.5625f * a6 * g + 15836.1328125f * a7),
+                     Ah * (1680.0f * a4 * g4 - 83160.0f * a5 * g3 + 472972.5f * a6 * g2 - 591215.625f * a7 * g +
+                           134607.12890625f * a8));
+  c9_12 = make_float4(
+      Ah * (83160.0f * a5 * g4 - 1621620.0f * a6 * g3 + 6385128.75f * a7 * g2 - 6461142.1875f * a8 * g),
+      Ah * (-30240.0f * a5 * g5 + 2702700.0f * a6 * g4 - 30405375.0f * a7 * g3 + 90455990.625f * a8 * g2),
+      Ah * (-2162160.0f * a6 * g5 + 74324250.0f * a7 * g4 - 568580512.5f * a8 * g3),
+      Ah * (665280.0f * a6 * g6 - 97297200.0f * a7 * g5 + 1895268375.0f * a8 * g4));
+  c13 = Ah * (64864800.0f * a7 * g6 - 3583780200.0f * a8 * g5);
+  c14 = Ah * (-17297280.0f * a7 * g7 + 3859455600.0f * a8 * g6);
+  c15 = Ah * (-2205403200.0f * a8 * g7);
+  c16 = Ah * (518918400.0f * a8 * g8);
+}
+
 __device__ __forceinline__ void wing_coeffs(float a, float g, float Ah, float4& KA, float4& KB, float& KC) {
   const float a2 = a * a, a3 = a2 * a, g2 = g * g;
   const float c2_2 = -2.0f * a * g;
@@ -769,15 +810,16 @@ __device__ __forceinline__ bool core_rel(float alpha, float gam, float delta, fl
 }
 
 // Stage one line for a span (64 P points from global point span0) from its grid record and its
-// strength/width at T: the FP32 quantities of the evaluation, and the code word: bits 0-2 the
-// series order K its span points need (0: the line does not reach the span), bit 3 some
-// points fall outside its cut range, bit 4 some of its points are core points. Every decision
-// that needs FP64 (cut bounds, reference point, offset) is already in the grid record; the
-// rest needs ~1e-7 and is done in FP32 (products ordered so that no intermediate underflows
-// for relevant lines).
+// strength/width at T: the FP32 quantities of the evaluation, and the code word: bits 0-3 the
+// highest series order its span points need (0: the line does not reach the span), bit 4 some
+// points fall outside its cut range, bit 5 some of its points are core points (|z| < zcore).
+// Every decision that needs FP64 (cut bounds, reference point, offset) is already in the grid
+// record; the rest needs ~1e-7 and is done in FP32 (products ordered so that no intermediate
+// underflows for relevant lines).
 template <int P>
 __device__ __forceinline__ uint32_t stage_span_line(WaveLDS& L, int lane, const int4 gr, double nu0, float S,
-                                                    float gTv, const PairDesc& pd, const float* zK, int64_t span0) {
+                                                    float gTv, const PairDesc& pd, const float* zw, float zcore,
+                                                    int64_t span0) {
   constexpr int W = kWave * P;
   const int jref = gr.y, jlo = gr.z, jhi = gr.w;
   if (!(S > 0.0f) || jlo > jhi || (int64_t)jhi < span0 || (int64_t)jlo > span0 + (W - 1)) return 0u;
@@ -791,10 +833,10 @@ __device__ __forceinline__ uint32_t stage_span_line(WaveLDS& L, int lane, const 
   const float delta = __int_as_float(gr.x);
   const int jt = (int)((int64_t)jref - span0);
   const float Ah = S * (gam * isc) * 0.318309886183790672f;  // S gamma / (pi s)
-  L.F0[lane] = make_float4(delta * rs, (float)jt, (float)pd.dnu * rs, g2 * isc);
-  L.F1[lane] = make_float4(Ah, (float)(jlo - jref), (float)(jhi - jref), a2 * isc);
-  wing_coeffs(a2 * isc, g2 * isc, Ah, L.KA[lane], L.KB[lane], L.KC[lane]);
-  // zone K: points with |z| < zK[K], i.e. |j - c| < sqrt(zK^2 alpha^2 - gamma^2)/dnu around the
+  const float av = a2 * isc, gv = g2 * isc;
+  L.F0[lane] = make_float4(delta * rs, (float)jt, (float)pd.dnu * rs, gv);
+  L.F1[lane] = make_float4(Ah, (float)(jlo - jref), (float)(jhi - jref), av);
+  // zone K: points with |z| < zw[K], i.e. |j - c| < sqrt(zw^2 alpha^2 - gamma^2)/dnu around the
   // centre c (span-local points); a slot [s0, s1] meets it when s0 < c + h and s1 > c - h
   const float inv_dnu = (float)(1.0 / pd.dnu);
   const float af = alpha * inv_dnu, gf = gam * inv_dnu;
@@ -803,10 +845,10 @@ __device__ __forceinline__ uint32_t stage_span_line(WaveLDS& L, int lane, const 
   const int chi = (int)((int64_t)jhi - span0 > W ? W : (int64_t)jhi - span0);
   // zone half-widths, once per line (the hardware square root: the bounds carry a relative slack
   // of 1e-5 and only choose how many series terms the span's points get)
-  float hz[kKmax - 1];
+  float hz[kKw - 1];
 #pragma unroll
-  for (int z = 0; z < kKmax - 1; ++z) {
-    const float zz = zK[z] * af;
+  for (int z = 0; z < kKw - 1; ++z) {
+    const float zz = zw[z] * af;
     const float h2 = zz * zz - gf * gf;
     hz[z] = h2 > 0.0f ? __builtin_amdgcn_sqrtf(h2) * 1.00001f + 1e-3f : -1.0f;
   }
@@ -814,32 +856,45 @@ __device__ __forceinline__ uint32_t stage_span_line(WaveLDS& L, int lane, const 
 #pragma unroll
   for (int p = 0; p < P; ++p) {
     const int s0 = p * kWave, s1 = s0 + kWave - 1;
-    if (s1 < clo || s0 > chi) continue;
+    if (s1 < clo || s0 > chi) continue;  // no point of the slot in the cut
     uint32_t path = 1u;
 #pragma unroll
-    for (int z = 0; z < kKmax - 1; ++z) path += ((float)s0 < c + hz[z] && (float)s1 > c - hz[z]) ? 1u : 0u;
+    for (int z = 0; z < kKw - 1; ++z) path += ((float)s0 < c + hz[z] && (float)s1 > c - hz[z]) ? 1u : 0u;
     K = path > K ? path : K;
   }
-  // core points: strictly inside the last zone, and within the cut range
+  // core points: strictly inside the core zone, and within the cut range
   int czl = 1, czh = 0, rlo, rhi;
-  if (core_rel(alpha, gam, delta, inv_dnu, zK[kKmax - 1], rlo, rhi)) {
+  if (core_rel(alpha, gam, delta, inv_dnu, zcore, rlo, rhi)) {
     const int64_t gl = (int64_t)jref + rlo - span0, gh = (int64_t)jref + rhi - span0;
     czl = (int)(gl < clo ? clo : (gl > W + 1 ? W + 1 : gl));
     czh = (int)(gh > chi ? chi : (gh < -2 ? -2 : gh));
   }
-  L.CZ[lane] = make_int2(czl, czh);
   const bool core = (czl > 0 ? czl : 0) <= (czh < W - 1 ? czh : W - 1);
-  if (core) K = kKmax;  // the wing points next to the core need the highest order
-  if (K == (uint32_t)kKmax) {
-    const float av = a2 * isc, gv = g2 * isc;
-    const float a3 = av * av * av, a4 = a3 * av, g2v = gv * gv, g3v = g2v * gv;
-    L.K5[lane] = make_float4(Ah * (12.0f * av * av * g2v - 105.0f * a3 * gv + 59.0625f * a4),
-                             Ah * (210.0f * a3 * g2v - 787.5f * a4 * gv), Ah * (-120.0f * a3 * g3v + 2835.0f * a4 * g2v),
-                             Ah * (-3780.0f * a4 * g3v));
-    L.K5C[lane] = Ah * (1680.0f * a4 * g2v * g2v);
+  if (core || K > (uint32_t)kKmax) {
+    // order kKw for all its span points (the coefficient layout of the order-kKw group)
+    float4 c1_4, c5_8, c9_12;
+    float c13, c14, c15, c16;
+    order9_coeffs(av, gv, Ah, c1_4, c5_8, c9_12, c13, c14, c15, c16);
+    L.KA[lane] = c1_4;
+    L.KB[lane] = c5_8;
+    L.K5[lane] = c9_12;
+    L.KC[lane] = c13;
+    L.K5C[lane] = c14;
+    L.F1[lane].w = c15;
+    L.CZ[lane] = make_int2((int)(((uint32_t)czl & 0xffffu) | ((uint32_t)czh << 16)), __float_as_int(c16));
+    if (core) K = kKw;
+  } else {
+    wing_coeffs(av, gv, Ah, L.KA[lane], L.KB[lane], L.KC[lane]);
+    if (K == (uint32_t)kKmax) {
+      const float a3 = av * av * av, a4 = a3 * av, g2v = gv * gv, g3v = g2v * gv;
+      L.K5[lane] = make_float4(Ah * (12.0f * av * av * g2v - 105.0f * a3 * gv + 59.0625f * a4),
+                               Ah * (210.0f * a3 * g2v - 787.5f * a4 * gv), Ah * (-120.0f * a3 * g3v + 2835.0f * a4 * g2v),
+                               Ah * (-3780.0f * a4 * g3v));
+      L.K5C[lane] = Ah * (1680.0f * a4 * g2v * g2v);
+    }
   }
   const bool masked = !(clo <= 0 && chi >= W - 1);
-  return K | (masked ? 8u : 0u) | (core ? 16u : 0u);
+  return K | (masked ? 16u : 0u) | (core ? 32u : 0u);
 }
 
 // One line, all slots of this wave, series order K. MASK: lanes outside the cut range add
@@ -910,24 +965,71 @@ __device__ __forceinline__ void wing_line(const WaveLDS& L, int l, float jl0, fl
   wing_slots<P, K, MASK, false>(part, jl0 - f0.y, f0, f1, ka, kb, kc);
 }
 
-// One staged line of order 5 or with core points on the span (those add nothing here).
+// One staged line of order 5 (no core points on the span), all slots, points outside the cut
+// masked.
 template <int P>
-__device__ __forceinline__ void wing_line_general(const WaveLDS& L, int l, uint32_t code, float jl0,
-                                                  float (&part)[P]) {
+__device__ __forceinline__ void wing_line_order5(const WaveLDS& L, int l, float jl0, float (&part)[P]) {
   const float4 f0 = L.F0[l];
   const float4 f1 = L.F1[l];
   const float4 ka = L.KA[l], kb = L.KB[l], k5 = L.K5[l];
-  const float kf0 = jl0 - f0.y;
   // order 5 as wing_slots takes it: ka = (c1, c2, c3, c4), kb = (c5, c6, c7, c8)
   const float4 k5a = make_float4(ka.x, ka.z, kb.y, k5.x);
   const float4 k5b = make_float4(k5.y, k5.z, k5.w, L.K5C[l]);
-  if (code & 16u) {
-    const int czl = __builtin_amdgcn_readfirstlane(L.CZ[l].x);
-    const int czh = __builtin_amdgcn_readfirstlane(L.CZ[l].y);
+  wing_slots<P, 5, true, false>(part, jl0 - f0.y, f0, f1, k5a, k5b, 0.f);
+}
+
+// One staged line of order kKw (points next to its core on the span), all slots: Horner in q
+// over c16..c1 and the amplitude; points outside the cut, and with EXCL its core points
+// [xl, xh] (relative index; they may have R = 0, q infinite: the sum is selected, not the
+// term), add nothing.
+template <int P, bool EXCL>
+__device__ __forceinline__ void wing_slots9(float (&part)[P], float kf0, const float4& f0, const float4& f1,
+                                            const float4& c1_4, const float4& c5_8, const float4& c9_12, float c13,
+                                            float c14, float c15, float c16, float xl, float xh) {
+#pragma unroll
+  for (int p = 0; p < P; ++p) {
+    const float kf = kf0 + (float)(kWave * p);
+    const float D = __builtin_fmaf(kf, f0.z, f0.x);
+    const float R = __builtin_fmaf(D, D, f0.w);
+    const float q = __builtin_amdgcn_rcpf(R);
+    float t = __builtin_fmaf(c16, q, c15);
+    t = __builtin_fmaf(t, q, c14);
+    t = __builtin_fmaf(t, q, c13);
+    t = __builtin_fmaf(t, q, c9_12.w);
+    t = __builtin_fmaf(t, q, c9_12.z);
+    t = __builtin_fmaf(t, q, c9_12.y);
+    t = __builtin_fmaf(t, q, c9_12.x);
+    t = __builtin_fmaf(t, q, c5_8.w);
+    t = __builtin_fmaf(t, q, c5_8.z);
+    t = __builtin_fmaf(t, q, c5_8.y);
+    t = __builtin_fmaf(t, q, c5_8.x);
+    t = __builtin_fmaf(t, q, c1_4.w);
+    t = __builtin_fmaf(t, q, c1_4.z);
+    t = __builtin_fmaf(t, q, c1_4.y);
+    t = __builtin_fmaf(t, q, c1_4.x);
+    t = __builtin_fmaf(t, q, f1.x);
+    bool in = (kf >= f1.y) && (kf <= f1.z);
+    if (EXCL) in = in && ((kf < xl) || (kf > xh));
+    part[p] = in ? __builtin_fmaf(t, q, part[p]) : part[p];
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void wing_line_order9(const WaveLDS& L, int l, uint32_t code, float jl0,
+                                                 float (&part)[P]) {
+  const float4 f0 = L.F0[l];
+  const float4 f1 = L.F1[l];
+  const float4 c1_4 = L.KA[l], c5_8 = L.KB[l], c9_12 = L.K5[l];
+  const float c13 = L.KC[l], c14 = L.K5C[l];
+  const int2 cz = L.CZ[l];
+  const float kf0 = jl0 - f0.y;
+  if (code & 32u) {
+    const uint32_t zz = (uint32_t)__builtin_amdgcn_readfirstlane(cz.x);
     const float jt = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(f0.y)));
-    wing_slots<P, 5, true, true>(part, kf0, f0, f1, k5a, k5b, 0.f, (float)czl - jt, (float)czh - jt);
+    const float xl = (float)(int)(int16_t)(zz & 0xffffu) - jt, xh = (float)(int)(int16_t)(zz >> 16) - jt;
+    wing_slots9<P, true>(part, kf0, f0, f1, c1_4, c5_8, c9_12, c13, c14, f1.w, __int_as_float(cz.y), xl, xh);
   } else {
-    wing_slots<P, 5, true, false>(part, kf0, f0, f1, k5a, k5b, 0.f);
+    wing_slots9<P, false>(part, kf0, f0, f1, c1_4, c5_8, c9_12, c13, c14, f1.w, __int_as_float(cz.y), 0.f, -1.f);
   }
 }
 
@@ -1428,7 +1530,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P <= 4 ? 
           for (int b = i0; b < i1; b += kWave) {
             const int li = b + lane;
             uint32_t code = 0u;
-            if (li < i1) code = stage_span_line<P>(L, lane, grec[li], a.nu[li], S_T[li], gT[li], pd, a.zK, span0);
+            if (li < i1)
+              code = stage_span_line<P>(L, lane, grec[li], a.nu[li], S_T[li], gT[li], pd, a.zw, a.zcore, span0);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -1457,9 +1560,14 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P <= 4 ? 
             direct_loop<P, 3, true>(L, o[7], o[8], jl0, part, s, cc);
             direct_loop<P, 4, true>(L, o[8], o[9], jl0, part, s, cc);
             for (int i = o[9]; i < o[10]; ++i) {
-              const int l = __builtin_amdgcn_readfirstlane((int)L.list[i]);
-              wing_line_general<P>(L, l, (uint32_t)__builtin_amdgcn_readlane((int)code, l), jl0, part);
+              wing_line_order5<P>(L, __builtin_amdgcn_readfirstlane((int)L.list[i]), jl0, part);
               if (((i - o[9]) & 15) == 15) kahan_flush<P>(part, s, cc);
+            }
+            kahan_flush<P>(part, s, cc);
+            for (int i = o[10]; i < o[11]; ++i) {
+              const int l = __builtin_amdgcn_readfirstlane((int)L.list[i]);
+              wing_line_order9<P>(L, l, (uint32_t)__builtin_amdgcn_readlane((int)code, l), jl0, part);
+              if (((i - o[10]) & 15) == 15) kahan_flush<P>(part, s, cc);
             }
             kahan_flush<P>(part, s, cc);
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1701,7 +1809,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
 #pragma unroll
   for (int p = 0; p < P; ++p) L.acc[p * kWave + lane] = 0.0f;
   const int total = a.item_base[a.n_tiles_total];
-  const float zc = a.zK[kKmax - 1];
+  const float zc = a.zcore;
   long long ncore = 0;  // core evaluations of this wave (statistics only)
 
   for (;;) {
@@ -2005,11 +2113,11 @@ struct DirectLDS {
 // r is gamma^2 / scale^2 (Voigt) or dnu / (2 alpha) (binned Gaussian). For the Voigt profile the
 // series order K is the one the line's points on the span need (as in the wing pass: one more
 // term per zone |z| < zK of the thresholds the points reach), and KA, KB hold that order's
-// coefficients c1..c(2K-2) (zero beyond).
+// coefficients c1..c(2K-2) (zero beyond); its points with |z| < zc are k_core's.
 template <int P, int PROF>
 __device__ __forceinline__ int stage_direct(DirectLDS& L, int lane, const int4 gr, double nu0, float S, float gTv,
-                                            float pl, const PairDesc& pd, const float* zK, int64_t span0) {
-  const float zc = zK[kKmax - 1];
+                                            float pl, const PairDesc& pd, const float* zK, float zc,
+                                            int64_t span0) {
   constexpr int W = kWave * P;
   const int jref = gr.y, jlo = gr.z, jhi = gr.w;
   if (!(S > 0.0f) || jlo > jhi || (int64_t)jhi < span0 || (int64_t)jlo > span0 + (W - 1)) return 0;
@@ -2327,7 +2435,7 @@ __global__ __launch_bounds__(kWave) void k_direct(VoigtArgs a, const float* __re
       float pl = 0.0f;
       if (li < line_hi) {
         pl = plin ? plin[li] : 0.0f;
-        code = stage_direct<P, PROF>(L, lane, grec[li], a.nu[li], S_T[li], gT[li], pl, pd, a.zK, span0);
+        code = stage_direct<P, PROF>(L, lane, grec[li], a.nu[li], S_T[li], gT[li], pl, pd, a.zK, a.zcore, span0);
       }
       if (code > 0 && code < kDirGeneral) pl_full += (double)pl;
       // the list, grouped: full-span groups 1..kKmax in order, then the general one
