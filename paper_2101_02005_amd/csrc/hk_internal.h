@@ -15,7 +15,7 @@ constexpr int kWeidN = 18;       // terms of the FP64 core rational approximatio
 constexpr int kWeidN40 = 40;     // terms of the FP64 approximation of the plinth values (one per line)
 constexpr int kKeyBits = 24;     // linear wavenumber-bin key width
 constexpr int kRadixBits = 8;
-constexpr int kSortItems = 16;   // keys per thread per sort block
+constexpr int kSortItems = 32;   // keys per thread per sort block
 constexpr int kSortBlock = kThreads * kSortItems;
 constexpr int kFillPairs = 48;   // pair descriptors per fill launch (kernel-argument space)
 constexpr int kNodes = 16;       // Chebyshev nodes of a span or tile for lines far from it
