@@ -186,7 +186,7 @@ int64_t hk_lines_count(const hk_lines* lines);
  *   mode 1: hk_opacity_batched (n_pairs pairs, grids[n_pairs] host array; n_temps distinct
  *           temperatures, pass n_pairs if unknown: it is an upper bound)
  *   mode 2: hk_opacity_backward (n_pairs = 1; grows with the line count and with the grid:
- *           per line 80 B, per grid point 128 B of node sums of dL/dk)
+ *           per line 80 B, per grid point 384 B of node sums of dL/dk, three unit widths)
  * The workspace must be 256-byte aligned. Returns HK_EINVAL for bad arguments.
  */
 hk_status hk_workspace_size(const hk_lines* lines, int mode, int32_t n_pairs, int32_t n_temps,

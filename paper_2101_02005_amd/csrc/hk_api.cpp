@@ -123,6 +123,7 @@ struct DevInfo {
   float mid_x[4][hk::kMidNodes] = {};
   float* mask_w[4] = {};      // device: the span's nodes for lines with a cut bound on it (FP32)
   float mask_x[4][hk::kMaskNodes] = {};
+  double* adj_w[hk::kAdjLevels] = {};  // device: node weights of the adjoint's far units, per level
   int far_per_cu = 1;         // tile-far kernel occupancy
   int direct_per_cu[4] = {};  // direct-evaluation kernel occupancy per slots
   void* scratch = nullptr;    // device address of the allocation-free entry point's scratch array
@@ -248,6 +249,13 @@ hk_status device_init(int* dev_out, DevInfo* info) {
       std::vector<float> wf(wts.begin(), wts.end());
       HK_HIP(hipMalloc(&di.mask_w[si], sizeof(float) * wf.size()));  // held for the process lifetime
       HK_HIP(hipMemcpy(di.mask_w[si], wf.data(), sizeof(float) * wf.size(), hipMemcpyHostToDevice));
+    }
+    for (int lv = 0; lv < hk::kAdjLevels; ++lv) {
+      float xs[hk::kNodes];
+      std::vector<double> wts;
+      span_nodes(hk::kAdjSpan << (2 * lv), hk::kNodes, xs, wts);
+      HK_HIP(hipMalloc(&di.adj_w[lv], sizeof(double) * wts.size()));  // held for the process lifetime
+      HK_HIP(hipMemcpy(di.adj_w[lv], wts.data(), sizeof(double) * wts.size(), hipMemcpyHostToDevice));
     }
     di.far_per_cu = hk::far_max_blocks_per_cu();
     HK_HIP(hipMalloc(&di.stats_buf, 4 * sizeof(unsigned long long)));  // held for the process lifetime
@@ -677,7 +685,7 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
 // per-line FP64 records and the node weights of dL/dk per span of the grid.
 constexpr int kBwdPartials = 256;
 struct BwdLayout {
-  size_t off_gr = 0, off_contrib = 0, off_part = 0, off_lrec = 0, off_pref = 0, total = 0;
+  size_t off_gr = 0, off_contrib = 0, off_part = 0, off_lrec = 0, off_pref[hk::kAdjLevels] = {}, total = 0;
 };
 BwdLayout backward_layout(int64_t N, int64_t n_grid) {
   BwdLayout b;
@@ -687,8 +695,11 @@ BwdLayout backward_layout(int64_t N, int64_t n_grid) {
   b.off_contrib = take(2 * sizeof(double) * (size_t)N);
   b.off_part = take(2 * sizeof(double) * kBwdPartials);
   b.off_lrec = take(6 * sizeof(double) * (size_t)N);
-  const size_t spans = (size_t)((n_grid + hk::kAdjSpan - 1) / hk::kAdjSpan);
-  b.off_pref = take(sizeof(double) * hk::kNodes * hk::kAdjSpan * spans);
+  for (int lv = 0; lv < hk::kAdjLevels; ++lv) {
+    const size_t W = (size_t)hk::kAdjSpan << (2 * lv);
+    const size_t units = ((size_t)n_grid + W - 1) / W;
+    b.off_pref[lv] = take(sizeof(double) * hk::kNodes * W * units);
+  }
   b.total = off;
   return b;
 }
@@ -1954,15 +1965,19 @@ hk_status hk_opacity_backward(const hk_lines* lines, const hk_line_override* ovr
   a.dn = dL_dn;
   a.contrib = contrib;
   a.lrec = reinterpret_cast<double*>(w + bl.off_lrec);
-  double* gpref = reinterpret_cast<double*>(w + bl.off_pref);
-  a.gpref = gpref;
+  double* gpref[hk::kAdjLevels];
+  for (int lv = 0; lv < hk::kAdjLevels; ++lv) {
+    gpref[lv] = reinterpret_cast<double*>(w + bl.off_pref[lv]);
+    a.gpref[lv] = gpref[lv];
+  }
   const int64_t want = (lines->N + hk::kWavesPerWG - 1) / hk::kWavesPerWG;
   const int64_t cap = (int64_t)di.cus * 8;
   const int blocks = (int)std::max<int64_t>(1, std::min(want, cap));
   if (lines->N > 0) {
-    // node weights of the adjoint's far spans: Lagrange weights of the 16 nodes of a 256-point span
-    static_assert(hk::kWavesPerWG * hk::kWave == hk::kAdjSpan, "adjoint span = tile of one slot");
-    HK_HIP(hk::launch_adj_nodes(dL_dk, grid.n, di.tile_w[0], gpref, stream));
+    // node weights of the adjoint's far units: Lagrange weights of 16 nodes over 256, 1024 and
+    // 4096 points
+    for (int lv = 0; lv < hk::kAdjLevels; ++lv)
+      HK_HIP(hk::launch_adj_nodes(dL_dk, grid.n, lv, di.adj_w[lv], gpref[lv], stream));
     HK_HIP(hk::launch_adjoint(a, blocks, stream));
   }
   HK_HIP(hk::launch_reduce2(contrib, lines->N, part, kBwdPartials, dL_dT_lnP, stream));

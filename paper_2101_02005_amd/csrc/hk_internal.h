@@ -257,10 +257,12 @@ struct AdjArgs {
   float* dn;               // caller order, nullable
   double* contrib;         // [N][2], sorted order: per-line dL/dT and dL/dlnP terms
   double* lrec;            // [N][6], sorted order: per-line FP64 quantities (k_adj_lines)
-  const double* gpref;     // [span][kNodes][kAdjSpan]: per span of kAdjSpan points, the prefix sums
-                           // over its points j of dL/dk_j times node k's Lagrange weight at j
+  const double* gpref[3];  // per level L: [unit][kNodes][kAdjSpan 4^L]: per far unit of kAdjSpan 4^L
+                           // points, the prefix sums over its points j of dL/dk_j times node k's
+                           // Lagrange weight at j
 };
-constexpr int kAdjSpan = 256;  // points per span of the adjoint (one step of a wave)
+constexpr int kAdjSpan = 256;   // points per span of the adjoint (one step of a wave)
+constexpr int kAdjLevels = 3;   // far units of kAdjSpan, 4 kAdjSpan and 16 kAdjSpan points
 
 // Line profiles and cutting-length modes of the options path.
 enum { kProfVoigt = 0, kProfLorentz = 1, kProfDoppler = 2, kProfBinned = 3 };
@@ -336,7 +338,8 @@ hipError_t launch_far(const FarArgs& a, int cls, int grid, hipStream_t st);
 hipError_t launch_combine_far(const FarArgs& a, hipStream_t st);
 int far_max_blocks_per_cu();
 // gpref of AdjArgs from dL/dk (g, n points) and the node weights w [kNodes][kAdjSpan]
-hipError_t launch_adj_nodes(const float* g, int64_t n, const double* w, double* gpref, hipStream_t st);
+// the prefix sums of one level of far units (kAdjSpan << 2 level points each) with its node weights
+hipError_t launch_adj_nodes(const float* g, int64_t n, int level, const double* w, double* gpref, hipStream_t st);
 hipError_t launch_adjoint(const AdjArgs& a, int grid, hipStream_t st);
 hipError_t launch_reduce2(const double* contrib, int64_t N, double* partial, int n_partial, double* out,
                           hipStream_t st);

@@ -2746,29 +2746,44 @@ __device__ __forceinline__ void adj_step(const AdjPoly& P, int jc, int lane, int
 }
 
 
-// Node weights of dL/dk for the adjoint's far spans: for span s (points s kAdjSpan + jj) and
-// node k, the prefix sums over jj of g_j L_k(jj) (L_k: the Lagrange weight of node k of the span
-// at its point jj), in FP64 by a fixed-order scan. A line that covers points a..b of a span far
-// from its centre then takes sum_j g_j f(j) = sum_k f(x_k) (P_k(b) - P_k(a - 1)) up to the
-// interpolation error of f on the span.
+// Node weights of dL/dk for the adjoint's far units, one level (units of W points): for unit u
+// (points u W + jj) and node k, the prefix sums over jj of g_j L_k(jj) (L_k: the Lagrange weight
+// of node k of the unit at its point jj), in FP64 in a fixed order (each thread sums its
+// W / kAdjSpan consecutive points, then a scan over the threads' totals). A line that covers
+// points a..b of a unit far from its centre then takes sum_j g_j f(j) = sum_k f(x_k) (P_k(b) -
+// P_k(a - 1)) up to the interpolation error of f on the unit.
+template <int W>
 __global__ __launch_bounds__(kAdjSpan) void k_adj_nodes(const float* __restrict__ g, int64_t n,
                                                         const double* __restrict__ w, double* __restrict__ gpref) {
+  constexpr int R = W / kAdjSpan;  // points per thread
   __shared__ double sc[kAdjSpan];
-  const int s = blockIdx.x, jj = threadIdx.x;
-  const int64_t j = (int64_t)s * kAdjSpan + jj;
-  const double gv = j < n ? (double)g[j] : 0.0;
+  const int u = blockIdx.x, t = threadIdx.x;
+  const int64_t j0 = (int64_t)u * W + (int64_t)t * R;
+  double gv[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) gv[r] = j0 + r < n ? (double)g[j0 + r] : 0.0;
   for (int k = 0; k < kNodes; ++k) {
-    double v = gv * w[k * kAdjSpan + jj];
-    sc[jj] = v;
+    double loc[R];
+    double run = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      run += gv[r] * w[k * W + t * R + r];
+      loc[r] = run;
+    }
+    double v = run;
+    sc[t] = v;
     __syncthreads();
     for (int off = 1; off < kAdjSpan; off <<= 1) {
-      const double t = jj >= off ? sc[jj - off] : 0.0;
+      const double x = t >= off ? sc[t - off] : 0.0;
       __syncthreads();
-      v += t;
-      sc[jj] = v;
+      v += x;
+      sc[t] = v;
       __syncthreads();
     }
-    gpref[((int64_t)s * kNodes + k) * kAdjSpan + jj] = v;
+    const double excl = v - run;
+    double* out = gpref + ((int64_t)u * kNodes + k) * W + (int64_t)t * R;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[r] = R == 1 ? v : loc[r] + excl;
     __syncthreads();
   }
 }
@@ -2803,10 +2818,13 @@ __global__ __launch_bounds__(kThreads) void k_adj_lines(AdjArgs a) {
   r[5] = nexp * gam / T;
 }
 
-// Far spans of the adjoint: kAdjSpan-point spans at least this many span widths from the line
-// centre (span centre to line centre) and clear of its core zone take the node weights of dL/dk.
+// Far units of the adjoint: a unit (a span of kAdjSpan points, or 4 or 16 of them) at least this
+// many unit widths from the line centre (unit centre to line centre) and clear of its core zone
+// takes the node weights of dL/dk over its points.
 constexpr double kAdjFarSpans = 1.5;
-constexpr int kAdjSpansPerPass = kWave / kNodes;  // far spans per wave pass (one lane per node)
+constexpr int kAdjSpansPerPass = kWave / kNodes;  // far units per wave pass (one lane per node)
+
+__device__ __forceinline__ int floor_div4(int x) { return x >= 0 ? x / 4 : -((-x + 3) / 4); }
 
 // One far-span pass: lanes 16 q + k evaluate the profile polynomials of the set P at node k of
 // span s (lane-dependent), weighted by that span's node weight G of dL/dk over the line's points.
@@ -2827,11 +2845,15 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t nw = (int64_t)gridDim.x * kWavesPerWG;
   const PrepArgs& pa = a.pa;
-  // node position of this lane in its far span (node k = lane mod kNodes)
+  // node position of this lane in a far unit of each level (node k = lane mod kNodes)
   const int kn = lane & (kNodes - 1);
-  float xk = 0.0f;
+  float xk0 = 0.0f, xk1 = 0.0f, xk2 = 0.0f;
 #pragma unroll
-  for (int k = 0; k < kNodes; ++k) xk = kn == k ? node_pos(kAdjSpan, kNodes, k) : xk;
+  for (int k = 0; k < kNodes; ++k) {
+    xk0 = kn == k ? node_pos(kAdjSpan, kNodes, k) : xk0;
+    xk1 = kn == k ? node_pos(4 * kAdjSpan, kNodes, k) : xk1;
+    xk2 = kn == k ? node_pos(16 * kAdjSpan, kNodes, k) : xk2;
+  }
   for (int64_t i = (int64_t)blockIdx.x * kWavesPerWG + wv; i < pa.N; i += nw) {
     const double* lr = a.lrec + 6 * i;
     const double gam = lr[1];
@@ -2883,42 +2905,88 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
       // spans sa..sb of the line's points: far on the left up to sL, far on the right from sR,
       // direct in between (the direct spans are the ones near the centre and its core zone)
       const int sa = jlo0 / kAdjSpan, sb = jhi0 / kAdjSpan;
-      const double reach = kAdjFarSpans * kAdjSpan, half = 0.5 * (kAdjSpan - 1);
-      int sL, sR;
-      {
-        const double l1 = floor((cpos - reach - half) / kAdjSpan);
-        const double l2 = floor(((double)zlo[kKmax - 1] - kAdjSpan) / kAdjSpan);
-        const double r1 = ceil((cpos + reach - half) / kAdjSpan);
-        const double r2 = floor((double)zhi[kKmax - 1] / kAdjSpan) + 1.0;
-        const double l = fmin(fmin(l1, l2), (double)sb), r = fmax(fmax(r1, r2), (double)sa);
-        sL = __builtin_amdgcn_readfirstlane(l < sa - 1.0 ? sa - 1 : (int)l);
-        sR = __builtin_amdgcn_readfirstlane(r > sb + 1.0 ? sb + 1 : (int)r);
+      // the last far unit of each level on the left and the first on the right (level L: units of
+      // kAdjSpan 4^L points)
+      int uL[kAdjLevels], uR[kAdjLevels];
+#pragma unroll
+      for (int L = 0; L < kAdjLevels; ++L) {
+        const double Wd = (double)(kAdjSpan << (2 * L));
+        const double reach = kAdjFarSpans * Wd, half = 0.5 * (Wd - 1.0);
+        const double l = fmin(floor((cpos - reach - half) / Wd), floor(((double)zlo[kKmax - 1] - Wd) / Wd));
+        const double r = fmax(ceil((cpos + reach - half) / Wd), floor((double)zhi[kKmax - 1] / Wd) + 1.0);
+        uL[L] = __builtin_amdgcn_readfirstlane(l < -2.0 ? -2 : (l > 1.0e8 ? 100000000 : (int)l));
+        uR[L] = __builtin_amdgcn_readfirstlane(r > 1.0e8 ? 100000000 : (r < -2.0 ? -2 : (int)r));
       }
-      const int nL = sL - sa + 1, nF = nL + (sb - sR + 1);
+      const int sL = uL[0] < sb ? (uL[0] < sa - 1 ? sa - 1 : uL[0]) : sb;
+      const int sR = uR[0] > sa ? (uR[0] > sb + 1 ? sb + 1 : uR[0]) : sa;
+      // walking outward from the direct spans, a side switches to the next level at the first
+      // unit boundary whose unit of that level is far: left, spans sL down to s1 + 1, level-1
+      // units t1 down to u2 + 1, level-2 units t2 = u2 / 4 down; right, spans sR up to r1 - 1,
+      // level-1 units f1 = r1 / 4 up to v2 - 1, level-2 units f2 = v2 / 4 up (each level clipped
+      // to the cut range)
+      int n0L, n1L = 0, n2L = 0, t1 = 0, t2 = 0, n0R, n1R = 0, n2R = 0, f1 = 0, f2 = 0;
+      {
+        const int s1 = min(4 * floor_div4(sL + 1) - 1, 4 * uL[1] + 3);
+        if (s1 < sa) {
+          n0L = sL - sa + 1;
+        } else {
+          n0L = sL - s1;
+          t1 = s1 / 4;
+          const int b1 = sa / 4;
+          const int u2 = min(4 * floor_div4(t1 + 1) - 1, 4 * uL[2] + 3);
+          if (u2 < b1) {
+            n1L = t1 - b1 + 1;
+          } else {
+            n1L = t1 - u2;
+            t2 = u2 / 4;
+            n2L = t2 - sa / 16 + 1;
+          }
+        }
+        const int r1 = max(4 * ((sR + 3) / 4), 4 * uR[1]);
+        if (r1 > sb) {
+          n0R = sb - sR + 1;
+        } else {
+          n0R = r1 - sR;
+          f1 = r1 / 4;
+          const int e1 = sb / 4;
+          const int v2 = max(4 * ((f1 + 3) / 4), 4 * uR[2]);
+          if (v2 > e1) {
+            n1R = e1 - f1 + 1;
+          } else {
+            n1R = v2 - f1;
+            f2 = v2 / 4;
+            n2R = sb / 16 - f2 + 1;
+          }
+        }
+        n0L = n0L < 0 ? 0 : n0L;
+        n0R = n0R < 0 ? 0 : n0R;
+      }
+      const int nF = n0L + n1L + n2L + n0R + n1R + n2R;
       for (int fb = 0; fb < nF; fb += kAdjSpansPerPass) {
         asm volatile("" ::: "memory");
         const int f = fb + (lane >> 4);
-        const int fs = f < nF ? f : nF - 1;
-        const int s = fs < nL ? sa + fs : sR + (fs - nL);
-        const int s0 = s * kAdjSpan;
-        const int pa0 = (jlo0 > s0 ? jlo0 : s0) - s0, pb = (jhi0 < s0 + kAdjSpan - 1 ? jhi0 : s0 + kAdjSpan - 1) - s0;
-        const double* pr = a.gpref + ((int64_t)s * kNodes + kn) * kAdjSpan;
+        int r = f < nF ? f : nF - 1;
+        int lv, u;  // this lane's unit: level and index
+        if (r < n0L) { lv = 0; u = sL - r; }
+        else if ((r -= n0L) < n1L) { lv = 1; u = t1 - r; }
+        else if ((r -= n1L) < n2L) { lv = 2; u = t2 - r; }
+        else if ((r -= n2L) < n0R) { lv = 0; u = sR + r; }
+        else if ((r -= n0R) < n1R) { lv = 1; u = f1 + r; }
+        else { lv = 2; u = f2 + (r - n1R); }
+        const int Wl = kAdjSpan << (2 * lv);
+        const int s0 = u * Wl;
+        const int pa0 = (jlo0 > s0 ? jlo0 : s0) - s0, pb = (jhi0 < s0 + Wl - 1 ? jhi0 : s0 + Wl - 1) - s0;
+        const double* pr = a.gpref[lv] + ((int64_t)u * kNodes + kn) * Wl;
         double Gd = pr[pb];
         if (pa0 > 0) Gd -= pr[pa0 - 1];
         const float G = f < nF ? (float)Gd : 0.0f;
-        // series terms for this group: as for a direct step over the group's spans
-        const int fl = fb + kAdjSpansPerPass - 1 < nF ? fb + kAdjSpansPerPass - 1 : nF - 1;
-        const int e0 = (fb < nL ? sa + fb : sR + (fb - nL)) * kAdjSpan;
-        const int e1 = (fl < nL ? sa + fl : sR + (fl - nL)) * kAdjSpan + kAdjSpan - 1;
-        int KD = 2;
+        // series terms for this pass: one more than the profile needs at the pass's points
+        int KL = 2;
 #pragma unroll
-        for (int z = 0; z < kKmax - 1; ++z) {
-          // a group may straddle the centre (left and right spans): test each side's range
-          const bool hitL = fb < nL && (sa + (fl < nL ? fl : nL - 1)) * kAdjSpan + kAdjSpan - 1 >= zlo[z] && e0 <= zhi[z];
-          const bool hitR = fl >= nL && e1 >= zlo[z] && (sR + (fb > nL ? fb - nL : 0)) * kAdjSpan <= zhi[z];
-          KD += (hitL || hitR) ? 1 : 0;
-        }
+        for (int z = 0; z < kKmax - 1; ++z) KL += (s0 + pb >= zlo[z] && s0 + pa0 <= zhi[z]) ? 1 : 0;
+        const int KD = 2 + (__ballot(KL >= 3) != 0ull ? 1 : 0) + (__ballot(KL >= 4) != 0ull ? 1 : 0);
         const float xoff = (float)(s0 - jref);
+        const float xk = lv == 0 ? xk0 : (lv == 1 ? xk1 : xk2);
         if (KD == 2) {
           adj_far<3, 3, 4>(sP[wv][0], G, xoff, xk, dnh, dh, gh, bV, bA, bG);
         } else if (KD == 3) {
@@ -3253,8 +3321,15 @@ int far_max_blocks_per_cu() {
   return n > 0 ? n : 1;
 }
 
-hipError_t launch_adj_nodes(const float* g, int64_t n, const double* w, double* gpref, hipStream_t st) {
-  hipLaunchKernelGGL(k_adj_nodes, dim3(blocks_for(n, kAdjSpan)), dim3(kAdjSpan), 0, st, g, n, w, gpref);
+hipError_t launch_adj_nodes(const float* g, int64_t n, int level, const double* w, double* gpref, hipStream_t st) {
+  if (level == 0)
+    hipLaunchKernelGGL(k_adj_nodes<kAdjSpan>, dim3(blocks_for(n, kAdjSpan)), dim3(kAdjSpan), 0, st, g, n, w, gpref);
+  else if (level == 1)
+    hipLaunchKernelGGL(k_adj_nodes<4 * kAdjSpan>, dim3(blocks_for(n, 4 * kAdjSpan)), dim3(kAdjSpan), 0, st, g, n, w,
+                       gpref);
+  else
+    hipLaunchKernelGGL(k_adj_nodes<16 * kAdjSpan>, dim3(blocks_for(n, 16 * kAdjSpan)), dim3(kAdjSpan), 0, st, g, n,
+                       w, gpref);
   return hipGetLastError();
 }
 
