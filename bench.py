@@ -256,7 +256,7 @@ def bench_batched(hk, n_lines, repeats=5):
             "max_rel_diff_batched_vs_plain": diff, "oracle_window_max_rel_err": orc}
 
 
-ADJ_FLOPS_PER_PAIR = 16  # the adjoint's FP32 work per (line, point) pair: the profile (8) plus the
+ADJ_FLOPS_PER_EVAL = 16  # the adjoint's FP32 work per evaluation made: the profile (8) plus the
                          # two derivative polynomials and three dL/dk-weighted accumulations
 
 
@@ -282,7 +282,9 @@ def bench_backward(hk, n_lines, repeats=5):
         out2, dS, dg, dn = hk.hk_opacity_backward(lines, w.T[0], w.P[0], grd, w.cut, g, ws=ws)
         torch.cuda.synchronize()
         tb.append(time.perf_counter() - t0)
-        tk.append(hk.hk_get_timings().backward_ms)
+        tm = hk.hk_get_timings()
+        tk.append(tm.backward_ms)
+    evals = int(tm.backward_evals)  # direct points and 16 per far unit (each stands for its points)
     wsf = hk._lib._workspace(hk.hk_workspace_size(lines, 0, [grd], w.cut))
     kf = torch.empty(w.n_grid, dtype=torch.float32, device="cuda")
     hk.hk_opacity(lines, w.T[0], w.P[0], grd, w.cut, k=kf, ws=wsf)
@@ -296,14 +298,15 @@ def bench_backward(hk, n_lines, repeats=5):
     ne = count_evals(hk, lines, grd, w.cut)
     lines.release()
     t, kms = _median(tb), _median(tk)
-    ach = ADJ_FLOPS_PER_PAIR * ne / (kms * 1e-3) / 1e12
+    ach = ADJ_FLOPS_PER_EVAL * evals / (kms * 1e-3) / 1e12
     return {"workload": "%d lines, grid %g-%g cm^-1 at %g (%d points), cut %g, T=%g K, P=%g atm, dL/dk ~ N(0,1)"
                         % (w.N, w.nu_start, w.nu_end, w.dnu, w.n_grid, w.cut, w.T[0], w.P[0]),
             "backward_s": t, "backward_kernel_ms": kms, "forward_s": _median(tf), "backward_over_forward": t / _median(tf),
-            "pairs": ne, "pairs_per_s_backward": ne / t,
+            "pairs": ne, "pairs_per_s_backward": ne / t, "evals_made": evals,
             "roofline": {"bound": "alu", "achieved": ach, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                         "frac": ach / PEAK_FP32_TFLOPS, "flops_per_pair": ADJ_FLOPS_PER_PAIR,
-                         "kernel": "adjoint (k_adj_nodes + k_adj_lines + k_adjoint + k_reduce2)"},
+                         "frac": ach / PEAK_FP32_TFLOPS, "flops_per_eval": ADJ_FLOPS_PER_EVAL,
+                         "kernel": "adjoint (k_adj_nodes + k_adj_lines + k_adjoint + k_reduce2), on the "
+                                   "evaluations made (direct points, 16 nodes per far unit)"},
             "dL_dT": out2[0].item(), "dL_dlnP": out2[1].item()}
 
 

@@ -108,6 +108,9 @@ typedef struct hk_timings {
                               cut bound on the span at its 6 nodes, [5] and [6] tile-far lines at
                               a tile's 16 and 8 nodes, [7] core evaluations (FP64) */
   int32_t status;          /* status word of the last timed call (0: every work item stored) */
+  int64_t backward_evals;  /* profile evaluations the last timed hk_opacity_backward made: every
+                              point of a line's direct spans, 16 per far unit of 256, 1024 or
+                              4096 points (each with the profile and its two width derivatives) */
 } hk_timings;
 
 /* Options of hk_opacity_ex / hk_opacity_batched_ex (NULL: all zero).

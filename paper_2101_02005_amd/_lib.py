@@ -36,7 +36,8 @@ class Timings(ctypes.Structure):
                 ("tile_width", ctypes.c_int32), ("lines_per_batch", ctypes.c_int32),
                 ("chunk_lines", ctypes.c_int32), ("n_items", ctypes.c_int32), ("core_ms", ctypes.c_double),
                 ("core_evals", ctypes.c_int64), ("far_ms", ctypes.c_double),
-                ("wing_evals", ctypes.c_int64), ("class_evals", ctypes.c_int64 * 8), ("status", ctypes.c_int32)]
+                ("wing_evals", ctypes.c_int64), ("class_evals", ctypes.c_int64 * 8), ("status", ctypes.c_int32),
+                ("backward_evals", ctypes.c_int64)]
 
 
 # evaluation classes of Timings.class_evals

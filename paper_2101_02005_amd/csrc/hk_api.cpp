@@ -78,7 +78,7 @@ constexpr double kZW[hk::kKw] = {870.0, 37.5, 13.8, 8.7, 6.75, 5.65, 5.0, 4.65, 
 double core_threshold(bool default_path) { return default_path ? kZW[hk::kKw - 1] : kZK[hk::kKmax - 1]; }
 
 thread_local std::string g_err;
-thread_local hk_timings g_tim = {-1, -1, -1, -1, -1, -1, 0, 0, 0, 0, -1, -1, -1, -1, {-1, -1, -1, -1, -1, -1, -1, -1}, 0};
+thread_local hk_timings g_tim = {-1, -1, -1, -1, -1, -1, 0, 0, 0, 0, -1, -1, -1, -1, {-1, -1, -1, -1, -1, -1, -1, -1}, 0, -1};
 
 hk_status fail(hk_status s, const char* fmt, ...) {
   char buf[512];
@@ -685,13 +685,16 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
 // per-line FP64 records and the node weights of dL/dk per span of the grid.
 constexpr int kBwdPartials = 256;
 struct BwdLayout {
-  size_t off_gr = 0, off_contrib = 0, off_part = 0, off_lrec = 0, off_pref[hk::kAdjLevels] = {}, total = 0;
+  size_t off_gr = 0, off_contrib = 0, off_part = 0, off_lrec = 0, off_pref[hk::kAdjLevels] = {}, off_stats = 0,
+         total = 0;
 };
+constexpr int64_t kAdjMaxWaves = 1 << 16;  // bound of the adjoint's waves (its grid is capped below)
 BwdLayout backward_layout(int64_t N, int64_t n_grid) {
   BwdLayout b;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes, 256); return o; };
   b.off_gr = take(sizeof(int4) * (size_t)N);
+  b.off_stats = take(sizeof(long long) * kAdjMaxWaves);
   b.off_contrib = take(2 * sizeof(double) * (size_t)N);
   b.off_part = take(2 * sizeof(double) * kBwdPartials);
   b.off_lrec = take(6 * sizeof(double) * (size_t)N);
@@ -1971,8 +1974,10 @@ hk_status hk_opacity_backward(const hk_lines* lines, const hk_line_override* ovr
     a.gpref[lv] = gpref[lv];
   }
   const int64_t want = (lines->N + hk::kWavesPerWG - 1) / hk::kWavesPerWG;
-  const int64_t cap = (int64_t)di.cus * 8;
+  const int64_t cap = std::min<int64_t>((int64_t)di.cus * 8, kAdjMaxWaves / hk::kWavesPerWG);
   const int blocks = (int)std::max<int64_t>(1, std::min(want, cap));
+  long long* stats = reinterpret_cast<long long*>(w + bl.off_stats);
+  a.stats = tm.on ? stats : nullptr;
   if (lines->N > 0) {
     // node weights of the adjoint's far units: Lagrange weights of 16 nodes over 256, 1024 and
     // 4096 points
@@ -1987,6 +1992,14 @@ hk_status hk_opacity_backward(const hk_lines* lines, const hk_line_override* ovr
   g_tim.core_evals = g_tim.wing_evals = -1;
   for (int c = 0; c < 8; ++c) g_tim.class_evals[c] = -1;
   g_tim.backward_ms = tm.ms(0);
+  g_tim.backward_evals = -1;
+  if (tm.on && lines->N > 0) {
+    std::vector<long long> h((size_t)blocks * hk::kWavesPerWG);
+    HK_HIP(hipMemcpy(h.data(), stats, sizeof(long long) * h.size(), hipMemcpyDeviceToHost));
+    long long t = 0;
+    for (long long v : h) t += v;
+    g_tim.backward_evals = t;
+  }
   note_use(const_cast<hk_lines*>(lines), stream, true);
   return HK_OK;
 }

@@ -257,6 +257,7 @@ struct AdjArgs {
   float* dn;               // caller order, nullable
   double* contrib;         // [N][2], sorted order: per-line dL/dT and dL/dlnP terms
   double* lrec;            // [N][6], sorted order: per-line FP64 quantities (k_adj_lines)
+  long long* stats;        // nullable: per wave of k_adjoint, the evaluations it made
   const double* gpref[3];  // per level L: [unit][kNodes][kAdjSpan 4^L]: per far unit of kAdjSpan 4^L
                            // points, the prefix sums over its points j of dL/dk_j times node k's
                            // Lagrange weight at j

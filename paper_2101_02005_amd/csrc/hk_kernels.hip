@@ -2854,6 +2854,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
     xk1 = kn == k ? node_pos(4 * kAdjSpan, kNodes, k) : xk1;
     xk2 = kn == k ? node_pos(16 * kAdjSpan, kNodes, k) : xk2;
   }
+  long long n_eval = 0;  // evaluations this wave made (statistics only)
   for (int64_t i = (int64_t)blockIdx.x * kWavesPerWG + wv; i < pa.N; i += nw) {
     const double* lr = a.lrec + 6 * i;
     const double gam = lr[1];
@@ -2962,6 +2963,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
         n0R = n0R < 0 ? 0 : n0R;
       }
       const int nF = n0L + n1L + n2L + n0R + n1R + n2R;
+      n_eval += (long long)kNodes * nF;
       for (int fb = 0; fb < nF; fb += kAdjSpansPerPass) {
         asm volatile("" ::: "memory");
         const int f = fb + (lane >> 4);
@@ -3000,6 +3002,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
       // direct points: the line's points in spans sL + 1 .. sR - 1
       const int jlo = jlo0 > (sL + 1) * kAdjSpan ? jlo0 : (sL + 1) * kAdjSpan;
       const int jhi = jhi0 < sR * kAdjSpan - 1 ? jhi0 : sR * kAdjSpan - 1;
+      if (jhi >= jlo) n_eval += jhi - jlo + 1;
       // steps of kAdjP x 64 points (kAdjP per lane); the next step's dL/dk is loaded ahead
       constexpr int kAdjP = 4, kStep = kAdjP * kWave;
       float gcur[kAdjP];
@@ -3102,6 +3105,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
       a.contrib[2 * i + 1] = lr[1] * Gg;
     }
   }
+  if (a.stats && lane == 0) a.stats[(int64_t)blockIdx.x * kWavesPerWG + wv] = n_eval;
 }
 
 // Fixed-order sums of the per-line (dL/dT, dL/dlnP) terms: per-block tree sums, then one block.
