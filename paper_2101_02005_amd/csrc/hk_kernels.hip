@@ -2687,16 +2687,16 @@ __constant__ float c_adjT[6][8] = {{1, -2, 0, 0, 0, 0, 0, 0},           {1, -8, 
                                    {1, -18, 48, -32, 0, 0, 0, 0},       {1, -32, 160, -256, 128, 0, 0, 0},
                                    {1, -50, 400, -1120, 1280, -512, 0, 0}, {1, -72, 840, -3584, 6912, -6144, 2048, 0}};
 
-// Coefficients of q^M (one M per lane) of the three polynomials, series truncated after KD terms.
-template <int KD>
-__device__ __forceinline__ void adj_coef(int M, float a, float g, float& v, float& da, float& dg) {
+// Coefficients of q^M (one M per lane) of the three polynomials, series truncated after KD terms
+// (1..kKmax + 1; three sets are formed in one pass, one per 16-lane group).
+__device__ __forceinline__ void adj_coef_rt(int KD, int M, float a, float g, float& v, float& da, float& dg) {
   constexpr float ak[6] = {1.0f, 0.5f, 0.75f, 1.875f, 6.5625f, 29.53125f};
   v = da = dg = 0.0f;
   float ap = 1.0f;
 #pragma unroll
-  for (int k = 0; k < KD; ++k) {
+  for (int k = 0; k < kKmax + 1; ++k) {
     const int j = M - k - 1;  // power of u
-    if (j >= 0 && j <= k + 1) {
+    if (k < KD && j >= 0 && j <= k + 1) {
       float gp = 1.0f;
       for (int r = 0; r < j; ++r) gp *= g;
       const float w = ak[k] * ap * gp;
@@ -2839,7 +2839,7 @@ __device__ __forceinline__ void adj_far(const AdjPoly& P, float G, float xoff, f
   bG = __builtin_fmaf(gq, adj_horner1<DG>(P.dg, q), bG);
 }
 
-__global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_adjoint(AdjArgs a) {
   __shared__ AdjPoly sP[kWavesPerWG][3];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -2868,21 +2868,20 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
     if (jlo0 <= jhi0 && scd > 0.0) {
       const float rs = (float)(1.0 / sqrt(scd));
       const float dh = __int_as_float(gr.x) * rs, dnh = (float)a.dnu * rs, gh = (float)gam * rs;
-      // coefficient sets of this line: 3 terms (chunks of series order <= 2) and 6 terms
+      // coefficient sets of this line, 2, 3 and 6 terms (chunks of series order <= 1, 2 and the
+      // rest), one set per 16-lane group, one power of q per lane
       {
         const float ah = (float)(a2d / scd), gh2 = (float)(g2d / scd);
-        if (lane < kAdjDeg) {
+        const int M = lane & 15, set = lane >> 4;
+        if (M < kAdjDeg && set < 3) {
           float v, da, dg;
-          adj_coef<2>(lane, ah, gh2, v, da, dg);
-          sP[wv][0].v[lane] = v; sP[wv][0].da[lane] = da; sP[wv][0].dg[lane] = dg;
-          adj_coef<3>(lane, ah, gh2, v, da, dg);
-          sP[wv][1].v[lane] = v; sP[wv][1].da[lane] = da; sP[wv][1].dg[lane] = dg;
-          adj_coef<kKmax + 1>(lane, ah, gh2, v, da, dg);
-          sP[wv][2].v[lane] = v; sP[wv][2].da[lane] = da; sP[wv][2].dg[lane] = dg;
+          adj_coef_rt(set == 0 ? 2 : (set == 1 ? 3 : kKmax + 1), M, ah, gh2, v, da, dg);
+          sP[wv][set].v[M] = v; sP[wv][set].da[M] = da; sP[wv][set].dg[M] = dg;
         }
       }
       // zones in grid points around the centre
-      const double cpos = (double)jref - (double)__int_as_float(gr.x) / a.dnu;
+      const double inv_dnu = 1.0 / a.dnu;
+      const double cpos = (double)jref - (double)__int_as_float(gr.x) * inv_dnu;
       int zlo[kKmax], zhi[kKmax];
 #pragma unroll
       for (int K = 0; K < kKmax; ++K) {
@@ -2891,7 +2890,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
         zlo[K] = 2000000000;  // empty zone: no chunk intersects it
         zhi[K] = -2000000000;
         if (h2 > 0.0) {
-          const double h = sqrt(h2) / a.dnu * 1.00001 + 1e-3;
+          const double h = sqrt(h2) * inv_dnu * 1.00001 + 1e-3;
           const double lo = ceil(cpos - h), hi = floor(cpos + h);
           zlo[K] = lo < -1.0 ? -1 : (lo > 2.0e9 ? 2000000000 : (int)lo);
           zhi[K] = hi < -1.0 ? -1 : (hi > 2.0e9 ? 2000000000 : (int)hi);
@@ -2900,7 +2899,7 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
         zhi[K] = __builtin_amdgcn_readfirstlane(zhi[K]);
       }
       const double d64 = __dsub_rn(grid_nu(a.nu_start, a.dnu, (int64_t)jref), nu0);
-      const double ia = 1.0 / alpha, y = gam / alpha;
+      const double ia = 1.0 / alpha, y = gam * ia;
       const double zc2 = (double)a.zK[kKmax - 1] * (double)a.zK[kKmax - 1];
       float bV = 0.f, bG = 0.f, bA = 0.f;
       // spans sa..sb of the line's points: far on the left up to sL, far on the right from sR,
@@ -2911,10 +2910,10 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
       int uL[kAdjLevels], uR[kAdjLevels];
 #pragma unroll
       for (int L = 0; L < kAdjLevels; ++L) {
-        const double Wd = (double)(kAdjSpan << (2 * L));
+        const double Wd = (double)(kAdjSpan << (2 * L)), iW = 1.0 / Wd;  // a power of two: exact
         const double reach = kAdjFarSpans * Wd, half = 0.5 * (Wd - 1.0);
-        const double l = fmin(floor((cpos - reach - half) / Wd), floor(((double)zlo[kKmax - 1] - Wd) / Wd));
-        const double r = fmax(ceil((cpos + reach - half) / Wd), floor((double)zhi[kKmax - 1] / Wd) + 1.0);
+        const double l = fmin(floor((cpos - reach - half) * iW), floor(((double)zlo[kKmax - 1] - Wd) * iW));
+        const double r = fmax(ceil((cpos + reach - half) * iW), floor((double)zhi[kKmax - 1] * iW) + 1.0);
         uL[L] = __builtin_amdgcn_readfirstlane(l < -2.0 ? -2 : (l > 1.0e8 ? 100000000 : (int)l));
         uR[L] = __builtin_amdgcn_readfirstlane(r > 1.0e8 ? 100000000 : (r < -2.0 ? -2 : (int)r));
       }
@@ -3081,17 +3080,14 @@ __global__ __launch_bounds__(kThreads) void k_adjoint(AdjArgs a) {
         for (int p = 0; p < kAdjP; ++p) gcur[p] = gnx[p];
       }
       SVw += (double)bV; SGw += (double)bG; SAw += (double)bA;
-      // per-lane sums to per-wave sums (fixed butterfly order)
-      SVw = wave_sum64(SVw); SGw = wave_sum64(SGw); SAw = wave_sum64(SAw);
-      SVc = wave_sum64(SVc); SGc = wave_sum64(SGc); SAc = wave_sum64(SAc);
+      // the wing and core sums of each lane with the line's factors, then per-wave sums (fixed
+      // butterfly order)
       const double isp = 0.56418958354775628695;  // 1/sqrt(pi)
-      const double gL = lr[1], aL = pa.nu[i] * pa.beta, SL = lr[0];
-      const double iaL = 1.0 / aL;
-      const double sL2 = aL * aL > gL * gL ? aL * aL : gL * gL;
-      const double GV = gL / (M_PI * sL2) * SVw + SVc * isp * iaL;               // sum g V
-      const double GGs = SGw / (M_PI * sL2) + SGc * isp * iaL * iaL;             // sum g dV/dgamma
-      const double GAs = gL / (M_PI * sL2 * aL) * SAw + SAc * isp * iaL * iaL;   // sum g dV/dalpha
-      SVw = GV; SGw = SL * GGs; SAw = SL * GAs;
+      const double ipis = 1.0 / (M_PI * scd);     // 1/(pi s), s = max(alpha^2, gamma^2)
+      const double GV = wave_sum64(gam * ipis * SVw + SVc * isp * ia);                 // sum g V
+      const double GGs = wave_sum64(ipis * SGw + SGc * isp * ia * ia);                 // sum g dV/dgamma
+      const double GAs = wave_sum64(gam * ipis * ia * SAw + SAc * isp * ia * ia);      // sum g dV/dalpha
+      SVw = GV; SGw = lr[0] * GGs; SAw = lr[0] * GAs;
     }
     if (lane == 0) {
       // SVw, SGw, SAw now hold sum_j g_j V_ij, dL/dgamma_i, dL/dalpha_i (zero without points)
@@ -3234,8 +3230,8 @@ hipError_t launch_gridrec(const double* nu, int64_t N, double nu_start, double d
   return hipGetLastError();
 }
 
-// Tunings: P (64-point slots per lane group; tile width 256 P) in {1, 2, 4, 8} and the LDS
-// line batch LB in {128, 256} of the wing pass.
+// Tunings: P (64-point slots per wave; tile width 256 P) in {1, 2, 4, 8}; a wave stages 64 lines
+// (one per lane) per LDS batch.
 template <template <int> class F, typename... A>
 static hipError_t by_slots(int slots, A... args) {
   switch (slots) {
