@@ -106,7 +106,7 @@ typedef struct hk_timings {
                               [1] far lines at a span's 16 nodes, [2] very far lines at its 8
                               nodes, [3] middle-distance lines at its 32 nodes, [4] lines with a
                               cut bound on the span at its 6 nodes, [5] and [6] tile-far lines at
-                              a tile's 16 and 8 nodes, [7] core evaluations (FP64) */
+                              a tile's 16 and 8 nodes, [7] core evaluations */
   int32_t status;          /* status word of the last timed call (0: every work item stored) */
   int64_t backward_evals;  /* profile evaluations the last timed hk_opacity_backward made: every
                               point of a line's direct spans, 16 per far unit of 256, 1024 or
@@ -133,7 +133,7 @@ typedef struct hk_timings {
  *              at its Chebyshev nodes and interpolated. For measurement of the per-pair rate.
  * Any option other than the default Voigt with a fixed cut and no plinth runs a direct pass that
  * evaluates every (line, point) pair inside each line's own cut in FP32 with compensated sums
- * (the Voigt core points, |z| < 6.75, keep the FP64 core pass). */
+ * (the Voigt core points, |z| < 6.75, go to the core pass). */
 enum { HK_PROFILE_VOIGT = 0, HK_PROFILE_LORENTZ = 1, HK_PROFILE_DOPPLER = 2, HK_PROFILE_BINNED_GAUSS = 3 };
 enum { HK_CUT_FIXED = 0, HK_CUT_DOPPLER = 1, HK_CUT_LORENTZ = 2 };
 typedef struct hk_options {
@@ -260,7 +260,7 @@ hk_status hk_workspace_size_ex(const hk_lines* lines, int mode, int32_t n_pairs,
  * shift can change the order of the centres along nu (the paper sorts after applying it, Sec.
  * 2.4.3 step 3), so each call bins the list again by nu* in its workspace, then evaluates every
  * (line, point) pair inside each line's cut (the direct pass of the options path; the Voigt core
- * points by the FP64 core pass). options as hk_opacity_ex (direct must be 0); the workspace must
+ * points by the core pass). options as hk_opacity_ex (direct must be 0); the workspace must
  * hold hk_workspace_size_hitran bytes (about 68 bytes per line more than hk_opacity_ex).
  */
 hk_status hk_prepare_lines_hitran(const double* nu, const double* S_ref, const double* E_low,

@@ -144,10 +144,12 @@ std::map<std::string, GraphEntry> g_graphs;
 std::map<int, hipStream_t> g_capture_stream;  // per device
 
 // Weideman (1994) coefficients: a = Re DFT(fftshift(f)) / (2M), f(t) = e^{-t^2}(L^2 + t^2) at
-// t = L tan(theta/2), theta = k pi / M, k = -M+1..M-1 (f = 0 at k = -M), M = 2N, L = sqrt(N/sqrt2).
+// t = L tan(theta/2), theta = k pi / M, k = -M+1..M-1 (f = 0 at k = -M), M = 2N, L = sqrt(N/sqrt2)
+// rounded to FP32 (any L > 0 is valid with its own coefficients; an L that FP32 holds exactly
+// keeps the line-core pass's FP32 evaluation consistent with its coefficients).
 void weideman_coeffs(int N, double* a_out, double* L_out) {
   const int M = 2 * N, n2 = 2 * M;
-  const double L = sqrt(N / sqrt(2.0));
+  const double L = (double)(float)sqrt(N / sqrt(2.0));
   std::vector<double> f(n2), g(n2);
   f[0] = 0.0;
   for (int k = -M + 1; k <= M - 1; ++k) {
@@ -885,7 +887,6 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   va.n_pairs = pl.n_pairs;
   va.n_tiles_total = pl.n_tiles_c;
   va.status = status;
-  va.nu_pos = L->nu_pos;
   const int64_t icap = env_int("HK_DEBUG_ITEMS_CAP", 0);  // tests of the overflow flag only
   auto cap = [&](int64_t bound) { return (int32_t)std::min<int64_t>(icap > 0 ? icap : bound, INT32_MAX); };
   if (dflt) {

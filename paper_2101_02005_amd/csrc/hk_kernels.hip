@@ -24,6 +24,8 @@ namespace hk {
 
 __constant__ double c_weid[kWeidN];  // Weideman (1994) coefficients a_1..a_N (host-computed)
 __constant__ double c_weidL;         // its scale L = sqrt(N / sqrt 2)
+__constant__ float c_weid32[kWeidN];  // the same coefficients and scale rounded to FP32
+__constant__ float c_weidL32;
 
 // grid point nu_j = nu_start + j dnu: a rounded product, then a rounded sum (no FMA)
 __device__ __forceinline__ double grid_nu(double nu_start, double dnu, int64_t j) {
@@ -609,7 +611,8 @@ __global__ __launch_bounds__(1024) void k_item_scan(const int32_t* __restrict__ 
 // ----------------------------------------------------------------- Voigt profile
 // Re w(x + iy), y >= 0, by J.A.C. Weideman's rational approximation ("Computation of the
 // complex error function", SIAM J. Numer. Anal. 31 (1994) 1497-1518) with N = kWeidN terms:
-// w = 2 p(Z)/(L - iz)^2 + (1/sqrt(pi))/(L - iz), Z = (L + iz)/(L - iz), in FP64.
+// w = 2 p(Z)/(L - iz)^2 + (1/sqrt(pi))/(L - iz), Z = (L + iz)/(L - iz). The line-core pass
+// evaluates it in FP32 (weideman_re32), the adjoint in FP64 (weideman_w).
 // 1/d for normal d > 0 to ~1 ulp: hardware estimate refined by two Newton steps
 __device__ __forceinline__ double rcp64(double d) {
   double r = __builtin_amdgcn_rcp(d);
@@ -641,19 +644,38 @@ __device__ __forceinline__ void weideman_poly(double Zr, double Zi, double& pr, 
   pi = Zi * b1;
 }
 
-__device__ __forceinline__ double weideman_re(double x, double y) {
-  const double L = c_weidL;
-  const double dr = L + y, di = -x;  // L - iz
-  const double inv = rcp64(fma(dr, dr, di * di));
-  const double ur = dr * inv, ui = -di * inv;  // u = 1/(L - iz)
-  // Z = (L + iz)/(L - iz) = 2 L u - 1
-  const double Zr = fma(2.0 * L, ur, -1.0), Zi = 2.0 * L * ui;
-  double pr, pi;
-  weideman_poly(Zr, Zi, pr, pi);
-  // Re(2 p u^2 + u/sqrt(pi)) = Re(u t), t = 2 p u + 1/sqrt(pi)
-  const double tr = 2.0 * fma(pr, ur, -pi * ui) + 0.56418958354775628695;
-  const double ti = 2.0 * fma(pr, ui, pi * ur);
-  return fma(ur, tr, -ui * ti);
+// Re w(x + iy), y >= 0, in FP32 (the line-core pass): Re(2 p u^2 + u/sqrt(pi)) = Re(u t) with
+// t = 2 p u + 1/sqrt(pi). Two
+// choices keep it within about 4.5e-7 of the profile's peak Re w(iy) for |z| < 6.75 (against
+// scipy's wofz; the FP64 form's own error is 7.4e-9): the reciprocal of |L - iz|^2 takes one
+// Newton step, and Z is formed as 1 + (Z - 1) with Z - 1 = 2iz u computed from z and
+// u = 1/(L - iz), not as 2Lu - 1, whose rounding the polynomial amplifies most near z = 0
+// (7e-7 of the peak with 2Lu - 1).
+__device__ __forceinline__ float weideman_re32(float x, float y) {
+  const float L = c_weidL32;
+  const float dr = L + y;  // L - iz = dr - ix
+  const float d = __builtin_fmaf(dr, dr, x * x);
+  float inv = __builtin_amdgcn_rcpf(d);
+  inv = __builtin_fmaf(inv, __builtin_fmaf(-d, inv, 1.0f), inv);
+  const float ur = dr * inv, ui = x * inv;  // u = (dr + ix)/(dr^2 + x^2)
+  // Z - 1 = 2iz u = -2(y ur + x ui) + 2i(x ur - y ui)
+  const float Zr = __builtin_fmaf(-2.0f * x, ui, __builtin_fmaf(-2.0f * y, ur, 1.0f));
+  const float Zi = 2.0f * __builtin_fmaf(x, ur, -y * ui);
+  // p(Z) by the real-quadratic recurrence, as in the FP64 form
+  const float r = 2.0f * Zr, s = __builtin_fmaf(Zr, Zr, Zi * Zi);
+  float b2 = c_weid32[kWeidN - 1];
+  float b1 = __builtin_fmaf(r, b2, c_weid32[kWeidN - 2]);
+#pragma unroll
+  for (int m = kWeidN - 3; m >= 1; --m) {
+    const float t = __builtin_fmaf(r, b1, __builtin_fmaf(-s, b2, c_weid32[m]));
+    b2 = b1;
+    b1 = t;
+  }
+  const float pr = __builtin_fmaf(Zr, b1, __builtin_fmaf(-s, b2, c_weid32[0]));
+  const float pi = Zi * b1;
+  const float tr = 2.0f * __builtin_fmaf(pr, ur, -pi * ui) + 0.564189583547756287f;
+  const float ti = 2.0f * __builtin_fmaf(pr, ui, pi * ur);
+  return __builtin_fmaf(ur, tr, -ui * ti);
 }
 
 // Per-line, per-grid record: the parts of a line's evaluation that depend on the grid but
@@ -1770,27 +1792,28 @@ __global__ __launch_bounds__(kThreads) void k_combine_far(FarArgs a) {
 // largest core half-width of the tile. The wave stages 64 lines at a time (one per lane; the
 // next batch is loaded while the current one is queued), appends the (line, point) pairs of
 // lines with core points on the tile to a queue held in registers (one pair per lane, with
-// the line's FP64 constants), evaluates 64 pairs at a time with the FP64 rational
-// approximation, and adds them to its LDS accumulator one line segment at a time (a line's
+// the line's constants), evaluates 64 pairs at a time with the FP32 rational approximation,
+// and adds them to its LDS accumulator one line segment at a time (a line's
 // pairs are contiguous in the queue and have distinct points, so each segment is one
 // conflict-free update, applied in line order). Every 8 rounds the accumulator goes into
 // compensated per-lane sums. No workgroup barrier couples waves with unequal work.
 template <int P>
 struct CoreLDS {
   float acc[kWave * P];
-  // the staged batch, one entry per line (lane): 1/alpha, offset of the reference point, y,
+  // the staged batch, one entry per line (lane), in units of alpha: offset of the reference point
+  // (from the grid record's offset, subtracted in FP64) and grid step; y = gamma/alpha; the
   // tile-local point of the line's pair g minus g, tile-local reference point, amplitude
-  double ia[kWave], d64[kWave], y[kWave];
+  float x0[kWave], h[kWave], y[kWave];
   int off[kWave], jr[kWave];
   float amp[kWave];
   int mark[kWave];  // queue position -> line whose first pair of the current fill lands there
 };
 
 template <int P>
-__device__ __forceinline__ void core_round(CoreLDS<P>& L, int lane, int qn, uint64_t segs, double qx, double qy,
+__device__ __forceinline__ void core_round(CoreLDS<P>& L, int lane, int qn, uint64_t segs, float qx, float qy,
                                            float qa, int qj) {
   float v = 0.0f;
-  if (lane < qn) v = qa * (float)weideman_re(qx, qy);
+  if (lane < qn) v = qa * weideman_re32(qx, qy);
   // one conflict-free LDS update per line segment, in queue (line) order
   uint64_t rem = segs & ((qn >= 64) ? ~0ull : ((1ull << qn) - 1ull));
   while (rem) {
@@ -1844,7 +1867,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
     // the queue: lane k < qn holds one pair (x, y, amplitude, tile-local point)
     int qn = 0;
     uint64_t segs = 0ull;  // lanes where a line's segment starts
-    double qx = 0.0, qy = 0.0;
+    float qx = 0.0f, qy = 0.0f;
     float qa = 0.0f;
     int qj = 0;
 
@@ -1887,7 +1910,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
       }
       // this lane's line: its core points on the tile (tile-local, inclusive)
       int czl = 1, czh = 0;
-      double lia = 0.0, ld64 = 0.0, ly = 0.0;
+      float lx0 = 0.0f, lh = 0.0f, ly = 0.0f;
       float lamp = 0.0f;
       const int jref = gr.y, jlo = gr.z, jhi = gr.w;
       if (valid && S > 0.0f && jlo <= jhi) {
@@ -1904,11 +1927,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
           if (gl <= gh) {
             czl = (int)(gl - tile0);
             czh = (int)(gh - tile0);
-            lamp = S / (1.7724538509055160273f * alpha);
-            lia = rcp64(nu0 * pd.beta);
-            ld64 = __dsub_rn(grid_nu(pd.nu_start, pd.dnu, (int64_t)jref),
-                             a.nu_pos ? a.nu_pos[b + lane] : nu0);
-            ly = (double)gTv * pd.pfac * lia;
+            const float ia = 1.0f / alpha;
+            lamp = S * ia * 0.564189583547756287f;  // S/(sqrt(pi) alpha)
+            lx0 = __int_as_float(gr.x) * ia;
+            lh = (float)pd.dnu * ia;
+            ly = gam * ia;
           }
         }
       }
@@ -1927,8 +1950,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
       L.off[lane] = czl - excl;
       L.jr[lane] = jrl;
       L.amp[lane] = lamp;
-      L.ia[lane] = lia;
-      L.d64[lane] = ld64;
+      L.x0[lane] = lx0;
+      L.h[lane] = lh;
       L.y[lane] = ly;
       // fills: pairs g0 .. g0 + take - 1 go to queue positions qn .. qn + take - 1
       for (int g0 = 0; g0 < T;) {
@@ -1949,7 +1972,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
           const int li = mark[sp];
           const int j = g0 + (lane - qn) + L.off[li];
           qj = j;
-          qx = ((double)(j - L.jr[li]) * pd.dnu + L.d64[li]) * L.ia[li];
+          qx = __builtin_fmaf((float)(j - L.jr[li]), L.h[li], L.x0[li]);
           qy = L.y[li];
           qa = L.amp[li];
         }
@@ -3457,7 +3480,14 @@ hipError_t upload_weideman40(const double* coef, double L) {
 hipError_t upload_weideman(const double* coef, double L) {
   hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_weid), coef, sizeof(double) * kWeidN);
   if (e != hipSuccess) return e;
-  return hipMemcpyToSymbol(HIP_SYMBOL(c_weidL), &L, sizeof(double));
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_weidL), &L, sizeof(double));
+  if (e != hipSuccess) return e;
+  float c32[kWeidN];
+  for (int i = 0; i < kWeidN; ++i) c32[i] = (float)coef[i];
+  const float L32 = (float)L;
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_weid32), c32, sizeof(c32));
+  if (e != hipSuccess) return e;
+  return hipMemcpyToSymbol(HIP_SYMBOL(c_weidL32), &L32, sizeof(float));
 }
 
 }  // namespace hk

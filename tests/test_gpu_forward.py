@@ -122,6 +122,34 @@ def test_edge_cases(case):
     lines.release()
 
 
+def test_isolated_line_cores():
+    """Lines far apart on a grid that resolves their cores (spacing alpha/16), y = gamma/alpha
+    from 0 to 4.3: each line's window is its own profile, so the comparison pins the FP32
+    line-core evaluation (|z| < 4.4) point by point, relative to the line's peak."""
+    T, P = 1000.0, 1.0
+    sp = (18.0, 296.0, 1.0, 0.05, 1.5)
+    ys = np.array([0.0, 0.02, 0.1, 0.3, 0.6, 1.0, 1.5, 2.2, 3.0, 3.7, 4.1, 4.3])
+    nu = 1000.0 + 2.0 * np.arange(ys.size) + 0.37e-4 * np.arange(ys.size)  # off-grid centres
+    alpha = oracle.line_params(_lines(nu), oracle.species(*sp), T, P)[1]
+    L = _lines(nu, S=1e-20, E=100.0, g=ys * alpha, n=0.0)  # n = 0, P = P_ref: gamma = gamma_ref
+    assert np.allclose(oracle.line_params(L, oracle.species(*sp), T, P)[2], ys * alpha)
+    dnu, cut = 0.0002, 0.5
+    nu_start = 999.0
+    n = int((nu[-1] + 1.0 - nu_start) / dnu)
+    lines = prepare(L, sp)
+    k = gpu_k(lines, T, P, nu_start, dnu, n, cut)
+    lines.release()
+    ko = oracle_k(L, sp, T, P, nu_start, dnu, cut, np.arange(n))
+    worst = 0.0
+    for i in range(ys.size):
+        j0 = int((nu[i] - cut - nu_start) / dnu) + 2
+        j1 = int((nu[i] + cut - nu_start) / dnu) - 1
+        e = np.max(np.abs(k[j0:j1] - ko[j0:j1])) / ko[j0:j1].max()
+        print("y = %.2f: max |dk| / line peak = %.3e" % (ys[i], e))
+        worst = max(worst, e)
+    assert worst <= 6e-7, worst
+
+
 def test_deterministic_bitwise():
     w, L = workload_lines("c1")
     lines = prepare(L, w.species_tuple())
