@@ -2675,18 +2675,32 @@ hipError_t scratch_address(void** p) {
 }
 
 // ------------------------------------------------------------------------ adjoint
-// w(x + iy) = K + iL in FP64 by the same rational approximation (both parts).
-__device__ __forceinline__ void weideman_w(double x, double y, double& K, double& L) {
-  const double Lw = c_weidL;
-  const double dr = Lw + y, di = -x;
-  const double inv = rcp64(fma(dr, dr, di * di));
-  const double ur = dr * inv, ui = -di * inv;
-  const double Zr = fma(2.0 * Lw, ur, -1.0), Zi = 2.0 * Lw * ui;
-  double pr, pi;
-  weideman_poly(Zr, Zi, pr, pi);
-  const double vr = ur * ur - ui * ui, vi = 2.0 * ur * ui;
-  K = 2.0 * (pr * vr - pi * vi) + 0.56418958354775628695 * ur;
-  L = 2.0 * (pr * vi + pi * vr) + 0.56418958354775628695 * ui;
+// w(x + iy) = K + iL in FP32 by the same rational approximation as the line-core pass (both
+// parts): w = u t, t = 2 p u + 1/sqrt(pi).
+__device__ __forceinline__ void weideman_w32(float x, float y, float& K, float& L) {
+  const float Lw = c_weidL32;
+  const float dr = Lw + y;
+  const float d = __builtin_fmaf(dr, dr, x * x);
+  float inv = __builtin_amdgcn_rcpf(d);
+  inv = __builtin_fmaf(inv, __builtin_fmaf(-d, inv, 1.0f), inv);
+  const float ur = dr * inv, ui = x * inv;
+  const float Zr = __builtin_fmaf(-2.0f * x, ui, __builtin_fmaf(-2.0f * y, ur, 1.0f));
+  const float Zi = 2.0f * __builtin_fmaf(x, ur, -y * ui);
+  const float r = 2.0f * Zr, s = __builtin_fmaf(Zr, Zr, Zi * Zi);
+  float b2 = c_weid32[kWeidN - 1];
+  float b1 = __builtin_fmaf(r, b2, c_weid32[kWeidN - 2]);
+#pragma unroll
+  for (int m = kWeidN - 3; m >= 1; --m) {
+    const float t = __builtin_fmaf(r, b1, __builtin_fmaf(-s, b2, c_weid32[m]));
+    b2 = b1;
+    b1 = t;
+  }
+  const float pr = __builtin_fmaf(Zr, b1, __builtin_fmaf(-s, b2, c_weid32[0]));
+  const float pi = Zi * b1;
+  const float tr = 2.0f * __builtin_fmaf(pr, ur, -pi * ui) + 0.564189583547756287f;
+  const float ti = 2.0f * __builtin_fmaf(pr, ui, pi * ur);
+  K = __builtin_fmaf(ur, tr, -ui * ti);
+  L = __builtin_fmaf(ur, ti, ui * tr);
 }
 
 // Far-wing profile and its gamma and alpha derivatives as real polynomials in q = s/(D^2 +
@@ -2711,23 +2725,31 @@ __constant__ float c_adjT[6][8] = {{1, -2, 0, 0, 0, 0, 0, 0},           {1, -8, 
                                    {1, -50, 400, -1120, 1280, -512, 0, 0}, {1, -72, 840, -3584, 6912, -6144, 2048, 0}};
 
 // Coefficients of q^M (one M per lane) of the three polynomials, series truncated after KD terms
-// (1..kKmax + 1; three sets are formed in one pass, one per 16-lane group).
-__device__ __forceinline__ void adj_coef_rt(int KD, int M, float a, float g, float& v, float& da, float& dg) {
+// (1..kKmax + 1; three sets are formed in one pass, one per 16-lane group). U and T are the
+// workgroup's LDS copies of c_adjU and c_adjT (the lanes index them by their own M).
+__device__ __forceinline__ void adj_coef_rt(int KD, int M, float a, float g, const float (*U)[8],
+                                            const float (*T)[8], float& v, float& da, float& dg) {
   constexpr float ak[6] = {1.0f, 0.5f, 0.75f, 1.875f, 6.5625f, 29.53125f};
   v = da = dg = 0.0f;
+  // powers of g up to kKmax + 1, picked by selects (no per-lane loop)
+  float gpw[kKmax + 2];
+  gpw[0] = 1.0f;
+#pragma unroll
+  for (int t = 1; t < kKmax + 2; ++t) gpw[t] = gpw[t - 1] * g;
   float ap = 1.0f;
 #pragma unroll
   for (int k = 0; k < kKmax + 1; ++k) {
     const int j = M - k - 1;  // power of u
     if (k < KD && j >= 0 && j <= k + 1) {
-      float gp = 1.0f;
-      for (int r = 0; r < j; ++r) gp *= g;
+      float gp = gpw[0];
+#pragma unroll
+      for (int t = 1; t <= k + 1; ++t) gp = j == t ? gpw[t] : gp;
       const float w = ak[k] * ap * gp;
       if (j <= k) {
-        v += w * c_adjU[k][j];
-        da += 2.0f * k * w * c_adjU[k][j];
+        v += w * U[k][j];
+        da += 2.0f * k * w * U[k][j];
       }
-      dg += (2.0f * k + 1.0f) * w * c_adjT[k][j];
+      dg += (2.0f * k + 1.0f) * w * T[k][j];
     }
     ap *= a;
   }
@@ -2754,14 +2776,14 @@ __device__ __forceinline__ float adj_horner1(const float* c, float q) {
 // One step of NP x 64 far-wing points: accumulate g V, g dV/dalpha, g dV/dgamma (per unit
 // strength, up to the line's constant factors) with polynomials of the given degrees.
 template <int NP, int DV, int DA, int DG>
-__device__ __forceinline__ void adj_step(const AdjPoly& P, int jc, int lane, int jref, float dnh, float dh, float gh,
-                                         const float (&gcur)[NP], float& bV, float& bA, float& bG) {
+__device__ __forceinline__ void adj_step(const AdjPoly& P, int jc, int lane, int jref, int jhi, float dnh, float dh,
+                                         float gh, const float (&gcur)[NP], float& bV, float& bA, float& bG) {
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     const int j = jc + p * kWave + lane;
     const float D = __builtin_fmaf((float)(j - jref), dnh, dh);
     const float q = __builtin_amdgcn_rcpf(__builtin_fmaf(D, D, gh * gh));  // q = s/(D^2 + gamma^2) <= 1
-    const float gq = gcur[p] * q;
+    const float gq = (j <= jhi ? gcur[p] : 0.0f) * q;  // points beyond jhi hold a clamped load
     bV = __builtin_fmaf(gq, adj_horner1<DV>(P.v, q), bV);
     bA = __builtin_fmaf(gq, adj_horner1<DA>(P.da, q), bA);
     bG = __builtin_fmaf(gq, adj_horner1<DG>(P.dg, q), bG);
@@ -2864,7 +2886,19 @@ __device__ __forceinline__ void adj_far(const AdjPoly& P, float G, float xoff, f
 
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_adjoint(AdjArgs a) {
   __shared__ AdjPoly sP[kWavesPerWG][3];
+  __shared__ float sU[6][8], sT[6][8];
   const int tid = threadIdx.x, lane = tid & 63;
+  if (tid < 48) {
+    sU[tid >> 3][tid & 7] = c_adjU[tid >> 3][tid & 7];
+    sT[tid >> 3][tid & 7] = c_adjT[tid >> 3][tid & 7];
+  }
+  __syncthreads();
+  // the far units' node weights per level (uniform pointers: a lane selects one without a
+  // memory access)
+  static_assert(kAdjLevels == 3, "one pointer per far-unit level");
+  const double* const gp0 = a.gpref[0];
+  const double* const gp1 = a.gpref[1];
+  const double* const gp2 = a.gpref[2];
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t nw = (int64_t)gridDim.x * kWavesPerWG;
   const PrepArgs& pa = a.pa;
@@ -2878,10 +2912,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     xk2 = kn == k ? node_pos(16 * kAdjSpan, kNodes, k) : xk2;
   }
   long long n_eval = 0;  // evaluations this wave made (statistics only)
+  const double inv_dnu = 1.0 / a.dnu, inv_2T = 0.5 / a.T;
   for (int64_t i = (int64_t)blockIdx.x * kWavesPerWG + wv; i < pa.N; i += nw) {
+    // every per-line value is loaded here, before any store of the line (one memory latency)
     const double* lr = a.lrec + 6 * i;
-    const double gam = lr[1];
+    const double lS = lr[0], gam = lr[1], lRs = lr[2], lgf = lr[3], lST = lr[4], lgT = lr[5];
     const double nu0 = pa.nu[i];
+    const int32_t lc = pa.perm[i];
     const double alpha = nu0 * pa.beta;
     const int4 gr = a.grec[i];
     const int jref = gr.y, jlo0 = gr.z, jhi0 = gr.w;
@@ -2889,21 +2926,22 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     const double a2d = alpha * alpha, g2d = gam * gam;
     const double scd = a2d > g2d ? a2d : g2d;
     if (jlo0 <= jhi0 && scd > 0.0) {
-      const float rs = (float)(1.0 / sqrt(scd));
+      const double rsd = 1.0 / sqrt(scd), isc = rsd * rsd;  // 1/sqrt(s), 1/s
+      const float rs = (float)rsd;
       const float dh = __int_as_float(gr.x) * rs, dnh = (float)a.dnu * rs, gh = (float)gam * rs;
       // coefficient sets of this line, 2, 3 and 6 terms (chunks of series order <= 1, 2 and the
       // rest), one set per 16-lane group, one power of q per lane
       {
-        const float ah = (float)(a2d / scd), gh2 = (float)(g2d / scd);
+        const float ah = (float)(a2d * isc), gh2 = (float)(g2d * isc);
         const int M = lane & 15, set = lane >> 4;
         if (M < kAdjDeg && set < 3) {
           float v, da, dg;
-          adj_coef_rt(set == 0 ? 2 : (set == 1 ? 3 : kKmax + 1), M, ah, gh2, v, da, dg);
+          adj_coef_rt(set == 0 ? 2 : (set == 1 ? 3 : kKmax + 1), M, ah, gh2, sU, sT, v, da, dg);
           sP[wv][set].v[M] = v; sP[wv][set].da[M] = da; sP[wv][set].dg[M] = dg;
         }
       }
-      // zones in grid points around the centre
-      const double inv_dnu = 1.0 / a.dnu;
+      // zones in grid points around the centre (half-widths from an FP32 square root: they carry a
+      // relative slack of 1e-5 and only choose how many series terms a step takes)
       const double cpos = (double)jref - (double)__int_as_float(gr.x) * inv_dnu;
       int zlo[kKmax], zhi[kKmax];
 #pragma unroll
@@ -2913,7 +2951,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         zlo[K] = 2000000000;  // empty zone: no chunk intersects it
         zhi[K] = -2000000000;
         if (h2 > 0.0) {
-          const double h = sqrt(h2) * inv_dnu * 1.00001 + 1e-3;
+          const double h = (double)__builtin_amdgcn_sqrtf((float)h2) * inv_dnu * 1.00001 + 1e-3;
           const double lo = ceil(cpos - h), hi = floor(cpos + h);
           zlo[K] = lo < -1.0 ? -1 : (lo > 2.0e9 ? 2000000000 : (int)lo);
           zhi[K] = hi < -1.0 ? -1 : (hi > 2.0e9 ? 2000000000 : (int)hi);
@@ -2921,9 +2959,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         zlo[K] = __builtin_amdgcn_readfirstlane(zlo[K]);  // uniform: scalar registers
         zhi[K] = __builtin_amdgcn_readfirstlane(zhi[K]);
       }
-      const double d64 = __dsub_rn(grid_nu(a.nu_start, a.dnu, (int64_t)jref), nu0);
-      const double ia = 1.0 / alpha, y = gam * ia;
-      const double zc2 = (double)a.zK[kKmax - 1] * (double)a.zK[kKmax - 1];
+      const double ia = 1.0 / alpha;
+      // core points in units of alpha, FP32: x = (j - jref) h + x0 (x0 from the grid record's
+      // offset, subtracted in FP64)
+      const float yf = (float)(gam * ia), x0f = __int_as_float(gr.x) * (float)ia, hf = (float)(a.dnu * ia);
+      const float zc2 = a.zK[kKmax - 1] * a.zK[kKmax - 1];
       float bV = 0.f, bG = 0.f, bA = 0.f;
       // spans sa..sb of the line's points: far on the left up to sL, far on the right from sR,
       // direct in between (the direct spans are the ones near the centre and its core zone)
@@ -2942,6 +2982,23 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
       }
       const int sL = uL[0] < sb ? (uL[0] < sa - 1 ? sa - 1 : uL[0]) : sb;
       const int sR = uR[0] > sa ? (uR[0] > sb + 1 ? sb + 1 : uR[0]) : sa;
+      // direct points: the line's points in spans sL + 1 .. sR - 1, in steps of kAdjP x 64 points
+      // (kAdjP per lane); the first step's dL/dk is loaded now (its latency overlaps the far
+      // passes), each later step's one step ahead
+      const int jlo = jlo0 > (sL + 1) * kAdjSpan ? jlo0 : (sL + 1) * kAdjSpan;
+      const int jhi = jhi0 < sR * kAdjSpan - 1 ? jhi0 : sR * kAdjSpan - 1;
+      if (jhi >= jlo) n_eval += jhi - jlo + 1;
+      constexpr int kAdjP = 4, kStep = kAdjP * kWave;
+      // dL/dk of a step's points, loaded without a condition from indices clamped to the cut range
+      // (no select waits on the load); points beyond jhi are masked where they are used
+      float gcur[kAdjP];
+      auto load_first_step = [&]() {
+#pragma unroll
+        for (int p = 0; p < kAdjP; ++p) {
+          const int j = jlo + p * kWave + lane;
+          gcur[p] = a.g[j < jhi0 ? j : jhi0];
+        }
+      };
       // walking outward from the direct spans, a side switches to the next level at the first
       // unit boundary whose unit of that level is far: left, spans sL down to s1 + 1, level-1
       // units t1 down to u2 + 1, level-2 units t2 = u2 / 4 down; right, spans sR up to r1 - 1,
@@ -2986,62 +3043,76 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
       }
       const int nF = n0L + n1L + n2L + n0R + n1R + n2R;
       n_eval += (long long)kNodes * nF;
-      for (int fb = 0; fb < nF; fb += kAdjSpansPerPass) {
-        asm volatile("" ::: "memory");
-        const int f = fb + (lane >> 4);
+      // this lane's far unit of pass entry f (level and index); f is clamped to the last unit
+      auto unit_of = [&](int f, int& lv, int& u) {
         int r = f < nF ? f : nF - 1;
-        int lv, u;  // this lane's unit: level and index
         if (r < n0L) { lv = 0; u = sL - r; }
         else if ((r -= n0L) < n1L) { lv = 1; u = t1 - r; }
         else if ((r -= n1L) < n2L) { lv = 2; u = t2 - r; }
         else if ((r -= n2L) < n0R) { lv = 0; u = sR + r; }
         else if ((r -= n0R) < n1R) { lv = 1; u = f1 + r; }
         else { lv = 2; u = f2 + (r - n1R); }
-        const int Wl = kAdjSpan << (2 * lv);
-        const int s0 = u * Wl;
-        const int pa0 = (jlo0 > s0 ? jlo0 : s0) - s0, pb = (jhi0 < s0 + Wl - 1 ? jhi0 : s0 + Wl - 1) - s0;
-        const double* pr = a.gpref[lv] + ((int64_t)u * kNodes + kn) * Wl;
-        double Gd = pr[pb];
-        if (pa0 > 0) Gd -= pr[pa0 - 1];
-        const float G = f < nF ? (float)Gd : 0.0f;
-        // series terms for this pass: one more than the profile needs at the pass's points
-        int KL = 2;
+      };
+      // the far passes in chunks: the node weights of a chunk's passes are loaded together
+      // (independent loads in flight at once), then the passes are evaluated
+      constexpr int kFarChunk = 6;
+      for (int fc = 0; fc < nF; fc += kFarChunk * kAdjSpansPerPass) {
+        float Gc[kFarChunk];
 #pragma unroll
-        for (int z = 0; z < kKmax - 1; ++z) KL += (s0 + pb >= zlo[z] && s0 + pa0 <= zhi[z]) ? 1 : 0;
-        const int KD = 2 + (__ballot(KL >= 3) != 0ull ? 1 : 0) + (__ballot(KL >= 4) != 0ull ? 1 : 0);
-        const float xoff = (float)(s0 - jref);
-        const float xk = lv == 0 ? xk0 : (lv == 1 ? xk1 : xk2);
-        if (KD == 2) {
-          adj_far<3, 3, 4>(sP[wv][0], G, xoff, xk, dnh, dh, gh, bV, bA, bG);
-        } else if (KD == 3) {
-          adj_far<5, 5, 6>(sP[wv][1], G, xoff, xk, dnh, dh, gh, bV, bA, bG);
-        } else {
-          adj_far<kAdjDeg - 2, kAdjDeg - 2, kAdjDeg - 1>(sP[wv][2], G, xoff, xk, dnh, dh, gh, bV, bA, bG);
+        for (int c = 0; c < kFarChunk; ++c) {
+          const int f = fc + c * kAdjSpansPerPass + (lane >> 4);
+          int lv, u;
+          unit_of(f, lv, u);
+          const int Wl = kAdjSpan << (2 * lv);
+          const int s0 = u * Wl;
+          const int pa0 = (jlo0 > s0 ? jlo0 : s0) - s0, pb = (jhi0 < s0 + Wl - 1 ? jhi0 : s0 + Wl - 1) - s0;
+          const double* pr = (lv == 0 ? gp0 : (lv == 1 ? gp1 : gp2)) + ((int64_t)u * kNodes + kn) * Wl;
+          const double hi = pr[pb];
+          const double lo = pa0 > 0 ? pr[pa0 - 1] : 0.0;
+          Gc[c] = f < nF ? (float)(hi - lo) : 0.0f;
         }
-        SVw += (double)bV; SGw += (double)bG; SAw += (double)bA;
-        bV = bG = bA = 0.f;
-      }
-      // direct points: the line's points in spans sL + 1 .. sR - 1
-      const int jlo = jlo0 > (sL + 1) * kAdjSpan ? jlo0 : (sL + 1) * kAdjSpan;
-      const int jhi = jhi0 < sR * kAdjSpan - 1 ? jhi0 : sR * kAdjSpan - 1;
-      if (jhi >= jlo) n_eval += jhi - jlo + 1;
-      // steps of kAdjP x 64 points (kAdjP per lane); the next step's dL/dk is loaded ahead
-      constexpr int kAdjP = 4, kStep = kAdjP * kWave;
-      float gcur[kAdjP];
+        load_first_step();  // in flight with the chunk's loads (the same values in every chunk)
 #pragma unroll
-      for (int p = 0; p < kAdjP; ++p) {
-        const int j = jlo + p * kWave + lane;
-        gcur[p] = j <= jhi ? a.g[j] : 0.0f;
+        for (int c = 0; c < kFarChunk; ++c) {
+          const int fb = fc + c * kAdjSpansPerPass;
+          if (fb >= nF) break;
+          asm volatile("" ::: "memory");
+          int lv, u;
+          unit_of(fb + (lane >> 4), lv, u);
+          const int Wl = kAdjSpan << (2 * lv);
+          const int s0 = u * Wl;
+          const int pa0 = (jlo0 > s0 ? jlo0 : s0) - s0, pb = (jhi0 < s0 + Wl - 1 ? jhi0 : s0 + Wl - 1) - s0;
+          const float G = Gc[c];
+          // series terms for this pass: one more than the profile needs at the pass's points
+          int KL = 2;
+#pragma unroll
+          for (int z = 0; z < kKmax - 1; ++z) KL += (s0 + pb >= zlo[z] && s0 + pa0 <= zhi[z]) ? 1 : 0;
+          const int KD = 2 + (__ballot(KL >= 3) != 0ull ? 1 : 0) + (__ballot(KL >= 4) != 0ull ? 1 : 0);
+          const float xoff = (float)(s0 - jref);
+          const float xk = lv == 0 ? xk0 : (lv == 1 ? xk1 : xk2);
+          if (KD == 2) {
+            adj_far<3, 3, 4>(sP[wv][0], G, xoff, xk, dnh, dh, gh, bV, bA, bG);
+          } else if (KD == 3) {
+            adj_far<5, 5, 6>(sP[wv][1], G, xoff, xk, dnh, dh, gh, bV, bA, bG);
+          } else {
+            adj_far<kAdjDeg - 2, kAdjDeg - 2, kAdjDeg - 1>(sP[wv][2], G, xoff, xk, dnh, dh, gh, bV, bA, bG);
+          }
+          SVw += (double)bV; SGw += (double)bG; SAw += (double)bA;
+          bV = bG = bA = 0.f;
+        }
       }
+      if (nF == 0) load_first_step();
       int nstep = 0;
       for (int jc = jlo; jc <= jhi; jc += kStep) {
         // the coefficient sets are read from LDS in every step rather than held in registers
         asm volatile("" ::: "memory");
-        float gnx[kAdjP];
+        float gnx[kAdjP] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (jc + kStep <= jhi) {  // no loads past the last step (the line's last writes would wait for them)
 #pragma unroll
-        for (int p = 0; p < kAdjP; ++p) {
-          const int j = jc + kStep + p * kWave + lane;
-          gnx[p] = j <= jhi ? a.g[j] : 0.0f;
+          for (int p = 0; p < kAdjP; ++p) {
+            const int j = jc + kStep + p * kWave + lane;
+            gnx[p] = a.g[j < jhi0 ? j : jhi0];
+          }
         }
         const int je = jc + kStep - 1;
         // terms of the series for this step: one more than the profile needs, for dV/dalpha
@@ -3050,24 +3121,24 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         for (int z = 0; z < kKmax - 1; ++z) KD += (je >= zlo[z] && jc <= zhi[z]) ? 1 : 0;
         const bool core_step = je >= zlo[kKmax - 1] && jc <= zhi[kKmax - 1];
         if (core_step) {
-          // lanes with |z| below the last threshold take the FP64 rational approximation, the
+          // lanes with |z| below the last threshold take the rational approximation, the
           // others the longest series
           const AdjPoly& PP = sP[wv][2];
 #pragma unroll 1
           for (int p = 0; p < kAdjP; ++p) {
             asm volatile("" ::: "memory");
             const int j = jc + p * kWave + lane;
-            const float gv = gcur[p];
-            const double x = ((double)(j - jref) * a.dnu + d64) * ia;
-            if (x * x + y * y < zc2) {
-              double K, L;
-              weideman_w(x, y, K, L);
-              const double Kx = -2.0 * (x * K - y * L);
-              const double Ky = 2.0 * (x * L + y * K) - 1.1283791670955125739;
+            const float gv = j <= jhi ? gcur[p] : 0.0f;
+            const float x = __builtin_fmaf((float)(j - jref), hf, x0f);
+            if (__builtin_fmaf(x, x, yf * yf) < zc2) {
+              float K, L;
+              weideman_w32(x, yf, K, L);
+              const float Kx = -2.0f * __builtin_fmaf(x, K, -yf * L);
+              const float Ky = 2.0f * __builtin_fmaf(x, L, yf * K) - 1.12837916709551257f;
               const double gd = (double)gv;
-              SVc += gd * K;
-              SGc += gd * Ky;
-              SAc += gd * (-(K + x * Kx + y * Ky));
+              SVc += gd * (double)K;
+              SGc += gd * (double)Ky;
+              SAc += gd * (double)(-(K + __builtin_fmaf(x, Kx, yf * Ky)));
             } else {
               const float D = __builtin_fmaf((float)(j - jref), dnh, dh);
               const float q = __builtin_amdgcn_rcpf(__builtin_fmaf(D, D, gh * gh));
@@ -3078,9 +3149,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
             }
           }
         } else if (KD == 2) {
-          adj_step<kAdjP, 3, 3, 4>(sP[wv][0], jc, lane, jref, dnh, dh, gh, gcur, bV, bA, bG);
+          adj_step<kAdjP, 3, 3, 4>(sP[wv][0], jc, lane, jref, jhi, dnh, dh, gh, gcur, bV, bA, bG);
         } else if (KD == 3) {
-          adj_step<kAdjP, 5, 5, 6>(sP[wv][1], jc, lane, jref, dnh, dh, gh, gcur, bV, bA, bG);
+          adj_step<kAdjP, 5, 5, 6>(sP[wv][1], jc, lane, jref, jhi, dnh, dh, gh, gcur, bV, bA, bG);
         } else {
           // rare steps near the core: one point at a time, coefficients re-read from LDS
 #pragma unroll 1
@@ -3090,8 +3161,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
             if (p == 1) g1[0] = gcur[1];
             if (p == 2) g1[0] = gcur[2];
             if (p == 3) g1[0] = gcur[3];
-            adj_step<1, kAdjDeg - 2, kAdjDeg - 2, kAdjDeg - 1>(sP[wv][2], jc + p * kWave, lane, jref, dnh, dh, gh, g1,
-                                                             bV, bA, bG);
+            adj_step<1, kAdjDeg - 2, kAdjDeg - 2, kAdjDeg - 1>(sP[wv][2], jc + p * kWave, lane, jref, jhi, dnh, dh, gh,
+                                                             g1, bV, bA, bG);
           }
         }
         if (++nstep == 2) {
@@ -3106,22 +3177,21 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
       // the wing and core sums of each lane with the line's factors, then per-wave sums (fixed
       // butterfly order)
       const double isp = 0.56418958354775628695;  // 1/sqrt(pi)
-      const double ipis = 1.0 / (M_PI * scd);     // 1/(pi s), s = max(alpha^2, gamma^2)
+      const double ipis = isc * 0.31830988618379067154;  // 1/(pi s), s = max(alpha^2, gamma^2)
       const double GV = wave_sum64(gam * ipis * SVw + SVc * isp * ia);                 // sum g V
       const double GGs = wave_sum64(ipis * SGw + SGc * isp * ia * ia);                 // sum g dV/dgamma
       const double GAs = wave_sum64(gam * ipis * ia * SAw + SAc * isp * ia * ia);      // sum g dV/dalpha
-      SVw = GV; SGw = lr[0] * GGs; SAw = lr[0] * GAs;
+      SVw = GV; SGw = lS * GGs; SAw = lS * GAs;
     }
     if (lane == 0) {
       // SVw, SGw, SAw now hold sum_j g_j V_ij, dL/dgamma_i, dL/dalpha_i (zero without points)
       const double GS = SVw, Gg = SGw, Ga = SAw;
-      const int32_t c = pa.perm[i];
-      const double aL = pa.nu[i] * pa.beta;
-      if (a.dSref) a.dSref[c] = lr[2] * GS;
-      if (a.dgref) a.dgref[c] = (float)(lr[3] * Gg);
-      if (a.dn) a.dn[c] = (float)(lr[1] * pa.log_tr * Gg);
-      a.contrib[2 * i] = GS * lr[4] + Ga * aL / (2.0 * a.T) - Gg * lr[5];
-      a.contrib[2 * i + 1] = lr[1] * Gg;
+      const int32_t c = lc;
+      if (a.dSref) a.dSref[c] = lRs * GS;
+      if (a.dgref) a.dgref[c] = (float)(lgf * Gg);
+      if (a.dn) a.dn[c] = (float)(gam * pa.log_tr * Gg);
+      a.contrib[2 * i] = GS * lST + Ga * alpha * inv_2T - Gg * lgT;
+      a.contrib[2 * i + 1] = gam * Gg;
     }
   }
   if (a.stats && lane == 0) a.stats[(int64_t)blockIdx.x * kWavesPerWG + wv] = n_eval;
