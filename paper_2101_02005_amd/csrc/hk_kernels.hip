@@ -22,10 +22,8 @@
 
 namespace hk {
 
-__constant__ double c_weid[kWeidN];  // Weideman (1994) coefficients a_1..a_N (host-computed)
-__constant__ double c_weidL;         // its scale L = sqrt(N / sqrt 2)
-__constant__ float c_weid32[kWeidN];  // the same coefficients and scale rounded to FP32
-__constant__ float c_weidL32;
+__constant__ float c_weid32[kWeidN];  // Weideman (1994) coefficients a_1..a_N (host-computed in
+__constant__ float c_weidL32;         // FP64, rounded) and the scale L (an FP32 number)
 
 // grid point nu_j = nu_start + j dnu: a rounded product, then a rounded sum (no FMA)
 __device__ __forceinline__ double grid_nu(double nu_start, double dnu, int64_t j) {
@@ -609,45 +607,19 @@ __global__ __launch_bounds__(1024) void k_item_scan(const int32_t* __restrict__ 
 }
 
 // ----------------------------------------------------------------- Voigt profile
-// Re w(x + iy), y >= 0, by J.A.C. Weideman's rational approximation ("Computation of the
-// complex error function", SIAM J. Numer. Anal. 31 (1994) 1497-1518) with N = kWeidN terms:
-// w = 2 p(Z)/(L - iz)^2 + (1/sqrt(pi))/(L - iz), Z = (L + iz)/(L - iz). The line-core pass
-// evaluates it in FP32 (weideman_re32), the adjoint in FP64 (weideman_w).
-// 1/d for normal d > 0 to ~1 ulp: hardware estimate refined by two Newton steps
-__device__ __forceinline__ double rcp64(double d) {
-  double r = __builtin_amdgcn_rcp(d);
-  double e = fma(-d, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-d, r, 1.0);
-  return fma(r, e, r);
-}
-
-// Re w(x + iy) by Weideman's rational series: w = 2 p(Z)/(L - iz)^2 + 1/(sqrt(pi)(L - iz)),
-// Z = (L + iz)/(L - iz), p(Z) = sum_n a_n Z^(n-1). The coefficients live in constant memory
-// and are read with scalar loads into SGPRs (the loop is fully unrolled).
-// p(Z) = sum_m a_m Z^m for the real coefficients a_m at the complex point Z, by the second-order
-// recurrence of division by the real quadratic Z^2 - r Z + s (r = 2 Re Z, s = |Z|^2) of which Z is
-// a root (Knuth, TAOCP vol. 2, Sec. 4.6.4): b_m = a_m + r b_(m+1) - s b_(m+2), p = a_0 - s b_2 +
-// Z b_1; two real FMAs per coefficient instead of four for complex Horner.
+// w(x + iy), y >= 0, by J.A.C. Weideman's rational approximation ("Computation of the complex
+// error function", SIAM J. Numer. Anal. 31 (1994) 1497-1518) with N = kWeidN terms:
+// w = 2 p(Z) u^2 + u/sqrt(pi), u = 1/(L - iz), Z = (L + iz)/(L - iz), p(Z) = sum_m a_m Z^m. The
+// coefficients live in constant memory and are read with scalar loads into SGPRs (the loops are
+// fully unrolled). p has real coefficients, so it is evaluated by the second-order recurrence
+// of division by the real quadratic Z^2 - r Z + s (r = 2 Re Z, s = |Z|^2) of which Z is a root
+// (Knuth, TAOCP vol. 2, Sec. 4.6.4): b_m = a_m + r b_(m+1) - s b_(m+2), p = a_0 - s b_2 + Z b_1;
+// two real FMAs per coefficient instead of four for complex Horner.
 static_assert(kWeidN >= 3, "the recurrence needs three coefficients");
-__device__ __forceinline__ void weideman_poly(double Zr, double Zi, double& pr, double& pi) {
-  const double r = 2.0 * Zr, s = fma(Zr, Zr, Zi * Zi);
-  double b2 = c_weid[kWeidN - 1];
-  double b1 = fma(r, b2, c_weid[kWeidN - 2]);
-#pragma unroll
-  for (int m = kWeidN - 3; m >= 1; --m) {
-    const double t = fma(r, b1, fma(-s, b2, c_weid[m]));
-    b2 = b1;
-    b1 = t;
-  }
-  pr = fma(Zr, b1, fma(-s, b2, c_weid[0]));
-  pi = Zi * b1;
-}
 
 // Re w(x + iy), y >= 0, in FP32 (the line-core pass): Re(2 p u^2 + u/sqrt(pi)) = Re(u t) with
-// t = 2 p u + 1/sqrt(pi). Two
-// choices keep it within about 4.5e-7 of the profile's peak Re w(iy) for |z| < 6.75 (against
-// scipy's wofz; the FP64 form's own error is 7.4e-9): the reciprocal of |L - iz|^2 takes one
+// t = 2 p u + 1/sqrt(pi). Two choices keep it within about 4.5e-7 of the profile's peak Re w(iy)
+// for |z| < 6.75 (against scipy's wofz; the approximation's own error is 7.4e-9): the reciprocal of |L - iz|^2 takes one
 // Newton step, and Z is formed as 1 + (Z - 1) with Z - 1 = 2iz u computed from z and
 // u = 1/(L - iz), not as 2Lu - 1, whose rounding the polynomial amplifies most near z = 0
 // (7e-7 of the peak with 2Lu - 1).
@@ -3548,14 +3520,10 @@ hipError_t upload_weideman40(const double* coef, double L) {
 }
 
 hipError_t upload_weideman(const double* coef, double L) {
-  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_weid), coef, sizeof(double) * kWeidN);
-  if (e != hipSuccess) return e;
-  e = hipMemcpyToSymbol(HIP_SYMBOL(c_weidL), &L, sizeof(double));
-  if (e != hipSuccess) return e;
   float c32[kWeidN];
   for (int i = 0; i < kWeidN; ++i) c32[i] = (float)coef[i];
   const float L32 = (float)L;
-  e = hipMemcpyToSymbol(HIP_SYMBOL(c_weid32), c32, sizeof(c32));
+  hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_weid32), c32, sizeof(c32));
   if (e != hipSuccess) return e;
   return hipMemcpyToSymbol(HIP_SYMBOL(c_weidL32), &L32, sizeof(float));
 }

@@ -19,6 +19,13 @@ def _device_lines(w):
     return out
 
 
+def _progress(capsys, msg):
+    """The test's own per-window results, written as they come (not held by output capture): a
+    window of the densest band takes the oracle tens of seconds."""
+    with capsys.disabled():
+        print(msg, flush=True)
+
+
 def _windows(w, k, rng, n_rand, width):
     """Window starts: the low-wavenumber edge, the densest band, the largest k, random ones, the end."""
     n = w.n_grid
@@ -29,7 +36,7 @@ def _windows(w, k, rng, n_rand, width):
 
 @pytest.mark.parametrize("cut,dnu,direct", [(25.0, 0.01, 0), (100.0, 0.01, 0), (25.0, 0.1, 0), (100.0, 0.1, 0),
                                              (25.0, 0.1, 1)])
-def test_large_list_windows(cut, dnu, direct):
+def test_large_list_windows(cut, dnu, direct, capsys):
     """The full 5e8-line list at both resolutions and both cutting lengths; direct = 1: every
     (line, point) pair evaluated (no Chebyshev-node classes)."""
     import torch
@@ -55,10 +62,10 @@ def test_large_list_windows(cut, dnu, direct):
         ko = oracle.opacity(L, sp, w.T[0], w.P[0], w.nu_start, w.dnu, w.cut, pts)
         e = rel_err(k[pts].astype(np.float64), ko)
         worst = max(worst, e)
-        print("c2 cut %g dnu %g direct %d window @%d (%.2f cm^-1): %d lines, max rel err %.3e"
-              % (cut, dnu, direct, s0, w.nu_start + s0 * w.dnu, len(L["nu"]), e))
+        _progress(capsys, "c2 cut %g dnu %g direct %d window @%d (%.2f cm^-1): %d lines, max rel err %.3e"
+                  % (cut, dnu, direct, s0, w.nu_start + s0 * w.dnu, len(L["nu"]), e))
         assert e <= TOL_K
-    print("c2 cut %g dnu %g direct %d: worst window %.3e" % (cut, dnu, direct, worst))
+    _progress(capsys, "c2 cut %g dnu %g direct %d: worst window %.3e" % (cut, dnu, direct, worst))
 
 
 def test_uncut_precision_per_decade():
