@@ -887,6 +887,7 @@ hk_status run_forward(const hk_lines* L, const hk_line_override* ovr, const Plan
   va.n_pairs = pl.n_pairs;
   va.n_tiles_total = pl.n_tiles_c;
   va.status = status;
+  va.nu_pos = L->nu_pos;
   const int64_t icap = env_int("HK_DEBUG_ITEMS_CAP", 0);  // tests of the overflow flag only
   auto cap = [&](int64_t bound) { return (int32_t)std::min<int64_t>(icap > 0 ? icap : bound, INT32_MAX); };
   if (dflt) {

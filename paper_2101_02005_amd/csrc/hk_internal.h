@@ -192,6 +192,8 @@ struct VoigtArgs {
   const double* mid_w;     // [kMidNodes][64 P] the same for the middle-distance nodes
   const float* mask_w;     // [kMaskNodes][64 P] the same for the nodes of lines with a cut bound on it
   int* status;             // nullable: bit 0 set when a work item fell beyond the partial rows
+  const double* nu_pos;    // nullable: line centres when they differ from nu (a shifted list's
+                           // view; nu then holds the transition wavenumbers the widths are taken at)
 };
 
 // Arguments of the tile-far pass (lines evaluated at the tile's Chebyshev nodes) and its combine.

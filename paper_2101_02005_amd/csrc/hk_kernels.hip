@@ -24,6 +24,7 @@ namespace hk {
 
 __constant__ float c_weid32[kWeidN];  // Weideman (1994) coefficients a_1..a_N (host-computed in
 __constant__ float c_weidL32;         // FP64, rounded) and the scale L (an FP32 number)
+__constant__ double c_weid64[kWeidN];  // the same coefficients in FP64 (same L)
 
 // grid point nu_j = nu_start + j dnu: a rounded product, then a rounded sum (no FMA)
 __device__ __forceinline__ double grid_nu(double nu_start, double dnu, int64_t j) {
@@ -648,6 +649,40 @@ __device__ __forceinline__ float weideman_re32(float x, float y) {
   const float tr = 2.0f * __builtin_fmaf(pr, ur, -pi * ui) + 0.564189583547756287f;
   const float ti = 2.0f * __builtin_fmaf(pr, ui, pi * ur);
   return __builtin_fmaf(ur, tr, -ui * ti);
+}
+
+// The same in FP64, for the line-core rounds that hold a pair of a line whose peak falls between
+// grid points (there the FP32 form's error, a fraction of the line's peak, can be a large part of
+// the values the grid samples): 7.4e-9 of the peak, the approximation's own error.
+__device__ __forceinline__ double rcp64(double d) {  // 1/d for normal d > 0: estimate, two Newton steps
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return fma(r, fma(-d, r, 1.0), r);
+}
+
+// The coefficients c (FP64) come from LDS: as constants they would take 36 scalar registers
+// from the FP32 form, whose coefficients then spill.
+__device__ __forceinline__ double weideman_re64(double x, double y, const double* c) {
+  const double L = (double)c_weidL32;
+  const double dr = L + y;
+  const double inv = rcp64(fma(dr, dr, x * x));
+  const double ur = dr * inv, ui = x * inv;
+  const double Zr = fma(-2.0 * x, ui, fma(-2.0 * y, ur, 1.0));
+  const double Zi = 2.0 * fma(x, ur, -y * ui);
+  const double r = 2.0 * Zr, s = fma(Zr, Zr, Zi * Zi);
+  double b2 = c[kWeidN - 1];
+  double b1 = fma(r, b2, c[kWeidN - 2]);
+#pragma unroll
+  for (int m = kWeidN - 3; m >= 1; --m) {
+    const double t = fma(r, b1, fma(-s, b2, c[m]));
+    b2 = b1;
+    b1 = t;
+  }
+  const double pr = fma(Zr, b1, fma(-s, b2, c[0]));
+  const double pi = Zi * b1;
+  const double tr = 2.0 * fma(pr, ur, -pi * ui) + 0.56418958354775628695;
+  const double ti = 2.0 * fma(pr, ui, pi * ur);
+  return fma(ur, tr, -ui * ti);
 }
 
 // Per-line, per-grid record: the parts of a line's evaluation that depend on the grid but
@@ -1776,16 +1811,31 @@ struct CoreLDS {
   // (from the grid record's offset, subtracted in FP64) and grid step; y = gamma/alpha; the
   // tile-local point of the line's pair g minus g, tile-local reference point, amplitude
   float x0[kWave], h[kWave], y[kWave];
+  // for a line whose peak falls between grid points (its reference point more than a quarter of
+  // max(alpha, gamma) from the centre): its FP64 offset and 1/alpha (0: an FP32 line)
+  double d64[kWave], ia64[kWave];
+  double w64[kWeidN];  // the FP64 Weideman coefficients
   int off[kWave], jr[kWave];
   float amp[kWave];
   int mark[kWave];  // queue position -> line whose first pair of the current fill lands there
 };
 
 template <int P>
-__device__ __forceinline__ void core_round(CoreLDS<P>& L, int lane, int qn, uint64_t segs, float qx, float qy,
-                                           float qa, int qj) {
+__device__ __forceinline__ void core_round(CoreLDS<P>& L, int lane, int qn, uint64_t segs, float qx, float qxlo,
+                                           float qy, float qa, int qj) {
+  // a round with a pair of a line whose peak falls between grid points (marked by a negative
+  // amplitude; its x is qx + qxlo to FP64 precision) is evaluated in FP64, every lane (the
+  // round's branch stays uniform)
+  const bool any64 = __ballot(lane < qn && qa < 0.0f) != 0ull;
   float v = 0.0f;
-  if (lane < qn) v = qa * weideman_re32(qx, qy);
+  if (lane < qn) {
+    if (any64) {
+      asm volatile("" ::: "memory");  // the FP64 coefficients are read from LDS here, not held
+      v = fabsf(qa) * (float)weideman_re64((double)qx + (double)qxlo, (double)qy, L.w64);
+    } else {
+      v = qa * weideman_re32(qx, qy);
+    }
+  }
   // one conflict-free LDS update per line segment, in queue (line) order
   uint64_t rem = segs & ((qn >= 64) ? ~0ull : ((1ull << qn) - 1ull));
   while (rem) {
@@ -1803,6 +1853,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
   const int lane = threadIdx.x;
 #pragma unroll
   for (int p = 0; p < P; ++p) L.acc[p * kWave + lane] = 0.0f;
+  if (lane < kWeidN) L.w64[lane] = c_weid64[lane];
   const int total = a.item_base[a.n_tiles_total];
   const float zc = a.zcore;
   long long ncore = 0;  // core evaluations of this wave (statistics only)
@@ -1839,7 +1890,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
     // the queue: lane k < qn holds one pair (x, y, amplitude, tile-local point)
     int qn = 0;
     uint64_t segs = 0ull;  // lanes where a line's segment starts
-    float qx = 0.0f, qy = 0.0f;
+    float qx = 0.0f, qxlo = 0.0f, qy = 0.0f;
     float qa = 0.0f;
     int qj = 0;
 
@@ -1852,7 +1903,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
       kahan_flush<P>(part, s, cc);
     };
     auto run_round = [&]() {
-      core_round<P>(L, lane, qn, segs, qx, qy, qa, qj);
+      core_round<P>(L, lane, qn, segs, qx, qxlo, qy, qa, qj);
       ncore += qn;
       qn = 0;
       segs = 0ull;
@@ -1884,6 +1935,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
       int czl = 1, czh = 0;
       float lx0 = 0.0f, lh = 0.0f, ly = 0.0f;
       float lamp = 0.0f;
+      double ld64 = 0.0, lia64 = 0.0;
       const int jref = gr.y, jlo = gr.z, jhi = gr.w;
       if (valid && S > 0.0f && jlo <= jhi) {
         const float alpha = (float)(nu0 * pd.beta);
@@ -1904,6 +1956,10 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
             lx0 = __int_as_float(gr.x) * ia;
             lh = (float)pd.dnu * ia;
             ly = gam * ia;
+            if (fabsf(__int_as_float(gr.x)) > 0.25f * (alpha > gam ? alpha : gam)) {
+              lia64 = 1.0 / (nu0 * pd.beta);
+              ld64 = __dsub_rn(grid_nu(pd.nu_start, pd.dnu, (int64_t)jref), a.nu_pos ? a.nu_pos[b + lane] : nu0);
+            }
           }
         }
       }
@@ -1911,10 +1967,14 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
       // the batch's pairs in staging order: line l (lane l) holds pairs excl .. incl - 1
       const int nl = czl <= czh ? czh - czl + 1 : 0;
       int incl = nl;
+      // the lane index is made opaque here, so that the shuffles' lane addresses are formed per
+      // batch rather than held in registers across the loop (where they were spilled)
+      int ls = lane;
+      asm volatile("" : "+v"(ls));
 #pragma unroll
       for (int d = 1; d < kWave; d <<= 1) {
-        const int t = __shfl_up(incl, d, kWave);
-        if (lane >= d) incl += t;
+        const int t = __builtin_amdgcn_ds_bpermute((ls - d) << 2, incl);  // lanes below d: masked
+        if (ls >= d) incl += t;
       }
       const int T = __builtin_amdgcn_readlane(incl, kWave - 1);
       if (T == 0) continue;
@@ -1925,6 +1985,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
       L.x0[lane] = lx0;
       L.h[lane] = lh;
       L.y[lane] = ly;
+      L.d64[lane] = ld64;
+      L.ia64[lane] = lia64;
       // fills: pairs g0 .. g0 + take - 1 go to queue positions qn .. qn + take - 1
       for (int g0 = 0; g0 < T;) {
         const int take = (T - g0) < (kWave - qn) ? (T - g0) : (kWave - qn);
@@ -1945,8 +2007,16 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
           const int j = g0 + (lane - qn) + L.off[li];
           qj = j;
           qx = __builtin_fmaf((float)(j - L.jr[li]), L.h[li], L.x0[li]);
+          qxlo = 0.0f;
           qy = L.y[li];
           qa = L.amp[li];
+          const double ia64 = L.ia64[li];
+          if (ia64 > 0.0) {  // x to FP64 precision as qx + qxlo; the negative amplitude marks the pair
+            const double x64 = ((double)(j - L.jr[li]) * pd.dnu + L.d64[li]) * ia64;
+            qx = (float)x64;
+            qxlo = (float)(x64 - (double)qx);
+            qa = -qa;
+          }
         }
         qn += take;
         g0 += take;
@@ -3520,6 +3590,8 @@ hipError_t upload_weideman40(const double* coef, double L) {
 }
 
 hipError_t upload_weideman(const double* coef, double L) {
+  hipError_t e0 = hipMemcpyToSymbol(HIP_SYMBOL(c_weid64), coef, sizeof(double) * kWeidN);
+  if (e0 != hipSuccess) return e0;
   float c32[kWeidN];
   for (int i = 0; i < kWeidN; ++i) c32[i] = (float)coef[i];
   const float L32 = (float)L;
