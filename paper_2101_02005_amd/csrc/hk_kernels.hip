@@ -1812,7 +1812,8 @@ struct CoreLDS {
   // tile-local point of the line's pair g minus g, tile-local reference point, amplitude
   float x0[kWave], h[kWave], y[kWave];
   // for a line whose peak falls between grid points (its reference point more than a quarter of
-  // max(alpha, gamma) from the centre): its FP64 offset and 1/alpha (0: an FP32 line)
+  // max(alpha, gamma) from the centre; its amplitude is stored negated): its FP64 offset and
+  // 1/alpha
   double d64[kWave], ia64[kWave];
   double w64[kWeidN];  // the FP64 Weideman coefficients
   int off[kWave], jr[kWave];
@@ -1959,6 +1960,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
             if (fabsf(__int_as_float(gr.x)) > 0.25f * (alpha > gam ? alpha : gam)) {
               lia64 = 1.0 / (nu0 * pd.beta);
               ld64 = __dsub_rn(grid_nu(pd.nu_start, pd.dnu, (int64_t)jref), a.nu_pos ? a.nu_pos[b + lane] : nu0);
+              lamp = -lamp;  // marks the line's pairs for the FP64 rounds
             }
           }
         }
@@ -2009,13 +2011,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
           qx = __builtin_fmaf((float)(j - L.jr[li]), L.h[li], L.x0[li]);
           qxlo = 0.0f;
           qy = L.y[li];
-          qa = L.amp[li];
-          const double ia64 = L.ia64[li];
-          if (ia64 > 0.0) {  // x to FP64 precision as qx + qxlo; the negative amplitude marks the pair
-            const double x64 = ((double)(j - L.jr[li]) * pd.dnu + L.d64[li]) * ia64;
+          qa = L.amp[li];  // negative: a line whose peak falls between grid points
+          if (qa < 0.0f) {  // its x to FP64 precision, as qx + qxlo
+            const double x64 = ((double)(j - L.jr[li]) * pd.dnu + L.d64[li]) * L.ia64[li];
             qx = (float)x64;
             qxlo = (float)(x64 - (double)qx);
-            qa = -qa;
           }
         }
         qn += take;
