@@ -12,7 +12,7 @@ constexpr int kWavesPerWG = kThreads / kWave;  // spans per tile of the tile-far
 constexpr int kKmax = 5;         // highest order of the far-wing series
 constexpr int kKw = 9;           // ... in the wing pass next to the line cores (the default path)
 constexpr int kWeidN = 18;       // terms of the FP64 core rational approximation
-constexpr int kWeidN40 = 40;     // terms of the FP64 approximation of the plinth values (one per line)
+constexpr int kWeidN40 = 40;     // terms of the FP64 approximation (plinth values, line-core FP64 rounds)
 constexpr int kKeyBits = 24;     // linear wavenumber-bin key width
 constexpr int kRadixBits = 8;
 constexpr int kSortItems = 32;   // keys per thread per sort block

@@ -24,7 +24,8 @@ namespace hk {
 
 __constant__ float c_weid32[kWeidN];  // Weideman (1994) coefficients a_1..a_N (host-computed in
 __constant__ float c_weidL32;         // FP64, rounded) and the scale L (an FP32 number)
-__constant__ double c_weid64[kWeidN];  // the same coefficients in FP64 (same L)
+__constant__ double c_weid40[kWeidN40];  // the coefficients of the 40-term form in FP64 (the plinth
+__constant__ double c_weid40L;           // values and the line-core pass's FP64 rounds) and its L
 
 // grid point nu_j = nu_start + j dnu: a rounded product, then a rounded sum (no FMA)
 __device__ __forceinline__ double grid_nu(double nu_start, double dnu, int64_t j) {
@@ -651,29 +652,31 @@ __device__ __forceinline__ float weideman_re32(float x, float y) {
   return __builtin_fmaf(ur, tr, -ui * ti);
 }
 
-// The same in FP64, for the line-core rounds that hold a pair of a line whose peak falls between
-// grid points (there the FP32 form's error, a fraction of the line's peak, can be a large part of
-// the values the grid samples): 7.4e-9 of the peak, the approximation's own error.
+// The same in FP64 with kWeidN40 = 40 terms, for the line-core rounds that hold a pair of a line
+// whose peak falls between grid points: the grid samples such a line only on its flanks, where
+// the FP32 form's error, a fraction of the line's peak, can be a large part of the values, and
+// 18 terms in FP64 still leave 7e-9 of the peak (a relative 1e-3 of a Gaussian at |x| = 3.5); 40
+// terms keep 3.4e-9 of the value itself out to |x| = 4.3.
 __device__ __forceinline__ double rcp64(double d) {  // 1/d for normal d > 0: estimate, two Newton steps
   double r = __builtin_amdgcn_rcp(d);
   r = fma(r, fma(-d, r, 1.0), r);
   return fma(r, fma(-d, r, 1.0), r);
 }
 
-// The coefficients c (FP64) come from LDS: as constants they would take 36 scalar registers
+// The coefficients c (FP64) come from LDS: as constants they would take 80 scalar registers
 // from the FP32 form, whose coefficients then spill.
 __device__ __forceinline__ double weideman_re64(double x, double y, const double* c) {
-  const double L = (double)c_weidL32;
+  const double L = c_weid40L;
   const double dr = L + y;
   const double inv = rcp64(fma(dr, dr, x * x));
   const double ur = dr * inv, ui = x * inv;
   const double Zr = fma(-2.0 * x, ui, fma(-2.0 * y, ur, 1.0));
   const double Zi = 2.0 * fma(x, ur, -y * ui);
   const double r = 2.0 * Zr, s = fma(Zr, Zr, Zi * Zi);
-  double b2 = c[kWeidN - 1];
-  double b1 = fma(r, b2, c[kWeidN - 2]);
-#pragma unroll
-  for (int m = kWeidN - 3; m >= 1; --m) {
+  double b2 = c[kWeidN40 - 1];
+  double b1 = fma(r, b2, c[kWeidN40 - 2]);
+#pragma unroll 4
+  for (int m = kWeidN40 - 3; m >= 1; --m) {
     const double t = fma(r, b1, fma(-s, b2, c[m]));
     b2 = b1;
     b1 = t;
@@ -1815,7 +1818,7 @@ struct CoreLDS {
   // max(alpha, gamma) from the centre; its amplitude is stored negated): its FP64 offset and
   // 1/alpha
   double d64[kWave], ia64[kWave];
-  double w64[kWeidN];  // the FP64 Weideman coefficients
+  double w64[kWeidN40];  // the FP64 Weideman coefficients (40 terms)
   int off[kWave], jr[kWave];
   float amp[kWave];
   int mark[kWave];  // queue position -> line whose first pair of the current fill lands there
@@ -1854,7 +1857,7 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
   const int lane = threadIdx.x;
 #pragma unroll
   for (int p = 0; p < P; ++p) L.acc[p * kWave + lane] = 0.0f;
-  if (lane < kWeidN) L.w64[lane] = c_weid64[lane];
+  if (lane < kWeidN40) L.w64[lane] = c_weid40[lane];
   const int total = a.item_base[a.n_tiles_total];
   const float zc = a.zcore;
   long long ncore = 0;  // core evaluations of this wave (statistics only)
@@ -2061,8 +2064,6 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
 // every point inside its cut. The cutting length (Sec. 2.4.3 step 4) is a fixed length, or a
 // multiple of the line's Doppler half-width sqrt(ln 2) alpha or of its Lorentz half-width gamma.
 
-__constant__ double c_weid40[kWeidN40];  // Weideman coefficients a_1..a_40 (host-computed)
-__constant__ double c_weid40L;
 
 // Re w(x + iy), y >= 0, for the plinth values (one evaluation per line, in FP64): Weideman's
 // approximation with 40 terms for |z| < 8 (about 1e-15 of w(0)), the Laplace continued fraction
@@ -3590,8 +3591,6 @@ hipError_t upload_weideman40(const double* coef, double L) {
 }
 
 hipError_t upload_weideman(const double* coef, double L) {
-  hipError_t e0 = hipMemcpyToSymbol(HIP_SYMBOL(c_weid64), coef, sizeof(double) * kWeidN);
-  if (e0 != hipSuccess) return e0;
   float c32[kWeidN];
   for (int i = 0; i < kWeidN; ++i) c32[i] = (float)coef[i];
   const float L32 = (float)L;

@@ -150,6 +150,39 @@ def test_isolated_line_cores():
     assert worst <= 6e-7, worst
 
 
+def test_unresolved_line_cores():
+    """Strong pure-Doppler lines (P = 0) whose width is a tenth of the spacing, each alone, placed
+    so that their nearest grid point sits at x = d/alpha from 0.3 to 4.3: the grid samples each
+    only there, so that point is its window's max k. It pins the line-core pass's FP64 rounds
+    (40 terms) for lines whose peak falls between grid points, point by point relative to that
+    sampled value (FP32 rounds there would be 4e-4 off at x = 3, 18 FP64 terms 5e-5)."""
+    T, P = 300.0, 0.0
+    sp = (18.0, 296.0, 1.0, 0.05, 1.5)
+    xs = np.array([0.3, 1.0, 2.0, 2.5, 3.0, 3.5, 4.0, 4.3])
+    dnu, cut, nu_start = 0.002, 0.3, 99.0
+    g = 100.0 + np.arange(xs.size)  # grid points (multiples of dnu from nu_start)
+    alpha = oracle.line_params(_lines(g), oracle.species(*sp), T, P)[1]
+    nu = g + xs * alpha
+    for _ in range(3):  # alpha is taken at the line's own wavenumber
+        alpha = oracle.line_params(_lines(nu), oracle.species(*sp), T, P)[1]
+        nu = g + xs * alpha
+    assert np.all(alpha < 0.1 * dnu)
+    L = _lines(nu, S=1e-20, E=100.0, g=0.05, n=0.5)
+    n = int((nu[-1] + 1.0 - nu_start) / dnu)
+    lines = prepare(L, sp)
+    k = gpu_k(lines, T, P, nu_start, dnu, n, cut)
+    lines.release()
+    worst = 0.0
+    for i in range(xs.size):
+        j0 = int((nu[i] - cut - nu_start) / dnu) + 2
+        j1 = int((nu[i] + cut - nu_start) / dnu) - 1
+        ko = oracle_k(L, sp, T, P, nu_start, dnu, cut, np.arange(j0, j1))
+        e = np.max(np.abs(k[j0:j1] - ko)) / ko.max()
+        print("x = %.1f: max |dk| / window max = %.3e" % (xs[i], e))
+        worst = max(worst, e)
+    assert worst <= 1e-6, worst
+
+
 def test_deterministic_bitwise():
     w, L = workload_lines("c1")
     lines = prepare(L, w.species_tuple())
