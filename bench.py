@@ -29,16 +29,14 @@ FLOPS_PER_EVAL = 8           # FP32 work per wing evaluation made (at a grid poi
                              # offset FMA, D^2+gamma^2 FMA, reciprocal, amplitude multiply, accumulate
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "wing_pass_c2_5e8_cut25_traffic.txt")
 TRAFFIC_FILE_DIRECT = os.path.join(ROOT, "profiles", "wing_direct_c2_5e8_cut25_traffic.txt")
+SQ_FILE = os.path.join(ROOT, "profiles", "voigt_kernels_c2_5e8_cut25_sq.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2101_02005_amd", "csrc", "hk_kernels.hip")
 
 
-def wing_traffic(lines, cut, dnu, tile_width, direct=False):
-    """HBM bytes of one launch of the wing kernel evaluating every pair (direct) or of one wing
-    pass (k_wing + k_far + k_combine_far) from the committed FETCH_SIZE / WRITE_SIZE counter runs,
-    scaled by the same counters on a plain copy; None when absent, taken on another workload or
-    span width, or taken on a different kernel source."""
+def _profile_kv(path, lines, cut, dnu):
+    """Key: value lines of a committed profile summary, or None when it is absent, was taken on
+    another workload or on a different kernel source."""
     import hashlib
-    path = TRAFFIC_FILE_DIRECT if direct else TRAFFIC_FILE
     if not os.path.exists(path):
         return None
     kv = {}
@@ -54,10 +52,34 @@ def wing_traffic(lines, cut, dnu, tile_width, direct=False):
             return None
         if (float(kv["lines"]), float(kv["cut"]), float(kv["dnu"])) != (float(lines), float(cut), float(dnu)):
             return None
-        if int(kv["tile_width"]) != int(tile_width):
+    except (KeyError, ValueError, OSError):
+        return None
+    return kv
+
+
+def direct_counter_flops(lines, cut, dnu, tile_width):
+    """FP32 flops the direct-mode wing kernel executes per pair by the SQ counters (2 FMA + ADD +
+    MUL + TRANS, from the committed counter runs), or None when stale."""
+    kv = _profile_kv(SQ_FILE, lines, cut, dnu)
+    try:
+        if kv is None or int(kv["tile_width_direct"]) != int(tile_width):
+            return None
+        return float(kv["counter_fp32_flops_per_direct_pair"])
+    except (KeyError, ValueError):
+        return None
+
+
+def wing_traffic(lines, cut, dnu, tile_width, direct=False):
+    """HBM bytes of one launch of the wing kernel evaluating every pair (direct) or of one wing
+    pass (k_wing + k_far + k_combine_far) from the committed FETCH_SIZE / WRITE_SIZE counter runs,
+    scaled by the same counters on a plain copy; None when absent, taken on another workload or
+    span width, or taken on a different kernel source."""
+    kv = _profile_kv(TRAFFIC_FILE_DIRECT if direct else TRAFFIC_FILE, lines, cut, dnu)
+    try:
+        if kv is None or int(kv["tile_width"]) != int(tile_width):
             return None
         return float(kv["hbm_bytes_per_launch"])
-    except (KeyError, ValueError, OSError):
+    except (KeyError, ValueError):
         return None
 
 
@@ -565,6 +587,8 @@ def main():
     print("bench: direct-evaluation leg", file=sys.stderr, flush=True)
     direct = bench_direct(hk, dev, sp, w, grd, n_pairs)
     rf_traffic = wing_traffic(N, w.cut, w.dnu, direct["tile_width"], direct=True)
+    cflops = direct_counter_flops(N, w.cut, w.dnu, direct["tile_width"])
+    c_ach = (cflops * direct["wing_pairs"] / (direct["k_wing_ms"] * 1e-3) / 1e12) if cflops else None
     out = {
         "metric": METRIC, "value": N / dt, "unit": "lines/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt * 1e3, "median_ms_per_step": _median(host) * 1e3,
@@ -581,7 +605,11 @@ def main():
                      "kernel": "k_wing<%d> evaluating every (line, point) pair outside the line cores (direct mode)"
                                % (direct["tile_width"] // 64),
                      "flops_per_pair": FLOPS_PER_EVAL, "pairs_per_launch": direct["wing_pairs"],
-                     "avg_launch_ms": direct["k_wing_ms"]},
+                     "avg_launch_ms": direct["k_wing_ms"],
+                     # the flops the kernel executes per pair by the SQ counters (series terms, Kahan
+                     # flushes), and the FP32 fraction on them, next to the nominal 8 per pair
+                     "counter_flops_per_pair": cflops, "counter_achieved": c_ach,
+                     "counter_frac": (c_ach / PEAK_FP32_TFLOPS) if c_ach else None},
         "interpolated": {
             "kernel": "wing pass: k_wing<%d> + k_far + k_combine_far (lines far from a span or tile at its "
                       "Chebyshev nodes)" % (tm.tile_width // 64),
