@@ -1818,10 +1818,11 @@ struct CoreLDS {
   // max(alpha, gamma) from the centre; its amplitude is stored negated): its FP64 offset and
   // 1/alpha
   double d64[kWave], ia64[kWave];
-  double w64[kWeidN40];  // the FP64 Weideman coefficients (40 terms)
-  int off[kWave], jr[kWave];
+  int off[kWave], jr[kWave];  // (256-byte aligned: one address reads both)
   float amp[kWave];
-  int mark[kWave];  // queue position -> line whose first pair of the current fill lands there
+  int ex[kWave];    // the first pair of each line (slot) in the batch's staging order
+  int mark[kWave];  // queue positions where a line starts inside a fill: the fill's tag
+  double w64[kWeidN40];  // the FP64 Weideman coefficients (40 terms)
 };
 
 template <int P>
@@ -1829,25 +1830,29 @@ __device__ __forceinline__ void core_round(CoreLDS<P>& L, int lane, int qn, uint
                                            float qy, float qa, int qj) {
   // a round with a pair of a line whose peak falls between grid points (marked by a negative
   // amplitude; its x is qx + qxlo to FP64 precision) is evaluated in FP64, every lane (the
-  // round's branch stays uniform)
-  const bool any64 = __ballot(lane < qn && qa < 0.0f) != 0ull;
-  float v = 0.0f;
-  if (lane < qn) {
-    if (any64) {
-      asm volatile("" ::: "memory");  // the FP64 coefficients are read from LDS here, not held
-      v = fabsf(qa) * (float)weideman_re64((double)qx + (double)qxlo, (double)qy, L.w64);
-    } else {
-      v = qa * weideman_re32(qx, qy);
-    }
+  // round's branch stays uniform). Lanes at and above qn evaluate what they hold from an earlier
+  // round (finite values, or the zeros they start with) and add nothing.
+  const uint64_t qmask = (qn >= 64) ? ~0ull : ((1ull << qn) - 1ull);
+  const bool any64 = (__builtin_amdgcn_ballot_w64(qa < 0.0f) & qmask) != 0ull;
+  float v;
+  if (any64) {
+    asm volatile("" ::: "memory");  // the FP64 coefficients are read from LDS here, not held
+    const double xlo = qa < 0.0f ? (double)qxlo : 0.0;  // qxlo is set for marked pairs only
+    v = fabsf(qa) * (float)weideman_re64((double)qx + xlo, (double)qy, L.w64);
+  } else {
+    v = qa * weideman_re32(qx, qy);
   }
-  // one conflict-free LDS update per line segment, in queue (line) order
-  uint64_t rem = segs & ((qn >= 64) ? ~0ull : ((1ull << qn) - 1ull));
-  while (rem) {
-    const int s0 = (int)__builtin_ctzll(rem);
-    rem &= rem - 1ull;
-    const int s1 = rem ? (int)__builtin_ctzll(rem) : qn;
-    if (lane >= s0 && lane < s1) L.acc[qj] += v;  // LDS operations of a wave stay in order
-  }
+  // one conflict-free LDS update per line segment, in queue (line) order. Position 0 always
+  // starts a segment, so a lane's segment is the number of starts at positions 1 .. lane (lanes
+  // at and above qn count as further starts: their segments lie beyond the last); a line's pairs
+  // have distinct points, and the LDS operations of a wave (its workgroup) complete in order.
+  // (LDS atomic adds in place of the read and write were much slower here.)
+  const int nseg = __popcll(segs & qmask);
+  const uint64_t above = (segs | ~qmask) >> 1;
+  const int sid = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(above >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)above, 0u));
+  for (int k = 0; k < nseg; ++k)
+    if (sid == k) L.acc[qj] += v;
 }
 
 template <int P>
@@ -1858,6 +1863,8 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
 #pragma unroll
   for (int p = 0; p < P; ++p) L.acc[p * kWave + lane] = 0.0f;
   if (lane < kWeidN40) L.w64[lane] = c_weid40[lane];
+  L.mark[lane] = -1;
+  int tag = 0;  // the fills' tags, one per fill over the wave's lifetime
   const int total = a.item_base[a.n_tiles_total];
   const float zc = a.zcore;
   long long ncore = 0;  // core evaluations of this wave (statistics only)
@@ -1984,35 +1991,49 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
       const int T = __builtin_amdgcn_readlane(incl, kWave - 1);
       if (T == 0) continue;
       const int excl = incl - nl;
-      L.off[lane] = czl - excl;
-      L.jr[lane] = jrl;
-      L.amp[lane] = lamp;
-      L.x0[lane] = lx0;
-      L.h[lane] = lh;
-      L.y[lane] = ly;
-      L.d64[lane] = ld64;
-      L.ia64[lane] = lia64;
+      // the lines with pairs, compacted into slots in lane order (their first pairs increase)
+      const uint64_t hasp = __builtin_amdgcn_ballot_w64(nl > 0);
+      const int nslots = __popcll(hasp);
+      if (nl > 0) {
+        const int sl = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(hasp >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)hasp, 0u));
+        L.off[sl] = czl - excl;
+        L.jr[sl] = jrl;
+        L.amp[sl] = lamp;
+        L.x0[sl] = lx0;
+        L.h[sl] = lh;
+        L.y[sl] = ly;
+        L.d64[sl] = ld64;
+        L.ia64[sl] = lia64;
+        L.ex[sl] = excl;
+      }
+      // lane s: the first pair of slot s (none beyond the last slot)
+      const int exs = lane < nslots ? ((volatile __attribute__((address_space(3))) int*)L.ex)[lane] : 0x7fffffff;
+      const int exs1 = exs - 1;
       // fills: pairs g0 .. g0 + take - 1 go to queue positions qn .. qn + take - 1
       for (int g0 = 0; g0 < T;) {
         const int take = (T - g0) < (kWave - qn) ? (T - g0) : (kWave - qn);
-        // each line with pairs in the fill marks the position of its first one (a segment start;
-        // position qn always gets one). LDS operations of a wave stay in order; the accesses are
-        // volatile so that the compiler keeps every one of them (a lane reads marks that other
-        // lanes wrote, which it cannot see)
+        // a line that starts inside the fill (after its first pair) marks its queue position with
+        // this fill's tag. LDS operations of a wave stay in order; the accesses are volatile so
+        // that the compiler keeps every one of them (a lane reads marks that other lanes wrote,
+        // which it cannot see)
         volatile __attribute__((address_space(3))) int* mark = (volatile __attribute__((address_space(3))) int*)L.mark;
-        mark[lane] = -1;
-        const int first = excl > g0 ? excl : g0;
-        if (nl > 0 && first < g0 + take && incl > g0) mark[first - g0 + qn] = lane;
-        const uint64_t starts = __ballot(mark[lane] >= 0);
-        segs |= starts;
-        if (lane >= qn && lane < qn + take) {
-          // this position's line: the one of the last start at or below it
-          const int sp = 63 - __builtin_clzll(starts & ((2ull << lane) - 1ull));
-          const int li = mark[sp];
-          const int j = g0 + (lane - qn) + L.off[li];
+        ++tag;
+        const int t1 = exs1 - g0;  // the line's start after pair g0, less one
+        if ((unsigned)t1 < (unsigned)(take - 1)) mark[t1 + qn + 1] = tag;
+        const uint64_t inner = __builtin_amdgcn_ballot_w64(mark[lane] == tag);  // positions qn+1 ..
+        // the slot of the line of pair g0 (slot 0 starts at pair 0)
+        const int cur = __popcll(__builtin_amdgcn_ballot_w64(exs <= g0)) - 1;
+        segs |= inner | (1ull << qn);  // position qn starts a segment
+        const int r = lane - qn;
+        if ((unsigned)r < (unsigned)take) {
+          // this position's line: cur plus the starts at positions qn+1 .. lane
+          const uint64_t sh = inner >> 1;
+          const int li = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(sh >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)sh, (uint32_t)cur));
+          const int j = g0 + r + L.off[li];
           qj = j;
           qx = __builtin_fmaf((float)(j - L.jr[li]), L.h[li], L.x0[li]);
-          qxlo = 0.0f;
           qy = L.y[li];
           qa = L.amp[li];  // negative: a line whose peak falls between grid points
           if (qa < 0.0f) {  // its x to FP64 precision, as qx + qxlo
@@ -2043,8 +2064,11 @@ __global__ __launch_bounds__(kWave) __attribute__((amdgpu_waves_per_eu(P == 2 ? 
         }
       }
     } else if (it < a.items_cap) {
+      // the address is formed here (an opaque lane), not held in registers across the item loop
+      int ls = lane;
+      asm volatile("" : "+v"(ls));
 #pragma unroll
-      for (int p = 0; p < P; ++p) a.partial[(int64_t)it * W + p * kWave + lane] = s[p] - cc[p];
+      for (int p = 0; p < P; ++p) a.partial[(int64_t)it * W + p * kWave + ls] = s[p] - cc[p];
     } else if (a.status && lane == 0) {
       atomicOr(a.status, 1);
     }
