@@ -210,7 +210,7 @@ hk_status hk_opacity(const hk_lines* lines, const hk_line_override* ovr, double 
 
 /*
  * hk_opacity_batched -- k for many (T, P) pairs in one persistent launch (the paper's
- * several pressures per run, Sec. 2.4.6 and Table timing2, extended to temperatures).
+ * several pressures per run, Sec. 3.5 and Table timing2, extended to temperatures).
  *   n_pairs >= 1; T, P_atm : host float64[n_pairs]; grids : host hk_grid[n_pairs] (may
  *   differ per pair); out_offset : host int64[n_pairs], pair p writes
  *   k[out_offset[p] .. out_offset[p] + grids[p].n). Output ranges must not overlap.

@@ -1802,7 +1802,8 @@ __global__ __launch_bounds__(kThreads) void k_combine_far(FarArgs a) {
 // largest core half-width of the tile. The wave stages 64 lines at a time (one per lane; the
 // next batch is loaded while the current one is queued), appends the (line, point) pairs of
 // lines with core points on the tile to a queue held in registers (one pair per lane, with
-// the line's constants), evaluates 64 pairs at a time with the FP32 rational approximation,
+// the line's constants; a position finds its line by a bit count of the line starts below it),
+// evaluates 64 pairs at a time with the FP32 rational approximation,
 // and adds them to its LDS accumulator one line segment at a time (a line's
 // pairs are contiguous in the queue and have distinct points, so each segment is one
 // conflict-free update, applied in line order). Every 8 rounds the accumulator goes into
@@ -1810,9 +1811,10 @@ __global__ __launch_bounds__(kThreads) void k_combine_far(FarArgs a) {
 template <int P>
 struct CoreLDS {
   float acc[kWave * P];
-  // the staged batch, one entry per line (lane), in units of alpha: offset of the reference point
-  // (from the grid record's offset, subtracted in FP64) and grid step; y = gamma/alpha; the
-  // tile-local point of the line's pair g minus g, tile-local reference point, amplitude
+  // the staged batch, one entry per line with pairs on the tile (its slot: such lines in lane
+  // order), in units of alpha: offset of the reference point (from the grid record's offset,
+  // subtracted in FP64) and grid step; y = gamma/alpha; the tile-local point of the line's pair g
+  // minus g, tile-local reference point, amplitude
   float x0[kWave], h[kWave], y[kWave];
   // for a line whose peak falls between grid points (its reference point more than a quarter of
   // max(alpha, gamma) from the centre; its amplitude is stored negated): its FP64 offset and
