@@ -125,6 +125,7 @@ struct DevInfo {
   float mask_x[4][hk::kMaskNodes] = {};
   double* adj_w[hk::kAdjLevels] = {};  // device: node weights of the adjoint's far units, per level
   int far_per_cu = 1;         // tile-far kernel occupancy
+  int adj_per_cu = 1;         // adjoint kernel occupancy
   int direct_per_cu[4] = {};  // direct-evaluation kernel occupancy per slots
   void* scratch = nullptr;    // device address of the allocation-free entry point's scratch array
   unsigned long long* stats_buf = nullptr;  // device: line statistics (3 words)
@@ -260,6 +261,7 @@ hk_status device_init(int* dev_out, DevInfo* info) {
       HK_HIP(hipMemcpy(di.adj_w[lv], wts.data(), sizeof(double) * wts.size(), hipMemcpyHostToDevice));
     }
     di.far_per_cu = hk::far_max_blocks_per_cu();
+    di.adj_per_cu = hk::adj_max_blocks_per_cu();
     HK_HIP(hipMalloc(&di.stats_buf, 4 * sizeof(unsigned long long)));  // held for the process lifetime
     it = g_dev.emplace(dev, di).first;
   }
@@ -687,8 +689,8 @@ hk_status make_plan(const hk_lines* L, int n_pairs, int n_temps_bound, const dou
 // per-line FP64 records and the node weights of dL/dk per span of the grid.
 constexpr int kBwdPartials = 256;
 struct BwdLayout {
-  size_t off_gr = 0, off_contrib = 0, off_part = 0, off_lrec = 0, off_pref[hk::kAdjLevels] = {}, off_stats = 0,
-         total = 0;
+  size_t off_gr = 0, off_contrib = 0, off_part = 0, off_lrec = 0, off_lzone = 0, off_pref[hk::kAdjLevels] = {},
+         off_stats = 0, total = 0;
 };
 constexpr int64_t kAdjMaxWaves = 1 << 16;  // bound of the adjoint's waves (its grid is capped below)
 BwdLayout backward_layout(int64_t N, int64_t n_grid) {
@@ -699,7 +701,8 @@ BwdLayout backward_layout(int64_t N, int64_t n_grid) {
   b.off_stats = take(sizeof(long long) * kAdjMaxWaves);
   b.off_contrib = take(2 * sizeof(double) * (size_t)N);
   b.off_part = take(2 * sizeof(double) * kBwdPartials);
-  b.off_lrec = take(6 * sizeof(double) * (size_t)N);
+  b.off_lrec = take(8 * sizeof(double) * (size_t)N);
+  b.off_lzone = take(16 * sizeof(int) * (size_t)N);
   for (int lv = 0; lv < hk::kAdjLevels; ++lv) {
     const size_t W = (size_t)hk::kAdjSpan << (2 * lv);
     const size_t units = ((size_t)n_grid + W - 1) / W;
@@ -1970,13 +1973,15 @@ hk_status hk_opacity_backward(const hk_lines* lines, const hk_line_override* ovr
   a.dn = dL_dn;
   a.contrib = contrib;
   a.lrec = reinterpret_cast<double*>(w + bl.off_lrec);
+  a.lzone = reinterpret_cast<int*>(w + bl.off_lzone);
   double* gpref[hk::kAdjLevels];
   for (int lv = 0; lv < hk::kAdjLevels; ++lv) {
     gpref[lv] = reinterpret_cast<double*>(w + bl.off_pref[lv]);
     a.gpref[lv] = gpref[lv];
   }
   const int64_t want = (lines->N + hk::kWavesPerWG - 1) / hk::kWavesPerWG;
-  const int64_t cap = std::min<int64_t>((int64_t)di.cus * 8, kAdjMaxWaves / hk::kWavesPerWG);
+  // two rounds of resident workgroups (lines are assigned statically, round-robin over the waves)
+  const int64_t cap = std::min<int64_t>((int64_t)di.cus * 2 * di.adj_per_cu, kAdjMaxWaves / hk::kWavesPerWG);
   const int blocks = (int)std::max<int64_t>(1, std::min(want, cap));
   long long* stats = reinterpret_cast<long long*>(w + bl.off_stats);
   a.stats = tm.on ? stats : nullptr;

@@ -256,7 +256,8 @@ struct AdjArgs {
   float* dgref;            // caller order, nullable
   float* dn;               // caller order, nullable
   double* contrib;         // [N][2], sorted order: per-line dL/dT and dL/dlnP terms
-  double* lrec;            // [N][6], sorted order: per-line FP64 quantities (k_adj_lines)
+  double* lrec;            // [N][8], sorted order: per-line FP64 quantities (k_adj_lines)
+  int* lzone;              // [N][16], sorted order: per-line walk bounds (k_adj_lines), 16-byte aligned
   long long* stats;        // nullable: per wave of k_adjoint, the evaluations it made
   const double* gpref[3];  // per level L: [unit][kNodes][kAdjSpan 4^L]: per far unit of kAdjSpan 4^L
                            // points, the prefix sums over its points j of dL/dk_j times node k's
@@ -338,6 +339,7 @@ hipError_t launch_cut_bounds(const double* nu, const int32_t* perm, int64_t N, d
 hipError_t launch_far(const FarArgs& a, int cls, int grid, hipStream_t st);
 hipError_t launch_combine_far(const FarArgs& a, hipStream_t st);
 int far_max_blocks_per_cu();
+int adj_max_blocks_per_cu();
 // gpref of AdjArgs from dL/dk (g, n points) and the node weights w [kNodes][kAdjSpan]
 // the prefix sums of one level of far units (kAdjSpan << 2 level points each) with its node weights
 hipError_t launch_adj_nodes(const float* g, int64_t n, int level, const double* w, double* gpref, hipStream_t st);

@@ -2902,10 +2902,55 @@ __global__ __launch_bounds__(kAdjSpan) void k_adj_nodes(const float* __restrict_
   }
 }
 
+// Far units of the adjoint: a unit (a span of kAdjSpan points, or 4 or 16 of them) at least this
+// many unit widths from the line centre (unit centre to line centre) and clear of its core zone
+// takes the node weights of dL/dk over its points.
+constexpr double kAdjFarSpans = 1.5;
+
+// Per-line bounds of the adjoint's walk over a line's points (grid indices): the series zones
+// zlo[K] .. zhi[K] (|z| < zK[K]; the last is the core zone; half-widths from an FP32 square root:
+// they carry a relative slack of 1e-5 and only choose how many series terms a step takes) and,
+// per far-unit level L (units of kAdjSpan 4^L points), the last far unit on the left uL[L] and the
+// first on the right uR[L]. out = zlo[kKmax], zhi[kKmax], uL[kAdjLevels], uR[kAdjLevels].
+static_assert(2 * kKmax + 2 * kAdjLevels == 16, "16 bounds per line");
+__device__ __forceinline__ void adj_line_bounds(const AdjArgs& a, double alpha, double g2d, const int4 gr,
+                                                int4* __restrict__ out) {
+  const double inv_dnu = 1.0 / a.dnu;
+  const double cpos = (double)gr.y - (double)__int_as_float(gr.x) * inv_dnu;
+  int b[16];
+#pragma unroll
+  for (int K = 0; K < kKmax; ++K) {
+    const double zz = (double)a.zK[K] * alpha;
+    const double h2 = zz * zz - g2d;
+    int lo_i = 2000000000, hi_i = -2000000000;  // empty zone: no chunk intersects it
+    if (h2 > 0.0) {
+      const double h = (double)__builtin_amdgcn_sqrtf((float)h2) * inv_dnu * 1.00001 + 1e-3;
+      const double lo = ceil(cpos - h), hi = floor(cpos + h);
+      lo_i = lo < -1.0 ? -1 : (lo > 2.0e9 ? 2000000000 : (int)lo);
+      hi_i = hi < -1.0 ? -1 : (hi > 2.0e9 ? 2000000000 : (int)hi);
+    }
+    b[K] = lo_i;
+    b[kKmax + K] = hi_i;
+  }
+#pragma unroll
+  for (int L = 0; L < kAdjLevels; ++L) {
+    const double Wd = (double)(kAdjSpan << (2 * L)), iW = 1.0 / Wd;  // a power of two: exact
+    const double reach = kAdjFarSpans * Wd, half = 0.5 * (Wd - 1.0);
+    const double l = fmin(floor((cpos - reach - half) * iW), floor(((double)b[kKmax - 1] - Wd) * iW));
+    const double r = fmax(ceil((cpos + reach - half) * iW), floor((double)b[2 * kKmax - 1] * iW) + 1.0);
+    b[2 * kKmax + L] = l < -2.0 ? -2 : (l > 1.0e8 ? 100000000 : (int)l);
+    b[2 * kKmax + kAdjLevels + L] = r > 1.0e8 ? 100000000 : (r < -2.0 ? -2 : (int)r);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) out[q] = make_int4(b[4 * q], b[4 * q + 1], b[4 * q + 2], b[4 * q + 3]);
+}
+
 // One wave per line (static assignment), lanes over its grid points inside the cut.
 // Per-line FP64 quantities of the adjoint, one thread per line (sorted order), kept apart from
 // the point loop so that the transcendental functions do not hold registers there:
-// rec[6 i ..] = (S, gamma, S/S_ref, gamma/gamma_ref, S dlnS/dT, n gamma / T).
+// rec[8 i ..] = (S, gamma, S/S_ref, gamma/gamma_ref, S dlnS/dT, n gamma / T, 1/sqrt(s), 1/alpha)
+// with s = max(alpha^2, gamma^2), and the line's walk bounds (adj_line_bounds): values uniform
+// over the line's wave in k_adjoint, computed here once rather than on each of its lanes.
 __global__ __launch_bounds__(kThreads) void k_adj_lines(AdjArgs a) {
   const PrepArgs& pa = a.pa;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2923,19 +2968,21 @@ __global__ __launch_bounds__(kThreads) void k_adj_lines(AdjArgs a) {
   const double T = a.T;
   const double c2nu = pa.c2_over_T * nu0;
   const double dlnS_dT = -a.q_b / T + pa.c2_over_T * E / T - (c2nu / T) / expm1(c2nu);
-  double* r = a.lrec + 6 * i;
+  double* r = a.lrec + 8 * i;
   r[0] = S;
   r[1] = gam;
   r[2] = Rs;
   r[3] = gfac;
   r[4] = S * dlnS_dT;
   r[5] = nexp * gam / T;
+  const double alpha = nu0 * pa.beta;
+  const double a2d = alpha * alpha, g2d = gam * gam;
+  const double scd = a2d > g2d ? a2d : g2d;
+  r[6] = 1.0 / sqrt(scd);
+  r[7] = 1.0 / alpha;
+  adj_line_bounds(a, alpha, g2d, a.grec[i], reinterpret_cast<int4*>(a.lzone) + 4 * i);
 }
 
-// Far units of the adjoint: a unit (a span of kAdjSpan points, or 4 or 16 of them) at least this
-// many unit widths from the line centre (unit centre to line centre) and clear of its core zone
-// takes the node weights of dL/dk over its points.
-constexpr double kAdjFarSpans = 1.5;
 constexpr int kAdjSpansPerPass = kWave / kNodes;  // far units per wave pass (one lane per node)
 
 __device__ __forceinline__ int floor_div4(int x) { return x >= 0 ? x / 4 : -((-x + 3) / 4); }
@@ -2953,7 +3000,7 @@ __device__ __forceinline__ void adj_far(const AdjPoly& P, float G, float xoff, f
   bG = __builtin_fmaf(gq, adj_horner1<DG>(P.dg, q), bG);
 }
 
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_adjoint(AdjArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_adjoint(AdjArgs a) {
   __shared__ AdjPoly sP[kWavesPerWG][3];
   __shared__ float sU[6][8], sT[6][8];
   const int tid = threadIdx.x, lane = tid & 63;
@@ -2984,8 +3031,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
   const double inv_dnu = 1.0 / a.dnu, inv_2T = 0.5 / a.T;
   for (int64_t i = (int64_t)blockIdx.x * kWavesPerWG + wv; i < pa.N; i += nw) {
     // every per-line value is loaded here, before any store of the line (one memory latency)
-    const double* lr = a.lrec + 6 * i;
+    const double* lr = a.lrec + 8 * i;
     const double lS = lr[0], gam = lr[1], lRs = lr[2], lgf = lr[3], lST = lr[4], lgT = lr[5];
+    const double lrsd = lr[6], lia = lr[7];
+    const int4* lb = reinterpret_cast<const int4*>(a.lzone) + 4 * i;
+    const int4 b0 = lb[0], b1 = lb[1], b2 = lb[2], b3 = lb[3];
     const double nu0 = pa.nu[i];
     const int32_t lc = pa.perm[i];
     const double alpha = nu0 * pa.beta;
@@ -2995,7 +3045,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     const double a2d = alpha * alpha, g2d = gam * gam;
     const double scd = a2d > g2d ? a2d : g2d;
     if (jlo0 <= jhi0 && scd > 0.0) {
-      const double rsd = 1.0 / sqrt(scd), isc = rsd * rsd;  // 1/sqrt(s), 1/s
+      const double rsd = lrsd, isc = rsd * rsd;  // 1/sqrt(s), 1/s
       const float rs = (float)rsd;
       const float dh = __int_as_float(gr.x) * rs, dnh = (float)a.dnu * rs, gh = (float)gam * rs;
       // coefficient sets of this line, 2, 3 and 6 terms (chunks of series order <= 1, 2 and the
@@ -3009,26 +3059,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
           sP[wv][set].v[M] = v; sP[wv][set].da[M] = da; sP[wv][set].dg[M] = dg;
         }
       }
-      // zones in grid points around the centre (half-widths from an FP32 square root: they carry a
-      // relative slack of 1e-5 and only choose how many series terms a step takes)
-      const double cpos = (double)jref - (double)__int_as_float(gr.x) * inv_dnu;
+      // the line's zones and far-unit limits (adj_line_bounds), in scalar registers
+      const int bnd[16] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w, b2.x, b2.y, b2.z, b2.w, b3.x, b3.y, b3.z, b3.w};
       int zlo[kKmax], zhi[kKmax];
 #pragma unroll
       for (int K = 0; K < kKmax; ++K) {
-        const double zz = (double)a.zK[K] * alpha;
-        const double h2 = zz * zz - g2d;
-        zlo[K] = 2000000000;  // empty zone: no chunk intersects it
-        zhi[K] = -2000000000;
-        if (h2 > 0.0) {
-          const double h = (double)__builtin_amdgcn_sqrtf((float)h2) * inv_dnu * 1.00001 + 1e-3;
-          const double lo = ceil(cpos - h), hi = floor(cpos + h);
-          zlo[K] = lo < -1.0 ? -1 : (lo > 2.0e9 ? 2000000000 : (int)lo);
-          zhi[K] = hi < -1.0 ? -1 : (hi > 2.0e9 ? 2000000000 : (int)hi);
-        }
-        zlo[K] = __builtin_amdgcn_readfirstlane(zlo[K]);  // uniform: scalar registers
-        zhi[K] = __builtin_amdgcn_readfirstlane(zhi[K]);
+        zlo[K] = __builtin_amdgcn_readfirstlane(bnd[K]);
+        zhi[K] = __builtin_amdgcn_readfirstlane(bnd[kKmax + K]);
       }
-      const double ia = 1.0 / alpha;
+      const double ia = lia;
       // core points in units of alpha, FP32: x = (j - jref) h + x0 (x0 from the grid record's
       // offset, subtracted in FP64)
       const float yf = (float)(gam * ia), x0f = __int_as_float(gr.x) * (float)ia, hf = (float)(a.dnu * ia);
@@ -3042,12 +3081,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
       int uL[kAdjLevels], uR[kAdjLevels];
 #pragma unroll
       for (int L = 0; L < kAdjLevels; ++L) {
-        const double Wd = (double)(kAdjSpan << (2 * L)), iW = 1.0 / Wd;  // a power of two: exact
-        const double reach = kAdjFarSpans * Wd, half = 0.5 * (Wd - 1.0);
-        const double l = fmin(floor((cpos - reach - half) * iW), floor(((double)zlo[kKmax - 1] - Wd) * iW));
-        const double r = fmax(ceil((cpos + reach - half) * iW), floor((double)zhi[kKmax - 1] * iW) + 1.0);
-        uL[L] = __builtin_amdgcn_readfirstlane(l < -2.0 ? -2 : (l > 1.0e8 ? 100000000 : (int)l));
-        uR[L] = __builtin_amdgcn_readfirstlane(r > 1.0e8 ? 100000000 : (r < -2.0 ? -2 : (int)r));
+        uL[L] = __builtin_amdgcn_readfirstlane(bnd[2 * kKmax + L]);
+        uR[L] = __builtin_amdgcn_readfirstlane(bnd[2 * kKmax + kAdjLevels + L]);
       }
       const int sL = uL[0] < sb ? (uL[0] < sa - 1 ? sa - 1 : uL[0]) : sb;
       const int sR = uR[0] > sa ? (uR[0] > sb + 1 ? sb + 1 : uR[0]) : sa;
@@ -3475,6 +3510,12 @@ hipError_t launch_combine_far(const FarArgs& a, hipStream_t st) {
   if (a.n_tiles_total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_combine_far, dim3(a.n_tiles_total), dim3(kThreads), 0, st, a);
   return hipGetLastError();
+}
+
+int adj_max_blocks_per_cu() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_adjoint, kThreads, 0) != hipSuccess) return 1;
+  return n > 0 ? n : 1;
 }
 
 int far_max_blocks_per_cu() {
