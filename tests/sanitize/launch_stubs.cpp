@@ -31,6 +31,7 @@ hipError_t launch_cut_bounds(const double*, const int32_t*, int64_t, double, dou
 hipError_t launch_far(const FarArgs&, int, int, hipStream_t) { return none(); }
 hipError_t launch_combine_far(const FarArgs&, hipStream_t) { return none(); }
 int far_max_blocks_per_cu() { return 1; }
+int adj_max_blocks_per_cu() { return 1; }
 hipError_t launch_adj_nodes(const float*, int64_t, int, const double*, double*, hipStream_t) { return none(); }
 hipError_t launch_adjoint(const AdjArgs&, int, hipStream_t) { return none(); }
 hipError_t launch_reduce2(const double*, int64_t, double*, int, double*, hipStream_t) { return none(); }
